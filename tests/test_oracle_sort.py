@@ -1,0 +1,141 @@
+"""Pins of the oracle's sort against definitions and library routines.
+
+The oracle must reach the unique result the sort is defined by (Sec. 2.1:
+position = number of keys before it; Sec. 2.2: the output must be sorted):
+the stable sort in IEEE totalOrder (float64) or numeric order (uint64).
+None of these checks reuses the oracle's key transform.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_08637_amd import inputs
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def f64(u):
+    return np.array([u], dtype=np.uint64).view(np.float64)[0]
+
+
+# IEEE 754-2008 totalOrder (5.10), written out class by class in ascending order.
+TOTAL_ORDER = [
+    f64(0xFFF8000000000001),   # negative quiet NaN with the larger payload
+    f64(0xFFF8000000000000),   # negative quiet NaN
+    -np.inf, -1.7976931348623157e308, -1.0, -2.2250738585072014e-308, -2.225073858507201e-308, -5e-324,
+    -0.0, 0.0,
+    5e-324, 2.225073858507201e-308, 2.2250738585072014e-308, 1.0, 1.7976931348623157e308, np.inf,
+    f64(0x7FF8000000000000),   # positive quiet NaN
+    f64(0x7FF8000000000001),
+]
+
+
+def test_total_order_classes():
+    want = np.array(TOTAL_ORDER)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        got, _ = oracle.sort(rng.permutation(want))
+        assert np.array_equal(bits(got), bits(want))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 10, 1000, 100_000])
+def test_matches_numpy_sort_finite(n):
+    rng = np.random.default_rng(n)
+    a = rng.normal(0, 1e3, n)
+    a = a[a != 0]
+    got, _ = oracle.sort(a)
+    assert np.array_equal(got, np.sort(a, kind="stable"))
+    u = rng.integers(0, 2**64, n, dtype=np.uint64, endpoint=False)
+    got, _ = oracle.sort(u)
+    assert np.array_equal(got, np.sort(u))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "u64"])
+def test_stable_perm_matches_argsort(dtype):
+    rng = np.random.default_rng(1)
+    n = 50_000
+    if dtype == "f64":
+        a = rng.integers(-50, 50, n).astype(np.float64) + 0.5   # duplicates, no zeros
+    else:
+        a = rng.integers(0, 100, n).astype(np.uint64)
+    pay = np.arange(n, dtype=np.uint32)
+    got, gp, perm = oracle.sort(a, pay, want_perm=True)
+    ref = np.argsort(a, kind="stable")
+    assert np.array_equal(perm, ref.astype(np.uint64))
+    assert np.array_equal(gp, ref.astype(np.uint32))
+    assert np.array_equal(got, a[ref])
+
+
+def precedes(x, y):
+    """x strictly before y in totalOrder, for non-NaN doubles."""
+    if x < y:
+        return True
+    return x == 0 and y == 0 and np.signbit(x) and not np.signbit(y)
+
+
+def test_dest_closed_form_bruteforce():
+    rng = np.random.default_rng(2)
+    for n in (1, 2, 7, 64, 500, 2000):
+        a = rng.choice(np.array([-3.0, -0.0, 0.0, 1.5, 2.0, 1e300, -1e-300]), n)
+        _, _, perm = oracle.sort(a, want_perm=True)
+        dest = np.empty(n, dtype=np.int64)
+        dest[perm.astype(np.int64)] = np.arange(n)
+        for i in range(n):
+            before = sum(precedes(a[j], a[i]) for j in range(n))
+            ties = sum(1 for j in range(i) if bits(a[j:j + 1])[0] == bits(a[i:i + 1])[0])
+            assert dest[i] == before + ties
+
+
+def test_all_permutations_small():
+    alphabet = [-0.0, 0.0, 1.0, 1.0, -2.5, 0.0]
+    want = None
+    for p in itertools.permutations(range(len(alphabet))):
+        a = np.array([alphabet[i] for i in p])
+        pay = np.array(p, dtype=np.uint32)
+        got, gp = oracle.sort(a, pay)
+        if want is None:
+            want = bits(got).copy()
+        assert np.array_equal(bits(got), want)
+        # stable: equal keys keep input order, i.e. payload order within a run
+        for v in set(bits(got).tolist()):
+            run = gp[bits(got) == v]
+            pos = [list(p).index(x) for x in run]
+            assert pos == sorted(pos)
+    assert np.array_equal(want, bits(np.array([-2.5, -0.0, 0.0, 0.0, 1.0, 1.0])))
+
+
+@pytest.mark.parametrize("kind", inputs.ADVERSARIAL_F64 + inputs.ADVERSARIAL_U64)
+def test_adversarial_invariants(kind):
+    a = inputs.adversarial(kind, 20_000, seed=3)
+    pay = np.arange(a.size, dtype=np.uint32)
+    got, gp = oracle.sort(a, pay)
+    # a permutation of the input, with the payload travelling with its key
+    assert np.array_equal(np.sort(bits(got)), np.sort(bits(a)))
+    assert np.array_equal(bits(a)[gp], bits(got))
+    # sorted: non-NaN keys agree with numpy's value order wherever values differ
+    if a.dtype == np.float64:
+        g = got[~np.isnan(got)]
+        assert np.all(g[:-1] <= g[1:])
+        nan_sign = np.signbit(got[np.isnan(got)])
+        k = int(nan_sign.sum())
+        assert np.all(np.isnan(got[:k])) and np.all(np.isnan(got[got.size - (nan_sign.size - k):]))
+    else:
+        assert np.all(got[:-1] <= got[1:])
+    # stable
+    b = bits(got)
+    same = b[1:] == b[:-1]
+    assert np.all(gp[1:][same] > gp[:-1][same])
+
+
+def test_segmented_matches_per_segment():
+    keys, off, pay, _ = inputs.segmented(30, seed=4, lo=1, hi=5000)
+    got, gp = oracle.sort_segmented(keys, off, pay)
+    for s in range(30):
+        a, b = int(off[s]), int(off[s + 1])
+        r = np.argsort(keys[a:b], kind="stable")
+        assert np.array_equal(got[a:b], keys[a:b][r])
+        assert np.array_equal(gp[a:b], pay[a:b][r])
