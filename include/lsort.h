@@ -1,0 +1,244 @@
+/*
+ * lsort.h -- C ABI of liblsort: a learned sample sort for AMD MI355X (gfx950).
+ *
+ * Method: "LearnedSort as a learning-augmented SampleSort" (Carvalho &
+ * Lawrence, SSDBM 2023).  A CDF model fitted on a random sample maps each key
+ * to a bucket (Sec. 2.2, bucket = floor(B * F(x))); buckets are histogrammed,
+ * prefix-summed and scattered; large buckets recurse, buckets whose keys are
+ * all equal stop (Sec. 2.2 homogeneity check; Sec. 2.4 equality buckets) and
+ * small ones get a base-case sort (Sec. 4).  The model is a monotone
+ * two-level linear RMI (Sec. 2.1; monotone constraint of Sec. 4), an optional
+ * monotone FP32 MLP, or -- when the input is small or duplicate-heavy (Alg. 5)
+ * and whenever a bucket comes out more than twice its expected size -- a
+ * splitter tree (Sec. 2.4).
+ *
+ * Conventions for every entry point:
+ *   - Pointers to keys, payloads, offsets and outputs are DEVICE pointers
+ *     (memory from hipMalloc / torch on the current device) unless a
+ *     parameter says "host".  The library never frees caller memory.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns without waiting, except where noted.
+ *   - Return value: LS_OK (0) or a negative ls_status; ls_last_error() then
+ *     holds a message (thread-local).  Nothing aborts or throws across the
+ *     ABI.
+ *   - Keys are float64 ordered by IEEE-754 totalOrder
+ *     (-NaN < -inf < ... < -0.0 < +0.0 < ... < +inf < +NaN) or uint64 in
+ *     numeric order.  Sorting is stable: a uint32 payload follows its key and
+ *     equal keys keep their input order.
+ *   - Calls that share a workspace (the library's own, per device, unless
+ *     ls_set_workspace gave one) must not overlap in time: the library
+ *     serialises them on one stream per call; two threads that sort on two
+ *     streams at once must each set their own workspace.
+ */
+#ifndef LSORT_H
+#define LSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { LS_F64 = 0, LS_U64 = 1 } ls_dtype;
+
+typedef enum {
+    LS_OK = 0,
+    LS_EINVAL = -1,       /* bad argument: null pointer with n > 0, bad dtype, misalignment, bad option */
+    LS_ENOMEM = -2,       /* workspace could not be allocated or is too small */
+    LS_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+    LS_EUNSUPPORTED = -4  /* option combination not implemented */
+} ls_status;
+
+/* Partition model of the first level (Alg. 5 decides under LS_MODEL_AUTO). */
+typedef enum {
+    LS_MODEL_AUTO = 0,     /* RMI if n >= 1e5 and <= 10% sample duplicates, else splitter tree */
+    LS_MODEL_RMI = 1,      /* same as AUTO (the policy may still pick the tree) */
+    LS_MODEL_MLP = 2,      /* monotone 1-16-16-1 FP32 MLP CDF trained on the GPU (single-array sort only) */
+    LS_MODEL_SPLITTER = 3  /* classic SampleSort: splitter tree at every level */
+} ls_model;
+
+/* Option flags. */
+#define LS_FLAG_NO_FALLBACK   0x1u  /* never replace an oversized learned bucket's model by a splitter tree */
+#define LS_FLAG_SYNC_LEVELS   0x2u  /* (host) read back the work count after each level to stop early; default on */
+#define LS_FLAG_FIXED_LEVELS  0x4u  /* launch exactly max_levels levels with no host read-back (graph capture) */
+#define LS_FLAG_COLLECT_STATS 0x8u  /* record per-level statistics (read with ls_get_stats) */
+
+/* Options.  Zero-initialise and set struct_size = sizeof(ls_options); every
+ * zero field takes its default. */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t model;          /* ls_model; default AUTO */
+    uint32_t buckets;        /* B of a learned level; default 1000 (Sec. 2.1/2.2); 2..1024 */
+    uint32_t leaves;         /* RMI leaves L; default 1000 (Sec. 2.1); 2..1024 */
+    uint32_t tree_buckets;   /* splitter-tree fan-out; default 256 (Sec. 4); power of two 2..512 */
+    uint32_t cutoff;         /* base case below this many keys; default 4096 (Sec. 4); 1..4096 */
+    uint32_t max_levels;     /* model-based levels before range radix (8 bits per level) takes over; default 16; 1..23 */
+    uint32_t flags;          /* LS_FLAG_* */
+    double sample_frac;      /* sample size as a fraction of n; default 0.01 (Sec. 2.2) */
+    double fallback_ratio;   /* oversized bucket threshold, x expected; default 2.0 */
+    uint64_t seed;           /* sampling seed; default 0x5EED */
+    uint32_t mlp_steps;      /* MLP Adam steps; default 200 */
+    uint32_t mlp_sample;     /* MLP training sample; default 1e6 (capped at n) */
+    float mlp_lr;            /* MLP Adam learning rate; default 1e-2 */
+    uint32_t reserved[5];
+} ls_options;
+
+/* Per-call statistics (LS_FLAG_COLLECT_STATS). */
+#define LS_MAX_STAT_LEVELS 32
+typedef struct {
+    uint64_t segments;       /* sub-arrays partitioned at this level */
+    uint64_t keys;           /* keys partitioned at this level */
+    uint64_t buckets;        /* buckets produced (sum over segments) */
+    uint64_t max_bucket;     /* largest bucket */
+    uint64_t max_bucket_x1000_over_mean; /* max over segments of 1000 * max bucket / (n_seg / B_seg) */
+    uint64_t empty;          /* empty buckets */
+    uint64_t equality;       /* equality buckets (or single-value buckets) finished here */
+    uint64_t base;           /* buckets sent to the base case */
+    uint64_t recurse;        /* buckets partitioned again */
+    uint64_t fallback;       /* oversized buckets re-partitioned by a splitter tree */
+    uint64_t learned;        /* segments partitioned by a learned model (RMI or MLP) */
+    uint64_t tree;           /* segments partitioned by a splitter tree */
+    uint64_t radix;          /* segments partitioned by range radix */
+} ls_level_stats;
+
+typedef struct {
+    uint32_t levels;         /* partition levels run */
+    uint32_t first_model;    /* ls_model actually used by the first level of the first segment */
+    uint64_t base_items;     /* base-case sub-arrays sorted */
+    uint64_t copy_items;     /* finished runs copied back to the caller's buffer */
+    double mlp_loss_first;   /* MLP training: loss at step 1 and at the last step */
+    double mlp_loss_last;
+    ls_level_stats level[LS_MAX_STAT_LEVELS];
+} ls_stats;
+
+/* ---- Sorting -------------------------------------------------------------- */
+
+/* Sort keys[0..n) in place (stable), permuting payload (nullable) with them.
+ * keys: device, 8-byte aligned, n keys of `dtype`.  payload: device, 4-byte
+ * aligned, n entries, or NULL.  opt: NULL for defaults.  n = 0 or 1 is a
+ * no-op.  Errors: LS_EINVAL (null keys with n > 0, bad dtype, misalignment,
+ * option out of range), LS_ENOMEM, LS_EHIP. */
+ls_status ls_sort(void *keys, uint64_t n, ls_dtype dtype, uint32_t *payload,
+                  const ls_options *opt, void *stream);
+
+/* Sort each segment [offsets[i], offsets[i+1]) of keys independently, in
+ * place, in one batched pass (all segments share every kernel launch).
+ * offsets: DEVICE array of m + 1 non-decreasing uint64 values; offsets[m] is
+ * the total length.  host_total: offsets[m] as known by the host (sizes the
+ * workspace; must be >= offsets[m]).  Malformed offsets are undefined
+ * behaviour.  Errors as ls_sort; LS_EUNSUPPORTED for LS_MODEL_MLP. */
+ls_status ls_sort_segmented(void *keys, const uint64_t *offsets, uint64_t m, uint64_t host_total,
+                            ls_dtype dtype, uint32_t *payload, const ls_options *opt, void *stream);
+
+/* Bytes of workspace a call with these sizes needs (written to *out, host). */
+ls_status ls_workspace_bytes(uint64_t n_total, uint64_t m, ls_dtype dtype, int has_payload,
+                             const ls_options *opt, size_t *out);
+
+/* Use caller memory (device, 256-byte aligned) as the workspace of later
+ * calls on this device; dev_ptr = NULL returns to the library's own pool.
+ * The library never allocates while a workspace is set: a call that needs
+ * more than `bytes` fails with LS_ENOMEM. */
+ls_status ls_set_workspace(void *dev_ptr, size_t bytes);
+
+/* Statistics of the last completed call made with LS_FLAG_COLLECT_STATS on
+ * this thread.  Waits for that call's stream. out: host. */
+ls_status ls_get_stats(ls_stats *out);
+
+/* Message for the last non-OK status on this thread (never NULL). */
+const char *ls_last_error(void);
+
+/* Library version string, e.g. "lsort 0.1 gfx950". */
+const char *ls_version(void);
+
+/* ---- Single steps (exposed so each step can be checked on its own) -------- */
+
+/* Random sample with replacement (Sec. 2.2: the model is trained on a ~1%
+ * sample; Alg. 5 Sample): out[k] = keys[idx_k], idx_k = high 64 bits of
+ * SplitMix64(seed, k) * n (SplitMix64 of Steele, Lea & Flood, output k =
+ * finaliser(seed + (k+1) * 0x9E3779B97F4A7C15)).  keys, out: device. */
+ls_status ls_sample(const void *keys, uint64_t n, ls_dtype dtype, uint64_t seed, uint64_t S,
+                    void *out, void *stream);
+
+/* Fit the monotone two-level linear RMI (Sec. 2.1; monotone clamp of Sec. 4)
+ * on a SORTED sample of S keys (device).  Writes 2 + 4L doubles to params
+ * (device): alpha_r = L*a_root, beta_r = L*b_root, then for each leaf j
+ * R*(a_j, b_j, c_j, d_j), where leaf j's line a_j x + b_j is the least-squares
+ * fit to (x_i, i/S) over the sample points the root sends to leaf j (slope
+ * clamped >= 0), and [c_j, d_j] is its monotone clamp interval
+ * (c_j = clip01(max(line(min_j), d_{j-1})), d_j = clip01(max(line(max_j), c_j)),
+ * d_{-1} = 0; an empty leaf is the flat line at d_{j-1}).  R: total bucket
+ * resolution the scaled leaf parameters target.  Requires finite keys,
+ * S >= 2, 2 <= L <= 1024. */
+ls_status ls_rmi_fit(const void *sorted_sample, uint64_t S, ls_dtype dtype, uint32_t L, double R,
+                     double *params, void *stream);
+
+/* Bucket ids of keys under RMI params (the layout ls_rmi_fit writes):
+ * j = clamp(floor(fma(alpha_r, x, beta_r)), 0, L-1),
+ * g = clamp(floor(clamp(fma(alpha_j, x, beta_j), gamma_j, delta_j)), 0, R-1)
+ * (Sec. 2.2 bucket formula; Alg. 4 line computing g).  Non-finite float64
+ * keys: bucket 0 for negative sign, R-1 otherwise.  out: device uint32[n]. */
+ls_status ls_rmi_buckets(const void *keys, uint64_t n, ls_dtype dtype, const double *params,
+                         uint32_t L, double R, uint32_t *out, void *stream);
+
+/* Splitters of a SORTED sample (Sec. 2.4): candidate i = sample[floor((i+1)S/B)],
+ * i < B-1, de-duplicated; a repeated candidate gets an equality bucket.
+ * Writes m unique splitters in ordered-key form (device uint64[B-1]),
+ * equality flags (device uint8[B-1]) and m (device uint32[1]). */
+ls_status ls_splitters(const void *sorted_sample, uint64_t S, ls_dtype dtype, uint32_t B,
+                       uint64_t *splitters, uint8_t *eq, uint32_t *m, void *stream);
+
+/* Bucket ids under splitters: with k = #{splitters <= key}, buckets run in
+ * key order -- the range below splitter 0, then per splitter its equality
+ * bucket (if flagged) and the range above it.  m: host.  out: device. */
+ls_status ls_splitter_buckets(const void *keys, uint64_t n, ls_dtype dtype, const uint64_t *splitters,
+                              const uint8_t *eq, uint32_t m, uint32_t *out, void *stream);
+
+/* One stable partition level (Sec. 2.2 partitioning): bucket ids from the RMI
+ * params at resolution R with every R/nb consecutive fine buckets merged into
+ * one (nb divides R), histogram, prefix sum (decoupled look-back), stable
+ * scatter of keys (and payload) into out_keys / out_payload.  counts: device
+ * uint64[nb] (bucket sizes).  All arrays device; payload nullable. */
+ls_status ls_partition_rmi(const void *keys, const uint32_t *payload, uint64_t n, ls_dtype dtype,
+                           const double *params, uint32_t L, double R, uint32_t nb,
+                           void *out_keys, uint32_t *out_payload, uint64_t *counts, void *stream);
+
+/* Same with the splitter-tree bucket function (m host, splitters/eq device). */
+ls_status ls_partition_splitters(const void *keys, const uint32_t *payload, uint64_t n, ls_dtype dtype,
+                                 const uint64_t *splitters, const uint8_t *eq, uint32_t m,
+                                 void *out_keys, uint32_t *out_payload, uint64_t *counts, void *stream);
+
+/* ---- Monotone MLP CDF (1-16-16-1, FP32) ----------------------------------- */
+/* Parameter vector: 321 floats V1[16] b1[16] V2[16x16] b2[16] V3[16] b3[1];
+ * effective weights |V|; hidden units 0..7 use max(z,0), 8..15 use min(z,0);
+ * so the network is non-decreasing in its input (Sec. 3.1 monotone CDF).
+ * Input t = clamp((x - lo) * inv, 0, 1) in fp64 rounded to fp32. */
+
+/* Mean squared error of the unclamped output against targets y and its
+ * gradient over the 321 parameters, on the GPU in FP32 with a fixed-order
+ * two-stage reduction.  t, y: device float[S].  params: device float[321].
+ * grad: device float[321].  loss: device float[1]. */
+ls_status ls_mlp_loss_grad(const float *params, const float *t, const float *y, uint64_t S,
+                           float *grad, float *loss, void *stream);
+
+/* Train on a SORTED sample (device, S keys): targets i/S, full-batch Adam
+ * (Kingma & Ba 2015) for `steps` steps with learning rate lr, betas (0.9,
+ * 0.999), eps 1e-8, from params_init (device float[321]) or, if NULL, a
+ * seeded initialisation.  Writes the trained parameters to params_out
+ * (device float[321]), lo and inv (device double[2]) and the loss after each
+ * step to losses (device float[steps], nullable). */
+ls_status ls_mlp_train(const void *sorted_sample, uint64_t S, ls_dtype dtype, const float *params_init,
+                       uint32_t steps, float lr, uint64_t seed, float *params_out, double *lo_inv,
+                       float *losses, void *stream);
+
+/* Bucket ids under a trained MLP: g = min(floor(F * R), R - 1) in fp32 with
+ * F = clamp(net(t), 0, 1) evaluated as fmaf chains in index order.
+ * lo_inv: device double[2].  out: device uint32[n]. */
+ls_status ls_mlp_buckets(const void *keys, uint64_t n, ls_dtype dtype, const float *params,
+                         const double *lo_inv, uint32_t R, uint32_t *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSORT_H */

@@ -1,0 +1,720 @@
+// lsort_api.hip -- host planner and C ABI of liblsort.
+//
+// The planner lays out one workspace per call (temporary key/payload
+// buffers, per-level segment and tile lists, base-case items, bucket counts,
+// look-back status words, model arenas), enqueues the fixed kernel sequence
+// of each partition level on the caller's stream and, unless asked to launch
+// a fixed number of levels, reads back one counter per level to stop when no
+// sub-array needs another level.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lsort.h"
+#include "lsort_internal.hpp"
+#include "lsort_kernels.hpp"
+
+namespace ls {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err = "";
+
+static ls_status fail(ls_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(LS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------
+struct Opts {
+    uint32_t model, buckets, leaves, tree_buckets, cutoff, max_levels, flags;
+    double sample_frac, fallback_ratio;
+    uint64_t seed;
+    uint32_t mlp_steps, mlp_sample;
+    float mlp_lr;
+};
+
+static ls_status normalize(const ls_options* o, Opts& r) {
+    r.model = LS_MODEL_AUTO; r.buckets = 1000; r.leaves = 1000; r.tree_buckets = 256; r.cutoff = 4096;
+    r.max_levels = 16; r.flags = LS_FLAG_SYNC_LEVELS; r.sample_frac = 0.01; r.fallback_ratio = 2.0; r.seed = 0x5EED;
+    r.mlp_steps = 200; r.mlp_sample = 1000000; r.mlp_lr = 1e-2f;
+    if (!o) return LS_OK;
+    if (o->struct_size != sizeof(ls_options)) return fail(LS_EINVAL, "ls_options.struct_size mismatch");
+    if (o->model > LS_MODEL_SPLITTER) return fail(LS_EINVAL, "unknown model");
+    r.model = o->model;
+    if (o->buckets) r.buckets = o->buckets;
+    if (o->leaves) r.leaves = o->leaves;
+    if (o->tree_buckets) r.tree_buckets = o->tree_buckets;
+    if (o->cutoff) r.cutoff = o->cutoff;
+    if (o->max_levels) r.max_levels = o->max_levels;
+    if (o->flags) r.flags = o->flags;
+    if (o->sample_frac > 0) r.sample_frac = o->sample_frac;
+    if (o->fallback_ratio > 0) r.fallback_ratio = o->fallback_ratio;
+    if (o->seed) r.seed = o->seed;
+    if (o->mlp_steps) r.mlp_steps = o->mlp_steps;
+    if (o->mlp_sample) r.mlp_sample = o->mlp_sample;
+    if (o->mlp_lr > 0) r.mlp_lr = o->mlp_lr;
+    if (r.buckets < 2 || r.buckets > B_MAX) return fail(LS_EINVAL, "buckets must be in [2, 1024]");
+    if (r.leaves < 2 || r.leaves > L_MAX) return fail(LS_EINVAL, "leaves must be in [2, 1024]");
+    if (r.tree_buckets < 2 || r.tree_buckets > 512 || (r.tree_buckets & (r.tree_buckets - 1)))
+        return fail(LS_EINVAL, "tree_buckets must be a power of two in [2, 512]");
+    if (r.cutoff < 1 || r.cutoff > C_MAX) return fail(LS_EINVAL, "cutoff must be in [1, 4096]");
+    if (r.max_levels < 1 || r.max_levels > MAXL - 9) return fail(LS_EINVAL, "max_levels must be in [1, 23]");
+    if (r.sample_frac > 1.0) return fail(LS_EINVAL, "sample_frac must be in (0, 1]");
+    return LS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+static inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+
+struct Layout {
+    uint64_t n, m;
+    int has_pay;
+    uint64_t seg_cap, tile_cap, item_cap, counts_cap, status_cap, arena_cap;
+    uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_counts, o_status,
+        o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested;
+    uint64_t S_big;       // large-path sample size (0: none)
+    uint64_t bytes;
+    std::vector<Layout> nested;  // sorting the large-path sample
+};
+
+static uint64_t big_sample_size(uint64_t n, uint64_t m, const Opts& o) {
+    if (m != 1) return 0;
+    uint64_t S = (uint64_t)std::ceil(o.sample_frac * (double)n);
+    return S > (uint64_t)S_LDS ? S : 0;
+}
+
+static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
+    Layout L{};
+    L.n = n; L.m = m; L.has_pay = has_pay;
+    const uint64_t C = o.cutoff;
+    L.seg_cap = std::max<uint64_t>(m, n / (C + 1)) + 16;
+    L.tile_cap = n / TILE + L.seg_cap + 16;
+    L.item_cap = n + m + 64;
+    L.counts_cap = 2 * (n / 4 + 2 * L.seg_cap) + 64;
+    L.status_cap = (n / TILE) * B_MAX + n / 4 + 2 * L.seg_cap + 64;
+    L.arena_cap = (n / 100000 + m + 2) * (8ull * MODEL_WORDS + 16) + (uint64_t)(0.7 * (double)n) + L.seg_cap * 32 + 65536;
+    uint64_t o_ = 0;
+    auto take = [&](uint64_t bytes) { uint64_t r = o_; o_ += align256(bytes); return r; };
+    L.o_persist = take(256);
+    L.o_ctl = take(sizeof(Ctl));
+    L.o_tmp = take(n * 8);
+    L.o_tmppay = has_pay ? take(n * 4) : 0;
+    L.o_ids = 0;
+    L.o_segs[0] = take(L.seg_cap * sizeof(Seg));
+    L.o_segs[1] = take(L.seg_cap * sizeof(Seg));
+    L.o_tiles[0] = take(L.tile_cap * sizeof(Tile));
+    L.o_tiles[1] = take(L.tile_cap * sizeof(Tile));
+    L.o_items = take(L.item_cap * 8);
+    L.o_counts = take(L.counts_cap * 8);
+    L.o_status = take(L.status_cap * 8);
+    L.o_arena[0] = take(L.arena_cap);
+    L.o_arena[1] = take(L.arena_cap);
+    L.o_bigmodel = take(8ull * MODEL_WORDS + 64);
+    L.o_part = take(FIT_G * 8 * 8);
+    L.o_leaf = take(L_MAX * 8 * 8);
+    L.o_flag = take(256);
+    L.S_big = big_sample_size(n, m, o);
+    if (L.S_big) {
+        L.o_sample = take(L.S_big * 8);
+        L.nested.push_back(plan(L.S_big, 1, 0, o));
+        L.o_nested = take(L.nested[0].bytes);
+    }
+    L.bytes = o_;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// library-owned workspace (per device, grow-only) and per-thread call state
+// ---------------------------------------------------------------------------
+struct DevPool {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    void* user = nullptr;
+    size_t user_bytes = 0;
+    hipEvent_t last = nullptr;
+    hipStream_t last_stream = nullptr;
+    uint64_t* pinned = nullptr;  // host read-back slots
+    int cus = 0;
+    uint64_t sig = 0;            // layout of the last call (status pools valid for it)
+};
+static std::mutex g_mu;
+static DevPool g_pool[64];
+
+struct LastCall {
+    Ctl* ctl = nullptr;
+    hipStream_t st = nullptr;
+    int dev = -1;
+    bool valid = false;
+};
+static thread_local LastCall g_last;
+
+static uint64_t layout_sig(const Layout& L) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+    mix(L.o_persist); mix(L.o_status); mix(L.status_cap); mix(L.bytes);
+    for (const Layout& c : L.nested) { mix(c.o_status); mix(c.status_cap); mix(c.bytes); }
+    return h;
+}
+
+// The look-back words of a workspace are only valid against the history of
+// that same layout: when the layout changes, clear them (and the epoch).
+static ls_status prepare_status(DevPool* pool, uint8_t* base, const Layout& L, hipStream_t st) {
+    uint64_t sig = layout_sig(L);
+    if (sig == pool->sig) return LS_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(LS_EINVAL, "first call with this size must run outside stream capture (workspace set-up)");
+    std::vector<std::pair<uint8_t*, const Layout*>> todo{{base, &L}};
+    while (!todo.empty()) {
+        auto [b, l] = todo.back();
+        todo.pop_back();
+        HIP_TRY(hipMemsetAsync(b + l->o_persist, 0, 256, st));
+        HIP_TRY(hipMemsetAsync(b + l->o_status, 0, l->status_cap * 8, st));
+        for (const Layout& c : l->nested) todo.push_back({b + l->o_nested, &c});
+    }
+    pool->sig = sig;
+    return LS_OK;
+}
+
+static ls_status acquire(uint64_t bytes, const Layout& L, DevPool*& pool, uint8_t*& base) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(LS_EINVAL, "device index out of range");
+    pool = &g_pool[dev];
+    if (!pool->cus) {
+        HIP_TRY(hipDeviceGetAttribute(&pool->cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HIP_TRY(hipEventCreateWithFlags(&pool->last, hipEventDisableTiming));
+        HIP_TRY(hipHostMalloc((void**)&pool->pinned, 4096, hipHostMallocDefault));
+    }
+    if (pool->user) {
+        if (bytes > pool->user_bytes)
+            return fail(LS_ENOMEM, "workspace set by ls_set_workspace is too small: need " + std::to_string(bytes) +
+                                       " bytes");
+        base = (uint8_t*)pool->user;
+        return LS_OK;
+    }
+    if (bytes > pool->bytes) {
+        if (pool->ptr) HIP_TRY(hipFree(pool->ptr));
+        pool->ptr = nullptr;
+        pool->bytes = 0;
+        pool->sig = 0;
+        size_t want = (size_t)(bytes + bytes / 8 + (1 << 20));
+        if (hipMalloc(&pool->ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            pool->ptr = nullptr;
+            return fail(LS_ENOMEM, "cannot allocate a workspace of " + std::to_string(want) + " bytes");
+        }
+        pool->bytes = want;
+        HIP_TRY(hipMemset(pool->ptr, 0, want));
+    }
+    base = (uint8_t*)pool->ptr;
+    (void)L;
+    return LS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the engine
+// ---------------------------------------------------------------------------
+struct Call {
+    uint64_t* keys;
+    uint32_t* pay;
+    uint64_t n;
+    uint64_t m;
+    const uint64_t* offsets;   // device, null for a single array
+    int u64;
+    Opts o;
+    hipStream_t st;
+    // first level given by the caller (single-step partition): model already
+    // at layout.o_bigmodel and described in segs[1][0]; run one level only
+    bool one_level = false;
+    uint64_t* out_keys = nullptr;
+    uint32_t* out_pay = nullptr;
+};
+
+static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
+    Params P{};
+    P.keys[0] = c.keys;
+    P.keys[1] = c.one_level ? c.out_keys : (uint64_t*)(base + L.o_tmp);
+    P.pay[0] = c.pay;
+    P.pay[1] = c.pay ? (c.one_level ? c.out_pay : (uint32_t*)(base + L.o_tmppay)) : nullptr;
+    P.u64 = c.u64;
+    P.has_pay = c.pay != nullptr;
+    P.buckets = c.o.buckets; P.leaves = c.o.leaves; P.tree_buckets = c.o.tree_buckets; P.cutoff = c.o.cutoff;
+    P.max_levels = c.o.max_levels; P.flags = c.o.flags; P.model = c.o.model;
+    P.sample_frac = c.o.sample_frac; P.fallback_ratio = c.o.fallback_ratio; P.seed = c.o.seed;
+    P.ctl = (Ctl*)(base + L.o_ctl);
+    for (int i = 0; i < 2; i++) {
+        P.segs[i] = (Seg*)(base + L.o_segs[i]);
+        P.tiles[i] = (Tile*)(base + L.o_tiles[i]);
+        P.arena[i] = base + L.o_arena[i];
+    }
+    P.items = (uint64_t*)(base + L.o_items);
+    P.counts = (unsigned long long*)(base + L.o_counts);
+    P.status = (unsigned long long*)(base + L.o_status);
+    P.ids = nullptr;
+    P.seg_cap = L.seg_cap; P.tile_cap = L.tile_cap; P.item_cap = L.item_cap; P.counts_cap = L.counts_cap;
+    P.status_cap = L.status_cap; P.arena_cap = L.arena_cap;
+    P.persist = (const uint64_t*)(base + L.o_persist);
+    P.level = 0;
+    return P;
+}
+
+static std::string overflow_text(uint32_t f) {
+    std::string s;
+    if (f & OVF_SEG) s += " segments";
+    if (f & OVF_TILE) s += " tiles";
+    if (f & OVF_ITEM) s += " base-case items";
+    if (f & OVF_COUNTS) s += " bucket counts";
+    if (f & OVF_STATUS) s += " look-back words";
+    if (f & OVF_ARENA) s += " model arena";
+    return s;
+}
+
+static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* pool);
+
+// Large first level: sample ~1% of the keys, sort the sample with the same
+// engine, then fit the RMI (or build the splitter tree) over it with the
+// multi-workgroup fit kernels (Alg. 5).  The model lands in o_bigmodel and its
+// descriptor in segs[1][0] for k_seed to pick up.
+static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPool* pool, const Params& P) {
+    uint64_t* smp = (uint64_t*)(base + L.o_sample);
+    const uint64_t sseed = 0;  // stream state for (offset 0, level 0): SplitMix64 output 0 of seed
+    (void)sseed;
+    // segment seed = splitmix64_at(seed, (off << 6) | level) with off = 0, level = 0
+    uint64_t z = c.o.seed + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    HIP_TRY(launch_gather(c.keys, c.n, z, L.S_big, smp, c.st));
+    Call nc{};
+    nc.keys = smp; nc.pay = nullptr; nc.n = L.S_big; nc.m = 1; nc.offsets = nullptr; nc.u64 = c.u64;
+    nc.o = c.o;
+    nc.o.flags = (c.o.flags & ~(uint32_t)LS_FLAG_FIXED_LEVELS) | LS_FLAG_SYNC_LEVELS;
+    if (c.o.flags & LS_FLAG_FIXED_LEVELS) nc.o.flags = c.o.flags;
+    nc.o.model = c.o.model == LS_MODEL_SPLITTER ? LS_MODEL_SPLITTER : LS_MODEL_AUTO;
+    nc.st = c.st;
+    ls_status s = run(nc, L.nested[0], base + L.o_nested, pool);
+    if (s) return s;
+    FitArgs A{};
+    A.s = smp; A.S = L.S_big; A.n = c.n; A.u64 = c.u64;
+    A.mode = c.o.model == LS_MODEL_SPLITTER ? 2 : 0;
+    A.mlp = 0;
+    A.L = c.o.leaves;
+    const uint64_t half = std::max<uint32_t>(1, c.o.cutoff / 2);
+    uint64_t B1 = std::min<uint64_t>(c.o.buckets, std::max<uint64_t>(2, (c.n + half - 1) / half));
+    B1 = std::min<uint64_t>(B1, std::max<uint64_t>(2, c.n / 4));
+    uint32_t log2B2 = 0;
+    uint64_t per = c.n / B1;
+    if (per > c.o.cutoff) {
+        uint64_t want = (per + half - 1) / half;
+        while ((1ull << log2B2) < want && log2B2 < 10) log2B2++;
+    }
+    A.B1 = (uint32_t)B1; A.log2B2 = log2B2; A.R = (double)(B1 << log2B2);
+    uint64_t nt = c.n / 16;
+    uint32_t Bt = 2;
+    while (Bt * 2 <= c.o.tree_buckets && Bt * 2 <= nt) Bt *= 2;
+    A.Bt = Bt;
+    A.G = FIT_G;
+    A.part = (double*)(base + L.o_part);
+    A.leaf = (double*)(base + L.o_leaf);
+    A.model = (uint64_t*)(base + L.o_bigmodel);
+    A.flag = (uint32_t*)(base + L.o_flag);
+    A.seg = P.segs[1];
+    HIP_TRY(launch_fit1(A, c.st));
+    HIP_TRY(launch_fit2(A, c.st));
+    HIP_TRY(launch_fit_root(A, c.st));
+    HIP_TRY(launch_fit_leaves(A, c.st));
+    HIP_TRY(launch_fit_finish(A, c.st));
+    return LS_OK;
+}
+
+static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* pool) {
+    Params P = make_params(c, L, base);
+    uint64_t* persist = (uint64_t*)(base + L.o_persist);
+    HIP_TRY(launch_reset(P, persist, c.st));
+    uint32_t prebuilt = 0;
+    if (c.one_level) {
+        prebuilt = 1;
+    } else if (L.S_big) {
+        ls_status s = big_model(c, L, base, pool, P);
+        if (s) return s;
+        prebuilt = 1;
+    }
+    const uint32_t seed_grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((c.m + 255) / 256, 256), 65535);
+    HIP_TRY(launch_seed(P, c.offsets, c.m, c.n, prebuilt, persist, seed_grid, c.st));
+    const uint32_t cus = (uint32_t)pool->cus;
+    const bool fixed = (c.o.flags & LS_FLAG_FIXED_LEVELS) != 0;
+    const uint32_t max_run = c.one_level ? 1 : std::min<uint32_t>(MAXL - 1, c.o.max_levels + 9);
+    uint32_t levels = 0;
+    for (uint32_t lvl = 0; lvl < max_run; lvl++) {
+        P.level = (int)lvl;
+        HIP_TRY(launch_model(P, lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024, c.st));
+        HIP_TRY(launch_hist(P, cus * 4, c.st));
+        HIP_TRY(launch_scan(P, lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024, c.st));
+        HIP_TRY(launch_scatter(P, cus, c.st));
+        levels = lvl + 1;
+        if (c.one_level || fixed) continue;
+        // read back the next level's work and the overflow flags
+        Ctl* ctl = P.ctl;
+        HIP_TRY(hipMemcpyAsync(pool->pinned, &ctl->nseg[lvl + 1], 4, hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 8, &ctl->overflow, 4, hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        uint32_t next = ((uint32_t*)pool->pinned)[0];
+        uint32_t ovf = ((uint32_t*)pool->pinned)[2];
+        if (ovf) return fail(LS_ENOMEM, "workspace capacity exceeded:" + overflow_text(ovf));
+        if (next == 0) break;
+    }
+    (void)levels;
+    if (!c.one_level) HIP_TRY(launch_base(P, cus * 2, c.st));
+    return LS_OK;
+}
+
+static ls_status check_keys(const void* keys, uint64_t n, ls_dtype dtype, const uint32_t* payload) {
+    if (dtype != LS_F64 && dtype != LS_U64) return fail(LS_EINVAL, "dtype must be LS_F64 or LS_U64");
+    if (n > 0 && !keys) return fail(LS_EINVAL, "keys is NULL");
+    if (((uintptr_t)keys) & 7) return fail(LS_EINVAL, "keys must be 8-byte aligned");
+    if (((uintptr_t)payload) & 3) return fail(LS_EINVAL, "payload must be 4-byte aligned");
+    if (n >= (1ull << 45)) return fail(LS_EINVAL, "n too large");
+    return LS_OK;
+}
+
+static ls_status order_after_last(DevPool* pool, hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusNone && pool->last_stream != st && pool->last_stream != nullptr)
+        HIP_TRY(hipStreamWaitEvent(st, pool->last, 0));
+    return LS_OK;
+}
+
+static ls_status mark_done(DevPool* pool, hipStream_t st, Ctl* ctl) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+        HIP_TRY(hipEventRecord(pool->last, st));
+        pool->last_stream = st;
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    g_last.ctl = ctl; g_last.st = st; g_last.dev = dev; g_last.valid = true;
+    return LS_OK;
+}
+
+static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, uint64_t n, ls_dtype dtype,
+                             uint32_t* payload, const ls_options* opt, void* stream) {
+    ls_status s = check_keys(keys, n, dtype, payload);
+    if (s) return s;
+    Opts o;
+    if ((s = normalize(opt, o))) return s;
+    if (o.model == LS_MODEL_MLP) return fail(LS_EUNSUPPORTED, "the MLP model is not available in this build");
+    if (n <= 1 || m == 0) return LS_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Layout L = plan(n, m, payload != nullptr, o);
+    DevPool* pool;
+    uint8_t* base;
+    if ((s = acquire(L.bytes, L, pool, base))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    if ((s = prepare_status(pool, base, L, st))) return s;
+    Call c{};
+    c.keys = (uint64_t*)keys; c.pay = payload; c.n = n; c.m = m; c.offsets = offsets; c.u64 = dtype == LS_U64;
+    c.o = o; c.st = st;
+    s = run(c, L, base, pool);
+    if (s) return s;
+    return mark_done(pool, st, (Ctl*)(base + L.o_ctl));
+}
+
+// Small scratch for the single-step entry points (model, fit partials).
+static ls_status step_scratch(uint8_t*& base, DevPool*& pool, Layout& L) {
+    Opts o;
+    normalize(nullptr, o);
+    L = plan(16, 1, 0, o);
+    ls_status s = acquire(L.bytes, L, pool, base);
+    if (!s) pool->sig = 0;  // this scratch may overlap another layout's look-back words
+    return s;
+}
+
+}  // namespace ls
+
+using namespace ls;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* ls_last_error(void) { return g_err.c_str(); }
+
+const char* ls_version(void) { return "lsort 0.1 gfx950"; }
+
+ls_status ls_sort(void* keys, uint64_t n, ls_dtype dtype, uint32_t* payload, const ls_options* opt, void* stream) {
+    return sort_common(keys, nullptr, 1, n, dtype, payload, opt, stream);
+}
+
+ls_status ls_sort_segmented(void* keys, const uint64_t* offsets, uint64_t m, uint64_t host_total, ls_dtype dtype,
+                            uint32_t* payload, const ls_options* opt, void* stream) {
+    if (m > 0 && !offsets) return fail(LS_EINVAL, "offsets is NULL");
+    if (((uintptr_t)offsets) & 7) return fail(LS_EINVAL, "offsets must be 8-byte aligned");
+    if (m >= (1ull << 32)) return fail(LS_EINVAL, "too many segments");
+    return sort_common(keys, offsets, m, host_total, dtype, payload, opt, stream);
+}
+
+ls_status ls_workspace_bytes(uint64_t n_total, uint64_t m, ls_dtype dtype, int has_payload, const ls_options* opt,
+                             size_t* out) {
+    if (!out) return fail(LS_EINVAL, "out is NULL");
+    if (dtype != LS_F64 && dtype != LS_U64) return fail(LS_EINVAL, "bad dtype");
+    Opts o;
+    ls_status s = normalize(opt, o);
+    if (s) return s;
+    *out = (size_t)plan(std::max<uint64_t>(n_total, 16), std::max<uint64_t>(m, 1), has_payload, o).bytes;
+    return LS_OK;
+}
+
+ls_status ls_set_workspace(void* dev_ptr, size_t bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(LS_EHIP, "hipGetDevice failed");
+    if (((uintptr_t)dev_ptr) & 255) return fail(LS_EINVAL, "workspace must be 256-byte aligned");
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevPool& p = g_pool[dev];
+    if (dev_ptr) {
+        if (hipMemset(dev_ptr, 0, bytes) != hipSuccess) return fail(LS_EHIP, "hipMemset of the workspace failed");
+        if (hipDeviceSynchronize() != hipSuccess) return fail(LS_EHIP, "hipDeviceSynchronize failed");
+    }
+    p.user = dev_ptr;
+    p.user_bytes = dev_ptr ? bytes : 0;
+    p.sig = 0;
+    return LS_OK;
+}
+
+ls_status ls_get_stats(ls_stats* out) {
+    if (!out) return fail(LS_EINVAL, "out is NULL");
+    if (!g_last.valid) return fail(LS_EINVAL, "no completed call on this thread");
+    HIP_TRY(hipStreamSynchronize(g_last.st));
+    Ctl c;
+    HIP_TRY(hipMemcpy(&c, g_last.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    uint32_t levels = 0;
+    for (int l = 0; l < MAXL && l < LS_MAX_STAT_LEVELS; l++) {
+        const LevelStats& s = c.lv[l];
+        ls_level_stats& d = out->level[l];
+        d.segments = s.segments; d.keys = s.keys; d.buckets = s.buckets; d.max_bucket = s.max_bucket;
+        d.max_bucket_x1000_over_mean = s.max_ratio_x1000; d.empty = s.empty; d.equality = s.equality;
+        d.base = s.base; d.recurse = s.recurse; d.fallback = s.fallback; d.learned = s.learned; d.tree = s.tree;
+        d.radix = s.radix;
+        if (s.segments) levels = l + 1;
+    }
+    out->levels = levels;
+    out->first_model = c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
+    out->base_items = c.nitems - c.ncopy;
+    out->copy_items = c.ncopy;
+    out->mlp_loss_first = c.mlp_loss[0];
+    out->mlp_loss_last = c.mlp_loss[1];
+    return LS_OK;
+}
+
+ls_status ls_sample(const void* keys, uint64_t n, ls_dtype dtype, uint64_t seed, uint64_t S, void* out, void* stream) {
+    ls_status s = check_keys(keys, n, dtype, nullptr);
+    if (s) return s;
+    if (S > 0 && (n == 0 || !out)) return fail(LS_EINVAL, "sampling needs n > 0 and an output");
+    if (S == 0) return LS_OK;
+    HIP_TRY(launch_gather((const uint64_t*)keys, n, seed, S, (uint64_t*)out, (hipStream_t)stream));
+    return LS_OK;
+}
+
+ls_status ls_rmi_fit(const void* sorted_sample, uint64_t S, ls_dtype dtype, uint32_t L, double R, double* params,
+                     void* stream) {
+    ls_status s = check_keys(sorted_sample, S, dtype, nullptr);
+    if (s) return s;
+    if (S < 2 || L < 2 || L > L_MAX || !params || !(R >= 1.0) || R > 4294967296.0)
+        return fail(LS_EINVAL, "ls_rmi_fit needs S >= 2, 2 <= L <= 1024, R >= 1, params");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    if ((s = step_scratch(base, pool, Lo))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    FitArgs A{};
+    A.s = (const uint64_t*)sorted_sample; A.S = S; A.n = S; A.u64 = dtype == LS_U64; A.mode = 1;
+    A.L = L; A.B1 = 1; A.log2B2 = 0; A.R = R; A.Bt = 2; A.G = FIT_G;
+    A.part = (double*)(base + Lo.o_part);
+    A.leaf = (double*)(base + Lo.o_leaf);
+    A.model = (uint64_t*)(base + Lo.o_bigmodel);
+    A.flag = (uint32_t*)(base + Lo.o_flag);
+    A.seg = nullptr;
+    HIP_TRY(launch_fit1(A, st));
+    HIP_TRY(launch_fit2(A, st));
+    HIP_TRY(launch_fit_root(A, st));
+    HIP_TRY(launch_fit_leaves(A, st));
+    HIP_TRY(launch_fit_finish(A, st));
+    HIP_TRY(launch_copy_words(A.model + 4, (uint64_t*)params, 2 + 4ull * L, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
+ls_status ls_rmi_buckets(const void* keys, uint64_t n, ls_dtype dtype, const double* params, uint32_t L, double R,
+                         uint32_t* out, void* stream) {
+    ls_status s = check_keys(keys, n, dtype, nullptr);
+    if (s) return s;
+    if (L < 2 || L > L_MAX || !params || !(R >= 1.0) || R > 4294967296.0 || (n && !out))
+        return fail(LS_EINVAL, "ls_rmi_buckets needs 2 <= L <= 1024, 1 <= R <= 2^32, params, out");
+    if (n == 0) return LS_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    if ((s = step_scratch(base, pool, Lo))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    uint64_t* mdl = (uint64_t*)(base + Lo.o_bigmodel);
+    HIP_TRY(launch_install_rmi(params, L, R, 1, 0, mdl, st));
+    HIP_TRY(launch_model_buckets(mdl, 6 + 4 * L, K_RMI_FINE, 0, 0, (const uint64_t*)keys, n, dtype == LS_U64, out, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
+ls_status ls_splitters(const void* sorted_sample, uint64_t S, ls_dtype dtype, uint32_t B, uint64_t* splitters,
+                       uint8_t* eq, uint32_t* m, void* stream) {
+    ls_status s = check_keys(sorted_sample, S, dtype, nullptr);
+    if (s) return s;
+    if (S < 1 || B < 2 || B > B_MAX || S >= (1ull << 32) || !splitters || !eq || !m)
+        return fail(LS_EINVAL, "ls_splitters needs S >= 1, 2 <= B <= 1024 and outputs");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    if ((s = step_scratch(base, pool, Lo))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    HIP_TRY(launch_splitters((const uint64_t*)sorted_sample, S, dtype == LS_U64, B, (uint64_t*)(base + Lo.o_bigmodel),
+                             splitters, eq, m, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
+ls_status ls_splitter_buckets(const void* keys, uint64_t n, ls_dtype dtype, const uint64_t* splitters, const uint8_t* eq,
+                              uint32_t m, uint32_t* out, void* stream) {
+    ls_status s = check_keys(keys, n, dtype, nullptr);
+    if (s) return s;
+    if (m < 1 || m >= B_MAX || !splitters || !eq || (n && !out))
+        return fail(LS_EINVAL, "ls_splitter_buckets needs 1 <= m < 1024, splitters, eq, out");
+    if (n == 0) return LS_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    if ((s = step_scratch(base, pool, Lo))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    uint64_t* mdl = (uint64_t*)(base + Lo.o_bigmodel);
+    HIP_TRY(launch_install_tree(splitters, eq, m, mdl, st));
+    uint32_t words = 2 + m + (m + 1 + 3) / 4;
+    HIP_TRY(launch_model_buckets(mdl, words, K_TREE, 0, 0, (const uint64_t*)keys, n, dtype == LS_U64, out, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
+static ls_status partition_one(const void* keys, const uint32_t* payload, uint64_t n, ls_dtype dtype, bool rmi,
+                               const double* params, uint32_t L, double R, uint32_t nb, const uint64_t* splitters,
+                               const uint8_t* eq, uint32_t m, void* out_keys, uint32_t* out_payload, uint64_t* counts,
+                               void* stream) {
+    ls_status s = check_keys(keys, n, dtype, payload);
+    if (s) return s;
+    if (n == 0) return LS_OK;
+    if (!out_keys || !counts || (payload && !out_payload)) return fail(LS_EINVAL, "missing output");
+    if (((uintptr_t)out_keys) & 7 || ((uintptr_t)out_payload) & 3) return fail(LS_EINVAL, "misaligned output");
+    uint32_t log2B2 = 0;
+    if (rmi) {
+        if (L < 2 || L > L_MAX || !params || nb < 1 || nb > B_MAX || !(R >= nb)) return fail(LS_EINVAL, "bad RMI arguments");
+        double ratio = R / nb;
+        while ((double)(1u << log2B2) < ratio && log2B2 < 20) log2B2++;
+        if ((double)(1u << log2B2) != ratio || (double)nb * (1u << log2B2) != R)
+            return fail(LS_EINVAL, "R / nb must be a power of two");
+    } else {
+        if (m < 1 || m >= B_MAX / 2 || !splitters || !eq) return fail(LS_EINVAL, "bad splitter arguments");
+    }
+    Opts o;
+    normalize(nullptr, o);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Layout Lo = plan(n, 1, payload != nullptr, o);
+    Lo.S_big = 0;
+    DevPool* pool;
+    uint8_t* base;
+    if ((s = acquire(Lo.bytes, Lo, pool, base))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    if ((s = prepare_status(pool, base, Lo, st))) return s;
+    uint64_t* mdl = (uint64_t*)(base + Lo.o_bigmodel);
+    Seg sg{};
+    if (rmi) {
+        HIP_TRY(launch_install_rmi(params, L, R, nb, log2B2, mdl, st));
+        sg.kind = K_RMI; sg.nb = nb; sg.flags = SEG_PREBUILT | ((6 + 4 * L) << 16);
+    } else {
+        HIP_TRY(launch_install_tree(splitters, eq, m, mdl, st));
+        sg.kind = K_TREE; sg.nb = 0;  // filled below from the flags
+        sg.flags = SEG_PREBUILT | ((2 + m + (m + 1 + 3) / 4) << 16);
+    }
+    sg.model = (uint64_t)mdl;
+    Call c{};
+    c.keys = (uint64_t*)keys; c.pay = (uint32_t*)payload; c.n = n; c.m = 1; c.offsets = nullptr; c.u64 = dtype == LS_U64;
+    c.o = o; c.st = st; c.one_level = true; c.out_keys = (uint64_t*)out_keys; c.out_pay = out_payload;
+    Params P = make_params(c, Lo, base);
+    if (!rmi) {
+        // number of buckets = m + 1 + (flags set); read the flags once on the host
+        std::vector<uint8_t> h(m);
+        HIP_TRY(hipMemcpyAsync(h.data(), eq, m, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        uint32_t ne = 0;
+        for (uint8_t f : h) ne += f ? 1 : 0;
+        sg.nb = m + 1 + ne;
+    }
+    HIP_TRY(hipMemcpyAsync(P.segs[1], &sg, sizeof(Seg), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));  // sg lives on this stack frame
+    if ((s = run(c, Lo, base, pool))) return s;
+    HIP_TRY(launch_copy_words((const uint64_t*)P.counts, counts, sg.nb, st));  // segment 0 takes counts[0..nb)
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
+ls_status ls_partition_rmi(const void* keys, const uint32_t* payload, uint64_t n, ls_dtype dtype, const double* params,
+                           uint32_t L, double R, uint32_t nb, void* out_keys, uint32_t* out_payload, uint64_t* counts,
+                           void* stream) {
+    return partition_one(keys, payload, n, dtype, true, params, L, R, nb, nullptr, nullptr, 0, out_keys, out_payload,
+                         counts, stream);
+}
+
+ls_status ls_partition_splitters(const void* keys, const uint32_t* payload, uint64_t n, ls_dtype dtype,
+                                 const uint64_t* splitters, const uint8_t* eq, uint32_t m, void* out_keys,
+                                 uint32_t* out_payload, uint64_t* counts, void* stream) {
+    return partition_one(keys, payload, n, dtype, false, nullptr, 0, 0, 0, splitters, eq, m, out_keys, out_payload,
+                         counts, stream);
+}
+
+ls_status ls_mlp_loss_grad(const float*, const float*, const float*, uint64_t, float*, float*, void*) {
+    return fail(LS_EUNSUPPORTED, "the MLP kernels are not available in this build");
+}
+
+ls_status ls_mlp_train(const void*, uint64_t, ls_dtype, const float*, uint32_t, float, uint64_t, float*, double*, float*,
+                       void*) {
+    return fail(LS_EUNSUPPORTED, "the MLP kernels are not available in this build");
+}
+
+ls_status ls_mlp_buckets(const void*, uint64_t, ls_dtype, const float*, const double*, uint32_t, uint32_t*, void*) {
+    return fail(LS_EUNSUPPORTED, "the MLP kernels are not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,440 @@
+// lsort_dev.hpp -- device-side building blocks of the learned sample sort
+// for gfx950 (CDNA4, wave64): key order, model inputs, the three bucket
+// functions (monotone RMI, splitter tree with equality buckets, range radix),
+// the monotone FP32 MLP, wave-level match and scans.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lsort_internal.hpp"
+
+namespace ls {
+
+// ---------------------------------------------------------------------------
+// Keys
+// ---------------------------------------------------------------------------
+
+// Order-preserving image of a key's bits (Sec. 5, float-to-integer key
+// extractor): IEEE totalOrder for binary64, identity for uint64.
+__device__ __forceinline__ uint64_t key_ord(uint64_t raw, int u64) {
+    if (u64) return raw;
+    return (raw >> 63) ? ~raw : (raw | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ uint64_t key_unord(uint64_t o, int u64) {
+    if (u64) return o;
+    return (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+}
+
+// Model input of a key. Returns 0 and sets x for a finite key; -1 / +1 for a
+// non-finite binary64 key of negative / positive sign (first / last bucket).
+__device__ __forceinline__ int key_x(uint64_t raw, int u64, double& x) {
+    if (u64) { x = (double)raw; return 0; }
+    if (((raw >> 52) & 0x7ffull) == 0x7ffull) return (raw >> 63) ? -1 : 1;
+    x = __longlong_as_double((long long)raw);
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Sampling: SplitMix64 (Steele, Lea & Flood 2014) output k from state seed,
+// mapped to [0, n) by the high half of a 64x64 product (Lemire).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t sample_index(uint64_t seed, uint64_t k, uint64_t n) {
+    return __umul64hi(splitmix64_at(seed, k), n);
+}
+
+// ---------------------------------------------------------------------------
+// Bucket functions. Every one is non-decreasing in the key's totalOrder, so a
+// partition never misorders keys; rounding can only unbalance buckets.
+// ---------------------------------------------------------------------------
+
+// Monotone two-level RMI at total resolution R (Sec. 2.1 formula, Sec. 2.2
+// bucket = floor(B F(x)), Sec. 4 clamp intervals). p: 2 + 4L pre-scaled
+// doubles (alpha_r, beta_r, then alpha_j, beta_j, gamma_j, delta_j).
+__device__ __forceinline__ uint32_t rmi_eval(const double* p, double Lm1, double Rm1, double x) {
+    double r = floor(__builtin_fma(p[0], x, p[1]));
+    r = fmin(fmax(r, 0.0), Lm1);
+    const double* q = p + 2 + 4 * (int)r;
+    double t = __builtin_fma(q[0], x, q[1]);
+    t = fmin(fmax(t, q[2]), q[3]);
+    double g = floor(t);
+    g = fmin(fmax(g, 0.0), Rm1);
+    return (uint32_t)g;
+}
+
+__device__ __forceinline__ uint32_t rmi_bucket(const double* p, double Lm1, double Rm1, uint64_t raw, int u64) {
+    double x;
+    int nf = key_x(raw, u64, x);
+    if (nf) return nf < 0 ? 0u : (uint32_t)Rm1;
+    return rmi_eval(p, Lm1, Rm1, x);
+}
+
+// Splitter tree (Sec. 2.4): k = #{u_i <= o} by branch-free binary lifting over
+// the ascending splitters (the search a Super Scalar SampleSort decision tree
+// performs), then the equality-bucket remap through lut[k] =
+// (equality buckets before splitter k) << 1 | (splitter k-1 has one).
+__device__ __forceinline__ uint32_t tree_bucket(const uint64_t* u, const uint16_t* lut, uint32_t m, uint32_t top,
+                                                uint64_t o) {
+    uint32_t k = 0;
+    for (uint32_t s = top; s > 0; s >>= 1) {
+        uint32_t nk = k + s;
+        if (nk <= m && u[nk - 1] <= o) k = nk;
+    }
+    uint32_t e = lut[k];
+    uint32_t id = k + (e >> 1);
+    if ((e & 1u) && u[k - 1] == o) id -= 1;
+    return id;
+}
+
+// Range radix: the top bits of (o - lo).
+__device__ __forceinline__ uint32_t radix_bucket(uint64_t lo, uint32_t shift, uint64_t o) {
+    return shift >= 64 ? 0u : (uint32_t)((o - lo) >> shift);
+}
+
+// Reserve `amt` consecutive slots of a list with capacity `cap`: returns the
+// first slot, or ~0 when the list would overflow (nothing is reserved then,
+// so every slot below the counter is always written).
+__device__ __forceinline__ uint64_t reserve32(uint32_t* ctr, uint32_t amt, uint64_t cap) {
+    uint32_t old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if ((uint64_t)old + amt > cap) return ~0ull;
+        uint32_t seen = atomicCAS(ctr, old, old + amt);
+        if (seen == old) return old;
+        old = seen;
+    }
+}
+
+__device__ __forceinline__ uint64_t reserve64(unsigned long long* ctr, unsigned long long amt, uint64_t cap) {
+    unsigned long long old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (old + amt > cap) return ~0ull;
+        unsigned long long seen = atomicCAS(ctr, old, old + amt);
+        if (seen == old) return old;
+        old = seen;
+    }
+}
+
+// Monotone MLP CDF in FP32 (1-16-16-1; non-negative effective weights;
+// units 0..7 max(z,0), 8..15 min(z,0)); fmaf chains in index order.
+__device__ __forceinline__ float mlp_eval(const float* w, float t) {
+    float h1[MLP_H];
+#pragma unroll
+    for (int i = 0; i < MLP_H; i++) {
+        float z = __builtin_fmaf(w[OFF_V1 + i], t, w[OFF_B1 + i]);
+        h1[i] = i < MLP_HALF ? fmaxf(z, 0.0f) : fminf(z, 0.0f);
+    }
+    float out = w[OFF_B3];
+#pragma unroll
+    for (int i = 0; i < MLP_H; i++) {
+        float z = w[OFF_B2 + i];
+#pragma unroll
+        for (int k = 0; k < MLP_H; k++) z = __builtin_fmaf(w[OFF_V2 + MLP_H * i + k], h1[k], z);
+        float h = i < MLP_HALF ? fmaxf(z, 0.0f) : fminf(z, 0.0f);
+        // The output layer consumes h2 in index order, so it can be folded in
+        // here without changing the operation sequence.
+        out = __builtin_fmaf(w[OFF_V3 + i], h, out);
+    }
+    return fminf(fmaxf(out, 0.0f), 1.0f);
+}
+
+__device__ __forceinline__ float mlp_input(double x, double lo, double inv) {
+    double t = (x - lo) * inv;
+    t = fmin(fmax(t, 0.0), 1.0);
+    return (float)t;
+}
+
+__device__ __forceinline__ uint32_t mlp_bucket(const float* w, double lo, double inv, float Rf, uint64_t raw, int u64) {
+    double x;
+    int nf = key_x(raw, u64, x);
+    if (nf) return nf < 0 ? 0u : (uint32_t)(Rf - 1.0f);
+    float F = mlp_eval(w, mlp_input(x, lo, inv));
+    float g = floorf(F * Rf);
+    g = fminf(g, Rf - 1.0f);
+    return (uint32_t)g;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Lanes of the active set whose value v equals this lane's (v < 2^bits):
+// one ballot per bit (wave64 has no native match instruction).
+__device__ __forceinline__ uint64_t match_peers(uint32_t v, int bits) {
+    uint64_t peers = __ballot(1);
+    for (int i = 0; i < bits; i++) {
+        uint32_t bit = (v >> i) & 1u;
+        uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// ===========================================================================
+// Block-level reductions and scans (deterministic: fixed combination order)
+// ===========================================================================
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T y = __shfl_xor(v, o);
+        v = y > v ? y : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T y = __shfl_xor(v, o);
+        v = y < v ? y : v;
+    }
+    return v;
+}
+
+// Sum over the block; every thread gets the total. sh: >= NT/64 entries.
+template <int NT, typename T>
+__device__ T block_sum(T v, T* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    T t = 0;
+    for (int i = 0; i < NT / 64; i++) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+template <int NT, typename T>
+__device__ T block_max(T v, T* sh) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    T t = sh[0];
+    for (int i = 1; i < NT / 64; i++) t = sh[i] > t ? sh[i] : t;
+    __syncthreads();
+    return t;
+}
+
+template <int NT, typename T>
+__device__ T block_min(T v, T* sh) {
+    v = wave_min(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    T t = sh[0];
+    for (int i = 1; i < NT / 64; i++) t = sh[i] < t ? sh[i] : t;
+    __syncthreads();
+    return t;
+}
+
+// Exclusive prefix sum of one value per thread; *total gets the sum.
+template <int NT, typename T>
+__device__ T block_excl_scan(T v, T* sh, T* total) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    T before = 0, all = 0;
+    for (int i = 0; i < NT / 64; i++) {
+        if (i < w) before += sh[i];
+        all += sh[i];
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return before + x - v;
+}
+
+// Inclusive prefix maximum of one double per thread.
+template <int NT>
+__device__ double block_incl_max(double v, double* sh) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        double y = __shfl_up(x, o);
+        if (lane >= o) x = y > x ? y : x;
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    double before = -INFINITY;
+    for (int i = 0; i < w; i++) before = sh[i] > before ? sh[i] : before;
+    __syncthreads();
+    return before > x ? before : x;
+}
+
+__device__ __forceinline__ uint32_t ceil_log2(uint32_t v) {  // smallest b with 2^b >= v
+    return v <= 1 ? 0 : 32 - __clz(v - 1);
+}
+__device__ __forceinline__ uint32_t floor_pow2(uint32_t v) { return v ? 1u << (31 - __clz(v)) : 0; }
+
+// In-LDS bitonic sort (Batcher 1968) of P (power of two) ordered keys.
+template <int NT>
+__device__ void bitonic_keys(uint64_t* a, uint32_t P) {
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t q = threadIdx.x; q < P / 2; q += NT) {
+                uint32_t i = 2 * j * (q / j) + (q % j);
+                uint32_t l = i + j;
+                bool up = (i & k) == 0;
+                uint64_t x = a[i], y = a[l];
+                if ((x > y) == up) { a[i] = y; a[l] = x; }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Same on (key, index) pairs, ordered lexicographically (stable tie-break).
+template <int NT>
+__device__ void bitonic_pairs(uint64_t* a, uint16_t* ix, uint32_t P) {
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t q = threadIdx.x; q < P / 2; q += NT) {
+                uint32_t i = 2 * j * (q / j) + (q % j);
+                uint32_t l = i + j;
+                bool up = (i & k) == 0;
+                uint64_t x = a[i], y = a[l];
+                uint16_t xi = ix[i], yi = ix[l];
+                bool gt = x > y || (x == y && xi > yi);
+                if (gt == up) { a[i] = y; a[l] = x; ix[i] = yi; ix[l] = xi; }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ===========================================================================
+// Model views in LDS
+// ===========================================================================
+
+struct View {
+    uint32_t kind, nb, win, log2B2;
+    double Lm1, Rm1;     // RMI
+    uint32_t m, top;     // tree
+    uint64_t lo;         // radix
+    uint32_t shift;
+};
+
+// Partition models evaluated inside the partition kernels.  The MLP is not
+// among them: an MLP level first stores every key's bucket id (K_STASH) so
+// that its 288 FMAs per key are paid once, not twice.
+__device__ __forceinline__ View make_view(const uint64_t* mdl, uint32_t kind, uint32_t nb, uint32_t win) {
+    View v{};
+    v.kind = kind; v.nb = nb; v.win = win;
+    if (kind == K_RMI || kind == K_RMI_FINE) {
+        const RmiModel* h = (const RmiModel*)mdl;
+        v.Lm1 = (double)h->L - 1.0; v.Rm1 = h->R - 1.0; v.log2B2 = h->log2B2;
+    } else if (kind == K_TREE || kind == K_TREE_FORCED) {
+        const TreeModel* h = (const TreeModel*)mdl;
+        v.m = h->m; v.top = h->top;
+    } else if (kind == K_RADIX) {
+        const RadixModel* h = (const RadixModel*)mdl;
+        v.lo = h->lo; v.shift = h->shift;
+    }
+    return v;
+}
+
+// Bucket of the key at absolute position pos (stash: precomputed id).
+__device__ __forceinline__ uint32_t view_bucket(const View& v, const uint64_t* mdl, uint64_t raw, int u64,
+                                                const uint16_t* ids, uint64_t pos) {
+    switch (v.kind) {
+    case K_RMI: return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) >> v.log2B2;
+    case K_RMI_FINE: return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) - v.win;
+    case K_TREE:
+    case K_TREE_FORCED:
+        return tree_bucket(mdl + 2, (const uint16_t*)(mdl + 2 + v.m), v.m, v.top, key_ord(raw, u64));
+    case K_RADIX: return radix_bucket(v.lo, v.shift, key_ord(raw, u64));
+    default: return ids[pos];  // K_MLP, K_MLP_FINE: ids stored by k_mlp_ids
+    }
+}
+
+constexpr int M_THREADS = 1024;  // threads of a one-workgroup model builder
+
+// Bytes of arena a model takes (16-byte multiple).
+__device__ __forceinline__ uint32_t rmi_words(uint32_t L) { return 4 + 2 + 4 * L; }
+__device__ __forceinline__ uint32_t tree_words(uint32_t m) { return 2 + m + (m + 1 + 3) / 4; }
+
+// Splitters of a sorted sample (ordered keys) -> TreeModel at dst.
+// Candidate i = smp[floor((i+1) S / B)], de-duplicated; repeated candidates
+// get equality buckets (Sec. 2.4).  Returns the bucket count.
+template <typename Get>
+__device__ uint32_t build_tree_block(Get get, uint32_t S, uint32_t B, uint64_t* dst, uint32_t* scratch32,
+                                     uint64_t* red64) {
+    const int tid = threadIdx.x;
+    const uint32_t nc = B - 1;
+    uint64_t cand = 0, prev = 0;
+    uint32_t isnew = 0;
+    if ((uint32_t)tid < nc) {
+        uint64_t r = ((uint64_t)(tid + 1) * S) / B;
+        if (r >= S) r = S - 1;
+        cand = get(r);
+        if (tid > 0) {
+            uint64_t rp = ((uint64_t)tid * S) / B;
+            if (rp >= S) rp = S - 1;
+            prev = get(rp);
+        }
+        isnew = (tid == 0) || (cand != prev);
+    }
+    uint64_t tot;
+    uint64_t idx = block_excl_scan<M_THREADS, uint64_t>((uint64_t)isnew, red64, &tot);  // unique index if new
+    const uint32_t m = (uint32_t)tot;
+    uint32_t* eqf = scratch32;  // m flags
+    for (uint32_t i = tid; i <= m; i += M_THREADS) eqf[i] = 0;
+    __syncthreads();
+    uint64_t* u = dst + 2;
+    if ((uint32_t)tid < nc) {
+        if (isnew) u[idx] = cand;
+        else eqf[idx - 1] = 1;  // idx counts new candidates before this one
+    }
+    __syncthreads();
+    uint32_t f = (uint32_t)tid < m ? eqf[tid] : 0;
+    uint64_t neq;
+    uint64_t pe = block_excl_scan<M_THREADS, uint64_t>((uint64_t)f, red64, &neq);
+    uint16_t* lut = (uint16_t*)(dst + 2 + m);
+    // lut[k] for k = 1..m from splitter k-1; lut[0] = 0
+    if ((uint32_t)tid < m) lut[tid + 1] = (uint16_t)(((pe + f) << 1) | f);
+    if (tid == 0) {
+        lut[0] = 0;
+        TreeModel* h = (TreeModel*)dst;
+        h->m = m; h->nb = m + 1 + (uint32_t)neq; h->top = floor_pow2(m); h->pad = 0;
+    }
+    __syncthreads();
+    return m + 1 + (uint32_t)neq;
+}
+
+}  // namespace ls

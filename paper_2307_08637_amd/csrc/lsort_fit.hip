@@ -1,0 +1,320 @@
+// lsort_fit.hip -- model construction over a large sorted sample (the first
+// level of a big array, where the ~1% sample does not fit one workgroup's
+// LDS), and the kernels behind the single-step entry points.
+#include <algorithm>
+
+#include "lsort_dev.hpp"
+#include "lsort_kernels.hpp"
+
+namespace ls {
+
+// Random sample with replacement (Sec. 2.2: ~1% sample; Alg. 5 Sample).
+__global__ void k_gather(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t S, uint64_t* out) {
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S; k += (uint64_t)gridDim.x * blockDim.x)
+        out[k] = keys[sample_index(seed, k, n)];
+}
+
+// ---------------------------------------------------------------------------
+// Least-squares passes over a sorted sample s[0..S) in global memory.
+// part[g*8 + 0..4]: sum x, adjacent duplicates, non-finite keys, centred
+// sum (x - mean)^2, centred sum (x - mean)(y - mean y).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(FIT_T) void k_fit1(FitArgs A) {
+    __shared__ double red[FIT_T / 64];
+    __shared__ uint64_t red64[FIT_T / 64];
+    const uint64_t chunk = (A.S + gridDim.x - 1) / gridDim.x;
+    const uint64_t lo = blockIdx.x * chunk, hi = min(A.S, lo + chunk);
+    double sx = 0;
+    uint64_t dup = 0, nf = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_T) {
+        uint64_t r = A.s[i];
+        double x;
+        if (key_x(r, A.u64, x)) nf++;
+        else sx += x;
+        if (i > 0) dup += key_ord(r, A.u64) == key_ord(A.s[i - 1], A.u64);
+    }
+    sx = block_sum<FIT_T, double>(sx, red);
+    dup = block_sum<FIT_T, uint64_t>(dup, red64);
+    nf = block_sum<FIT_T, uint64_t>(nf, red64);
+    if (threadIdx.x == 0) {
+        A.part[blockIdx.x * 8 + 0] = sx;
+        A.part[blockIdx.x * 8 + 1] = (double)dup;
+        A.part[blockIdx.x * 8 + 2] = (double)nf;
+    }
+}
+
+__global__ __launch_bounds__(FIT_T) void k_fit2(FitArgs A) {
+    __shared__ double red[FIT_T / 64];
+    double sxt = 0;
+    for (uint32_t g = 0; g < gridDim.x; g++) sxt += A.part[g * 8 + 0];  // same order in every workgroup
+    const double Sd = (double)A.S;
+    const double mx = sxt / Sd, my = (Sd - 1.0) / (2.0 * Sd);
+    const uint64_t chunk = (A.S + gridDim.x - 1) / gridDim.x;
+    const uint64_t lo = blockIdx.x * chunk, hi = min(A.S, lo + chunk);
+    double sxx = 0, sxy = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_T) {
+        double x;
+        if (key_x(A.s[i], A.u64, x)) continue;
+        double dx = x - mx, dy = (double)i / Sd - my;
+        sxx += dx * dx;
+        sxy += dx * dy;
+    }
+    sxx = block_sum<FIT_T, double>(sxx, red);
+    sxy = block_sum<FIT_T, double>(sxy, red);
+    if (threadIdx.x == 0) {
+        A.part[blockIdx.x * 8 + 3] = sxx;
+        A.part[blockIdx.x * 8 + 4] = sxy;
+    }
+}
+
+// Root line, the Alg. 5 policy, and (when the policy says so) the splitter
+// tree.  One workgroup.
+__global__ __launch_bounds__(M_THREADS) void k_fit_root(FitArgs A) {
+    __shared__ uint32_t scratch[B_MAX + 1];
+    __shared__ uint64_t red64[M_THREADS / 64];
+    double sx = 0, dup = 0, nf = 0, sxx = 0, sxy = 0;
+    for (uint32_t g = 0; g < A.G; g++) {
+        sx += A.part[g * 8 + 0];
+        dup += A.part[g * 8 + 1];
+        nf += A.part[g * 8 + 2];
+        sxx += A.part[g * 8 + 3];
+        sxy += A.part[g * 8 + 4];
+    }
+    const double Sd = (double)A.S;
+    double x0, x1;
+    int nf0 = key_x(A.s[0], A.u64, x0), nf1 = key_x(A.s[A.S - 1], A.u64, x1);
+    bool learned;
+    if (A.mode == 1) learned = true;
+    else if (A.mode == 2) learned = false;
+    else learned = (double)A.n >= 1e5 && dup <= 0.10 * (Sd - 1.0) && nf == 0 && !nf0 && !nf1 && x1 > x0;
+    uint64_t* dst = A.model;
+    uint32_t nb, words, kind;
+    if (learned) {
+        double mx = sx / Sd, my = (Sd - 1.0) / (2.0 * Sd);
+        double a = sxx > 0 ? sxy / sxx : 0.0;
+        if (a < 0) a = 0;
+        double b = my - a * mx;
+        if (threadIdx.x == 0) {
+            RmiModel* h = (RmiModel*)dst;
+            h->L = A.L; h->B1 = A.B1; h->log2B2 = A.log2B2; h->pad = 0;
+            h->R = A.R; h->pad2 = 0; h->pad3 = 0;
+            ((double*)dst)[4] = (double)A.L * a;
+            ((double*)dst)[5] = (double)A.L * b;
+        }
+        nb = A.B1;
+        words = rmi_words(A.L);
+        kind = A.mlp ? K_MLP : K_RMI;
+    } else {
+        const uint64_t* s = A.s;
+        const int u64 = A.u64;
+        nb = build_tree_block([&](uint64_t r) { return key_ord(s[r], u64); }, (uint32_t)min<uint64_t>(A.S, 0xffffffffull),
+                              A.Bt, dst, scratch, red64);
+        words = tree_words(((TreeModel*)dst)->m);
+        kind = K_TREE;
+    }
+    if (threadIdx.x == 0) {
+        A.flag[0] = learned ? 1u : 0u;
+        if (A.seg) {
+            Seg sg{};
+            sg.kind = kind; sg.nb = nb; sg.model = (uint64_t)dst;
+            sg.flags = SEG_PREBUILT | (words << 16);
+            *A.seg = sg;
+        }
+    }
+}
+
+// Leaf lines: one wave per leaf.  Leaf j covers the sample points the
+// pre-scaled root sends to j (a contiguous range, found by binary search).
+// leaf[j*8 + 0..4] = a, b, line(min), line(max), non-empty.
+__device__ __forceinline__ uint32_t root_leaf(double ar, double br, double Lm1, uint64_t raw, int u64) {
+    double x;
+    key_x(raw, u64, x);
+    return (uint32_t)fmin(fmax(floor(__builtin_fma(ar, x, br)), 0.0), Lm1);
+}
+
+__global__ __launch_bounds__(256) void k_fit_leaves(FitArgs A) {
+    if (A.flag[0] == 0) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t j = blockIdx.x * 4 + w;
+    if (j >= A.L) return;
+    const double ar = ((const double*)A.model)[4], br = ((const double*)A.model)[5];
+    const double Lm1 = (double)A.L - 1.0;
+    auto lower = [&](uint32_t leaf) {  // first i with root_leaf(s[i]) >= leaf
+        uint64_t lo = 0, hi = A.S;
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (root_leaf(ar, br, Lm1, A.s[mid], A.u64) < leaf) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const uint64_t lo = lower(j), hi = j + 1 < A.L ? lower(j + 1) : A.S;
+    const double Sd = (double)A.S;
+    double a = 0, b = 0, pmin = 0, pmax = 0;
+    if (hi > lo) {
+        const double cnt = (double)(hi - lo);
+        double s = 0;
+        for (uint64_t i = lo + lane; i < hi; i += 64) { double x; key_x(A.s[i], A.u64, x); s += x; }
+        s = wave_sum(s);
+        const double mx = s / cnt, my = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
+        double sxx = 0, sxy = 0;
+        for (uint64_t i = lo + lane; i < hi; i += 64) {
+            double x; key_x(A.s[i], A.u64, x);
+            double dx = x - mx, dy = (double)i / Sd - my;
+            sxx += dx * dx; sxy += dx * dy;
+        }
+        sxx = wave_sum(sxx);
+        sxy = wave_sum(sxy);
+        a = sxx > 0 ? sxy / sxx : 0.0;
+        if (a < 0) a = 0;
+        b = my - a * mx;
+        double x0, x1;
+        key_x(A.s[lo], A.u64, x0);
+        key_x(A.s[hi - 1], A.u64, x1);
+        pmin = a * x0 + b;
+        pmax = a * x1 + b;
+    }
+    if (lane == 0) {
+        double* q = A.leaf + (uint64_t)j * 8;
+        q[0] = a; q[1] = b; q[2] = pmin; q[3] = pmax; q[4] = hi > lo ? 1.0 : 0.0;
+    }
+}
+
+// Monotone clamp intervals (Sec. 4) via a prefix maximum, then pre-scaling
+// by the total resolution R.  One workgroup of 1024 threads (L <= 1024).
+__global__ __launch_bounds__(M_THREADS) void k_fit_finish(FitArgs A) {
+    __shared__ double red[M_THREADS / 64];
+    __shared__ double wave_last[M_THREADS / 64];
+    if (A.flag[0] == 0) return;
+    const int tid = threadIdx.x;
+    const bool in = (uint32_t)tid < A.L;
+    const double* q = A.leaf + (uint64_t)tid * 8;
+    double a = in ? q[0] : 0, b = in ? q[1] : 0, pmin = in ? q[2] : 0, pmax = in ? q[3] : 0;
+    const bool ne = in && q[4] != 0.0;
+    double v = ne ? pmax : -INFINITY;
+    double incl = block_incl_max<M_THREADS>(v, red);
+    double excl = __shfl_up(incl, 1);
+    if ((tid & 63) == 63) wave_last[tid >> 6] = incl;
+    __syncthreads();
+    if ((tid & 63) == 0) excl = tid == 0 ? -INFINITY : wave_last[(tid >> 6) - 1];
+    if (in) {
+        double dprev = fmin(fmax(excl, 0.0), 1.0);
+        double c, d;
+        if (ne) {
+            c = fmin(fmax(fmax(pmin, dprev), 0.0), 1.0);
+            d = fmin(fmax(fmax(pmax, c), 0.0), 1.0);
+        } else {
+            a = 0; b = dprev; c = dprev; d = dprev;
+        }
+        double* o = (double*)A.model + 6 + 4 * tid;
+        o[0] = A.R * a; o[1] = A.R * b; o[2] = A.R * c; o[3] = A.R * d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Single-step kernels
+// ---------------------------------------------------------------------------
+
+// Bucket ids of keys under a model in global memory (copied into LDS).
+__global__ __launch_bounds__(256) void k_model_buckets(const uint64_t* model, uint32_t words, uint32_t kind, uint32_t nb,
+                                                       uint32_t win, const uint64_t* keys, uint64_t n, int u64,
+                                                       uint32_t* out) {
+    __shared__ uint64_t mdl[MODEL_WORDS];
+    for (uint32_t i = threadIdx.x; i < words; i += 256) mdl[i] = model[i];
+    __syncthreads();
+    const View v = make_view(mdl, kind, nb, win);
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+        out[i] = view_bucket(v, mdl, keys[i], u64, nullptr, 0);
+}
+
+// RMI model header + parameters from a caller's parameter array.
+__global__ void k_install_rmi(const double* params, uint32_t L, double R, uint32_t B1, uint32_t log2B2, uint64_t* dst) {
+    for (uint32_t i = threadIdx.x; i < 2 + 4 * L; i += blockDim.x) ((double*)dst)[4 + i] = params[i];
+    if (threadIdx.x == 0) {
+        RmiModel* h = (RmiModel*)dst;
+        h->L = L; h->B1 = B1; h->log2B2 = log2B2; h->pad = 0; h->R = R; h->pad2 = 0; h->pad3 = 0;
+    }
+}
+
+// Splitter-tree model from caller splitters (ordered keys) and flags.
+__global__ __launch_bounds__(M_THREADS) void k_install_tree(const uint64_t* u, const uint8_t* eq, uint32_t m, uint64_t* dst) {
+    __shared__ uint64_t red64[M_THREADS / 64];
+    const int tid = threadIdx.x;
+    for (uint32_t i = tid; i < m; i += M_THREADS) dst[2 + i] = u[i];
+    uint32_t f = (uint32_t)tid < m ? (eq[tid] ? 1u : 0u) : 0u;
+    uint64_t neq;
+    uint64_t pe = block_excl_scan<M_THREADS, uint64_t>((uint64_t)f, red64, &neq);
+    uint16_t* lut = (uint16_t*)(dst + 2 + m);
+    if ((uint32_t)tid < m) lut[tid + 1] = (uint16_t)(((pe + f) << 1) | f);
+    if (tid == 0) {
+        lut[0] = 0;
+        TreeModel* h = (TreeModel*)dst;
+        h->m = m; h->nb = m + 1 + (uint32_t)neq; h->top = floor_pow2(m); h->pad = 0;
+    }
+}
+
+// Splitters of a sorted sample (ordered keys) through the tree builder,
+// exported as (unique splitters, equality flags, m).
+__global__ __launch_bounds__(M_THREADS) void k_splitters(const uint64_t* s, uint64_t S, int u64, uint32_t B,
+                                                         uint64_t* scratch_model, uint64_t* u_out, uint8_t* eq_out,
+                                                         uint32_t* m_out) {
+    __shared__ uint32_t scratch[B_MAX + 1];
+    __shared__ uint64_t red64[M_THREADS / 64];
+    build_tree_block([&](uint64_t r) { return key_ord(s[r], u64); }, (uint32_t)S, B, scratch_model, scratch, red64);
+    const TreeModel* h = (const TreeModel*)scratch_model;
+    const uint32_t m = h->m;
+    const uint16_t* lut = (const uint16_t*)(scratch_model + 2 + m);
+    for (uint32_t i = threadIdx.x; i < m; i += M_THREADS) {
+        u_out[i] = scratch_model[2 + i];
+        eq_out[i] = (uint8_t)(lut[i + 1] & 1u);
+    }
+    if (threadIdx.x == 0) *m_out = m;
+}
+
+// Copy n words (parameter export).
+__global__ void k_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+#define LAUNCH(kernel, grid, block, stream, ...)                                  \
+    do {                                                                          \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
+        return hipGetLastError();                                                 \
+    } while (0)
+
+hipError_t launch_gather(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t S, uint64_t* out, hipStream_t st) {
+    uint32_t grid = (uint32_t)std::min<uint64_t>((S + 255) / 256, 4096ull);
+    LAUNCH(k_gather, grid ? grid : 1, 256, st, keys, n, seed, S, out);
+}
+hipError_t launch_fit1(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit1, A.G, FIT_T, st, A); }
+hipError_t launch_fit2(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit2, A.G, FIT_T, st, A); }
+hipError_t launch_fit_root(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_root, 1, M_THREADS, st, A); }
+hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_leaves, (A.L + 3) / 4, 256, st, A); }
+hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_finish, 1, M_THREADS, st, A); }
+hipError_t launch_model_buckets(const uint64_t* model, uint32_t words, uint32_t kind, uint32_t nb, uint32_t win,
+                                const uint64_t* keys, uint64_t n, int u64, uint32_t* out, hipStream_t st) {
+    uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 2048ull);
+    LAUNCH(k_model_buckets, grid ? grid : 1, 256, st, model, words, kind, nb, win, keys, n, u64, out);
+}
+hipError_t launch_install_rmi(const double* params, uint32_t L, double R, uint32_t B1, uint32_t log2B2, uint64_t* dst,
+                              hipStream_t st) {
+    LAUNCH(k_install_rmi, 1, 256, st, params, L, R, B1, log2B2, dst);
+}
+hipError_t launch_install_tree(const uint64_t* u, const uint8_t* eq, uint32_t m, uint64_t* dst, hipStream_t st) {
+    LAUNCH(k_install_tree, 1, M_THREADS, st, u, eq, m, dst);
+}
+hipError_t launch_splitters(const uint64_t* s, uint64_t S, int u64, uint32_t B, uint64_t* scratch, uint64_t* u_out,
+                            uint8_t* eq_out, uint32_t* m_out, hipStream_t st) {
+    LAUNCH(k_splitters, 1, M_THREADS, st, s, S, u64, B, scratch, u_out, eq_out, m_out);
+}
+hipError_t launch_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t st) {
+    uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096ull);
+    LAUNCH(k_copy_words, grid ? grid : 1, 256, st, src, dst, n);
+}
+
+}  // namespace ls

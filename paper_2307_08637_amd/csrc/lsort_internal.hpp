@@ -1,0 +1,148 @@
+// lsort_internal.hpp -- data layout shared by the HIP kernels and the host
+// planner of liblsort (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ls {
+
+// ---- sizes ---------------------------------------------------------------
+constexpr int WAVE = 64;
+constexpr int P_THREADS = 512;                 // threads of a partition workgroup (8 waves)
+constexpr int P_WAVES = P_THREADS / WAVE;
+constexpr int KPT = 16;                        // keys per thread per tile
+constexpr int TILE = P_THREADS * KPT;          // 8192 keys per tile
+constexpr int WAVE_KEYS = WAVE * KPT;          // 1024 keys per wave per tile
+constexpr int B_MAX = 1024;                    // buckets of one partition
+constexpr int L_MAX = 1024;                    // RMI leaves
+constexpr int S_LDS = 16384;                   // largest sample one workgroup sorts in LDS
+constexpr int C_MAX = 4096;                    // largest base-case sub-array
+constexpr int MAXL = 32;                       // partition levels (arrays)
+constexpr int MODEL_WORDS = 4 + 2 + 4 * L_MAX; // 8-byte words of the largest model (RMI, L_MAX leaves)
+constexpr uint64_t COPY_CHUNK = 65536;         // keys per copy item
+
+// ---- MLP parameter layout (321 floats) -------------------------------------
+constexpr int MLP_H = 16, MLP_HALF = 8, MLP_NP = 321;
+constexpr int OFF_V1 = 0, OFF_B1 = 16, OFF_V2 = 32, OFF_B2 = 288, OFF_V3 = 304, OFF_B3 = 320;
+
+// ---- partition kinds -------------------------------------------------------
+enum Kind : uint32_t {
+    K_FRESH = 1,     // build a model from a sample of this segment (Alg. 5 policy)
+    K_RMI = 2,       // RMI fitted for this segment; bucket = g >> log2(B2)
+    K_RMI_FINE = 3,  // child of an RMI level: same model, bucket = g - win
+    K_TREE = 4,      // splitter tree (fallback or policy)
+    K_RADIX = 5,     // range radix (depth cap; guaranteed progress)
+    K_MLP = 6,       // MLP CDF; bucket = g >> log2(B2)
+    K_MLP_FINE = 7,  // child of an MLP level
+    K_TREE_FORCED = 8,  // splitter tree requested by the fallback rule
+};
+
+// Model headers (8-byte aligned, followed by their payload in the arena).
+struct RmiModel {     // followed by double p[2 + 4L]
+    uint32_t L, B1, log2B2, pad;
+    double R;         // B1 << log2B2
+    uint64_t pad2;    // header is 24 bytes + 8 = 32
+    uint64_t pad3;
+};
+struct TreeModel {    // followed by uint64 u[m] then uint16 lut[m+1]
+    uint32_t m, nb, top, pad;
+};
+struct RadixModel {
+    uint64_t lo;
+    uint32_t shift, nb;
+};
+struct MlpModel {     // followed by float w[321] (effective weights |V|, biases)
+    uint32_t B1, log2B2;
+    double lo, inv;
+    double R;
+};
+
+// One sub-array partitioned at some level.
+struct Seg {
+    uint64_t off;     // absolute index of the first key
+    uint64_t n;       // keys
+    uint64_t model;   // device address of the model
+    uint64_t cbase;   // bucket counts at counts[cbase..+nb), bucket starts at counts[cbase+nb..+nb)
+    uint64_t sbase;   // look-back status words at status[sbase + tile * nb + b]
+    uint32_t kind;    // Kind
+    uint32_t nb;      // buckets
+    uint32_t win;     // fine window base for *_FINE kinds
+    uint32_t tile0;   // first tile in the level's tile list
+    uint32_t ntiles;
+    uint32_t flags;   // SEG_* bits
+};
+constexpr uint32_t SEG_PREBUILT = 1u;  // model already built (large first level)
+constexpr uint32_t SEG_FAILED = 2u;    // capacity exceeded; not partitioned
+
+struct Tile {
+    uint32_t seg;     // index in the level's segment list
+    uint32_t idx;     // tile number within the segment
+};
+
+// Base-case / copy work item packed in 64 bits:
+// [63:18] offset, [17] source buffer (0 caller, 1 temp), [16] copy-only, [15:0] size - 1.
+__host__ __device__ inline uint64_t item_pack(uint64_t off, uint32_t src, uint32_t copy, uint32_t size) {
+    return (off << 18) | ((uint64_t)src << 17) | ((uint64_t)copy << 16) | (uint64_t)(size - 1);
+}
+
+// Per-level statistics (device; mirrors ls_level_stats).
+struct LevelStats {
+    unsigned long long segments, keys, buckets, max_bucket, max_ratio_x1000, empty, equality, base, recurse,
+        fallback, learned, tree, radix;
+};
+
+// Control block at the start of the workspace.
+struct Ctl {
+    uint32_t nseg[MAXL + 1];        // segments at each level
+    uint32_t ntile[MAXL + 1];       // tiles at each level
+    uint32_t ticket[MAXL + 1];      // scatter tile tickets
+    uint32_t pad0;
+    unsigned long long nitems;      // base-case + copy items
+    unsigned long long ncopy;
+    unsigned long long counts_used; // bump allocators (reset per level)
+    unsigned long long status_used;
+    unsigned long long arena_used[2];
+    uint32_t overflow;              // OVF_* bits
+    uint32_t big_learned;           // first-level policy result of the large path (1 RMI/MLP, 0 tree)
+    double big_stats[8];            // large-path fit scratch
+    double mlp_loss[2];
+    LevelStats lv[MAXL];
+};
+constexpr uint32_t OVF_SEG = 1, OVF_TILE = 2, OVF_ITEM = 4, OVF_COUNTS = 8, OVF_STATUS = 16, OVF_ARENA = 32;
+
+// Everything a level's kernels need, passed by value.
+struct Params {
+    // buffers: index 0 = caller's keys, 1 = temporary
+    uint64_t* keys[2];
+    uint32_t* pay[2];               // null when there is no payload
+    int u64;                        // dtype: 1 uint64, 0 float64
+    int has_pay;
+    // options
+    uint32_t buckets, leaves, tree_buckets, cutoff, max_levels, flags, model;
+    double sample_frac, fallback_ratio;
+    uint64_t seed;
+    // workspace
+    Ctl* ctl;
+    Seg* segs[2];
+    Tile* tiles[2];
+    uint64_t* items;
+    unsigned long long* counts;
+    unsigned long long* status;
+    uint8_t* arena[2];
+    uint16_t* ids;                  // per-key bucket ids of MLP levels (absolute positions)
+    uint64_t seg_cap, tile_cap, item_cap, counts_cap, status_cap, arena_cap;
+    const uint64_t* persist;        // [0] call epoch, [1] clear-status request (survives calls)
+    int level;
+};
+
+// Status word of the decoupled look-back:
+// [63:38] tag = call epoch * MAXL + level (never 0), [37:36] flag
+// (1 aggregate, 2 inclusive prefix), [35:0] value.
+constexpr int ST_TAG_BITS = 26;
+constexpr int ST_TAG_SHIFT = 38;
+constexpr uint64_t ST_VALUE_MASK = (1ull << 36) - 1;
+constexpr uint64_t ST_LOW_MASK = ST_VALUE_MASK;
+constexpr uint64_t ST_AGG = 1ull << 36, ST_PREFIX = 2ull << 36;
+
+}  // namespace ls

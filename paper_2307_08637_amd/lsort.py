@@ -1,0 +1,257 @@
+"""ctypes binding of liblsort (C ABI in include/lsort.h).
+
+Argument marshalling only: every step of the sort runs in the library's HIP
+kernels.  Tensors must be torch CUDA (ROCm) tensors on the current device;
+work is enqueued on torch's current stream.  If the library is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsort.so")
+
+LS_F64, LS_U64 = 0, 1
+MODEL = {"auto": 0, "rmi": 1, "mlp": 2, "splitter": 3}
+FLAG_NO_FALLBACK, FLAG_SYNC_LEVELS, FLAG_FIXED_LEVELS, FLAG_COLLECT_STATS = 1, 2, 4, 8
+MAX_STAT_LEVELS = 32
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("model", C.c_uint32), ("buckets", C.c_uint32), ("leaves", C.c_uint32),
+        ("tree_buckets", C.c_uint32), ("cutoff", C.c_uint32), ("max_levels", C.c_uint32), ("flags", C.c_uint32),
+        ("sample_frac", C.c_double), ("fallback_ratio", C.c_double), ("seed", C.c_uint64),
+        ("mlp_steps", C.c_uint32), ("mlp_sample", C.c_uint32), ("mlp_lr", C.c_float), ("reserved", C.c_uint32 * 5),
+    ]
+
+
+class LevelStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "segments", "keys", "buckets", "max_bucket", "max_bucket_x1000_over_mean", "empty", "equality", "base",
+        "recurse", "fallback", "learned", "tree", "radix")]
+
+
+class Stats(C.Structure):
+    _fields_ = [("levels", C.c_uint32), ("first_model", C.c_uint32), ("base_items", C.c_uint64),
+                ("copy_items", C.c_uint64), ("mlp_loss_first", C.c_double), ("mlp_loss_last", C.c_double),
+                ("level", LevelStats * MAX_STAT_LEVELS)]
+
+
+class LsortError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, u32, i32, dbl = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int, C.c_double
+        sig = {
+            "ls_sort": [vp, u64, i32, vp, vp, vp],
+            "ls_sort_segmented": [vp, vp, u64, u64, i32, vp, vp, vp],
+            "ls_workspace_bytes": [u64, u64, i32, i32, vp, vp],
+            "ls_set_workspace": [vp, C.c_size_t],
+            "ls_get_stats": [vp],
+            "ls_sample": [vp, u64, i32, u64, u64, vp, vp],
+            "ls_rmi_fit": [vp, u64, i32, u32, dbl, vp, vp],
+            "ls_rmi_buckets": [vp, u64, i32, vp, u32, dbl, vp, vp],
+            "ls_splitters": [vp, u64, i32, u32, vp, vp, vp, vp],
+            "ls_splitter_buckets": [vp, u64, i32, vp, vp, u32, vp, vp],
+            "ls_partition_rmi": [vp, vp, u64, i32, vp, u32, dbl, u32, vp, vp, vp, vp],
+            "ls_partition_splitters": [vp, vp, u64, i32, vp, vp, u32, vp, vp, vp, vp],
+            "ls_mlp_loss_grad": [vp, vp, vp, u64, vp, vp, vp],
+            "ls_mlp_train": [vp, u64, i32, vp, u32, C.c_float, u64, vp, vp, vp, vp],
+            "ls_mlp_buckets": [vp, u64, i32, vp, vp, u32, vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.ls_last_error.restype = C.c_char_p
+        L.ls_last_error.argtypes = []
+        L.ls_version.restype = C.c_char_p
+        L.ls_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LsortError(f"liblsort status {rc}: {lib().ls_last_error().decode()}")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return LS_F64
+    if t.dtype == torch.uint64:
+        return LS_U64
+    raise TypeError(f"keys must be float64 or uint64, got {t.dtype}")
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, max_levels=0, flags=0,
+                 sample_frac=0.0, fallback_ratio=0.0, seed=0, mlp_steps=0, mlp_sample=0, mlp_lr=0.0,
+                 stats=True, fixed_levels=False, no_fallback=False) -> Options:
+    o = Options()
+    o.struct_size = C.sizeof(Options)
+    o.model = MODEL[model] if isinstance(model, str) else int(model)
+    o.buckets, o.leaves, o.tree_buckets, o.cutoff, o.max_levels = buckets, leaves, tree_buckets, cutoff, max_levels
+    f = flags | (FLAG_COLLECT_STATS if stats else 0)
+    f |= FLAG_FIXED_LEVELS if fixed_levels else FLAG_SYNC_LEVELS
+    f |= FLAG_NO_FALLBACK if no_fallback else 0
+    o.flags = f
+    o.sample_frac, o.fallback_ratio, o.seed = sample_frac, fallback_ratio, seed
+    o.mlp_steps, o.mlp_sample, o.mlp_lr = mlp_steps, mlp_sample, mlp_lr
+    return o
+
+
+def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, **opts) -> None:
+    """Sort keys (float64 totalOrder / uint64) in place; payload (uint32) follows stably."""
+    _dev(keys, "keys")
+    if payload is not None:
+        _dev(payload, "payload")
+        if payload.dtype != torch.uint32 or payload.numel() != keys.numel():
+            raise ValueError("payload must be uint32 with one entry per key")
+    o = make_options(**opts)
+    _check(lib().ls_sort(_ptr(keys), keys.numel(), _dtype(keys), _ptr(payload), C.byref(o), _stream()))
+
+
+def sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, payload: torch.Tensor | None = None,
+                   total: int | None = None, **opts) -> None:
+    """Sort each [offsets[i], offsets[i+1]) independently in one batched pass."""
+    _dev(keys, "keys")
+    _dev(offsets, "offsets")
+    if offsets.dtype != torch.uint64:
+        raise ValueError("offsets must be uint64")
+    if payload is not None:
+        _dev(payload, "payload")
+        if payload.dtype != torch.uint32 or payload.numel() != keys.numel():
+            raise ValueError("payload must be uint32 with one entry per key")
+    m = offsets.numel() - 1
+    tot = keys.numel() if total is None else int(total)
+    o = make_options(**opts)
+    _check(lib().ls_sort_segmented(_ptr(keys), _ptr(offsets), m, tot, _dtype(keys), _ptr(payload), C.byref(o),
+                                   _stream()))
+
+
+def stats() -> dict:
+    s = Stats()
+    _check(lib().ls_get_stats(C.byref(s)))
+    levels = []
+    for i in range(s.levels):
+        lv = s.level[i]
+        levels.append({f: getattr(lv, f) for f, _ in LevelStats._fields_})
+    return {"levels": levels, "first_model": s.first_model, "base_items": s.base_items,
+            "copy_items": s.copy_items, "mlp_loss_first": s.mlp_loss_first, "mlp_loss_last": s.mlp_loss_last}
+
+
+def workspace_bytes(n: int, m: int = 1, dtype=torch.float64, payload: bool = False, **opts) -> int:
+    out = C.c_size_t()
+    o = make_options(**opts)
+    _check(lib().ls_workspace_bytes(n, m, LS_F64 if dtype == torch.float64 else LS_U64, int(payload), C.byref(o),
+                                    C.byref(out)))
+    return out.value
+
+
+def set_workspace(buf: torch.Tensor | None) -> None:
+    if buf is None:
+        _check(lib().ls_set_workspace(None, 0))
+    else:
+        _dev(buf, "workspace")
+        _check(lib().ls_set_workspace(_ptr(buf), buf.numel() * buf.element_size()))
+
+
+# -- single steps -------------------------------------------------------------------
+
+def sample(keys: torch.Tensor, seed: int, S: int) -> torch.Tensor:
+    _dev(keys, "keys")
+    out = torch.empty(S, dtype=keys.dtype, device=keys.device)
+    _check(lib().ls_sample(_ptr(keys), keys.numel(), _dtype(keys), seed, S, _ptr(out), _stream()))
+    return out
+
+
+def rmi_fit(sorted_sample: torch.Tensor, L: int, R: float) -> torch.Tensor:
+    _dev(sorted_sample, "sorted_sample")
+    out = torch.empty(2 + 4 * L, dtype=torch.float64, device=sorted_sample.device)
+    _check(lib().ls_rmi_fit(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), L, float(R), _ptr(out),
+                            _stream()))
+    return out
+
+
+def rmi_buckets(keys: torch.Tensor, params: torch.Tensor, L: int, R: float) -> torch.Tensor:
+    _dev(keys, "keys")
+    _dev(params, "params")
+    out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
+    _check(lib().ls_rmi_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(params), L, float(R), _ptr(out),
+                                _stream()))
+    return out
+
+
+def splitters(sorted_sample: torch.Tensor, B: int):
+    _dev(sorted_sample, "sorted_sample")
+    u = torch.empty(max(B - 1, 1), dtype=torch.uint64, device=sorted_sample.device)
+    eq = torch.zeros(max(B - 1, 1), dtype=torch.uint8, device=sorted_sample.device)
+    m = torch.zeros(1, dtype=torch.uint32, device=sorted_sample.device)
+    _check(lib().ls_splitters(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), B, _ptr(u), _ptr(eq),
+                              _ptr(m), _stream()))
+    k = int(m.cpu().item())
+    return u[:k], eq[:k]
+
+
+def splitter_buckets(keys: torch.Tensor, u: torch.Tensor, eq: torch.Tensor) -> torch.Tensor:
+    _dev(keys, "keys")
+    u = u.contiguous()
+    eq = eq.contiguous()
+    out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
+    _check(lib().ls_splitter_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(u), _ptr(eq), u.numel(), _ptr(out),
+                                     _stream()))
+    return out
+
+
+def partition_rmi(keys, params, L, R, nb, payload=None):
+    _dev(keys, "keys")
+    ok = torch.empty_like(keys)
+    op = None if payload is None else torch.empty_like(payload)
+    counts = torch.zeros(nb, dtype=torch.uint64, device=keys.device)
+    _check(lib().ls_partition_rmi(_ptr(keys), _ptr(payload), keys.numel(), _dtype(keys), _ptr(params), L, float(R), nb,
+                                  _ptr(ok), _ptr(op), _ptr(counts), _stream()))
+    return ok, op, counts
+
+
+def partition_splitters(keys, u, eq, payload=None):
+    _dev(keys, "keys")
+    ok = torch.empty_like(keys)
+    op = None if payload is None else torch.empty_like(payload)
+    nb = u.numel() + 1 + int(eq.to(torch.int64).sum().item())
+    counts = torch.zeros(nb, dtype=torch.uint64, device=keys.device)
+    _check(lib().ls_partition_splitters(_ptr(keys), _ptr(payload), keys.numel(), _dtype(keys), _ptr(u), _ptr(eq),
+                                        u.numel(), _ptr(ok), _ptr(op), _ptr(counts), _stream()))
+    return ok, op, counts
+
+
+def version() -> str:
+    return lib().ls_version().decode()

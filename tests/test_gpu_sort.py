@@ -1,0 +1,202 @@
+"""GPU parity of the full sort against the CPU oracle (bit-exact).
+
+Every case: seeded synthetic input -> liblsort on cuda:0 through the C ABI ->
+compare every output word (keys, and payload where given) with the oracle's
+stable sort of the same input.  Large inputs, where the oracle would take too
+long, are checked by properties that pin a sort at any size: sortedness in
+totalOrder plus equal multisets (count and two independent 64-bit hashes).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2307_08637_amd import inputs, lsort
+from tests.gpu_helpers import is_sorted, multiset_hash, signed_order_key, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_sort(keys, dev, payload=None, **opts):
+    t = to_dev(keys, dev)
+    p = None
+    if payload is not None:
+        p = torch.from_numpy(payload.view(np.int32).copy()).to(dev).view(torch.uint32)
+    print(f"[case] n={keys.size} dtype={keys.dtype} payload={payload is not None} opts={opts}", flush=True)
+    lsort.sort(t, p, **opts)
+    torch.cuda.synchronize()
+    out = to_host(t)
+    pout = None if p is None else p.view(torch.int32).cpu().numpy().view(np.uint32)
+    return out, pout
+
+
+def assert_same_bits(got, want):
+    g = np.ascontiguousarray(got).view(np.uint64)
+    w = np.ascontiguousarray(want).view(np.uint64)
+    assert g.shape == w.shape
+    bad = np.flatnonzero(g != w)
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}: got {g[bad[:5]]} want {w[bad[:5]]}"
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 17, 255, 256, 257, 4095, 4096, 4097, 8191, 8192, 8193,
+                               16385, 50_000, 99_999, 100_000, 250_001])
+def test_sizes_uniform(dev, n):
+    keys = inputs.generate("uniform", n, seed=11)
+    got, _ = gpu_sort(keys, dev)
+    want, _ = oracle.sort(keys)
+    assert_same_bits(got, want)
+
+
+@pytest.mark.parametrize("cutoff", [1, 16, 256, 4096])
+def test_cutoffs(dev, cutoff):
+    keys = inputs.generate("normal", 120_000, seed=12)
+    got, _ = gpu_sort(keys, dev, cutoff=cutoff)
+    assert_same_bits(got, oracle.sort(keys)[0])
+
+
+def test_config_small_uniform_1e6(dev):
+    """N = 1e6 uniform [0,1) float64, 1000 leaves, 1000 buckets, base case below 256 keys."""
+    keys = inputs.generate("uniform", 1_000_000, seed=1)
+    got, _ = gpu_sort(keys, dev, buckets=1000, leaves=1000, cutoff=256)
+    assert_same_bits(got, oracle.sort(keys)[0])
+    st = lsort.stats()
+    assert len(st["levels"]) >= 1
+    assert st["levels"] and st["levels"][0]["learned"] == 1  # Alg. 5 picks the RMI at n = 1e6
+
+
+@pytest.mark.parametrize("law", inputs.ALL_LAWS)
+def test_laws_1e6(dev, law):
+    keys = inputs.generate(law, 1_000_000, seed=21)
+    got, _ = gpu_sort(keys, dev)
+    assert_same_bits(got, oracle.sort(keys)[0])
+
+
+@pytest.mark.parametrize("law", ["uniform", "lognormal", "rootdups", "zipf"])
+def test_payload_stable(dev, law):
+    n = 300_000
+    keys = inputs.generate(law, n, seed=31)
+    pay = np.arange(n, dtype=np.uint32)
+    got, gp = gpu_sort(keys, dev, payload=pay)
+    want, wp = oracle.sort(keys, pay)
+    assert_same_bits(got, want)
+    assert np.array_equal(gp, wp)
+
+
+@pytest.mark.parametrize("kind", inputs.ADVERSARIAL_F64 + inputs.ADVERSARIAL_U64)
+@pytest.mark.parametrize("n", [2, 100, 5000, 70_000, 200_000])
+def test_adversarial(dev, kind, n):
+    keys = inputs.adversarial(kind, n, seed=5)
+    pay = np.arange(n, dtype=np.uint32)
+    got, gp = gpu_sort(keys, dev, payload=pay)
+    want, wp = oracle.sort(keys, pay)
+    assert_same_bits(got, want)
+    assert np.array_equal(gp, wp)
+
+
+@pytest.mark.parametrize("law", ["uniform", "normal", "rootdups", "u64"])
+def test_splitter_model(dev, law):
+    keys = inputs.generate(law, 400_000, seed=41)
+    got, _ = gpu_sort(keys, dev, model="splitter")
+    assert_same_bits(got, oracle.sort(keys)[0])
+    st = lsort.stats()
+    assert st["levels"][0]["learned"] == 0
+
+
+def test_no_fallback_and_small_buckets(dev):
+    keys = inputs.generate("lognormal", 500_000, seed=42)
+    got, _ = gpu_sort(keys, dev, no_fallback=True, buckets=64, leaves=32)
+    assert_same_bits(got, oracle.sort(keys)[0])
+
+
+def test_depth_cap_radix(dev):
+    # a one-level cap forces range-radix partitions after the first level
+    keys = inputs.generate("twodups", 400_000, seed=43)
+    got, _ = gpu_sort(keys, dev, max_levels=1, cutoff=64)
+    assert_same_bits(got, oracle.sort(keys)[0])
+    st = lsort.stats()
+    assert any(lv["radix"] > 0 for lv in st["levels"])
+
+
+def test_repeat_deterministic(dev):
+    keys = inputs.generate("mixgauss", 700_000, seed=44)
+    a, _ = gpu_sort(keys, dev)
+    b, _ = gpu_sort(keys, dev)
+    assert_same_bits(a, b)
+
+
+@pytest.mark.parametrize("law", ["uniform", "normal", "u64", "twodups"])
+def test_large_1e7_oracle(dev, law):
+    keys = inputs.generate(law, 10_000_000, seed=51)
+    got, _ = gpu_sort(keys, dev)
+    assert_same_bits(got, oracle.sort(keys)[0])
+
+
+@pytest.mark.parametrize("law", ["uniform", "normal", "lognormal", "exponential", "chisquared", "mixgauss", "u64",
+                                 "rootdups", "twodups", "zipf"])
+def test_full_size_1e8_properties(dev, law):
+    """Full benchmark size (1e8 keys) in the benchmark's launch configuration:
+    sorted in totalOrder, the same multiset as the input (count and two
+    64-bit hashes), and at sampled output positions i the value's rank in the
+    input satisfies #{keys < v} <= i < #{keys <= v} (the sorted-position
+    definition, counted directly)."""
+    n = 100_000_000
+    keys = inputs.generate(law, n, seed=61)
+    t = to_dev(keys, dev)
+    src = signed_order_key(t.clone())
+    h1, h2 = multiset_hash(t), multiset_hash(t, salt=0x5A5A5A5A5A5A5A5)
+    print(f"[case] 1e8 {law}", flush=True)
+    lsort.sort(t)
+    torch.cuda.synchronize()
+    assert t.numel() == n
+    assert is_sorted(t)
+    assert multiset_hash(t) == h1 and multiset_hash(t, salt=0x5A5A5A5A5A5A5A5) == h2
+    out = signed_order_key(t)
+    for i in np.random.default_rng(0).integers(0, n, 16).tolist() + [0, n - 1]:
+        v = out[i]
+        lt = int((src < v).sum().item())
+        le = int((src <= v).sum().item())
+        assert lt <= i < le, (i, lt, le)
+    del t, src, out
+
+
+def test_segmented_small(dev):
+    rng = np.random.default_rng(3)
+    sizes = np.array([0, 1, 2, 5, 300, 4096, 4097, 9000, 0, 70_000, 1, 250_000, 33], dtype=np.int64)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    keys = np.concatenate([inputs.generate(["uniform", "normal", "lognormal"][i % 3], int(s), seed=100 + i)
+                           for i, s in enumerate(sizes)])
+    pay = np.concatenate([np.arange(s, dtype=np.uint32) for s in sizes])
+    t = to_dev(keys, dev)
+    p = torch.from_numpy(pay.view(np.int32).copy()).to(dev).view(torch.uint32)
+    o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+    lsort.sort_segmented(t, o, p)
+    torch.cuda.synchronize()
+    want, wp = oracle.sort_segmented(keys, off, pay)
+    assert_same_bits(to_host(t), want)
+    assert np.array_equal(p.view(torch.int32).cpu().numpy().view(np.uint32), wp)
+    del rng
+
+
+@pytest.mark.parametrize("m", [1, 7, 200])
+def test_segmented_laws(dev, m):
+    keys, off, pay, _ = inputs.segmented(m, seed=77, lo=10, hi=2e5)
+    t = to_dev(keys, dev)
+    p = torch.from_numpy(pay.view(np.int32).copy()).to(dev).view(torch.uint32)
+    o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+    lsort.sort_segmented(t, o, p)
+    torch.cuda.synchronize()
+    want, wp = oracle.sort_segmented(keys, off, pay)
+    assert_same_bits(to_host(t), want)
+    assert np.array_equal(p.view(torch.int32).cpu().numpy().view(np.uint32), wp)
+
+
+def test_errors(dev):
+    t = torch.zeros(10, dtype=torch.float32, device=dev)
+    with pytest.raises(TypeError):
+        lsort.sort(t)
+    k = torch.zeros(10, dtype=torch.float64, device=dev)
+    with pytest.raises(lsort.LsortError):
+        lsort.sort(k, buckets=5000)
+    with pytest.raises(lsort.LsortError):
+        lsort.sort(k, tree_buckets=100)
