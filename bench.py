@@ -1,0 +1,212 @@
+"""Benchmark: Gkeys/s sorting 1e8 float64 keys on one MI355X, learned (RMI)
+partitioning vs the splitter-tree form, with the roofline of the dominant
+kernel and the CPU oracle's rate on the host.
+
+A step is one complete sort of the 1e8-key array (sampling, sample sort,
+model fit, every partition level and the base case).  The keys of every
+timed step are already in HBM: K unsorted copies are made before the timed
+region and step k sorts copy k in place.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--law normal]
+                       [--n 100000000] [--no-cpu-baseline] [--no-laws]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+# Algorithmic bytes each kernel must move per key it processes (keys only,
+# float64): read + write of the keys; see the design doc.
+BYTES_PER_KEY = {"k_hist": 8.0, "k_scatter": 16.0, "k_base": 16.0}
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2307_08637_amd", "csrc", f)
+                  for f in ("lsort_kernels.hip", "lsort_dev.hpp", "lsort_internal.hpp")]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--n", type=int, default=100_000_000)
+    p.add_argument("--law", default="normal")
+    p.add_argument("--seed", type=int, default=21)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-laws", action="store_true", help="skip the per-law table")
+    p.add_argument("--cpu-keys", type=int, default=50_000_000, help="keys in the oracle's timed sample")
+    return p.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2307_08637_amd import inputs, lsort
+
+    dev = torch.device("cuda:0")
+    lsort.lib()  # fail loudly if the HIP library is missing
+
+    def log(*x):
+        print("[bench]", *x, file=sys.stderr, flush=True)
+
+    log("generating", a.n, a.law)
+    host = inputs.generate(a.law, a.n, seed=a.seed)
+    dtype = torch.uint64 if host.dtype == np.uint64 else torch.float64
+    base = torch.from_numpy(host.view(np.int64) if host.dtype == np.uint64 else host).to(dev).view(dtype)
+    bufs = [torch.empty_like(base) for _ in range(a.steps)]
+    warm = torch.empty_like(base)
+
+    def run(model, steps, timed_bufs):
+        for _ in range(a.warmup):
+            warm.copy_(base)
+            lsort.sort(warm, model=model)
+        for b in timed_bufs[:steps]:
+            b.copy_(base)
+        torch.cuda.synchronize()
+        lsort.timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for b in timed_bufs[:steps]:
+            lsort.sort(b, model=model)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern = lsort.timing_read()
+        lsort.timing(False)
+        st = lsort.stats()
+        # the result must be a sorted permutation (cheap properties on the GPU)
+        k = timed_bufs[0].view(torch.int64)
+        key = k ^ (-(1 << 63)) if dtype == torch.uint64 else torch.where(k < 0, k ^ 0x7FFFFFFFFFFFFFFF, k)
+        if not bool((key[:-1] <= key[1:]).all().item()):
+            raise SystemExit(f"bench: output of model={model} is not sorted")
+        ms = e0.elapsed_time(e1) / steps
+        return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "kernels": kern, "stats": st}
+
+    log("learned", a.steps, "steps")
+    L = run("auto", a.steps, bufs)
+    log("splitter", a.steps, "steps")
+    S = run("splitter", a.steps, bufs)
+
+    gk = lambda r: a.n / (r["ms_per_step"] * 1e-3) / 1e9  # noqa: E731
+    kern = L["kernels"]
+    dom = max((k for k in kern if k in BYTES_PER_KEY), key=lambda k: kern[k]["ms"])
+    dk = kern[dom]
+    avg_ms = dk["ms"] / dk["launches"]
+    avg_bytes = dk["keys"] * BYTES_PER_KEY[dom] / dk["launches"]
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as f:
+            tr = json.load(f)
+        if tr.get("kernel") == dom and tr.get("source_sha") == kernel_source_sha() and tr.get("workload") == \
+                f"{a.n} {a.law} learned":
+            traffic = tr.get("bytes_per_launch")
+
+    def level_summary(st):
+        return [{"segments": lv["segments"], "keys": lv["keys"], "learned": lv["learned"], "tree": lv["tree"],
+                 "radix": lv["radix"], "max_over_mean": lv["max_bucket_x1000_over_mean"] / 1000.0,
+                 "fallback": lv["fallback"]} for lv in st["levels"]]
+
+    laws = {}
+    if not a.no_laws:
+        for law in ("uniform", "normal", "lognormal", "exponential", "chisquared", "mixgauss", "u64"):
+            if law == a.law:
+                laws[law] = {"learned": round(gk(L), 3), "splitter": round(gk(S), 3)}
+                continue
+            log("law", law)
+            h = inputs.generate(law, a.n, seed=a.seed)
+            dt = torch.uint64 if h.dtype == np.uint64 else torch.float64
+            src = torch.from_numpy(h.view(np.int64) if h.dtype == np.uint64 else h).to(dev).view(dt)
+            bb = [b.view(dt) for b in bufs[:3]]
+            rl = run_on(src, bb, "auto", lsort, torch)
+            rs = run_on(src, bb, "splitter", lsort, torch)
+            laws[law] = {"learned": round(a.n / (rl * 1e-3) / 1e9, 3), "splitter": round(a.n / (rs * 1e-3) / 1e9, 3)}
+            del src, h
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        m = min(a.cpu_keys, a.n)
+        log("oracle on", m, "keys")
+        t0 = time.perf_counter()
+        oracle.sort(host[:m])
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(m / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {m} of the same {a.n} {a.law} keys, one single-threaded oracle sort "
+                         f"({dt:.1f} s) on {os.cpu_count()} host CPUs"}
+
+    out = {
+        "metric": "Gkeys/s sorting 1e8 f64 keys, learned vs splitter buckets; % HBM peak",
+        "value": round(gk(L), 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(L["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if dtype == torch.float64 else "u64",
+        "data": "synthetic",
+        "config": {"workload": f"sort {a.n} {'float64' if dtype == torch.float64 else 'uint64'} keys, law {a.law}, "
+                               f"learned RMI partitioning (1% sample, 1000 leaves, 1000 buckets), stable, in place",
+                   "n": a.n, "law": a.law, "seed": a.seed, "model": "auto"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_key": BYTES_PER_KEY[dom], "avg_launch_ms": round(avg_ms, 4),
+                     "launches": dk["launches"]},
+        "cpu_baseline": cpu,
+        "splitter": {"value": round(gk(S), 4), "ms_per_step": round(S["ms_per_step"], 4),
+                     "levels": level_summary(S["stats"])},
+        "learned_over_splitter": round(gk(L) / gk(S), 4),
+        "levels": level_summary(L["stats"]),
+        "kernels": {k: {"launches": v["launches"], "ms_per_step": round(v["ms"] / a.steps, 4),
+                        "keys_per_step": v["keys"] / a.steps} for k, v in kern.items()},
+        "wall_ms_per_step": round(L["wall_ms_per_step"], 4),
+        "laws": laws,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_on(src, bufs, model, lsort, torch):
+    """ms per sort of `src` (K = len(bufs) copies, after one warm-up)."""
+    tmp = bufs[0]
+    tmp.copy_(src)
+    lsort.sort(tmp, model=model)
+    for b in bufs:
+        b.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for b in bufs:
+        lsort.sort(b, model=model)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / len(bufs)
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,28 @@ const char *ls_last_error(void);
 /* Library version string, e.g. "lsort 0.1 gfx950". */
 const char *ls_version(void);
 
+/* ---- Kernel timing (measurement tools) ------------------------------------ */
+
+/* Per-kernel totals over the calls made while timing was on.  keys: keys the
+ * launches processed (hist/scatter: keys of the level; base: keys in base-case
+ * and copy items; other kernels 0) -- the unit a kernel's algorithmic bytes
+ * are counted per. */
+typedef struct {
+    char name[32];
+    uint64_t launches;
+    double ms;               /* summed launch durations (HIP events on the call's stream) */
+    double keys;
+} ls_kernel_timing;
+
+/* Start (enable = 1) or stop (0) recording; starting clears earlier records.
+ * While on, every launch is bracketed by two events on its stream and each
+ * call waits for its last kernel before returning. */
+ls_status ls_timing(int enable);
+
+/* Totals per kernel name (host array of cap entries); *count gets the number
+ * of names written.  Waits for the recorded work to finish. */
+ls_status ls_timing_read(ls_kernel_timing *out, uint32_t cap, uint32_t *count);
+
 /* ---- Single steps (exposed so each step can be checked on its own) -------- */
 
 /* Random sample with replacement (Sec. 2.2: the model is trained on a ~1%

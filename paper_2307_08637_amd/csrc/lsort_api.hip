@@ -109,8 +109,11 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.seg_cap = std::max<uint64_t>(m, n / (C + 1)) + 16;
     L.tile_cap = n / TILE + L.seg_cap + 16;
     L.item_cap = n + m + 64;
-    L.counts_cap = 2 * (n / 4 + 2 * L.seg_cap) + 64;
-    L.status_cap = (n / TILE) * B_MAX + n / 4 + 2 * L.seg_cap + 64;
+    // Bucket counts per level: a segment gets at most n_seg / 4 buckets (at
+    // least 2), except one first-level segment whose model the caller gives
+    // (up to B_MAX).  Look-back words: tiles x buckets of each segment.
+    L.counts_cap = 2 * (n / 4 + 2 * L.seg_cap + B_MAX) + 64;
+    L.status_cap = (n / TILE) * B_MAX + n / 4 + 2 * L.seg_cap + 2 * B_MAX + 64;
     L.arena_cap = (n / 100000 + m + 2) * (8ull * MODEL_WORDS + 16) + (uint64_t)(0.7 * (double)n) + L.seg_cap * 32 + 65536;
     uint64_t o_ = 0;
     auto take = [&](uint64_t bytes) { uint64_t r = o_; o_ += align256(bytes); return r; };
@@ -166,6 +169,46 @@ struct LastCall {
     bool valid = false;
 };
 static thread_local LastCall g_last;
+
+// ---------------------------------------------------------------------------
+// optional kernel timing: an event pair around each launch
+// ---------------------------------------------------------------------------
+enum KernelId { KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_GATHER, KI_FIT, KI_N };
+static const char* KNAME[KI_N] = {"k_reset", "k_seed", "k_model", "k_hist", "k_scan", "k_scatter", "k_base",
+                                  "k_gather", "k_fit"};
+struct TRec {
+    int kid;
+    hipEvent_t a, b;
+    double keys;
+};
+static bool g_timing = false;
+static std::vector<TRec> g_trec;
+static std::vector<hipEvent_t> g_evfree;
+
+static hipEvent_t ev_get() {
+    if (!g_evfree.empty()) {
+        hipEvent_t e = g_evfree.back();
+        g_evfree.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `expr` (a hipError_t expression); when timing, bracket it with events.
+#define TIMED(kid, st, expr)                                              \
+    do {                                                                  \
+        if (g_timing) {                                                   \
+            TRec r_{(kid), ev_get(), ev_get(), 0.0};                      \
+            if (r_.a) HIP_TRY(hipEventRecord(r_.a, (st)));                \
+            HIP_TRY(expr);                                                \
+            if (r_.b) HIP_TRY(hipEventRecord(r_.b, (st)));                \
+            g_trec.push_back(r_);                                         \
+        } else {                                                          \
+            HIP_TRY(expr);                                                \
+        }                                                                 \
+    } while (0)
 
 static uint64_t layout_sig(const Layout& L) {
     uint64_t h = 1469598103934665603ull;
@@ -305,7 +348,7 @@ static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPoo
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
-    HIP_TRY(launch_gather(c.keys, c.n, z, L.S_big, smp, c.st));
+    TIMED(KI_GATHER, c.st, launch_gather(c.keys, c.n, z, L.S_big, smp, c.st));
     Call nc{};
     nc.keys = smp; nc.pay = nullptr; nc.n = L.S_big; nc.m = 1; nc.offsets = nullptr; nc.u64 = c.u64;
     nc.o = c.o;
@@ -340,18 +383,18 @@ static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPoo
     A.model = (uint64_t*)(base + L.o_bigmodel);
     A.flag = (uint32_t*)(base + L.o_flag);
     A.seg = P.segs[1];
-    HIP_TRY(launch_fit1(A, c.st));
-    HIP_TRY(launch_fit2(A, c.st));
-    HIP_TRY(launch_fit_root(A, c.st));
-    HIP_TRY(launch_fit_leaves(A, c.st));
-    HIP_TRY(launch_fit_finish(A, c.st));
+    TIMED(KI_FIT, c.st, launch_fit1(A, c.st));
+    TIMED(KI_FIT, c.st, launch_fit2(A, c.st));
+    TIMED(KI_FIT, c.st, launch_fit_root(A, c.st));
+    TIMED(KI_FIT, c.st, launch_fit_leaves(A, c.st));
+    TIMED(KI_FIT, c.st, launch_fit_finish(A, c.st));
     return LS_OK;
 }
 
 static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* pool) {
     Params P = make_params(c, L, base);
     uint64_t* persist = (uint64_t*)(base + L.o_persist);
-    HIP_TRY(launch_reset(P, persist, c.st));
+    TIMED(KI_RESET, c.st, launch_reset(P, persist, c.st));
     uint32_t prebuilt = 0;
     if (c.one_level) {
         prebuilt = 1;
@@ -361,31 +404,50 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         prebuilt = 1;
     }
     const uint32_t seed_grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((c.m + 255) / 256, 256), 65535);
-    HIP_TRY(launch_seed(P, c.offsets, c.m, c.n, prebuilt, persist, seed_grid, c.st));
+    TIMED(KI_SEED, c.st, launch_seed(P, c.offsets, c.m, c.n, prebuilt, persist, seed_grid, c.st));
     const uint32_t cus = (uint32_t)pool->cus;
     const bool fixed = (c.o.flags & LS_FLAG_FIXED_LEVELS) != 0;
     const uint32_t max_run = c.one_level ? 1 : std::min<uint32_t>(MAXL - 1, c.o.max_levels + 9);
     uint32_t levels = 0;
     for (uint32_t lvl = 0; lvl < max_run; lvl++) {
         P.level = (int)lvl;
-        HIP_TRY(launch_model(P, lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024, c.st));
-        HIP_TRY(launch_hist(P, cus * 4, c.st));
-        HIP_TRY(launch_scan(P, lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024, c.st));
-        HIP_TRY(launch_scatter(P, cus, c.st));
+        const size_t rec0 = g_trec.size();
+        const uint32_t g0 = lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024;
+        TIMED(KI_MODEL, c.st, launch_model(P, g0, c.st));
+        TIMED(KI_HIST, c.st, launch_hist(P, cus * 4, c.st));
+        TIMED(KI_SCAN, c.st, launch_scan(P, g0, c.st));
+        TIMED(KI_SCATTER, c.st, launch_scatter(P, cus, c.st));
         levels = lvl + 1;
-        if (c.one_level || fixed) continue;
-        // read back the next level's work and the overflow flags
+        if (c.one_level) {
+            HIP_TRY(hipMemcpyAsync(pool->pinned, &P.ctl->overflow, 4, hipMemcpyDeviceToHost, c.st));
+            HIP_TRY(hipStreamSynchronize(c.st));
+            uint32_t ovf = ((uint32_t*)pool->pinned)[0];
+            if (ovf) return fail(LS_ENOMEM, "workspace capacity exceeded:" + overflow_text(ovf));
+            continue;
+        }
+        if (fixed) continue;
+        // read back the next level's work, the overflow flags and this level's keys
         Ctl* ctl = P.ctl;
         HIP_TRY(hipMemcpyAsync(pool->pinned, &ctl->nseg[lvl + 1], 4, hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 8, &ctl->overflow, 4, hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 16, &ctl->lv[lvl].keys, 8, hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
         uint32_t next = ((uint32_t*)pool->pinned)[0];
         uint32_t ovf = ((uint32_t*)pool->pinned)[2];
+        double lkeys = (double)((uint64_t*)pool->pinned)[2];
+        for (size_t i = rec0; i < g_trec.size(); i++) g_trec[i].keys = lkeys;
         if (ovf) return fail(LS_ENOMEM, "workspace capacity exceeded:" + overflow_text(ovf));
         if (next == 0) break;
     }
     (void)levels;
-    if (!c.one_level) HIP_TRY(launch_base(P, cus * 2, c.st));
+    if (!c.one_level) {
+        TIMED(KI_BASE, c.st, launch_base(P, cus * 2, c.st));
+        if (g_timing) {
+            HIP_TRY(hipMemcpyAsync(pool->pinned, &P.ctl->base_keys, 16, hipMemcpyDeviceToHost, c.st));
+            HIP_TRY(hipStreamSynchronize(c.st));
+            g_trec.back().keys = (double)(pool->pinned[0] + pool->pinned[1]);
+        }
+    }
     return LS_OK;
 }
 
@@ -528,6 +590,43 @@ ls_status ls_get_stats(ls_stats* out) {
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
     out->mlp_loss_last = c.mlp_loss[1];
+    return LS_OK;
+}
+
+ls_status ls_timing(int enable) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (TRec& r : g_trec) {
+        if (r.a) g_evfree.push_back(r.a);
+        if (r.b) g_evfree.push_back(r.b);
+    }
+    g_trec.clear();
+    g_timing = enable != 0;
+    return LS_OK;
+}
+
+ls_status ls_timing_read(ls_kernel_timing* out, uint32_t cap, uint32_t* count) {
+    if (!out || !count) return fail(LS_EINVAL, "out / count is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    ls_kernel_timing agg[KI_N];
+    std::memset(agg, 0, sizeof(agg));
+    for (const TRec& r : g_trec) {
+        float ms = 0;
+        if (r.a && r.b) {
+            HIP_TRY(hipEventSynchronize(r.b));
+            HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        }
+        agg[r.kid].launches++;
+        agg[r.kid].ms += ms;
+        agg[r.kid].keys += r.keys;
+    }
+    uint32_t k = 0;
+    for (int i = 0; i < KI_N && k < cap; i++) {
+        if (!agg[i].launches) continue;
+        out[k] = agg[i];
+        std::snprintf(out[k].name, sizeof(out[k].name), "%s", KNAME[i]);
+        k++;
+    }
+    *count = k;
     return LS_OK;
 }
 

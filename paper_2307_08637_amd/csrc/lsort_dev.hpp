@@ -98,29 +98,6 @@ __device__ __forceinline__ uint32_t radix_bucket(uint64_t lo, uint32_t shift, ui
     return shift >= 64 ? 0u : (uint32_t)((o - lo) >> shift);
 }
 
-// Reserve `amt` consecutive slots of a list with capacity `cap`: returns the
-// first slot, or ~0 when the list would overflow (nothing is reserved then,
-// so every slot below the counter is always written).
-__device__ __forceinline__ uint64_t reserve32(uint32_t* ctr, uint32_t amt, uint64_t cap) {
-    uint32_t old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        if ((uint64_t)old + amt > cap) return ~0ull;
-        uint32_t seen = atomicCAS(ctr, old, old + amt);
-        if (seen == old) return old;
-        old = seen;
-    }
-}
-
-__device__ __forceinline__ uint64_t reserve64(unsigned long long* ctr, unsigned long long amt, uint64_t cap) {
-    unsigned long long old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        if (old + amt > cap) return ~0ull;
-        unsigned long long seen = atomicCAS(ctr, old, old + amt);
-        if (seen == old) return old;
-        old = seen;
-    }
-}
-
 // Monotone MLP CDF in FP32 (1-16-16-1; non-negative effective weights;
 // units 0..7 max(z,0), 8..15 min(z,0)); fmaf chains in index order.
 __device__ __forceinline__ float mlp_eval(const float* w, float t) {

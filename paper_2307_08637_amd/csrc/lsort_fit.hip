@@ -98,7 +98,7 @@ __global__ __launch_bounds__(M_THREADS) void k_fit_root(FitArgs A) {
         if (threadIdx.x == 0) {
             RmiModel* h = (RmiModel*)dst;
             h->L = A.L; h->B1 = A.B1; h->log2B2 = A.log2B2; h->pad = 0;
-            h->R = A.R; h->pad2 = 0; h->pad3 = 0;
+            h->R = A.R; h->pad2 = 0;
             ((double*)dst)[4] = (double)A.L * a;
             ((double*)dst)[5] = (double)A.L * b;
         }
@@ -233,7 +233,7 @@ __global__ void k_install_rmi(const double* params, uint32_t L, double R, uint32
     for (uint32_t i = threadIdx.x; i < 2 + 4 * L; i += blockDim.x) ((double*)dst)[4 + i] = params[i];
     if (threadIdx.x == 0) {
         RmiModel* h = (RmiModel*)dst;
-        h->L = L; h->B1 = B1; h->log2B2 = log2B2; h->pad = 0; h->R = R; h->pad2 = 0; h->pad3 = 0;
+        h->L = L; h->B1 = B1; h->log2B2 = log2B2; h->pad = 0; h->R = R; h->pad2 = 0;
     }
 }
 

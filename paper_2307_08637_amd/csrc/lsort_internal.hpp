@@ -39,24 +39,27 @@ enum Kind : uint32_t {
 };
 
 // Model headers (8-byte aligned, followed by their payload in the arena).
-struct RmiModel {     // followed by double p[2 + 4L]
+struct RmiModel {     // 32 bytes, followed by double p[2 + 4L] (model word 4 on)
     uint32_t L, B1, log2B2, pad;
     double R;         // B1 << log2B2
-    uint64_t pad2;    // header is 24 bytes + 8 = 32
-    uint64_t pad3;
+    uint64_t pad2;
 };
-struct TreeModel {    // followed by uint64 u[m] then uint16 lut[m+1]
+static_assert(sizeof(RmiModel) == 32, "RMI parameters start at model word 4");
+struct TreeModel {    // 16 bytes, followed by uint64 u[m] then uint16 lut[m+1]
     uint32_t m, nb, top, pad;
 };
+static_assert(sizeof(TreeModel) == 16, "splitters start at model word 2");
 struct RadixModel {
     uint64_t lo;
     uint32_t shift, nb;
 };
-struct MlpModel {     // followed by float w[321] (effective weights |V|, biases)
+static_assert(sizeof(RadixModel) == 16, "radix model is two words");
+struct MlpModel {     // 32 bytes, followed by float w[321] (effective weights |V|, biases)
     uint32_t B1, log2B2;
     double lo, inv;
     double R;
 };
+static_assert(sizeof(MlpModel) == 32, "MLP weights start at model word 4");
 
 // One sub-array partitioned at some level.
 struct Seg {
@@ -70,8 +73,9 @@ struct Seg {
     uint32_t win;     // fine window base for *_FINE kinds
     uint32_t tile0;   // first tile in the level's tile list
     uint32_t ntiles;
-    uint32_t flags;   // SEG_* bits
+    uint32_t flags;   // SEG_* bits; model size in 8-byte words in bits 16..31
 };
+static_assert(sizeof(Seg) == 64, "segment descriptor is 64 bytes");
 constexpr uint32_t SEG_PREBUILT = 1u;  // model already built (large first level)
 constexpr uint32_t SEG_FAILED = 2u;    // capacity exceeded; not partitioned
 
@@ -100,6 +104,8 @@ struct Ctl {
     uint32_t pad0;
     unsigned long long nitems;      // base-case + copy items
     unsigned long long ncopy;
+    unsigned long long base_keys;   // keys in base-case items
+    unsigned long long copy_keys;   // keys in copy items
     unsigned long long counts_used; // bump allocators (reset per level)
     unsigned long long status_used;
     unsigned long long arena_used[2];

@@ -34,38 +34,66 @@ __global__ void k_reset(Params P, uint64_t* persist) {
 }
 
 // Seed level 0 from the caller's segments; clear the status pool on epoch wrap.
-__global__ void k_seed(Params P, const uint64_t* offsets, uint64_t m, uint64_t n_single, uint32_t prebuilt,
-                       const uint64_t* persist) {
+// List slots are reserved with one atomicAdd per workgroup; every slot below
+// a list's capacity is written by its owner, so consumers never meet a stale
+// entry (slots at or above capacity are dropped and flagged as overflow).
+__global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets, uint64_t m, uint64_t n_single,
+                                              uint32_t prebuilt, const uint64_t* persist) {
+    __shared__ uint64_t red64[256 / 64];
+    __shared__ uint64_t base[3];
     if (persist[1]) {
         for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.status_cap;
              i += (uint64_t)gridDim.x * blockDim.x)
             P.status[i] = 0;
     }
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t lo = offsets ? offsets[s] : 0;
-        uint64_t n = offsets ? offsets[s + 1] - lo : n_single;
-        if (n <= 1) continue;
-        if (n <= P.cutoff) {
-            uint64_t it = reserve64(&P.ctl->nitems, 1ull, P.item_cap);
-            if (it != ~0ull) P.items[it] = item_pack(lo, 0, 0, (uint32_t)n);
-            else atomicOr(&P.ctl->overflow, OVF_ITEM);
-            continue;
+    const uint64_t rounds = (m + 255) / 256;
+    for (uint64_t rb = blockIdx.x; rb < rounds; rb += gridDim.x) {
+        const uint64_t s = rb * 256 + threadIdx.x;
+        uint64_t lo = 0, n = 0;
+        if (s < m) {
+            lo = offsets ? offsets[s] : 0;
+            n = offsets ? offsets[s + 1] - lo : n_single;
         }
-        uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
-        uint64_t si = reserve32(&P.ctl->nseg[0], 1u, P.seg_cap);
-        if (si == ~0ull) { atomicOr(&P.ctl->overflow, OVF_SEG); continue; }
-        uint64_t t0 = reserve32(&P.ctl->ntile[0], nt, P.tile_cap);
-        Seg sg{};
-        sg.off = lo; sg.n = n; sg.kind = K_FRESH; sg.tile0 = (uint32_t)t0; sg.ntiles = nt;
-        sg.flags = prebuilt ? SEG_PREBUILT : 0;
-        if (t0 == ~0ull) { atomicOr(&P.ctl->overflow, OVF_TILE); sg.flags |= SEG_FAILED; sg.ntiles = 0; }
-        if (prebuilt) {  // the large path wrote the model and its kind into segs[1][0]
-            Seg pb = P.segs[1][0];
-            sg.kind = pb.kind; sg.nb = pb.nb; sg.model = pb.model; sg.flags |= pb.flags & 0xffff0000u;
+        // prebuilt: the caller supplied the first level's model; always partition
+        const bool item = s < m && !prebuilt && n >= 2 && n <= P.cutoff;
+        const bool seg = s < m && (prebuilt ? n >= 1 : n > P.cutoff);
+        const uint32_t nt = seg ? (uint32_t)((n + TILE - 1) / TILE) : 0;
+        uint64_t itot, stot, ttot;
+        const uint64_t iex = block_excl_scan<256, uint64_t>(item ? 1 : 0, red64, &itot);
+        const uint64_t sex = block_excl_scan<256, uint64_t>(seg ? 1 : 0, red64, &stot);
+        const uint64_t tex = block_excl_scan<256, uint64_t>(nt, red64, &ttot);
+        if (threadIdx.x == 0) {
+            base[0] = itot ? atomicAdd(&P.ctl->nitems, (unsigned long long)itot) : 0;
+            base[1] = stot ? atomicAdd(&P.ctl->nseg[0], (uint32_t)stot) : 0;
+            base[2] = ttot ? atomicAdd(&P.ctl->ntile[0], (uint32_t)ttot) : 0;
         }
-        P.segs[0][si] = sg;
-        if (!(sg.flags & SEG_FAILED))
-            for (uint32_t i = 0; i < nt; i++) P.tiles[0][t0 + i] = Tile{(uint32_t)si, i};
+        __syncthreads();
+        if (item) {
+            uint64_t it = base[0] + iex;
+            if (it < P.item_cap) {
+                P.items[it] = item_pack(lo, 0, 0, (uint32_t)n);
+                atomicAdd(&P.ctl->base_keys, (unsigned long long)n);
+            } else {
+                atomicOr(&P.ctl->overflow, OVF_ITEM);
+            }
+        }
+        if (seg) {
+            uint64_t si = base[1] + sex, t0 = base[2] + tex;
+            if (si >= P.seg_cap) {
+                atomicOr(&P.ctl->overflow, OVF_SEG);
+            } else {
+                Seg sg{};
+                sg.off = lo; sg.n = n; sg.kind = K_FRESH; sg.tile0 = (uint32_t)t0; sg.ntiles = nt;
+                sg.flags = prebuilt ? SEG_PREBUILT : 0;
+                if (t0 + nt > P.tile_cap) { atomicOr(&P.ctl->overflow, OVF_TILE); sg.flags |= SEG_FAILED; }
+                if (prebuilt) {  // the first level's model and kind were written into segs[1][0]
+                    Seg pb = P.segs[1][0];
+                    sg.kind = pb.kind; sg.nb = pb.nb; sg.model = pb.model; sg.flags |= pb.flags & 0xffff0000u;
+                }
+                P.segs[0][si] = sg;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -78,8 +106,8 @@ __device__ uint64_t arena_alloc(Params& P, uint32_t words, uint64_t* sh) {
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t bytes = ((uint64_t)words * 8 + 15) & ~15ull;
-        uint64_t o = reserve64(&P.ctl->arena_used[P.level & 1], (unsigned long long)bytes, P.arena_cap);
-        if (o == ~0ull) {
+        uint64_t o = atomicAdd(&P.ctl->arena_used[P.level & 1], (unsigned long long)bytes);
+        if (o + bytes > P.arena_cap) {
             atomicOr(&P.ctl->overflow, OVF_ARENA);
             sh[0] = 0;
         } else {
@@ -187,7 +215,7 @@ __device__ void fit_rmi_block(const uint64_t* smp, uint32_t S, int u64, uint32_t
         RmiModel* h = (RmiModel*)dst;
         h->L = L; h->B1 = B1; h->log2B2 = log2B2; h->pad = 0;
         h->R = (double)((uint64_t)B1 << log2B2);
-        h->pad2 = 0; h->pad3 = 0;
+        h->pad2 = 0;
         dst[4] = alpha_r; dst[5] = beta_r;
     }
 }
@@ -289,10 +317,12 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             uint32_t fl = (sg.flags & 0xffffu) | (words << 16);
             uint64_t cb = 0, sb = 0;
             if (!(fl & SEG_FAILED)) {
-                cb = reserve64(&P.ctl->counts_used, 2ull * nb, P.counts_cap);
-                sb = reserve64(&P.ctl->status_used, (unsigned long long)sg.ntiles * nb, P.status_cap);
-                if (cb == ~0ull) { atomicOr(&P.ctl->overflow, OVF_COUNTS); fl |= SEG_FAILED; cb = 0; }
-                if (sb == ~0ull) { atomicOr(&P.ctl->overflow, OVF_STATUS); fl |= SEG_FAILED; sb = 0; }
+                cb = atomicAdd(&P.ctl->counts_used, 2ull * nb);
+                sb = atomicAdd(&P.ctl->status_used, (unsigned long long)sg.ntiles * nb);
+                if (cb + 2ull * nb > P.counts_cap) { atomicOr(&P.ctl->overflow, OVF_COUNTS); fl |= SEG_FAILED; cb = 0; }
+                if (sb + (uint64_t)sg.ntiles * nb > P.status_cap) {
+                    atomicOr(&P.ctl->overflow, OVF_STATUS); fl |= SEG_FAILED; sb = 0;
+                }
             }
             if (!model) fl |= SEG_FAILED;
             shv[0] = cb; shv[1] = sb; shv[2] = fl;
@@ -306,6 +336,9 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
         __syncthreads();
         if (!(shv[2] & SEG_FAILED))
             for (uint32_t b = tid; b < nb; b += M_THREADS) P.counts[shv[0] + b] = 0;
+        // this segment's tile descriptors (every reserved slot below capacity)
+        for (uint32_t i = tid; i < sg.ntiles; i += M_THREADS)
+            if ((uint64_t)sg.tile0 + i < P.tile_cap) P.tiles[lvl & 1][sg.tile0 + i] = Tile{s, i};
         __syncthreads();
     }
 }
@@ -329,8 +362,10 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
     Seg sg{};
     View v{};
     bool skip = false;
+    const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
     for (uint32_t t = t0; t < t1; t++) {
         Tile td = P.tiles[lvl & 1][t];
+        if (td.seg >= nseg) continue;
         if (td.seg != cur) {
             if (cur != 0xffffffffu && !skip) {
                 __syncthreads();
@@ -389,22 +424,10 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
 
 constexpr int S_THREADS = 1024;
 
-__device__ __forceinline__ void emit_items(Params& P, uint64_t off, uint64_t n, uint32_t src, uint32_t copy) {
-    uint64_t chunk = copy ? COPY_CHUNK : (uint64_t)C_MAX;
-    uint64_t cnt = (n + chunk - 1) / chunk;
-    uint64_t it = reserve64(&P.ctl->nitems, (unsigned long long)cnt, P.item_cap);
-    if (it == ~0ull) { atomicOr(&P.ctl->overflow, OVF_ITEM); return; }
-    if (copy) atomicAdd(&P.ctl->ncopy, (unsigned long long)cnt);
-    for (uint64_t c = 0; c < cnt; c++) {
-        uint64_t o = off + c * chunk;
-        uint64_t sz = min<uint64_t>(chunk, n - c * chunk);
-        P.items[it + c] = item_pack(o, src, copy, (uint32_t)sz);
-    }
-}
-
 __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
     __shared__ uint64_t red64[S_THREADS / 64];
     __shared__ uint8_t eqb[B_MAX];
+    __shared__ uint64_t resv[3];
     const int tid = threadIdx.x;
     const int lvl = P.level;
     if (blockIdx.x == 0 && tid == 0) {  // pools of the next level (this level's data stays readable)
@@ -449,76 +472,94 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         }
         __syncthreads();
         const double expected = (double)sg.n / (double)nb;
-        uint64_t is_empty = 0, is_eq = 0, is_base = 0, is_rec = 0, is_fb = 0;
+        // action of this bucket: 0 nothing, 1 copy items, 2 base item, 3..6 child of kind
+        // K_RADIX / fine / K_TREE_FORCED / K_FRESH
+        uint32_t act = 0;
+        uint64_t stat = 0;  // 12-bit fields: empty, equality, base, recurse
         if ((uint32_t)tid < nb && c > 0) {
-            bool homog = eqb[tid] || c == 1;
-            if (homog) {
-                is_eq = 1;
-                if (q == 1) emit_items(P, start, c, 1, 1);
+            if (eqb[tid] || c == 1) {
+                stat = 1ull << 12;
+                act = q == 1 ? 1 : 0;  // finished; only a run left in the temporary moves
             } else if (c <= P.cutoff || ((uint32_t)lvl + 1 >= P.max_levels && c <= (uint64_t)C_MAX)) {
                 // at the depth cap every bucket the base case can hold goes there,
                 // so range-radix levels only ever see more than C_MAX keys (8 bits each)
-                is_base = 1;
-                emit_items(P, start, c, q, 0);
+                stat = 1ull << 24;
+                act = 2;
             } else {
-                is_rec = 1;
-                bool oversized = (double)c > P.fallback_ratio * expected;
-                Seg ch{};
-                ch.off = start; ch.n = c;
-                ch.ntiles = (uint32_t)((c + TILE - 1) / TILE);
-                uint32_t B2 = 1u << log2B2;
-                if ((uint32_t)lvl + 1 >= P.max_levels) {
-                    ch.kind = K_RADIX;
-                } else if (fine_ok && !oversized && (uint64_t)B2 * 4 <= c) {
-                    ch.kind = sg.kind == K_RMI ? K_RMI_FINE : K_MLP_FINE;
-                    ch.model = sg.model;
-                    ch.nb = B2;
-                    ch.win = (uint32_t)tid << log2B2;
-                    ch.flags = sg.flags & 0xffff0000u;  // model words
-                } else if (oversized && !(P.flags & 0x1u)) {
-                    ch.kind = K_TREE_FORCED;
-                    is_fb = 1;
-                } else {
-                    ch.kind = K_FRESH;
-                }
-                uint64_t si = reserve32(&P.ctl->nseg[lvl + 1], 1u, P.seg_cap);
-                if (si == ~0ull) {
-                    atomicOr(&P.ctl->overflow, OVF_SEG);
-                } else {
-                    uint64_t t0 = reserve32(&P.ctl->ntile[lvl + 1], ch.ntiles, P.tile_cap);
-                    if (t0 == ~0ull) {
-                        atomicOr(&P.ctl->overflow, OVF_TILE);
-                        ch.flags |= SEG_FAILED;
-                        ch.ntiles = 0;
-                        P.segs[q][si] = ch;
-                    } else {
-                        ch.tile0 = (uint32_t)t0;
-                        P.segs[q][si] = ch;
-                        for (uint32_t i = 0; i < ch.ntiles; i++) P.tiles[q][t0 + i] = Tile{(uint32_t)si, i};
-                    }
-                }
+                const bool oversized = (double)c > P.fallback_ratio * expected;
+                stat = 1ull << 36;
+                if ((uint32_t)lvl + 1 >= P.max_levels) act = 3;
+                else if (fine_ok && !oversized && (4ull << log2B2) <= c) act = 4;
+                else if (oversized && !(P.flags & 0x1u)) act = 5;
+                else act = 6;
             }
         } else if ((uint32_t)tid < nb) {
-            is_empty = 1;
+            stat = 1ull;
+        }
+        const uint64_t nitem = act == 1 ? (c + COPY_CHUNK - 1) / COPY_CHUNK : (act == 2 ? 1 : 0);
+        const uint32_t ntl = act >= 3 ? (uint32_t)((c + TILE - 1) / TILE) : 0;
+        // one reservation per list for the whole workgroup
+        uint64_t itot, ctot, ttot;
+        const uint64_t iex = block_excl_scan<S_THREADS, uint64_t>(nitem, red64, &itot);
+        const uint64_t cex = block_excl_scan<S_THREADS, uint64_t>(act >= 3 ? 1 : 0, red64, &ctot);
+        const uint64_t tex = block_excl_scan<S_THREADS, uint64_t>(ntl, red64, &ttot);
+        const uint64_t ck = block_sum<S_THREADS, uint64_t>(act == 1 ? c : 0, red64);
+        const uint64_t bk = block_sum<S_THREADS, uint64_t>(act == 2 ? c : 0, red64);
+        const uint64_t nfb = block_sum<S_THREADS, uint64_t>(act == 5 ? 1 : 0, red64);
+        const uint64_t ncp = block_sum<S_THREADS, uint64_t>(act == 1 ? nitem : 0, red64);
+        if (tid == 0) {
+            resv[0] = itot ? atomicAdd(&P.ctl->nitems, (unsigned long long)itot) : 0;
+            resv[1] = ctot ? atomicAdd(&P.ctl->nseg[lvl + 1], (uint32_t)ctot) : 0;
+            resv[2] = ttot ? atomicAdd(&P.ctl->ntile[lvl + 1], (uint32_t)ttot) : 0;
+            if (ck) {
+                atomicAdd(&P.ctl->copy_keys, (unsigned long long)ck);
+                atomicAdd(&P.ctl->ncopy, (unsigned long long)ncp);
+            }
+            if (bk) atomicAdd(&P.ctl->base_keys, (unsigned long long)bk);
+        }
+        __syncthreads();
+        for (uint64_t k = 0; k < nitem; k++) {
+            const uint64_t it = resv[0] + iex + k;
+            if (it >= P.item_cap) { atomicOr(&P.ctl->overflow, OVF_ITEM); break; }
+            const uint64_t sz = act == 1 ? min<uint64_t>(COPY_CHUNK, c - k * COPY_CHUNK) : c;
+            P.items[it] = item_pack(start + k * COPY_CHUNK, act == 1 ? 1u : q, act == 1 ? 1u : 0u, (uint32_t)sz);
+        }
+        if (act >= 3) {
+            const uint64_t si = resv[1] + cex, t0 = resv[2] + tex;
+            if (si < P.seg_cap) {
+                Seg ch{};
+                ch.off = start; ch.n = c; ch.ntiles = ntl; ch.tile0 = (uint32_t)t0;
+                ch.kind = act == 3 ? K_RADIX : act == 4 ? (sg.kind == K_RMI ? K_RMI_FINE : K_MLP_FINE)
+                        : act == 5 ? K_TREE_FORCED : K_FRESH;
+                if (act == 4) {
+                    ch.model = sg.model;
+                    ch.nb = 1u << log2B2;
+                    ch.win = (uint32_t)tid << log2B2;
+                    ch.flags = sg.flags & 0xffff0000u;  // model words
+                }
+                if (t0 + ntl > P.tile_cap) { atomicOr(&P.ctl->overflow, OVF_TILE); ch.flags |= SEG_FAILED; }
+                P.segs[q][si] = ch;  // k_model of the next level writes its tile descriptors
+            } else {
+                atomicOr(&P.ctl->overflow, OVF_SEG);
+                for (uint32_t i = 0; i < ntl; i++)  // keep the tile list free of stale slots
+                    if (t0 + i < P.tile_cap) P.tiles[q][t0 + i] = Tile{0xffffffffu, 0};
+            }
         }
         // statistics
+        const uint64_t sc = block_sum<S_THREADS, uint64_t>(stat, red64);
         uint64_t mx = block_max<S_THREADS, uint64_t>(c, red64);
-        uint64_t ne = block_sum<S_THREADS, uint64_t>(is_empty, red64);
-        uint64_t nq = block_sum<S_THREADS, uint64_t>(is_eq, red64);
-        uint64_t nbs = block_sum<S_THREADS, uint64_t>(is_base, red64);
-        uint64_t nr = block_sum<S_THREADS, uint64_t>(is_rec, red64);
-        uint64_t nf = block_sum<S_THREADS, uint64_t>(is_fb, red64);
         if (tid == 0) {
+            const uint64_t m12 = 4095;
             atomicAdd(&st.segments, 1ull);
             atomicAdd(&st.keys, (unsigned long long)sg.n);
             atomicAdd(&st.buckets, (unsigned long long)nb);
             atomicMax(&st.max_bucket, (unsigned long long)mx);
             atomicMax(&st.max_ratio_x1000, (unsigned long long)(1000.0 * (double)mx / expected));
-            atomicAdd(&st.empty, (unsigned long long)ne);
-            atomicAdd(&st.equality, (unsigned long long)nq);
-            atomicAdd(&st.base, (unsigned long long)nbs);
-            atomicAdd(&st.recurse, (unsigned long long)nr);
-            atomicAdd(&st.fallback, (unsigned long long)nf);
+            atomicAdd(&st.empty, (unsigned long long)(sc & m12));
+            atomicAdd(&st.equality, (unsigned long long)((sc >> 12) & m12));
+            atomicAdd(&st.base, (unsigned long long)((sc >> 24) & m12));
+            atomicAdd(&st.recurse, (unsigned long long)((sc >> 36) & m12));
+            atomicAdd(&st.fallback, (unsigned long long)nfb);
         }
         __syncthreads();
     }
@@ -549,6 +590,7 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lvl = P.level;
     const uint32_t ntile = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
+    const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
     const uint64_t tag = ((uint64_t)(P.persist[0] * MAXL + lvl)) << ST_TAG_SHIFT;
     const uint64_t* src = P.keys[lvl & 1];
     uint64_t* dst = P.keys[(lvl + 1) & 1];
@@ -562,6 +604,7 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
         const uint32_t t = sh_t;
         if (t >= ntile) break;
         const Tile td = P.tiles[lvl & 1][t];
+        if (td.seg >= nseg) { __syncthreads(); continue; }
         const Seg sg = P.segs[lvl & 1][td.seg];
         if (sg.flags & SEG_FAILED) { __syncthreads(); continue; }
         if (sg.model != cur_model) {

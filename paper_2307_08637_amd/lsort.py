@@ -42,6 +42,10 @@ class Stats(C.Structure):
                 ("level", LevelStats * MAX_STAT_LEVELS)]
 
 
+class KernelTiming(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint64), ("ms", C.c_double), ("keys", C.c_double)]
+
+
 class LsortError(RuntimeError):
     pass
 
@@ -72,6 +76,8 @@ def lib():
             "ls_mlp_loss_grad": [vp, vp, vp, u64, vp, vp, vp],
             "ls_mlp_train": [vp, u64, i32, vp, u32, C.c_float, u64, vp, vp, vp, vp],
             "ls_mlp_buckets": [vp, u64, i32, vp, vp, u32, vp, vp],
+            "ls_timing": [i32],
+            "ls_timing_read": [vp, u32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -251,6 +257,20 @@ def partition_splitters(keys, u, eq, payload=None):
     _check(lib().ls_partition_splitters(_ptr(keys), _ptr(payload), keys.numel(), _dtype(keys), _ptr(u), _ptr(eq),
                                         u.numel(), _ptr(ok), _ptr(op), _ptr(counts), _stream()))
     return ok, op, counts
+
+
+def timing(enable: bool) -> None:
+    """Start (clearing earlier records) or stop per-kernel event timing."""
+    _check(lib().ls_timing(int(enable)))
+
+
+def timing_read() -> dict:
+    """{kernel name: {"launches", "ms", "keys"}} summed over the recorded calls."""
+    buf = (KernelTiming * 32)()
+    cnt = C.c_uint32()
+    _check(lib().ls_timing_read(buf, 32, C.byref(cnt)))
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "keys": buf[i].keys}
+            for i in range(cnt.value)}
 
 
 def version() -> str:

@@ -109,9 +109,10 @@ def test_no_fallback_and_small_buckets(dev):
 
 
 def test_depth_cap_radix(dev):
-    # a one-level cap forces range-radix partitions after the first level
+    # a one-level cap with a 4-way tree leaves buckets of ~1e5 keys, which the
+    # range radix (8 bits per level) must finish
     keys = inputs.generate("twodups", 400_000, seed=43)
-    got, _ = gpu_sort(keys, dev, max_levels=1, cutoff=64)
+    got, _ = gpu_sort(keys, dev, max_levels=1, cutoff=64, model="splitter", tree_buckets=4)
     assert_same_bits(got, oracle.sort(keys)[0])
     st = lsort.stats()
     assert any(lv["radix"] > 0 for lv in st["levels"])
