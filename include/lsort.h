@@ -72,7 +72,9 @@ typedef struct {
     uint32_t buckets;        /* B of a learned level; default 1000 (Sec. 2.1/2.2); 2..1024 */
     uint32_t leaves;         /* RMI leaves L; default 1000 (Sec. 2.1); 2..1024 */
     uint32_t tree_buckets;   /* splitter-tree fan-out; default 256 (Sec. 4); power of two 2..512 */
-    uint32_t cutoff;         /* base case below this many keys; default 4096 (Sec. 4); 1..4096 */
+    uint32_t cutoff;         /* base case at or below this many keys; default 512 (one wavefront sorts
+                                up to 512 keys in registers; the paper's CPU base case takes 4096, Sec. 4);
+                                1..4096 */
     uint32_t max_levels;     /* model-based levels before range radix (8 bits per level) takes over; default 16; 1..23 */
     uint32_t flags;          /* LS_FLAG_* */
     double sample_frac;      /* sample size as a fraction of n; default 0.01 (Sec. 2.2) */

@@ -51,7 +51,7 @@ struct Opts {
 };
 
 static ls_status normalize(const ls_options* o, Opts& r) {
-    r.model = LS_MODEL_AUTO; r.buckets = 1000; r.leaves = 1000; r.tree_buckets = 256; r.cutoff = 4096;
+    r.model = LS_MODEL_AUTO; r.buckets = 1000; r.leaves = 1000; r.tree_buckets = 256; r.cutoff = 512;
     r.max_levels = 16; r.flags = LS_FLAG_SYNC_LEVELS; r.sample_frac = 0.01; r.fallback_ratio = 2.0; r.seed = 0x5EED;
     r.mlp_steps = 200; r.mlp_sample = 1000000; r.mlp_lr = 1e-2f;
     if (!o) return LS_OK;
@@ -88,8 +88,8 @@ static inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 struct Layout {
     uint64_t n, m;
     int has_pay;
-    uint64_t seg_cap, tile_cap, item_cap, counts_cap, status_cap, arena_cap;
-    uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_counts, o_status,
+    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap;
+    uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_bigs, o_counts, o_status,
         o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested;
     uint64_t S_big;       // large-path sample size (0: none)
     uint64_t bytes;
@@ -107,13 +107,14 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.n = n; L.m = m; L.has_pay = has_pay;
     const uint64_t C = o.cutoff;
     L.seg_cap = std::max<uint64_t>(m, n / (C + 1)) + 16;
-    L.tile_cap = n / TILE + L.seg_cap + 16;
-    L.item_cap = n + m + 64;
+    L.tile_cap = n / UNIT + L.seg_cap + 16;
+    L.item_cap = n + m + 64;        // small items hold >= 1 key
+    L.big_cap = n / 2 + m + 64;     // large items > 512 keys, copy runs >= 2 keys
     // Bucket counts per level: a segment gets at most n_seg / 4 buckets (at
     // least 2), except one first-level segment whose model the caller gives
     // (up to B_MAX).  Look-back words: tiles x buckets of each segment.
     L.counts_cap = 2 * (n / 4 + 2 * L.seg_cap + B_MAX) + 64;
-    L.status_cap = (n / TILE) * B_MAX + n / 4 + 2 * L.seg_cap + 2 * B_MAX + 64;
+    L.status_cap = (n / UNIT) * B_MAX + n / 4 + 2 * L.seg_cap + 2 * B_MAX + 64;
     L.arena_cap = (n / 100000 + m + 2) * (8ull * MODEL_WORDS + 16) + (uint64_t)(0.7 * (double)n) + L.seg_cap * 32 + 65536;
     uint64_t o_ = 0;
     auto take = [&](uint64_t bytes) { uint64_t r = o_; o_ += align256(bytes); return r; };
@@ -127,13 +128,14 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.o_tiles[0] = take(L.tile_cap * sizeof(Tile));
     L.o_tiles[1] = take(L.tile_cap * sizeof(Tile));
     L.o_items = take(L.item_cap * 8);
+    L.o_bigs = take(L.big_cap * 8);
     L.o_counts = take(L.counts_cap * 8);
     L.o_status = take(L.status_cap * 8);
     L.o_arena[0] = take(L.arena_cap);
     L.o_arena[1] = take(L.arena_cap);
     L.o_bigmodel = take(8ull * MODEL_WORDS + 64);
     L.o_part = take(FIT_G * 8 * 8);
-    L.o_leaf = take(L_MAX * 8 * 8);
+    L.o_leaf = take(L_MAX * 8 * 8 + (L_MAX + 1) * 8);  // leaf lines, then leaf boundaries
     L.o_flag = take(256);
     L.S_big = big_sample_size(n, m, o);
     if (L.S_big) {
@@ -173,9 +175,9 @@ static thread_local LastCall g_last;
 // ---------------------------------------------------------------------------
 // optional kernel timing: an event pair around each launch
 // ---------------------------------------------------------------------------
-enum KernelId { KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_GATHER, KI_FIT, KI_N };
-static const char* KNAME[KI_N] = {"k_reset", "k_seed", "k_model", "k_hist", "k_scan", "k_scatter", "k_base",
-                                  "k_gather", "k_fit"};
+enum KernelId { KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_BASE_BIG, KI_GATHER, KI_FIT, KI_N };
+static const char* KNAME[KI_N] = {"k_reset", "k_seed", "k_model", "k_hist", "k_scan", "k_scatter", "k_base_small",
+                                  "k_base_big", "k_gather", "k_fit"};
 struct TRec {
     int kid;
     hipEvent_t a, b;
@@ -312,10 +314,11 @@ static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
         P.arena[i] = base + L.o_arena[i];
     }
     P.items = (uint64_t*)(base + L.o_items);
+    P.bigs = (uint64_t*)(base + L.o_bigs);
     P.counts = (unsigned long long*)(base + L.o_counts);
     P.status = (unsigned long long*)(base + L.o_status);
     P.ids = nullptr;
-    P.seg_cap = L.seg_cap; P.tile_cap = L.tile_cap; P.item_cap = L.item_cap; P.counts_cap = L.counts_cap;
+    P.seg_cap = L.seg_cap; P.tile_cap = L.tile_cap; P.item_cap = L.item_cap; P.big_cap = L.big_cap; P.counts_cap = L.counts_cap;
     P.status_cap = L.status_cap; P.arena_cap = L.arena_cap;
     P.persist = (const uint64_t*)(base + L.o_persist);
     P.level = 0;
@@ -330,6 +333,7 @@ static std::string overflow_text(uint32_t f) {
     if (f & OVF_COUNTS) s += " bucket counts";
     if (f & OVF_STATUS) s += " look-back words";
     if (f & OVF_ARENA) s += " model arena";
+    if (f & OVF_STATE) s += " (internal: look-back word out of sequence)";
     return s;
 }
 
@@ -441,11 +445,13 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     }
     (void)levels;
     if (!c.one_level) {
-        TIMED(KI_BASE, c.st, launch_base(P, cus * 2, c.st));
-        if (g_timing) {
-            HIP_TRY(hipMemcpyAsync(pool->pinned, &P.ctl->base_keys, 16, hipMemcpyDeviceToHost, c.st));
+        TIMED(KI_BASE, c.st, launch_base_small(P, cus * 8, c.st));
+        TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
+        if (g_timing) {  // keys through the base case (both kernels) and the copies
+            HIP_TRY(hipMemcpyAsync(pool->pinned, &P.ctl->small_keys, 16, hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));
-            g_trec.back().keys = (double)(pool->pinned[0] + pool->pinned[1]);
+            g_trec[g_trec.size() - 2].keys = (double)pool->pinned[0];
+            g_trec.back().keys = (double)pool->pinned[1];
         }
     }
     return LS_OK;
@@ -586,7 +592,7 @@ ls_status ls_get_stats(ls_stats* out) {
     }
     out->levels = levels;
     out->first_model = c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
-    out->base_items = c.nitems - c.ncopy;
+    out->base_items = c.nitems + c.nbig - c.ncopy;
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
     out->mlp_loss_last = c.mlp_loss[1];

@@ -285,7 +285,7 @@ __device__ void bitonic_keys(uint64_t* a, uint32_t P) {
     for (uint32_t k = 2; k <= P; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
             for (uint32_t q = threadIdx.x; q < P / 2; q += NT) {
-                uint32_t i = 2 * j * (q / j) + (q % j);
+                uint32_t i = ((q & ~(j - 1)) << 1) | (q & (j - 1));  // j is a power of two
                 uint32_t l = i + j;
                 bool up = (i & k) == 0;
                 uint64_t x = a[i], y = a[l];
@@ -302,7 +302,7 @@ __device__ void bitonic_pairs(uint64_t* a, uint16_t* ix, uint32_t P) {
     for (uint32_t k = 2; k <= P; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
             for (uint32_t q = threadIdx.x; q < P / 2; q += NT) {
-                uint32_t i = 2 * j * (q / j) + (q % j);
+                uint32_t i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
                 uint32_t l = i + j;
                 bool up = (i & k) == 0;
                 uint64_t x = a[i], y = a[l];
@@ -311,6 +311,50 @@ __device__ void bitonic_pairs(uint64_t* a, uint16_t* ix, uint32_t P) {
                 if (gt == up) { a[i] = y; a[l] = x; ix[i] = yi; ix[l] = xi; }
             }
             __syncthreads();
+        }
+    }
+}
+
+// Bitonic sort of 64*E (key, index) pairs held by one wavefront, lane l
+// holding elements l*E .. l*E+E-1 in registers.  Compare-exchanges between
+// elements of one lane stay in registers; those between lanes exchange
+// through cross-lane shuffles.  No LDS, no barriers.  Pairs are ordered by
+// key, then index (indices are distinct), so the result is the stable order.
+template <int E, bool PAIRS>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E], int lane) {
+    constexpr int N = 64 * E;
+#pragma unroll
+    for (int kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j < E) {
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    if ((e & j) == 0) {
+                        const int f = e | j;
+                        const bool up = ((lane * E + e) & kk) == 0;
+                        const bool gt = k[e] > k[f] || (PAIRS && k[e] == k[f] && ix[e] > ix[f]);
+                        if (gt == up) {
+                            uint64_t t = k[e]; k[e] = k[f]; k[f] = t;
+                            if (PAIRS) { uint32_t u = ix[e]; ix[e] = ix[f]; ix[f] = u; }
+                        }
+                    }
+                }
+            } else {
+                const int s = j / E;
+                const bool keep_min = (((lane * E) & kk) == 0) == ((lane & s) == 0);
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const uint64_t y = __shfl_xor(k[e], s);
+                    const uint32_t iy = PAIRS ? __shfl_xor(ix[e], s) : 0u;
+                    const bool lt = y < k[e] || (PAIRS && y == k[e] && iy < ix[e]);
+                    const bool gt = y > k[e] || (PAIRS && y == k[e] && iy > ix[e]);
+                    if (keep_min ? lt : gt) {
+                        k[e] = y;
+                        if (PAIRS) ix[e] = iy;
+                    }
+                }
+            }
         }
     }
 }

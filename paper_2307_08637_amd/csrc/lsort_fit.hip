@@ -46,8 +46,10 @@ __global__ __launch_bounds__(FIT_T) void k_fit1(FitArgs A) {
 
 __global__ __launch_bounds__(FIT_T) void k_fit2(FitArgs A) {
     __shared__ double red[FIT_T / 64];
+    // total of the first pass, combined in the same order by every workgroup
     double sxt = 0;
-    for (uint32_t g = 0; g < gridDim.x; g++) sxt += A.part[g * 8 + 0];  // same order in every workgroup
+    for (uint32_t g = threadIdx.x; g < gridDim.x; g += FIT_T) sxt += A.part[g * 8 + 0];
+    sxt = block_sum<FIT_T, double>(sxt, red);
     const double Sd = (double)A.S;
     const double mx = sxt / Sd, my = (Sd - 1.0) / (2.0 * Sd);
     const uint64_t chunk = (A.S + gridDim.x - 1) / gridDim.x;
@@ -73,14 +75,20 @@ __global__ __launch_bounds__(FIT_T) void k_fit2(FitArgs A) {
 __global__ __launch_bounds__(M_THREADS) void k_fit_root(FitArgs A) {
     __shared__ uint32_t scratch[B_MAX + 1];
     __shared__ uint64_t red64[M_THREADS / 64];
+    __shared__ double redd[M_THREADS / 64];
     double sx = 0, dup = 0, nf = 0, sxx = 0, sxy = 0;
-    for (uint32_t g = 0; g < A.G; g++) {
+    for (uint32_t g = threadIdx.x; g < A.G; g += M_THREADS) {
         sx += A.part[g * 8 + 0];
         dup += A.part[g * 8 + 1];
         nf += A.part[g * 8 + 2];
         sxx += A.part[g * 8 + 3];
         sxy += A.part[g * 8 + 4];
     }
+    sx = block_sum<M_THREADS, double>(sx, redd);
+    dup = block_sum<M_THREADS, double>(dup, redd);
+    nf = block_sum<M_THREADS, double>(nf, redd);
+    sxx = block_sum<M_THREADS, double>(sxx, redd);
+    sxy = block_sum<M_THREADS, double>(sxy, redd);
     const double Sd = (double)A.S;
     double x0, x1;
     int nf0 = key_x(A.s[0], A.u64, x0), nf1 = key_x(A.s[A.S - 1], A.u64, x1);
@@ -133,39 +141,46 @@ __device__ __forceinline__ uint32_t root_leaf(double ar, double br, double Lm1, 
     return (uint32_t)fmin(fmax(floor(__builtin_fma(ar, x, br)), 0.0), Lm1);
 }
 
-__global__ __launch_bounds__(256) void k_fit_leaves(FitArgs A) {
+// Leaf boundaries: the root's leaf index is non-decreasing along the sorted
+// sample, so leaf j covers [bounds[j], bounds[j+1]).  Each sample point
+// writes the starts of the leaves that begin at it.
+__global__ __launch_bounds__(FIT_T) void k_fit_bounds(FitArgs A) {
     if (A.flag[0] == 0) return;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t j = blockIdx.x * 4 + w;
-    if (j >= A.L) return;
     const double ar = ((const double*)A.model)[4], br = ((const double*)A.model)[5];
     const double Lm1 = (double)A.L - 1.0;
-    auto lower = [&](uint32_t leaf) {  // first i with root_leaf(s[i]) >= leaf
-        uint64_t lo = 0, hi = A.S;
-        while (lo < hi) {
-            uint64_t mid = lo + (hi - lo) / 2;
-            if (root_leaf(ar, br, Lm1, A.s[mid], A.u64) < leaf) lo = mid + 1;
-            else hi = mid;
-        }
-        return lo;
-    };
-    const uint64_t lo = lower(j), hi = j + 1 < A.L ? lower(j + 1) : A.S;
+    uint64_t* bounds = (uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
+    for (uint64_t i = (uint64_t)blockIdx.x * FIT_T + threadIdx.x; i < A.S; i += (uint64_t)gridDim.x * FIT_T) {
+        const uint32_t j = root_leaf(ar, br, Lm1, A.s[i], A.u64);
+        const int64_t jp = i > 0 ? (int64_t)root_leaf(ar, br, Lm1, A.s[i - 1], A.u64) : -1;
+        for (int64_t q = jp + 1; q <= (int64_t)j; q++) bounds[q] = i;
+        if (i == A.S - 1)
+            for (uint32_t q = j + 1; q <= A.L; q++) bounds[q] = A.S;
+    }
+}
+
+__global__ __launch_bounds__(FIT_T) void k_fit_leaves(FitArgs A) {
+    __shared__ double red[FIT_T / 64];
+    if (A.flag[0] == 0) return;
+    const uint32_t j = blockIdx.x;
+    const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
+    const uint64_t range[2] = {bounds[j], bounds[j + 1]};
+    const uint64_t lo = range[0], hi = range[1];
     const double Sd = (double)A.S;
     double a = 0, b = 0, pmin = 0, pmax = 0;
     if (hi > lo) {
         const double cnt = (double)(hi - lo);
         double s = 0;
-        for (uint64_t i = lo + lane; i < hi; i += 64) { double x; key_x(A.s[i], A.u64, x); s += x; }
-        s = wave_sum(s);
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_T) { double x; key_x(A.s[i], A.u64, x); s += x; }
+        s = block_sum<FIT_T, double>(s, red);
         const double mx = s / cnt, my = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
         double sxx = 0, sxy = 0;
-        for (uint64_t i = lo + lane; i < hi; i += 64) {
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_T) {
             double x; key_x(A.s[i], A.u64, x);
             double dx = x - mx, dy = (double)i / Sd - my;
             sxx += dx * dx; sxy += dx * dy;
         }
-        sxx = wave_sum(sxx);
-        sxy = wave_sum(sxy);
+        sxx = block_sum<FIT_T, double>(sxx, red);
+        sxy = block_sum<FIT_T, double>(sxy, red);
         a = sxx > 0 ? sxy / sxx : 0.0;
         if (a < 0) a = 0;
         b = my - a * mx;
@@ -175,7 +190,7 @@ __global__ __launch_bounds__(256) void k_fit_leaves(FitArgs A) {
         pmin = a * x0 + b;
         pmax = a * x1 + b;
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         double* q = A.leaf + (uint64_t)j * 8;
         q[0] = a; q[1] = b; q[2] = pmin; q[3] = pmax; q[4] = hi > lo ? 1.0 : 0.0;
     }
@@ -294,7 +309,13 @@ hipError_t launch_gather(const uint64_t* keys, uint64_t n, uint64_t seed, uint64
 hipError_t launch_fit1(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit1, A.G, FIT_T, st, A); }
 hipError_t launch_fit2(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit2, A.G, FIT_T, st, A); }
 hipError_t launch_fit_root(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_root, 1, M_THREADS, st, A); }
-hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_leaves, (A.L + 3) / 4, 256, st, A); }
+hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((A.S + FIT_T - 1) / FIT_T, 2048ull);
+    hipLaunchKernelGGL(k_fit_bounds, dim3(grid ? grid : 1), dim3(FIT_T), 0, st, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    LAUNCH(k_fit_leaves, A.L, FIT_T, st, A);
+}
 hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_finish, 1, M_THREADS, st, A); }
 hipError_t launch_model_buckets(const uint64_t* model, uint32_t words, uint32_t kind, uint32_t nb, uint32_t win,
                                 const uint64_t* keys, uint64_t n, int u64, uint32_t* out, hipStream_t st) {

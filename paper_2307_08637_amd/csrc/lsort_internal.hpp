@@ -12,12 +12,15 @@ constexpr int WAVE = 64;
 constexpr int P_THREADS = 512;                 // threads of a partition workgroup (8 waves)
 constexpr int P_WAVES = P_THREADS / WAVE;
 constexpr int KPT = 16;                        // keys per thread per tile
-constexpr int TILE = P_THREADS * KPT;          // 8192 keys per tile
+constexpr int TILE = P_THREADS * KPT;          // 8192 keys: one pass of a partition workgroup
+constexpr int UNIT_TILES = 4;
+constexpr int UNIT = TILE * UNIT_TILES;        // 32768 keys: work unit of k_hist / k_scatter
 constexpr int WAVE_KEYS = WAVE * KPT;          // 1024 keys per wave per tile
 constexpr int B_MAX = 1024;                    // buckets of one partition
 constexpr int L_MAX = 1024;                    // RMI leaves
 constexpr int S_LDS = 16384;                   // largest sample one workgroup sorts in LDS
 constexpr int C_MAX = 4096;                    // largest base-case sub-array
+constexpr int SMALL_MAX = 512;                 // largest sub-array one wavefront sorts in registers
 constexpr int MAXL = 32;                       // partition levels (arrays)
 constexpr int MODEL_WORDS = 4 + 2 + 4 * L_MAX; // 8-byte words of the largest model (RMI, L_MAX leaves)
 constexpr uint64_t COPY_CHUNK = 65536;         // keys per copy item
@@ -67,21 +70,21 @@ struct Seg {
     uint64_t n;       // keys
     uint64_t model;   // device address of the model
     uint64_t cbase;   // bucket counts at counts[cbase..+nb), bucket starts at counts[cbase+nb..+nb)
-    uint64_t sbase;   // look-back status words at status[sbase + tile * nb + b]
+    uint64_t sbase;   // look-back status words at status[sbase + unit * nb + b]
     uint32_t kind;    // Kind
     uint32_t nb;      // buckets
     uint32_t win;     // fine window base for *_FINE kinds
-    uint32_t tile0;   // first tile in the level's tile list
-    uint32_t ntiles;
+    uint32_t tile0;   // first work unit in the level's unit list
+    uint32_t ntiles;  // work units (UNIT keys each, the last one partial)
     uint32_t flags;   // SEG_* bits; model size in 8-byte words in bits 16..31
 };
 static_assert(sizeof(Seg) == 64, "segment descriptor is 64 bytes");
 constexpr uint32_t SEG_PREBUILT = 1u;  // model already built (large first level)
 constexpr uint32_t SEG_FAILED = 2u;    // capacity exceeded; not partitioned
 
-struct Tile {
+struct Tile {          // one work unit of UNIT keys
     uint32_t seg;     // index in the level's segment list
-    uint32_t idx;     // tile number within the segment
+    uint32_t idx;     // unit number within the segment
 };
 
 // Base-case / copy work item packed in 64 bits:
@@ -102,10 +105,11 @@ struct Ctl {
     uint32_t ntile[MAXL + 1];       // tiles at each level
     uint32_t ticket[MAXL + 1];      // scatter tile tickets
     uint32_t pad0;
-    unsigned long long nitems;      // base-case + copy items
+    unsigned long long nitems;      // small base-case items (<= SMALL_MAX keys)
+    unsigned long long nbig;        // large base-case items and copy items
     unsigned long long ncopy;
-    unsigned long long base_keys;   // keys in base-case items
-    unsigned long long copy_keys;   // keys in copy items
+    unsigned long long small_keys;  // keys in small base-case items
+    unsigned long long big_keys;    // keys in large base-case items and copy runs
     unsigned long long counts_used; // bump allocators (reset per level)
     unsigned long long status_used;
     unsigned long long arena_used[2];
@@ -115,7 +119,8 @@ struct Ctl {
     double mlp_loss[2];
     LevelStats lv[MAXL];
 };
-constexpr uint32_t OVF_SEG = 1, OVF_TILE = 2, OVF_ITEM = 4, OVF_COUNTS = 8, OVF_STATUS = 16, OVF_ARENA = 32;
+constexpr uint32_t OVF_SEG = 1, OVF_TILE = 2, OVF_ITEM = 4, OVF_COUNTS = 8, OVF_STATUS = 16, OVF_ARENA = 32,
+                   OVF_STATE = 64;  // a look-back word without this level's tag (never expected)
 
 // Everything a level's kernels need, passed by value.
 struct Params {
@@ -132,12 +137,13 @@ struct Params {
     Ctl* ctl;
     Seg* segs[2];
     Tile* tiles[2];
-    uint64_t* items;
+    uint64_t* items;                // small base-case items
+    uint64_t* bigs;                 // large base-case items and copy items
     unsigned long long* counts;
     unsigned long long* status;
     uint8_t* arena[2];
     uint16_t* ids;                  // per-key bucket ids of MLP levels (absolute positions)
-    uint64_t seg_cap, tile_cap, item_cap, counts_cap, status_cap, arena_cap;
+    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap;
     const uint64_t* persist;        // [0] call epoch, [1] clear-status request (survives calls)
     int level;
 };

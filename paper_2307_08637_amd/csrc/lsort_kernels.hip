@@ -40,7 +40,7 @@ __global__ void k_reset(Params P, uint64_t* persist) {
 __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets, uint64_t m, uint64_t n_single,
                                               uint32_t prebuilt, const uint64_t* persist) {
     __shared__ uint64_t red64[256 / 64];
-    __shared__ uint64_t base[3];
+    __shared__ uint64_t base[4];
     if (persist[1]) {
         for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.status_cap;
              i += (uint64_t)gridDim.x * blockDim.x)
@@ -56,29 +56,32 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
         }
         // prebuilt: the caller supplied the first level's model; always partition
         const bool item = s < m && !prebuilt && n >= 2 && n <= P.cutoff;
+        const bool small = item && n <= SMALL_MAX;
         const bool seg = s < m && (prebuilt ? n >= 1 : n > P.cutoff);
-        const uint32_t nt = seg ? (uint32_t)((n + TILE - 1) / TILE) : 0;
-        uint64_t itot, stot, ttot;
-        const uint64_t iex = block_excl_scan<256, uint64_t>(item ? 1 : 0, red64, &itot);
+        const uint32_t nt = seg ? (uint32_t)((n + UNIT - 1) / UNIT) : 0;
+        uint64_t itot, btot, stot, ttot;
+        const uint64_t iex = block_excl_scan<256, uint64_t>(small ? 1 : 0, red64, &itot);
+        const uint64_t bex = block_excl_scan<256, uint64_t>(item && !small ? 1 : 0, red64, &btot);
         const uint64_t sex = block_excl_scan<256, uint64_t>(seg ? 1 : 0, red64, &stot);
         const uint64_t tex = block_excl_scan<256, uint64_t>(nt, red64, &ttot);
+        const uint64_t sk = block_sum<256, uint64_t>(small ? n : 0, red64);
+        const uint64_t gk = block_sum<256, uint64_t>(item && !small ? n : 0, red64);
         if (threadIdx.x == 0) {
             base[0] = itot ? atomicAdd(&P.ctl->nitems, (unsigned long long)itot) : 0;
             base[1] = stot ? atomicAdd(&P.ctl->nseg[0], (uint32_t)stot) : 0;
             base[2] = ttot ? atomicAdd(&P.ctl->ntile[0], (uint32_t)ttot) : 0;
+            base[3] = btot ? atomicAdd(&P.ctl->nbig, (unsigned long long)btot) : 0;
+            if (sk) atomicAdd(&P.ctl->small_keys, (unsigned long long)sk);
+            if (gk) atomicAdd(&P.ctl->big_keys, (unsigned long long)gk);
         }
         __syncthreads();
         if (item) {
-            uint64_t it = base[0] + iex;
-            if (it < P.item_cap) {
-                P.items[it] = item_pack(lo, 0, 0, (uint32_t)n);
-                atomicAdd(&P.ctl->base_keys, (unsigned long long)n);
-            } else {
-                atomicOr(&P.ctl->overflow, OVF_ITEM);
-            }
+            const uint64_t it = small ? base[0] + iex : base[3] + bex;
+            if (it < (small ? P.item_cap : P.big_cap)) (small ? P.items : P.bigs)[it] = item_pack(lo, 0, 0, (uint32_t)n);
+            else atomicOr(&P.ctl->overflow, OVF_ITEM);
         }
         if (seg) {
-            uint64_t si = base[1] + sex, t0 = base[2] + tex;
+            const uint64_t si = base[1] + sex, t0 = base[2] + tex;
             if (si >= P.seg_cap) {
                 atomicOr(&P.ctl->overflow, OVF_SEG);
             } else {
@@ -344,77 +347,71 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
 }
 
 // ===========================================================================
-// k_hist: model evaluation fused with an LDS-private bucket histogram
+// k_hist: model evaluation fused with an LDS-private bucket histogram, one
+// work unit (32768 keys) at a time.  Each unit's per-bucket counts are
+// published as the aggregate words of the decoupled look-back and added to
+// the segment's bucket totals.
 // ===========================================================================
+
+__device__ __forceinline__ uint64_t st_load(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_store(unsigned long long* p, uint64_t v) {
+    __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
     __shared__ uint64_t mdl[MODEL_WORDS];
     __shared__ uint32_t h[B_MAX];
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int lvl = P.level;
-    const uint32_t ntile = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
-    const uint32_t chunk = (ntile + gridDim.x - 1) / gridDim.x;
-    const uint32_t t0 = blockIdx.x * chunk, t1 = min(t0 + chunk, ntile);
+    const uint32_t nunit = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
+    const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
+    const uint64_t tag = ((uint64_t)(P.persist[0] * MAXL + lvl)) << ST_TAG_SHIFT;
     const uint64_t* src = P.keys[lvl & 1];
     const int u64 = P.u64;
-    uint32_t cur = 0xffffffffu;
     uint64_t cur_model = 0;
-    Seg sg{};
-    View v{};
-    bool skip = false;
-    const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
-    for (uint32_t t = t0; t < t1; t++) {
-        Tile td = P.tiles[lvl & 1][t];
+    for (uint32_t t = blockIdx.x; t < nunit; t += gridDim.x) {
+        const Tile td = P.tiles[lvl & 1][t];
         if (td.seg >= nseg) continue;
-        if (td.seg != cur) {
-            if (cur != 0xffffffffu && !skip) {
-                __syncthreads();
-                for (uint32_t b = tid; b < sg.nb; b += P_THREADS)
-                    if (h[b]) atomicAdd(&P.counts[sg.cbase + b], (unsigned long long)h[b]);
-            }
-            __syncthreads();
-            sg = P.segs[lvl & 1][td.seg];
-            cur = td.seg;
-            skip = (sg.flags & SEG_FAILED) != 0;
-            if (!skip && sg.model != cur_model) {
-                load_model(mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, P_THREADS);
-                cur_model = sg.model;
-            }
-            for (uint32_t b = tid; b < B_MAX; b += P_THREADS) h[b] = 0;
-            __syncthreads();
-            v = make_view(mdl, sg.kind, sg.nb, sg.win);
+        const Seg sg = P.segs[lvl & 1][td.seg];
+        if (sg.flags & SEG_FAILED) continue;
+        __syncthreads();  // the previous unit is done with mdl and h
+        if (sg.model != cur_model) {
+            load_model(mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, P_THREADS);
+            cur_model = sg.model;
         }
-        if (skip) continue;
-        const uint64_t base = sg.off + (uint64_t)td.idx * TILE;
-        const uint64_t tn = min<uint64_t>(TILE, sg.n - (uint64_t)td.idx * TILE);
+        for (uint32_t b = tid; b < B_MAX; b += P_THREADS) h[b] = 0;
+        __syncthreads();
+        const View v = make_view(mdl, sg.kind, sg.nb, sg.win);
+        const uint64_t base = sg.off + (uint64_t)td.idx * UNIT;
+        const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
         const bool aggregate = v.kind == K_TREE || v.kind == K_TREE_FORCED || v.kind == K_RADIX;
         const int bits = ceil_log2(sg.nb);
-#pragma unroll 4
-        for (int r = 0; r < KPT; r++) {
-            uint32_t i = r * P_THREADS + tid;
-            if (i < tn) {
-                uint32_t b = view_bucket(v, mdl, src[base + i], u64, P.ids, base + i);
-                if (aggregate) {
-                    // wave-aggregated: one LDS add per distinct bucket in the wave
-                    uint64_t peers = match_peers(b, bits);
-                    if (mask_rank(peers) == 0) atomicAdd(&h[b], (uint32_t)__popcll(peers));
+#pragma unroll 8
+        for (uint32_t i = tid; i < un; i += P_THREADS) {
+            const uint32_t b = view_bucket(v, mdl, src[base + i], u64, P.ids, base + i);
+            if (aggregate) {
+                // wave-aggregated: one LDS add per distinct bucket in the wave
+                const uint64_t peers = match_peers(b, bits);
+                if (mask_rank(peers) == 0) atomicAdd(&h[b], (uint32_t)__popcll(peers));
+            } else {
+                const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
+                const uint64_t act = __ballot(1), same = __ballot(b == b0);
+                if (same == act) {
+                    if (mask_rank(act) == 0) atomicAdd(&h[b0], (uint32_t)__popcll(act));
                 } else {
-                    uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
-                    uint64_t act = __ballot(1), same = __ballot(b == b0);
-                    if (same == act) {
-                        if (mask_rank(act) == 0) atomicAdd(&h[b0], (uint32_t)__popcll(act));
-                    } else {
-                        atomicAdd(&h[b], 1u);
-                    }
+                    atomicAdd(&h[b], 1u);
                 }
             }
         }
-        (void)lane;
-    }
-    if (cur != 0xffffffffu && !skip) {
         __syncthreads();
-        for (uint32_t b = tid; b < sg.nb; b += P_THREADS)
-            if (h[b]) atomicAdd(&P.counts[sg.cbase + b], (unsigned long long)h[b]);
+        unsigned long long* row = P.status + sg.sbase + (uint64_t)td.idx * sg.nb;
+        for (uint32_t b = tid; b < sg.nb; b += P_THREADS) {
+            const uint32_t c = h[b];
+            st_store(row + b, tag | ST_AGG | c);
+            if (c) atomicAdd(&P.counts[sg.cbase + b], (unsigned long long)c);
+        }
     }
 }
 
@@ -422,12 +419,47 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
 // k_scan: bucket starts and classification of every bucket (one WG / segment)
 // ===========================================================================
 
-constexpr int S_THREADS = 1024;
+constexpr int S_THREADS = 256;
+constexpr int S_BPT = B_MAX / S_THREADS;  // buckets per thread
+
+// Per-bucket decision (Sec. 2.2 homogeneity check, Sec. 4 base case, the 2x
+// fallback rule): 0 nothing, 1 copy run, 2 base case, 3 range radix child,
+// 4 fine child (same model), 5 splitter-tree child (fallback), 6 fresh child.
+struct Decision {
+    uint32_t act;
+    uint64_t stat;  // 12-bit fields: empty, equality, base, recurse
+};
+
+__device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q, uint64_t c, bool single_value,
+                                           bool fine_ok, uint32_t log2B2, double expected) {
+    Decision d{0, 0};
+    if (c == 0) { d.stat = 1; return d; }
+    if (single_value || c == 1) {
+        d.stat = 1ull << 12;
+        // finished; only a run left in the temporary moves (one key: a trivial sort)
+        d.act = q == 1 ? (c == 1 ? 2u : 1u) : 0u;
+        return d;
+    }
+    const bool oversized = (double)c > P.fallback_ratio * expected;
+    const bool fine = fine_ok && !oversized && (4ull << log2B2) <= c && (uint32_t)lvl + 1 < P.max_levels;
+    // The base case takes a bucket at or below the cutoff, and any bucket it
+    // can hold (C_MAX) that would otherwise need a newly sampled model:
+    // sorting it directly is one pass, a new level is a sample plus a
+    // partition pass.  At the depth cap this leaves range radix (8 bits per
+    // level) only buckets of more than C_MAX keys.
+    if (c <= P.cutoff || (!fine && c <= (uint64_t)C_MAX)) { d.stat = 1ull << 24; d.act = 2; return d; }
+    d.stat = 1ull << 36;
+    if ((uint32_t)lvl + 1 >= P.max_levels) d.act = 3;
+    else if (fine) d.act = 4;
+    else if (oversized && !(P.flags & 0x1u)) d.act = 5;
+    else d.act = 6;
+    return d;
+}
 
 __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
     __shared__ uint64_t red64[S_THREADS / 64];
     __shared__ uint8_t eqb[B_MAX];
-    __shared__ uint64_t resv[3];
+    __shared__ uint64_t resv[4];
     const int tid = threadIdx.x;
     const int lvl = P.level;
     if (blockIdx.x == 0 && tid == 0) {  // pools of the next level (this level's data stays readable)
@@ -442,13 +474,27 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         const Seg sg = P.segs[lvl & 1][s];
         if (sg.flags & SEG_FAILED) continue;
         const uint32_t nb = sg.nb;
-        uint64_t c = (uint32_t)tid < nb ? P.counts[sg.cbase + tid] : 0;
+        // this thread's buckets: S_BPT * tid + i
+        uint64_t c[S_BPT], local = 0, cmax = 0;
+#pragma unroll
+        for (int i = 0; i < S_BPT; i++) {
+            const uint32_t b = S_BPT * tid + i;
+            c[i] = b < nb ? P.counts[sg.cbase + b] : 0;
+            local += c[i];
+            cmax = c[i] > cmax ? c[i] : cmax;
+        }
         uint64_t tot;
-        uint64_t ex = block_excl_scan<S_THREADS, uint64_t>(c, red64, &tot);
-        uint64_t start = sg.off + ex;
-        if ((uint32_t)tid < nb) P.counts[sg.cbase + nb + tid] = start;
+        uint64_t run = sg.off + block_excl_scan<S_THREADS, uint64_t>(local, red64, &tot);
+        uint64_t start[S_BPT];
+#pragma unroll
+        for (int i = 0; i < S_BPT; i++) {
+            const uint32_t b = S_BPT * tid + i;
+            start[i] = run;
+            run += c[i];
+            if (b < nb) P.counts[sg.cbase + nb + b] = start[i];
+        }
         // which buckets hold a single value
-        eqb[tid] = 0;
+        for (uint32_t b = tid; b < B_MAX; b += S_THREADS) eqb[b] = 0;
         __syncthreads();
         uint32_t log2B2 = 0;
         bool fine_ok = false;
@@ -456,7 +502,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const TreeModel* h = (const TreeModel*)sg.model;
             const uint16_t* lut = (const uint16_t*)((const uint64_t*)sg.model + 2 + h->m);
             for (uint32_t u = tid; u < h->m; u += S_THREADS) {
-                uint16_t e = lut[u + 1];
+                const uint16_t e = lut[u + 1];
                 if (e & 1) eqb[(u + 1) + (e >> 1) - 1] = 1;
             }
         } else if (sg.kind == K_RADIX) {
@@ -472,83 +518,44 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         }
         __syncthreads();
         const double expected = (double)sg.n / (double)nb;
-        // action of this bucket: 0 nothing, 1 copy items, 2 base item, 3..6 child of kind
-        // K_RADIX / fine / K_TREE_FORCED / K_FRESH
-        uint32_t act = 0;
-        uint64_t stat = 0;  // 12-bit fields: empty, equality, base, recurse
-        if ((uint32_t)tid < nb && c > 0) {
-            if (eqb[tid] || c == 1) {
-                stat = 1ull << 12;
-                act = q == 1 ? 1 : 0;  // finished; only a run left in the temporary moves
-            } else if (c <= P.cutoff || ((uint32_t)lvl + 1 >= P.max_levels && c <= (uint64_t)C_MAX)) {
-                // at the depth cap every bucket the base case can hold goes there,
-                // so range-radix levels only ever see more than C_MAX keys (8 bits each)
-                stat = 1ull << 24;
-                act = 2;
-            } else {
-                const bool oversized = (double)c > P.fallback_ratio * expected;
-                stat = 1ull << 36;
-                if ((uint32_t)lvl + 1 >= P.max_levels) act = 3;
-                else if (fine_ok && !oversized && (4ull << log2B2) <= c) act = 4;
-                else if (oversized && !(P.flags & 0x1u)) act = 5;
-                else act = 6;
-            }
-        } else if ((uint32_t)tid < nb) {
-            stat = 1ull;
+        uint32_t act[S_BPT];
+        uint64_t la = 0, lb = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0;
+#pragma unroll
+        for (int i = 0; i < S_BPT; i++) {
+            const uint32_t b = S_BPT * tid + i;
+            act[i] = 0;
+            if (b >= nb) continue;
+            const Decision d = decide(P, lvl, q, c[i], eqb[b] != 0, fine_ok, log2B2, expected);
+            act[i] = d.act;
+            lstat += d.stat;
+            const uint64_t nsm = d.act == 2 && c[i] <= SMALL_MAX ? 1 : 0;
+            const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && c[i] > SMALL_MAX ? 1 : 0);
+            const uint64_t ntl = d.act >= 3 ? (c[i] + UNIT - 1) / UNIT : 0;
+            // packed counters: small items | children << 16 | large items << 32, units | fallbacks << 32
+            la += nsm | ((uint64_t)(d.act >= 3) << 16) | (nbg << 32);
+            lb += ntl | ((uint64_t)(d.act == 5) << 32);
+            lsk += nsm ? c[i] : 0;
+            lgk += nbg ? c[i] : 0;
+            lcp += d.act == 1 ? nbg : 0;
         }
-        const uint64_t nitem = act == 1 ? (c + COPY_CHUNK - 1) / COPY_CHUNK : (act == 2 ? 1 : 0);
-        const uint32_t ntl = act >= 3 ? (uint32_t)((c + TILE - 1) / TILE) : 0;
         // one reservation per list for the whole workgroup
-        uint64_t itot, ctot, ttot;
-        const uint64_t iex = block_excl_scan<S_THREADS, uint64_t>(nitem, red64, &itot);
-        const uint64_t cex = block_excl_scan<S_THREADS, uint64_t>(act >= 3 ? 1 : 0, red64, &ctot);
-        const uint64_t tex = block_excl_scan<S_THREADS, uint64_t>(ntl, red64, &ttot);
-        const uint64_t ck = block_sum<S_THREADS, uint64_t>(act == 1 ? c : 0, red64);
-        const uint64_t bk = block_sum<S_THREADS, uint64_t>(act == 2 ? c : 0, red64);
-        const uint64_t nfb = block_sum<S_THREADS, uint64_t>(act == 5 ? 1 : 0, red64);
-        const uint64_t ncp = block_sum<S_THREADS, uint64_t>(act == 1 ? nitem : 0, red64);
+        uint64_t ta, tb;
+        uint64_t xa = block_excl_scan<S_THREADS, uint64_t>(la, red64, &ta);
+        uint64_t xb = block_excl_scan<S_THREADS, uint64_t>(lb, red64, &tb);
+        const uint64_t sk = block_sum<S_THREADS, uint64_t>(lsk, red64);
+        const uint64_t gk = block_sum<S_THREADS, uint64_t>(lgk, red64);
+        const uint64_t ncp = block_sum<S_THREADS, uint64_t>(lcp, red64);
+        const uint64_t sc = block_sum<S_THREADS, uint64_t>(lstat, red64);
+        const uint64_t mx = block_max<S_THREADS, uint64_t>(cmax, red64);
         if (tid == 0) {
+            const uint64_t itot = ta & 0xffff, ctot = (ta >> 16) & 0xffff, gtot = ta >> 32, ttot = tb & 0xffffffffull;
             resv[0] = itot ? atomicAdd(&P.ctl->nitems, (unsigned long long)itot) : 0;
             resv[1] = ctot ? atomicAdd(&P.ctl->nseg[lvl + 1], (uint32_t)ctot) : 0;
             resv[2] = ttot ? atomicAdd(&P.ctl->ntile[lvl + 1], (uint32_t)ttot) : 0;
-            if (ck) {
-                atomicAdd(&P.ctl->copy_keys, (unsigned long long)ck);
-                atomicAdd(&P.ctl->ncopy, (unsigned long long)ncp);
-            }
-            if (bk) atomicAdd(&P.ctl->base_keys, (unsigned long long)bk);
-        }
-        __syncthreads();
-        for (uint64_t k = 0; k < nitem; k++) {
-            const uint64_t it = resv[0] + iex + k;
-            if (it >= P.item_cap) { atomicOr(&P.ctl->overflow, OVF_ITEM); break; }
-            const uint64_t sz = act == 1 ? min<uint64_t>(COPY_CHUNK, c - k * COPY_CHUNK) : c;
-            P.items[it] = item_pack(start + k * COPY_CHUNK, act == 1 ? 1u : q, act == 1 ? 1u : 0u, (uint32_t)sz);
-        }
-        if (act >= 3) {
-            const uint64_t si = resv[1] + cex, t0 = resv[2] + tex;
-            if (si < P.seg_cap) {
-                Seg ch{};
-                ch.off = start; ch.n = c; ch.ntiles = ntl; ch.tile0 = (uint32_t)t0;
-                ch.kind = act == 3 ? K_RADIX : act == 4 ? (sg.kind == K_RMI ? K_RMI_FINE : K_MLP_FINE)
-                        : act == 5 ? K_TREE_FORCED : K_FRESH;
-                if (act == 4) {
-                    ch.model = sg.model;
-                    ch.nb = 1u << log2B2;
-                    ch.win = (uint32_t)tid << log2B2;
-                    ch.flags = sg.flags & 0xffff0000u;  // model words
-                }
-                if (t0 + ntl > P.tile_cap) { atomicOr(&P.ctl->overflow, OVF_TILE); ch.flags |= SEG_FAILED; }
-                P.segs[q][si] = ch;  // k_model of the next level writes its tile descriptors
-            } else {
-                atomicOr(&P.ctl->overflow, OVF_SEG);
-                for (uint32_t i = 0; i < ntl; i++)  // keep the tile list free of stale slots
-                    if (t0 + i < P.tile_cap) P.tiles[q][t0 + i] = Tile{0xffffffffu, 0};
-            }
-        }
-        // statistics
-        const uint64_t sc = block_sum<S_THREADS, uint64_t>(stat, red64);
-        uint64_t mx = block_max<S_THREADS, uint64_t>(c, red64);
-        if (tid == 0) {
+            resv[3] = gtot ? atomicAdd(&P.ctl->nbig, (unsigned long long)gtot) : 0;
+            if (ncp) atomicAdd(&P.ctl->ncopy, (unsigned long long)ncp);
+            if (sk) atomicAdd(&P.ctl->small_keys, (unsigned long long)sk);
+            if (gk) atomicAdd(&P.ctl->big_keys, (unsigned long long)gk);
             const uint64_t m12 = 4095;
             atomicAdd(&st.segments, 1ull);
             atomicAdd(&st.keys, (unsigned long long)sg.n);
@@ -559,50 +566,106 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             atomicAdd(&st.equality, (unsigned long long)((sc >> 12) & m12));
             atomicAdd(&st.base, (unsigned long long)((sc >> 24) & m12));
             atomicAdd(&st.recurse, (unsigned long long)((sc >> 36) & m12));
-            atomicAdd(&st.fallback, (unsigned long long)nfb);
+            atomicAdd(&st.fallback, (unsigned long long)(tb >> 32));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < S_BPT; i++) {
+            const uint32_t b = S_BPT * tid + i;
+            const uint32_t a = act[i];
+            const uint64_t ci = c[i];
+            const uint64_t nsm = a == 2 && ci <= SMALL_MAX ? 1 : 0;
+            const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && ci > SMALL_MAX ? 1 : 0);
+            const uint64_t ntl = a >= 3 ? (ci + UNIT - 1) / UNIT : 0;
+            const uint64_t iex = xa & 0xffff, cex = (xa >> 16) & 0xffff, gex = xa >> 32, tex = xb & 0xffffffffull;
+            if (nsm) {
+                const uint64_t it = resv[0] + iex;
+                if (it < P.item_cap) P.items[it] = item_pack(start[i], q, 0u, (uint32_t)ci);
+                else atomicOr(&P.ctl->overflow, OVF_ITEM);
+            }
+            for (uint64_t k = 0; k < nbg; k++) {
+                const uint64_t it = resv[3] + gex + k;
+                if (it >= P.big_cap) { atomicOr(&P.ctl->overflow, OVF_ITEM); break; }
+                const uint64_t sz = a == 1 ? min<uint64_t>(COPY_CHUNK, ci - k * COPY_CHUNK) : ci;
+                P.bigs[it] = item_pack(start[i] + k * COPY_CHUNK, a == 1 ? 1u : q, a == 1 ? 1u : 0u, (uint32_t)sz);
+            }
+            if (a >= 3) {
+                const uint64_t si = resv[1] + cex, t0 = resv[2] + tex;
+                if (si < P.seg_cap) {
+                    Seg ch{};
+                    ch.off = start[i]; ch.n = ci; ch.ntiles = (uint32_t)ntl; ch.tile0 = (uint32_t)t0;
+                    ch.kind = a == 3 ? K_RADIX : a == 4 ? (sg.kind == K_RMI ? K_RMI_FINE : K_MLP_FINE)
+                            : a == 5 ? K_TREE_FORCED : K_FRESH;
+                    if (a == 4) {
+                        ch.model = sg.model;
+                        ch.nb = 1u << log2B2;
+                        ch.win = b << log2B2;
+                        ch.flags = sg.flags & 0xffff0000u;  // model words
+                    }
+                    if (t0 + ntl > P.tile_cap) { atomicOr(&P.ctl->overflow, OVF_TILE); ch.flags |= SEG_FAILED; }
+                    P.segs[q][si] = ch;  // k_model of the next level writes its unit descriptors
+                } else {
+                    atomicOr(&P.ctl->overflow, OVF_SEG);
+                    for (uint32_t u = 0; u < ntl; u++)  // keep the unit list free of stale slots
+                        if (t0 + u < P.tile_cap) P.tiles[q][t0 + u] = Tile{0xffffffffu, 0};
+                }
+            }
+            xa += nsm | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
+            xb += ntl | ((uint64_t)(a == 5) << 32);
         }
         __syncthreads();
     }
 }
 
 // ===========================================================================
-// k_scatter: stable in-tile rank, decoupled look-back over tiles, LDS-staged
-// coalesced write of each bucket's run (one tile of 8192 keys per iteration)
+// k_scatter<PAY>: one work unit (4 tiles of 8192 keys) per iteration, units taken
+// in order through a ticket.  First the unit's exclusive prefix per bucket
+// comes from a decoupled look-back (Merrill & Garland) over the preceding
+// units of its segment: every such word already holds at least the unit's
+// aggregate (written by k_hist), so the walk never waits -- it stops at the
+// first inclusive prefix or at the segment's first unit -- and the unit
+// publishes its own inclusive prefix at once.  Then each tile: in-tile rank,
+// tile-local bucket starts, keys staged in LDS grouped by bucket and written
+// as contiguous runs.  The next tile's keys are loaded while the current one
+// is ranked.
+//   PAY = true: the rank is stable (wave match over the bucket bits and
+//   per-wave counters), so a payload keeps the input order of equal keys.
+//   PAY = false: keys only.  Order inside a bucket is not observable -- the
+//   bucket is sorted later and equal keys are identical -- so the rank is one
+//   LDS atomic per key.
 // ===========================================================================
 
-__device__ __forceinline__ uint64_t st_load(const unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_store(unsigned long long* p, uint64_t v) {
-    __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Barrier for LDS hand-offs only: global loads in flight stay in flight.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+template <bool PAY>
 __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
     __shared__ uint64_t mdl[MODEL_WORDS];
     __shared__ uint64_t stage[TILE];
     __shared__ uint16_t sbid[TILE];
-    __shared__ uint16_t wcnt[P_WAVES][B_MAX];
-    __shared__ uint16_t tcnt[B_MAX];
+    __shared__ uint16_t wcnt[PAY ? P_WAVES : 1][PAY ? B_MAX : 1];
+    __shared__ uint32_t tcnt[B_MAX];
     __shared__ uint16_t tstart[B_MAX];
-    __shared__ uint64_t goff[B_MAX];
+    __shared__ uint64_t run[B_MAX];
     __shared__ uint32_t sh_t;
     __shared__ uint64_t red64[P_THREADS / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lvl = P.level;
-    const uint32_t ntile = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
+    const uint32_t nunit = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
     const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
     const uint64_t tag = ((uint64_t)(P.persist[0] * MAXL + lvl)) << ST_TAG_SHIFT;
     const uint64_t* src = P.keys[lvl & 1];
     uint64_t* dst = P.keys[(lvl + 1) & 1];
     const uint32_t* psrc = P.pay[lvl & 1];
     uint32_t* pdst = P.pay[(lvl + 1) & 1];
-    const int u64 = P.u64, has_pay = P.has_pay;
+    const int u64 = P.u64;
+    constexpr bool has_pay = PAY;
     uint64_t cur_model = 0;
     for (;;) {
         if (tid == 0) sh_t = atomicAdd(&P.ctl->ticket[lvl], 1u);
         __syncthreads();
         const uint32_t t = sh_t;
-        if (t >= ntile) break;
+        if (t >= nunit) break;
         const Tile td = P.tiles[lvl & 1][t];
         if (td.seg >= nseg) { __syncthreads(); continue; }
         const Seg sg = P.segs[lvl & 1][td.seg];
@@ -610,138 +673,247 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
         if (sg.model != cur_model) {
             load_model(mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, P_THREADS);
             cur_model = sg.model;
-            __syncthreads();
+        }
+        const uint32_t nb = sg.nb;
+        // ---- look-back: exclusive prefix of this unit for every bucket ----
+        {
+            unsigned long long* row = P.status + sg.sbase + (uint64_t)td.idx * nb;
+            uint32_t bad = 0;
+            for (uint32_t j = tid; j < nb; j += P_THREADS) {
+                const uint64_t own = st_load(row + j);
+                uint64_t excl = 0;
+                for (int64_t pk = (int64_t)td.idx - 1; pk >= 0; pk--) {
+                    const uint64_t wv = st_load(P.status + sg.sbase + (uint64_t)pk * nb + j);
+                    const uint64_t hdr = wv & ~ST_LOW_MASK;
+                    if (hdr != (tag | ST_AGG) && hdr != (tag | ST_PREFIX)) { bad = 1; break; }
+                    excl += wv & ST_VALUE_MASK;
+                    if (hdr == (tag | ST_PREFIX)) break;
+                }
+                if ((own & ~ST_LOW_MASK) != (tag | ST_AGG) && (own & ~ST_LOW_MASK) != (tag | ST_PREFIX)) bad = 1;
+                st_store(row + j, tag | ST_PREFIX | (excl + (own & ST_VALUE_MASK)));
+                run[j] = P.counts[sg.cbase + nb + j] + excl;
+            }
+            if (__syncthreads_or(bad)) {  // never expected: refuse to write anything for this unit
+                if (tid == 0) atomicOr(&P.ctl->overflow, OVF_STATE);
+                __syncthreads();
+                continue;
+            }
         }
         const View v = make_view(mdl, sg.kind, sg.nb, sg.win);
-        const uint32_t nb = sg.nb;
         const int bits = ceil_log2(nb);
-        const uint64_t base = sg.off + (uint64_t)td.idx * TILE;
-        const uint32_t tn = (uint32_t)min<uint64_t>(TILE, sg.n - (uint64_t)td.idx * TILE);
-        // load: wave w owns keys [w*1024, (w+1)*1024) of the tile, 64 per round
-        uint64_t k[KPT];
-        uint32_t b[KPT];
-        uint32_t pl[KPT];
+        const uint64_t ubase = sg.off + (uint64_t)td.idx * UNIT;
+        const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
+        const uint32_t ntl = (un + TILE - 1) / TILE;
+        // wave w owns keys [w*1024, (w+1)*1024) of a tile, 64 per round
+        uint64_t k[KPT], kn[KPT];
+        uint32_t pl[KPT], pn[KPT];
 #pragma unroll
         for (int r = 0; r < KPT; r++) {
-            uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
-            k[r] = i < tn ? src[base + i] : 0;
-            pl[r] = (has_pay && i < tn) ? psrc[base + i] : 0;
+            const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+            k[r] = i < un ? src[ubase + i] : 0;
+            pl[r] = (has_pay && i < un) ? psrc[ubase + i] : 0;
         }
-        for (uint32_t j = lane; j < nb; j += WAVE) wcnt[w][j] = 0;
+        for (uint32_t tt = 0; tt < ntl; tt++) {
+            const uint64_t base = ubase + (uint64_t)tt * TILE;
+            const uint32_t tn = min<uint32_t>(TILE, un - tt * TILE);
+            if (tt + 1 < ntl) {  // prefetch the next tile
+                const uint32_t nn = min<uint32_t>(TILE, un - (tt + 1) * TILE);
 #pragma unroll
-        for (int r = 0; r < KPT; r++) {
-            uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
-            b[r] = i < tn ? view_bucket(v, mdl, k[r], u64, P.ids, base + i) : 0;
-        }
-        // stable rank within the wave: rounds in key order, lanes in key order
-        uint32_t rk[KPT];
-#pragma unroll
-        for (int r = 0; r < KPT; r++) {
-            uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
-            rk[r] = 0;
-            if (i < tn) {
-                uint64_t peers = match_peers(b[r], bits);
-                uint32_t below = mask_rank(peers);
-                uint32_t before = wcnt[w][b[r]];
-                if (below == 0) wcnt[w][b[r]] = (uint16_t)(before + __popcll(peers));
-                rk[r] = before + below;
-            }
-        }
-        __syncthreads();
-        // per bucket: exclusive prefix over waves (in place) and tile count
-        for (uint32_t j = tid; j < nb; j += P_THREADS) {
-            uint32_t run = 0;
-#pragma unroll
-            for (int x = 0; x < P_WAVES; x++) {
-                uint32_t c = wcnt[x][j];
-                wcnt[x][j] = (uint16_t)run;
-                run += c;
-            }
-            tcnt[j] = (uint16_t)run;
-        }
-        __syncthreads();
-        // tile-local bucket starts: exclusive scan over buckets, 2 per thread
-        {
-            uint32_t j0 = 2 * tid, j1 = 2 * tid + 1;
-            uint64_t c0 = j0 < nb ? tcnt[j0] : 0, c1 = j1 < nb ? tcnt[j1] : 0;
-            uint64_t ex = block_excl_scan<P_THREADS, uint64_t>(c0 + c1, red64, nullptr);
-            if (j0 < nb) tstart[j0] = (uint16_t)ex;
-            if (j1 < nb) tstart[j1] = (uint16_t)(ex + c0);
-        }
-        // decoupled look-back (Merrill & Garland): publish this tile's counts
-        // for every bucket first, then add predecessors' aggregates until an
-        // inclusive prefix is found.  The first tile of a segment publishes
-        // its inclusive prefix at once, so every wait ends.
-        unsigned long long* row = P.status + sg.sbase + (uint64_t)td.idx * nb;
-        for (uint32_t j = tid; j < nb; j += P_THREADS)
-            st_store(row + j, tag | (td.idx == 0 ? ST_PREFIX : ST_AGG) | (uint64_t)tcnt[j]);
-        for (uint32_t j = tid; j < nb; j += P_THREADS) {
-            uint64_t excl = 0;
-            if (td.idx > 0) {
-                int64_t pk = (int64_t)td.idx - 1;
-                for (;;) {
-                    uint64_t wv = st_load(P.status + sg.sbase + (uint64_t)pk * nb + j);
-                    uint64_t hdr = wv & ~ST_LOW_MASK;
-                    if (hdr == (tag | ST_PREFIX)) { excl += wv & ST_VALUE_MASK; break; }
-                    if (hdr == (tag | ST_AGG)) { excl += wv & ST_VALUE_MASK; pk--; continue; }
-                    __builtin_amdgcn_s_sleep(1);
+                for (int r = 0; r < KPT; r++) {
+                    const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+                    kn[r] = i < nn ? src[base + TILE + i] : 0;
+                    pn[r] = (has_pay && i < nn) ? psrc[base + TILE + i] : 0;
                 }
-                st_store(row + j, tag | ST_PREFIX | (excl + tcnt[j]));
             }
-            goff[j] = P.counts[sg.cbase + nb + j] + excl;
-        }
-        __syncthreads();
-        // stage keys grouped by bucket (stable positions)
-        uint32_t pos[KPT];
-#pragma unroll
-        for (int r = 0; r < KPT; r++) {
-            uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
-            pos[r] = 0xffffffffu;
-            if (i < tn) {
-                uint32_t p = tstart[b[r]] + wcnt[w][b[r]] + rk[r];
-                pos[r] = p;
-                stage[p] = k[r];
-                sbid[p] = (uint16_t)b[r];
+            uint32_t b[KPT], rk[KPT];
+            if (PAY) {
+                for (uint32_t j = lane; j < nb; j += WAVE) wcnt[w][j] = 0;
+            } else {
+                for (uint32_t j = tid; j < nb; j += P_THREADS) tcnt[j] = 0;
+                lds_barrier();
             }
-        }
-        __syncthreads();
-        for (uint32_t p = tid; p < tn; p += P_THREADS) {
-            uint32_t bb = sbid[p];
-            dst[goff[bb] + (p - tstart[bb])] = stage[p];
-        }
-        if (has_pay) {
-            __syncthreads();
-            uint32_t* st32 = (uint32_t*)stage;
 #pragma unroll
-            for (int r = 0; r < KPT; r++)
-                if (pos[r] != 0xffffffffu) st32[pos[r]] = pl[r];
-            __syncthreads();
+            for (int r = 0; r < KPT; r++) {
+                const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+                b[r] = i < tn ? view_bucket(v, mdl, k[r], u64, P.ids, base + i) : 0;
+            }
+            if (PAY) {
+                // stable rank within the wave: rounds in key order, lanes in key order
+#pragma unroll
+                for (int r = 0; r < KPT; r++) {
+                    const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+                    rk[r] = 0;
+                    if (i < tn) {
+                        const uint64_t peers = match_peers(b[r], bits);
+                        const uint32_t below = mask_rank(peers);
+                        const uint32_t before = wcnt[w][b[r]];
+                        if (below == 0) wcnt[w][b[r]] = (uint16_t)(before + __popcll(peers));
+                        rk[r] = before + below;
+                    }
+                }
+                lds_barrier();
+                // per bucket: exclusive prefix over waves (in place) and tile count
+                for (uint32_t j = tid; j < nb; j += P_THREADS) {
+                    uint32_t acc = 0;
+#pragma unroll
+                    for (int x = 0; x < P_WAVES; x++) {
+                        const uint32_t c = wcnt[x][j];
+                        wcnt[x][j] = (uint16_t)acc;
+                        acc += c;
+                    }
+                    tcnt[j] = acc;
+                }
+            } else {
+                // any order inside a bucket: one LDS atomic per key (one per wave
+                // when the whole wave falls into a single bucket)
+#pragma unroll
+                for (int r = 0; r < KPT; r++) {
+                    const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+                    rk[r] = 0;
+                    if (i < tn) {
+                        const uint32_t b0 = __builtin_amdgcn_readfirstlane(b[r]);
+                        const uint64_t act = __ballot(1), same = __ballot(b[r] == b0);
+                        if (same == act) {
+                            uint32_t bs = 0;
+                            if (mask_rank(act) == 0) bs = atomicAdd(&tcnt[b0], (uint32_t)__popcll(act));
+                            rk[r] = __shfl(bs, __ffsll((unsigned long long)act) - 1) + mask_rank(act);
+                        } else {
+                            rk[r] = atomicAdd(&tcnt[b[r]], 1u);
+                        }
+                    }
+                }
+            }
+            lds_barrier();
+            {  // tile-local bucket starts: exclusive scan over buckets, 2 per thread
+                const uint32_t j0 = 2 * tid, j1 = 2 * tid + 1;
+                const uint32_t c0 = j0 < nb ? tcnt[j0] : 0u, c1 = j1 < nb ? tcnt[j1] : 0u;
+                const uint32_t lane_sum = c0 + c1;
+                uint32_t x = lane_sum;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(x, o);
+                    if (lane >= o) x += y;
+                }
+                if (lane == 63) red64[w] = x;
+                lds_barrier();
+                uint32_t before = 0;
+#pragma unroll
+                for (int q = 0; q < P_WAVES; q++) before += q < w ? (uint32_t)red64[q] : 0u;
+                const uint32_t ex = before + x - lane_sum;
+                if (j0 < nb) tstart[j0] = (uint16_t)ex;
+                if (j1 < nb) tstart[j1] = (uint16_t)(ex + c0);
+            }
+            lds_barrier();
+            // stage keys grouped by bucket (stable positions)
+            uint32_t pos[KPT];
+#pragma unroll
+            for (int r = 0; r < KPT; r++) {
+                const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+                pos[r] = 0xffffffffu;
+                if (i < tn) {
+                    const uint32_t p = tstart[b[r]] + (PAY ? (uint32_t)wcnt[w][b[r]] : 0u) + rk[r];
+                    pos[r] = p;
+                    stage[p] = k[r];
+                    sbid[p] = (uint16_t)b[r];
+                }
+            }
+            lds_barrier();
             for (uint32_t p = tid; p < tn; p += P_THREADS) {
-                uint32_t bb = sbid[p];
-                pdst[goff[bb] + (p - tstart[bb])] = st32[p];
+                const uint32_t bb = sbid[p];
+                dst[run[bb] + (p - tstart[bb])] = stage[p];
             }
+            if (has_pay) {
+                lds_barrier();
+                uint32_t* st32 = (uint32_t*)stage;
+#pragma unroll
+                for (int r = 0; r < KPT; r++)
+                    if (pos[r] != 0xffffffffu) st32[pos[r]] = pl[r];
+                lds_barrier();
+                for (uint32_t p = tid; p < tn; p += P_THREADS) {
+                    const uint32_t bb = sbid[p];
+                    pdst[run[bb] + (p - tstart[bb])] = st32[p];
+                }
+            }
+            lds_barrier();
+            for (uint32_t j = tid; j < nb; j += P_THREADS) run[j] += tcnt[j];
+            lds_barrier();
+#pragma unroll
+            for (int r = 0; r < KPT; r++) { k[r] = kn[r]; pl[r] = pn[r]; }
         }
         __syncthreads();
     }
 }
 
 // ===========================================================================
-// k_base: in-LDS stable sort of every small bucket; copies of finished runs
+// Base case (Sec. 4: sub-arrays below the cutoff are sorted directly).
+// k_base_small: one wavefront per sub-array of at most 512 keys, sorted in
+// registers (wave_bitonic); k_base_big: one workgroup per larger sub-array
+// (up to 4096) sorted in LDS, and the copies of finished runs.
 // ===========================================================================
 
 constexpr int BASE_THREADS = 256;
 
-__global__ __launch_bounds__(BASE_THREADS) void k_base(Params P) {
+template <int E, bool PAY>
+__device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, int lane) {
+    const uint64_t* in = P.keys[srcb];
+    uint64_t* out = P.keys[0];
+    const int u64 = P.u64;
+    uint64_t k[E];
+    uint32_t ix[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const uint32_t i = lane * E + e;
+        k[e] = i < size ? key_ord(in[off + i], u64) : ~0ull;
+        ix[e] = i;
+    }
+    if (PAY) {
+        wave_bitonic<E, true>(k, ix, lane);
+        const uint32_t* pin = P.pay[srcb];
+        uint32_t* pout = P.pay[0];
+        uint32_t pv[E];
+#pragma unroll
+        for (int e = 0; e < E; e++) pv[e] = (lane * E + e < (int)size) ? pin[off + ix[e]] : 0u;
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            if (lane * E + e < (int)size) pout[off + lane * E + e] = pv[e];
+    } else {
+        wave_bitonic<E, false>(k, ix, lane);
+    }
+#pragma unroll
+    for (int e = 0; e < E; e++)
+        if (lane * E + e < (int)size) out[off + lane * E + e] = key_unord(k[e], u64);
+}
+
+template <bool PAY>
+__global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * (BASE_THREADS / 64);
+    const uint64_t nitems = min<unsigned long long>(P.ctl->nitems, P.item_cap);
+    for (uint64_t it = (uint64_t)blockIdx.x * (BASE_THREADS / 64) + (threadIdx.x >> 6); it < nitems; it += waves) {
+        const uint64_t wd = P.items[it];
+        const uint64_t off = wd >> 18;
+        const uint32_t srcb = (wd >> 17) & 1u;
+        const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
+        if (size <= 64) base_small_item<1, PAY>(P, off, size, srcb, lane);
+        else if (size <= 128) base_small_item<2, PAY>(P, off, size, srcb, lane);
+        else if (size <= 256) base_small_item<4, PAY>(P, off, size, srcb, lane);
+        else base_small_item<8, PAY>(P, off, size, srcb, lane);
+    }
+}
+
+constexpr int BIG_THREADS = 512;
+
+__global__ __launch_bounds__(BIG_THREADS) void k_base_big(Params P) {
     __shared__ uint64_t sk[C_MAX];
     __shared__ uint16_t si[C_MAX];
     __shared__ uint32_t sp[C_MAX];
     const int tid = threadIdx.x;
-    const uint64_t nitems = min<unsigned long long>(P.ctl->nitems, P.item_cap);
+    const uint64_t nitems = min<unsigned long long>(P.ctl->nbig, P.big_cap);
     const int u64 = P.u64, has_pay = P.has_pay;
     uint64_t* out = P.keys[0];
     uint32_t* pout = P.pay[0];
     for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint64_t wd = P.items[it];
+        const uint64_t wd = P.bigs[it];
         const uint64_t off = wd >> 18;
         const uint32_t srcb = (wd >> 17) & 1u, copy = (wd >> 16) & 1u;
         const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
@@ -749,14 +921,14 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base(Params P) {
         const uint32_t* pin = P.pay[srcb];
         if (copy) {
             if (srcb)
-                for (uint32_t i = tid; i < size; i += BASE_THREADS) {
+                for (uint32_t i = tid; i < size; i += BIG_THREADS) {
                     out[off + i] = in[off + i];
                     if (has_pay) pout[off + i] = pin[off + i];
                 }
             continue;
         }
         const uint32_t P2 = 1u << ceil_log2(size);
-        for (uint32_t i = tid; i < P2; i += BASE_THREADS) {
+        for (uint32_t i = tid; i < P2; i += BIG_THREADS) {
             sk[i] = i < size ? key_ord(in[off + i], u64) : ~0ull;
             if (has_pay) {
                 si[i] = (uint16_t)i;
@@ -764,9 +936,9 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base(Params P) {
             }
         }
         __syncthreads();
-        if (has_pay) bitonic_pairs<BASE_THREADS>(sk, si, P2);
-        else bitonic_keys<BASE_THREADS>(sk, P2);
-        for (uint32_t i = tid; i < size; i += BASE_THREADS) {
+        if (has_pay) bitonic_pairs<BIG_THREADS>(sk, si, P2);
+        else bitonic_keys<BIG_THREADS>(sk, P2);
+        for (uint32_t i = tid; i < size; i += BIG_THREADS) {
             out[off + i] = key_unord(sk[i], u64);
             if (has_pay) pout[off + i] = sp[si[i]];
         }
@@ -792,7 +964,14 @@ hipError_t launch_seed(const Params& P, const uint64_t* offsets, uint64_t m, uin
 hipError_t launch_model(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_model, grid, M_THREADS, st, P); }
 hipError_t launch_hist(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_hist, grid, P_THREADS, st, P); }
 hipError_t launch_scan(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_scan, grid, S_THREADS, st, P); }
-hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_scatter, grid, P_THREADS, st, P); }
-hipError_t launch_base(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_base, grid, BASE_THREADS, st, P); }
+hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st) {
+    if (P.has_pay) LAUNCH(k_scatter<true>, grid, P_THREADS, st, P);
+    LAUNCH(k_scatter<false>, grid, P_THREADS, st, P);
+}
+hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st) {
+    if (P.has_pay) LAUNCH(k_base_small<true>, grid, BASE_THREADS, st, P);
+    LAUNCH(k_base_small<false>, grid, BASE_THREADS, st, P);
+}
+hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_base_big, grid, BIG_THREADS, st, P); }
 
 }  // namespace ls
