@@ -102,6 +102,17 @@ static uint64_t big_sample_size(uint64_t n, uint64_t m, const Opts& o) {
     return S > (uint64_t)S_LDS ? S : 0;
 }
 
+// Options of the engine run that sorts a large first level's sample.  The
+// sample's own model only has to split the sample: a 0.4% sub-sample (4096
+// keys for a 1e6-key sample) keeps its one-workgroup sort short.
+static Opts nested_opts(const Opts& o) {
+    Opts r = o;
+    r.flags = (o.flags & LS_FLAG_FIXED_LEVELS) ? o.flags : ((o.flags & ~(uint32_t)LS_FLAG_FIXED_LEVELS) | LS_FLAG_SYNC_LEVELS);
+    r.model = o.model == LS_MODEL_SPLITTER ? LS_MODEL_SPLITTER : LS_MODEL_AUTO;
+    r.sample_frac = 0.004;
+    return r;
+}
+
 static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     Layout L{};
     L.n = n; L.m = m; L.has_pay = has_pay;
@@ -140,7 +151,7 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.S_big = big_sample_size(n, m, o);
     if (L.S_big) {
         L.o_sample = take(L.S_big * 8);
-        L.nested.push_back(plan(L.S_big, 1, 0, o));
+        L.nested.push_back(plan(L.S_big, 1, 0, nested_opts(o)));
         L.o_nested = take(L.nested[0].bytes);
     }
     L.bytes = o_;
@@ -355,10 +366,7 @@ static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPoo
     TIMED(KI_GATHER, c.st, launch_gather(c.keys, c.n, z, L.S_big, smp, c.st));
     Call nc{};
     nc.keys = smp; nc.pay = nullptr; nc.n = L.S_big; nc.m = 1; nc.offsets = nullptr; nc.u64 = c.u64;
-    nc.o = c.o;
-    nc.o.flags = (c.o.flags & ~(uint32_t)LS_FLAG_FIXED_LEVELS) | LS_FLAG_SYNC_LEVELS;
-    if (c.o.flags & LS_FLAG_FIXED_LEVELS) nc.o.flags = c.o.flags;
-    nc.o.model = c.o.model == LS_MODEL_SPLITTER ? LS_MODEL_SPLITTER : LS_MODEL_AUTO;
+    nc.o = nested_opts(c.o);
     nc.st = c.st;
     ls_status s = run(nc, L.nested[0], base + L.o_nested, pool);
     if (s) return s;

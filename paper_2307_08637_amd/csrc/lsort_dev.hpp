@@ -359,6 +359,75 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E]
     }
 }
 
+// Bitonic sort of NT*E (key[, index]) pairs by a workgroup of NT threads,
+// thread t holding elements t*E .. t*E+E-1 in registers.  Stages with
+// distance j < E stay in registers, E <= j < 64E exchange through cross-lane
+// shuffles, and only j >= 64E go through LDS (column layout ex[e*NT + t], so
+// a wavefront's accesses are conflict-free).  exk / exi: NT*E entries of LDS.
+template <int NT, int E, bool PAIRS>
+__device__ void block_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E], uint64_t* exk, uint32_t* exi) {
+    constexpr int N = NT * E;
+    const int t = threadIdx.x;
+    for (int kk = 2; kk <= N; kk <<= 1) {
+        int j = kk >> 1;
+        for (; j >= 64 * E; j >>= 1) {  // partner in another wavefront: through LDS
+            const int s = j / E;
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                exk[e * NT + t] = k[e];
+                if (PAIRS) exi[e * NT + t] = ix[e];
+            }
+            __syncthreads();
+            const bool keep_min = (((t * E) & kk) == 0) == ((t & s) == 0);
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                const uint64_t y = exk[e * NT + (t ^ s)];
+                const uint32_t iy = PAIRS ? exi[e * NT + (t ^ s)] : 0u;
+                const bool lt = y < k[e] || (PAIRS && y == k[e] && iy < ix[e]);
+                const bool gt = y > k[e] || (PAIRS && y == k[e] && iy > ix[e]);
+                if (keep_min ? lt : gt) {
+                    k[e] = y;
+                    if (PAIRS) ix[e] = iy;
+                }
+            }
+        }
+        for (; j >= E; j >>= 1) {  // partner in the same wavefront: shuffle
+            const int s = j / E;
+            const bool keep_min = (((t * E) & kk) == 0) == ((t & s) == 0);
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                const uint64_t y = __shfl_xor(k[e], s);
+                const uint32_t iy = PAIRS ? __shfl_xor(ix[e], s) : 0u;
+                const bool lt = y < k[e] || (PAIRS && y == k[e] && iy < ix[e]);
+                const bool gt = y > k[e] || (PAIRS && y == k[e] && iy > ix[e]);
+                if (keep_min ? lt : gt) {
+                    k[e] = y;
+                    if (PAIRS) ix[e] = iy;
+                }
+            }
+        }
+#pragma unroll
+        for (int jj = E / 2; jj > 0; jj >>= 1) {  // partner in the same thread
+            if (jj <= j) {
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    if ((e & jj) == 0) {
+                        const int f = e | jj;
+                        const bool up = ((t * E + e) & kk) == 0;
+                        const bool gt = k[e] > k[f] || (PAIRS && k[e] == k[f] && ix[e] > ix[f]);
+                        if (gt == up) {
+                            uint64_t tmp = k[e]; k[e] = k[f]; k[f] = tmp;
+                            if (PAIRS) { uint32_t u = ix[e]; ix[e] = ix[f]; ix[f] = u; }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // ===========================================================================
 // Model views in LDS
 // ===========================================================================

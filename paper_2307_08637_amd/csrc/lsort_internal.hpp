@@ -103,7 +103,7 @@ struct LevelStats {
 struct Ctl {
     uint32_t nseg[MAXL + 1];        // segments at each level
     uint32_t ntile[MAXL + 1];       // tiles at each level
-    uint32_t ticket[MAXL + 1];      // scatter tile tickets
+    uint32_t ticket[MAXL + 1];      // scatter unit tickets
     uint32_t pad0;
     unsigned long long nitems;      // small base-case items (<= SMALL_MAX keys)
     unsigned long long nbig;        // large base-case items and copy items

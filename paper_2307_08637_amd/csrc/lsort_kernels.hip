@@ -223,6 +223,26 @@ __device__ void fit_rmi_block(const uint64_t* smp, uint32_t S, int u64, uint32_t
     }
 }
 
+// Gather sample k -> element k of the sort (padding with the largest key),
+// sort M_THREADS * E of them in registers, leave the result in smp[].
+template <int E>
+__device__ void sample_sort(uint64_t* smp, const uint64_t* src, uint64_t off, uint64_t n, uint32_t S, uint64_t seed,
+                            int u64) {
+    uint64_t k[E];
+    uint32_t ix[E];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const uint32_t i = t * E + e;
+        k[e] = i < S ? key_ord(src[off + sample_index(seed, i, n)], u64) : ~0ull;
+        ix[e] = 0;
+    }
+    block_bitonic<M_THREADS, E, false>(k, ix, smp, nullptr);
+#pragma unroll
+    for (int e = 0; e < E; e++) smp[t * E + e] = k[e];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
     __shared__ uint64_t smp[S_LDS];
     __shared__ uint32_t lstart[L_MAX + 1];
@@ -274,10 +294,12 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             uint32_t S = (uint32_t)min<uint64_t>(S_LDS, max<uint64_t>(want, max<uint64_t>(floor_s, 2)));
             uint32_t P2 = 1u << ceil_log2(S);
             const uint64_t sseed = splitmix64_at(P.seed, (sg.off << 6) | (uint64_t)lvl);
-            for (uint32_t k = tid; k < P2; k += M_THREADS)
-                smp[k] = k < S ? key_ord(src[sg.off + sample_index(sseed, k, n)], u64) : ~0ull;
-            __syncthreads();
-            bitonic_keys<M_THREADS>(smp, P2);
+            // gather and sort in registers; the sorted sample lands in smp[]
+            if (P2 <= 1024) sample_sort<1>(smp, src, sg.off, n, S, sseed, u64);
+            else if (P2 <= 2048) sample_sort<2>(smp, src, sg.off, n, S, sseed, u64);
+            else if (P2 <= 4096) sample_sort<4>(smp, src, sg.off, n, S, sseed, u64);
+            else if (P2 <= 8192) sample_sort<8>(smp, src, sg.off, n, S, sseed, u64);
+            else sample_sort<16>(smp, src, sg.off, n, S, sseed, u64);
             // duplicates and finiteness (Alg. 5; Sec. 4: more than 10% duplicates -> tree)
             uint64_t dup = 0;
             for (uint32_t j = 1 + tid; j < S; j += M_THREADS) dup += smp[j] == smp[j - 1];
@@ -903,13 +925,48 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
 
 constexpr int BIG_THREADS = 512;
 
+// One sub-array of 513..4096 keys: gather into registers (BIG_THREADS * E
+// elements, padded with the largest key), block_bitonic, write back.  The
+// payload follows through the sorted local index, read before any write.
+template <int E>
+__device__ void base_big_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, uint64_t* sk, uint32_t* si) {
+    const uint64_t* in = P.keys[srcb];
+    uint64_t* out = P.keys[0];
+    const int t = threadIdx.x, u64 = P.u64;
+    uint64_t k[E];
+    uint32_t ix[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const uint32_t i = t * E + e;
+        k[e] = i < size ? key_ord(in[off + i], u64) : ~0ull;
+        ix[e] = i;
+    }
+    if (P.has_pay) {
+        block_bitonic<BIG_THREADS, E, true>(k, ix, sk, si);
+        const uint32_t* pin = P.pay[srcb];
+        uint32_t* pout = P.pay[0];
+        uint32_t pv[E];
+#pragma unroll
+        for (int e = 0; e < E; e++) pv[e] = t * E + e < size ? pin[off + ix[e]] : 0u;
+        __syncthreads();  // every payload read of this sub-array happens before any write
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            if (t * E + e < size) pout[off + t * E + e] = pv[e];
+    } else {
+        block_bitonic<BIG_THREADS, E, false>(k, ix, sk, si);
+    }
+#pragma unroll
+    for (int e = 0; e < E; e++)
+        if (t * E + e < size) out[off + t * E + e] = key_unord(k[e], u64);
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(BIG_THREADS) void k_base_big(Params P) {
     __shared__ uint64_t sk[C_MAX];
-    __shared__ uint16_t si[C_MAX];
-    __shared__ uint32_t sp[C_MAX];
+    __shared__ uint32_t si[C_MAX];
     const int tid = threadIdx.x;
     const uint64_t nitems = min<unsigned long long>(P.ctl->nbig, P.big_cap);
-    const int u64 = P.u64, has_pay = P.has_pay;
+    const int has_pay = P.has_pay;
     uint64_t* out = P.keys[0];
     uint32_t* pout = P.pay[0];
     for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -927,22 +984,9 @@ __global__ __launch_bounds__(BIG_THREADS) void k_base_big(Params P) {
                 }
             continue;
         }
-        const uint32_t P2 = 1u << ceil_log2(size);
-        for (uint32_t i = tid; i < P2; i += BIG_THREADS) {
-            sk[i] = i < size ? key_ord(in[off + i], u64) : ~0ull;
-            if (has_pay) {
-                si[i] = (uint16_t)i;
-                if (i < size) sp[i] = pin[off + i];
-            }
-        }
-        __syncthreads();
-        if (has_pay) bitonic_pairs<BIG_THREADS>(sk, si, P2);
-        else bitonic_keys<BIG_THREADS>(sk, P2);
-        for (uint32_t i = tid; i < size; i += BIG_THREADS) {
-            out[off + i] = key_unord(sk[i], u64);
-            if (has_pay) pout[off + i] = sp[si[i]];
-        }
-        __syncthreads();
+        if (size <= 1024) base_big_item<2>(P, off, size, srcb, sk, si);
+        else if (size <= 2048) base_big_item<4>(P, off, size, srcb, sk, si);
+        else base_big_item<8>(P, off, size, srcb, sk, si);
     }
 }
 
