@@ -77,6 +77,12 @@ def lib():
             "orc_splitter_buckets": (None, [vp, vp, u32, vp, u64, i32, vp]),
             "orc_radix_buckets": (None, [vp, u32, vp, u64, i32, vp]),
             "orc_mlp_buckets": (None, [vp, dbl, dbl, u32, vp, u64, i32, vp]),
+            "orc_mlp_init": (None, [vp, u64, dbl, vp]),
+            "orc_mlp_inputs": (None, [vp, u64, i32, dbl, dbl, vp]),
+            "orc_mlp_leaf": (u32, [vp, dbl, dbl, u32, dbl]),
+            "orc_mlp_rmi_fit": (None, [vp, u64, vp, dbl, dbl, u32, dbl, vp, vp, vp]),
+            "orc_mlp_rmi_bucket": (u32, [vp, dbl, dbl, vp, u32, dbl, u64, i32]),
+            "orc_mlp_rmi_buckets": (None, [vp, dbl, dbl, vp, u32, dbl, vp, u64, i32, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -292,6 +298,78 @@ def mlp_buckets(w: np.ndarray, lo: float, inv: float, R: int, keys: np.ndarray) 
     lib().orc_mlp_buckets(_p(ww), lo, inv, R, _p(r), r.size, dt, _p(out))
     return out
 
+
+
+def mlp_init(t_sorted: np.ndarray, eps: float = 1e-3) -> np.ndarray:
+    """Data-dependent start point (piecewise-linear interpolant of the sample
+    CDF through its octiles, plus eps-sized trainable weights)."""
+    t = np.ascontiguousarray(t_sorted, dtype=np.float64)
+    p = np.empty(MLP_NP)
+    lib().orc_mlp_init(_p(t), t.size, float(eps), _p(p))
+    return p
+
+
+def mlp_inputs(keys: np.ndarray, lo: float, inv: float) -> np.ndarray:
+    r = raw_bits(keys)
+    out = np.empty(r.size, dtype=np.float32)
+    lib().orc_mlp_inputs(_p(r), r.size, dtype_code(keys), lo, inv, _p(out))
+    return out
+
+
+def mlp_lo_inv(sorted_keys: np.ndarray):
+    """(lo, inv) of the model input from a sorted sample: smallest key and
+    1 / (largest - smallest), or inv = 0 when they are equal."""
+    x = model_x(sorted_keys[[0, -1]])
+    return float(x[0]), (1.0 / (x[1] - x[0]) if x[1] > x[0] else 0.0)
+
+
+def effective(params: np.ndarray) -> np.ndarray:
+    """fp32 effective weights |V| with the biases as they are."""
+    p = np.array(params, dtype=np.float64)
+    for a, b in ((0, 16), (32, 288), (304, 320)):
+        p[a:b] = np.abs(p[a:b])
+    return p.astype(np.float32)
+
+
+def mlp_train(t: np.ndarray, y: np.ndarray, p0: np.ndarray, steps: int, lr: float):
+    """Full-batch Adam on the mean squared error, fp64: returns the
+    parameters after `steps` steps and the loss before each step."""
+    p = np.array(p0, dtype=np.float64)
+    m = np.zeros(MLP_NP)
+    v = np.zeros(MLP_NP)
+    losses = []
+    for k in range(1, steps + 1):
+        loss, g = mlp_loss_grad(p, t, y)
+        losses.append(loss)
+        p, m, v = adam_step(p, m, v, g, k, lr=lr)
+    return p, np.array(losses)
+
+
+def mlp_leaf(w: np.ndarray, lo: float, inv: float, L: int, x: float) -> int:
+    ww = np.ascontiguousarray(w, dtype=np.float32)
+    return lib().orc_mlp_leaf(_p(ww), lo, inv, L, float(x))
+
+
+def mlp_rmi_fit(sorted_x: np.ndarray, w: np.ndarray, lo: float, inv: float, L: int, R: float):
+    """Leaves of the two-level model whose root is the MLP: (raw[4L],
+    scaled[4L], counts[L])."""
+    x = np.ascontiguousarray(sorted_x, dtype=np.float64)
+    ww = np.ascontiguousarray(w, dtype=np.float32)
+    raw = np.empty(4 * L)
+    scaled = np.empty(4 * L)
+    counts = np.empty(L, dtype=np.uint64)
+    lib().orc_mlp_rmi_fit(_p(x), x.size, _p(ww), lo, inv, L, float(R), _p(raw), _p(scaled), _p(counts))
+    return raw, scaled, counts
+
+
+def mlp_rmi_buckets(w: np.ndarray, lo: float, inv: float, scaled: np.ndarray, L: int, R: float,
+                    keys: np.ndarray) -> np.ndarray:
+    ww = np.ascontiguousarray(w, dtype=np.float32)
+    q = np.ascontiguousarray(scaled, dtype=np.float64)
+    r = raw_bits(keys)
+    out = np.empty(r.size, dtype=np.uint32)
+    lib().orc_mlp_rmi_buckets(_p(ww), lo, inv, _p(q), L, float(R), _p(r), r.size, dtype_code(keys), _p(out))
+    return out
 
 # -- 10. pivots ------------------------------------------------------------------------------
 

@@ -23,8 +23,10 @@
  *   6. splitter tree with equality buckets (Sec. 2.4 SampleSort, equality buckets)
  *   7. range-radix bucket (depth cap)      (Sec. 2.4 IPS2Ra MSD radix idea)
  *   8. one partition level                 (Sec. 2.2 partitioning into buckets)
- *   9. monotone FP32 MLP CDF: fp64 forward/backward, Adam, fp32 inference
- *                                          (Sec. 3.1 CDF-model properties)
+ *   9. monotone FP32 MLP CDF: fp64 forward/backward, Adam, start point,
+ *      fp32 inference, and the MLP as the root of a two-level model
+ *                                          (Sec. 3.1 CDF-model properties;
+ *                                           Sec. 2.1 RMI stages)
  *  10. pivot quality and implicit pivots   (Sec. 3.3 Alg. 4; Sec. 3.4 Table 1 metric)
  *
  * parity unpinned: none of the functions below lacks a pin; see the tests.
@@ -262,22 +264,21 @@ uint32_t orc_rmi_leaf(double alpha_r, double beta_r, uint32_t L, double x)
  *                   the parameters orc_rmi_bucket evaluates at total
  *                   resolution R.
  *   counts[L]     : sample points per leaf. */
-void orc_rmi_fit(const double *x, uint64_t S, uint32_t L, double R, const double *root_in,
-                 double *raw, double *scaled, uint64_t *counts)
-{
-    long double ar, br;
-    lsq_line(x, 0, S, S, &ar, &br);
-    double alpha_r = (double)((long double)L * ar);
-    double beta_r = (double)((long double)L * br);
-    if (root_in) { alpha_r = root_in[0]; beta_r = root_in[1]; }
-    if (raw) { raw[0] = (double)ar; raw[1] = (double)br; }
-    if (scaled) { scaled[0] = alpha_r; scaled[1] = beta_r; }
+/* Leaf lines of a two-level model over a sorted sample, for any
+ * non-decreasing root: leaf_of(ctx, x) gives the leaf of sample point x, so
+ * the points of leaf j form one contiguous run.  Each run gets its
+ * least-squares line (targets i/S) and the monotone clamp chain above;
+ * outputs as for orc_rmi_fit, leaf part only (4 entries per leaf). */
+typedef uint32_t (*leaf_fn)(const void *ctx, double x);
 
+static void fit_leaves(const double *x, uint64_t S, uint32_t L, double R, leaf_fn leaf_of, const void *ctx,
+                       double *raw, double *scaled, uint64_t *counts)
+{
     uint64_t lo = 0;
     double dprev = 0.0;
     for (uint32_t j = 0; j < L; j++) {
         uint64_t hi = lo;
-        while (hi < S && orc_rmi_leaf(alpha_r, beta_r, L, x[hi]) == j) hi++;
+        while (hi < S && leaf_of(ctx, x[hi]) == j) hi++;
         long double a = 0, b;
         double c, d;
         if (hi == lo) {
@@ -292,18 +293,40 @@ void orc_rmi_fit(const double *x, uint64_t S, uint32_t L, double R, const double
             long double dd = pmax > c ? pmax : c;
             d = clip01(dd);
         }
-        if (raw) { raw[2 + 4 * j] = (double)a; raw[3 + 4 * j] = (double)b; raw[4 + 4 * j] = c; raw[5 + 4 * j] = d; }
+        if (raw) { raw[4 * j] = (double)a; raw[1 + 4 * j] = (double)b; raw[2 + 4 * j] = c; raw[3 + 4 * j] = d; }
         if (scaled) {
             long double Rl = R;
-            scaled[2 + 4 * j] = (double)(Rl * a);
-            scaled[3 + 4 * j] = (double)(Rl * b);
-            scaled[4 + 4 * j] = (double)(Rl * (long double)c);
-            scaled[5 + 4 * j] = (double)(Rl * (long double)d);
+            scaled[4 * j] = (double)(Rl * a);
+            scaled[1 + 4 * j] = (double)(Rl * b);
+            scaled[2 + 4 * j] = (double)(Rl * (long double)c);
+            scaled[3 + 4 * j] = (double)(Rl * (long double)d);
         }
         if (counts) counts[j] = hi - lo;
         dprev = d;
         lo = hi;
     }
+}
+
+struct linear_root { double alpha_r, beta_r; uint32_t L; };
+
+static uint32_t linear_leaf(const void *ctx, double x)
+{
+    const struct linear_root *r = (const struct linear_root *)ctx;
+    return orc_rmi_leaf(r->alpha_r, r->beta_r, r->L, x);
+}
+
+void orc_rmi_fit(const double *x, uint64_t S, uint32_t L, double R, const double *root_in,
+                 double *raw, double *scaled, uint64_t *counts)
+{
+    long double ar, br;
+    lsq_line(x, 0, S, S, &ar, &br);
+    double alpha_r = (double)((long double)L * ar);
+    double beta_r = (double)((long double)L * br);
+    if (root_in) { alpha_r = root_in[0]; beta_r = root_in[1]; }
+    if (raw) { raw[0] = (double)ar; raw[1] = (double)br; }
+    if (scaled) { scaled[0] = alpha_r; scaled[1] = beta_r; }
+    struct linear_root root = {alpha_r, beta_r, L};
+    fit_leaves(x, S, L, R, linear_leaf, &root, raw ? raw + 2 : NULL, scaled ? scaled + 2 : NULL, counts);
 }
 
 /* Bucket of a key at total resolution R (Sec. 2.2: b = floor(B * F(x));
@@ -571,6 +594,112 @@ uint32_t orc_mlp_bucket(const float *w, double lo, double inv, uint32_t R, uint6
     float g = floorf(F * (float)R);
     g = fminf(g, (float)R - 1.0f);
     return (uint32_t)g;
+}
+
+/* Data-dependent starting point of training.  With knots k_m = t[floor(mS/8)]
+ * (m = 0..7) and k_8 = t[S-1] of the sorted inputs, widths
+ * w_m = max(k_{m+1} - k_m, 1e-6):
+ *   layer 1, units m = 0..7 (max):   V = 1 / w_m, b = -k_m / w_m, so
+ *                                     h = max((t - k_m) / w_m, 0);
+ *   layer 1, units 8 + m (min):       V = 1, b = -(m + 0.5) / 8;
+ *   layer 2, unit 8 + m (min):        V[8+m][m] = 1, b = -1, so
+ *                                     h = min(h_m, 1) - 1;
+ *   every other layer-2 weight:       eps / max(1, |V1_k| + |b1_k|) (column k),
+ *                                     biases of units 0..7 zero;
+ *   output:                           V3 = eps (units 0..7), 1/8 (units 8..15), b3 = 1.
+ * With eps = 0 the network is exactly sum_m min(max((t - k_m) / w_m, 0), 1) / 8,
+ * the piecewise-linear interpolant of the sample CDF through (k_m, m / 8);
+ * eps > 0 keeps the other weights trainable (the gradient of |V| vanishes at
+ * V = 0).  fp64 throughout; the GPU rounds the same values to fp32. */
+void orc_mlp_init(const double *t, uint64_t S, double eps, double *p)
+{
+    double M[MLP_H];
+    for (int m = 0; m < MLP_HALF; m++) {
+        double k = t[(uint64_t)m * S / 8];
+        double kn = m == MLP_HALF - 1 ? t[S - 1] : t[(uint64_t)(m + 1) * S / 8];
+        double w = kn - k;
+        if (w < 1e-6) w = 1e-6;
+        p[OFF_V1 + m] = 1.0 / w;
+        p[OFF_B1 + m] = -k / w;
+        p[OFF_V1 + MLP_HALF + m] = 1.0;
+        p[OFF_B1 + MLP_HALF + m] = -((double)m + 0.5) / 8.0;
+    }
+    for (int k = 0; k < MLP_H; k++) {
+        double bound = fabs(p[OFF_V1 + k]) + fabs(p[OFF_B1 + k]);
+        M[k] = bound > 1.0 ? bound : 1.0;
+    }
+    for (int i = 0; i < MLP_H; i++)
+        for (int k = 0; k < MLP_H; k++)
+            p[OFF_V2 + MLP_H * i + k] = (i >= MLP_HALF && k == i - MLP_HALF) ? 1.0 : eps / M[k];
+    for (int i = 0; i < MLP_H; i++) {
+        p[OFF_B2 + i] = i < MLP_HALF ? 0.0 : -1.0;
+        p[OFF_V3 + i] = i < MLP_HALF ? eps : 1.0 / 8.0;
+    }
+    p[OFF_B3] = 1.0;
+}
+
+void orc_mlp_inputs(const uint64_t *raw, uint64_t n, int dtype, double lo, double inv, float *t)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        double x;
+        orc_model_x(raw[i], dtype, &x);
+        t[i] = orc_mlp_input(x, lo, inv);
+    }
+}
+
+/* The MLP as the first stage of a two-level model (Sec. 2.1 RMI with a
+ * non-linear root): leaf j = min(floor(F * L), L - 1) in fp32, F the clamped
+ * network output; leaves are the monotone linear lines of orc_rmi_fit.
+ * Because F is non-decreasing, so is j, and the clamp chain keeps the whole
+ * model monotone (Sec. 4). */
+struct mlp_root { const float *w; double lo, inv; uint32_t L; };
+
+uint32_t orc_mlp_leaf(const float *w, double lo, double inv, uint32_t L, double x)
+{
+    float F = orc_mlp_eval_f32(w, orc_mlp_input(x, lo, inv));
+    float j = floorf(F * (float)L);
+    j = fminf(j, (float)L - 1.0f);
+    return (uint32_t)j;
+}
+
+static uint32_t mlp_leaf_fn(const void *ctx, double x)
+{
+    const struct mlp_root *r = (const struct mlp_root *)ctx;
+    return orc_mlp_leaf(r->w, r->lo, r->inv, r->L, x);
+}
+
+/* Leaf fit under an MLP root on a sorted sample of model inputs x[0..S):
+ * scaled[4L] = R * (a_j, b_j, c_j, d_j) as orc_rmi_fit. */
+void orc_mlp_rmi_fit(const double *x, uint64_t S, const float *w, double lo, double inv, uint32_t L, double R,
+                     double *raw, double *scaled, uint64_t *counts)
+{
+    struct mlp_root root = {w, lo, inv, L};
+    fit_leaves(x, S, L, R, mlp_leaf_fn, &root, raw, scaled, counts);
+}
+
+/* Bucket at total resolution R: j from the MLP, then
+ * t = clamp(fma(alpha_j, x, beta_j), gamma_j, delta_j), g = clamp(floor(t), 0, R-1);
+ * non-finite keys as for the RMI. */
+uint32_t orc_mlp_rmi_bucket(const float *w, double lo, double inv, const double *scaled, uint32_t L, double R,
+                            uint64_t raw, int dtype)
+{
+    double x;
+    int nf = orc_model_x(raw, dtype, &x);
+    if (nf < 0) return 0;
+    if (nf > 0) return (uint32_t)(R - 1.0);
+    uint32_t j = orc_mlp_leaf(w, lo, inv, L, x);
+    const double *q = scaled + 4 * (uint64_t)j;
+    double t = fma(q[0], x, q[1]);
+    t = fmin(fmax(t, q[2]), q[3]);
+    double g = floor(t);
+    g = fmin(fmax(g, 0.0), R - 1.0);
+    return (uint32_t)g;
+}
+
+void orc_mlp_rmi_buckets(const float *w, double lo, double inv, const double *scaled, uint32_t L, double R,
+                         const uint64_t *raw, uint64_t n, int dtype, uint32_t *out)
+{
+    for (uint64_t i = 0; i < n; i++) out[i] = orc_mlp_rmi_bucket(w, lo, inv, scaled, L, R, raw[i], dtype);
 }
 
 /* ------------------------------------------------------------------------ */

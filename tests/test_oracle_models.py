@@ -349,6 +349,135 @@ def test_adam_closed_form():
         assert np.allclose(p, p0 - k * step, rtol=1e-12, atol=1e-15)
 
 
+
+@pytest.mark.parametrize("law", ["uniform", "normal", "lognormal", "exponential"])
+def test_mlp_init_is_the_octile_interpolant(law):
+    """With eps = 0 the start point is the piecewise-linear interpolant of the
+    sample CDF through (k_m, m/8): exact at every knot, linear in between,
+    flat at 1 beyond the last knot.  Checked with an independent numpy
+    interpolation (np.interp)."""
+    S = 4096
+    t = np.sort(oracle.mlp_inputs(oracle.sort(inputs.generate(law, S, seed=9))[0], 0.0, 1.0).astype(np.float64))
+    if law != "uniform":  # map onto [0, 1] the way the model input does
+        s = oracle.sort(inputs.generate(law, S, seed=9))[0]
+        lo, inv = oracle.mlp_lo_inv(s)
+        t = oracle.mlp_inputs(s, lo, inv).astype(np.float64)
+    p = oracle.mlp_init(t, eps=0.0)
+    knots = [t[m * S // 8] for m in range(8)] + [t[-1]]
+    assert min(np.diff(knots)) >= 1e-6  # no segment narrow enough to be widened
+    probe = np.unique(np.concatenate([knots, np.linspace(0, 1, 101), (np.array(knots[:-1]) + knots[1:]) / 2]))
+    for q in probe:
+        f = oracle.mlp_forward(p, float(q))
+        seg = [m for m in range(8) if knots[m] <= q <= knots[m + 1]]
+        if q >= knots[-1]:
+            assert f == pytest.approx(1.0, abs=1e-12)
+        elif seg:
+            m = seg[0]
+            want = m / 8 + (q - knots[m]) / (knots[m + 1] - knots[m]) / 8
+            assert f == pytest.approx(want, abs=1e-9), (q, m)
+    # with the default eps the start point stays within 2% of the interpolant
+    pe = oracle.mlp_init(t, eps=1e-3)
+    for q in knots:
+        assert abs(oracle.mlp_forward(pe, float(q)) - oracle.mlp_forward(p, float(q))) < 0.02
+
+
+def mlp_root_case(law, S=20_000, L=200, seed=3, steps=0):
+    s = oracle.sort(inputs.generate(law, S, seed=seed))[0]
+    x = oracle.model_x(s)
+    lo, inv = oracle.mlp_lo_inv(s)
+    t = oracle.mlp_inputs(s, lo, inv).astype(np.float64)
+    p = oracle.mlp_init(t)
+    if steps:
+        p, _ = oracle.mlp_train(t[::20], np.arange(0, S, 20) / S, p, steps, 3e-3)
+    return s, x, lo, inv, oracle.effective(p)
+
+
+@pytest.mark.parametrize("law", ["uniform", "lognormal", "piecewise"])
+def test_mlp_root_leaves_match_polyfit_and_counting(law):
+    """Leaves under the MLP root: every leaf's line is the least-squares line
+    of its run (numpy polyfit), the runs are exactly the points the root sends
+    to each leaf (direct count), and the clamp chain is non-decreasing."""
+    S, L, R = 20_000, 200, 1000.0
+    s, x, lo, inv, w = mlp_root_case(law, S, L)
+    raw, sc, counts = oracle.mlp_rmi_fit(x, w, lo, inv, L, R)
+    leaves = np.array([oracle.mlp_leaf(w, lo, inv, L, v) for v in x])
+    assert np.all(np.diff(leaves) >= 0)
+    assert np.array_equal(np.bincount(leaves, minlength=L), counts)
+    q = raw.reshape(L, 4)
+    chain = q[:, 2:].ravel()
+    assert np.all(np.diff(chain) >= 0) and chain[0] >= 0 and chain[-1] <= 1
+    y = np.arange(S) / S
+    start = 0
+    for j in range(L):
+        k = int(counts[j])
+        if k >= 3 and np.ptp(x[start:start + k]) > 0:
+            xs = x[start:start + k]
+            sa, sb = np.polyfit(xs - xs.mean(), y[start:start + k], 1)
+            assert q[j, 0] == pytest.approx(max(sa, 0.0), rel=1e-6, abs=1e-12 / max(np.ptp(xs), 1e-300))
+        start += k
+    assert np.allclose(sc, R * raw, rtol=1e-15, atol=0)
+
+
+def test_mlp_root_arithmetic_progression_closed_form():
+    """x_i = i with targets i/S is a line: whatever monotone root splits it,
+    every leaf with two or more points fits slope 1/S and intercept 0."""
+    S, L = 5000, 64
+    x = np.arange(S, dtype=np.float64)
+    lo, inv = 0.0, 1.0 / (S - 1)
+    t = oracle.mlp_inputs(x, lo, inv).astype(np.float64)
+    w = oracle.effective(oracle.mlp_init(t))
+    raw, _, counts = oracle.mlp_rmi_fit(x, w, lo, inv, L, 1000.0)
+    q = raw.reshape(L, 4)
+    for j in np.flatnonzero(counts >= 2):
+        assert q[j, 0] == pytest.approx(1.0 / S, rel=1e-12)
+        assert abs(q[j, 1]) < 1e-12
+
+
+@pytest.mark.parametrize("law", ["normal", "piecewise", "mixgauss"])
+def test_mlp_root_buckets_monotone_and_alg4(law):
+    """Sec. 3.1 / Alg. 4 on the MLP-root model: bucket ids are non-decreasing
+    along the sorted keys, and every key's bucket is the first bucket whose
+    implicit pivot (largest key in it) is not below the key."""
+    n, R = 30_000, 1000.0
+    s, x, lo, inv, w = mlp_root_case(law, 3000, 100, seed=6)
+    _, sc, _ = oracle.mlp_rmi_fit(x, w, lo, inv, 100, R)
+    keys = inputs.generate(law, n, seed=7)
+    srt = oracle.sort(keys)[0]
+    b = oracle.mlp_rmi_buckets(w, lo, inv, sc, 100, R, srt).astype(np.int64)
+    assert np.all(np.diff(b) >= 0) and b.max() < R
+    piv, has = oracle.implicit_pivots(srt, b.astype(np.uint32), int(R))
+    ords = oracle.ord_keys(srt)
+    nz = np.flatnonzero(has)
+    first = nz[np.searchsorted(piv[nz], ords, side="left")]
+    assert np.array_equal(first, b)
+
+
+def test_mlp_root_gain_over_linear_root_on_piecewise():
+    """What the learned root buys on the 70/20/10 piecewise law (three
+    clusters over seven orders of magnitude): the linear root sends most keys
+    to a few leaves, the MLP root (octile start point, 200 Adam steps) spreads
+    them, so the largest of 1000 buckets shrinks severalfold; training also
+    beats the untrained start point."""
+    n, S, L, R = 400_000, 20_000, 1000, 1000.0
+    keys = inputs.generate("piecewise", n, seed=8)
+    s = oracle.sort(oracle.sample(keys, 5, S))[0]
+    x = oracle.model_x(s)
+    lo, inv = oracle.mlp_lo_inv(s)
+    t = oracle.mlp_inputs(s, lo, inv).astype(np.float64)
+    p, losses = oracle.mlp_train(t[::4], np.arange(0, S, 4) / S, oracle.mlp_init(t), 200, 3e-3)
+    assert losses[-1] < losses[0]
+    w = oracle.effective(p)
+    _, sc_m, _ = oracle.mlp_rmi_fit(x, w, lo, inv, L, R)
+    _, sc_r, _ = oracle.rmi_fit(x, L, R)
+    mx = lambda b: np.bincount(b.astype(np.int64), minlength=int(R)).max() / (n / R)  # noqa: E731
+    mlp_ratio = mx(oracle.mlp_rmi_buckets(w, lo, inv, sc_m, L, R, keys))
+    rmi_ratio = mx(oracle.rmi_buckets(sc_r, L, R, keys))
+    assert mlp_ratio * 2 < rmi_ratio, (mlp_ratio, rmi_ratio)
+    w0 = oracle.effective(oracle.mlp_init(t))
+    _, sc_0, _ = oracle.mlp_rmi_fit(x, w0, lo, inv, L, R)
+    init_ratio = mx(oracle.mlp_rmi_buckets(w0, lo, inv, sc_0, L, R, keys))
+    assert mlp_ratio < init_ratio, (mlp_ratio, init_ratio)
+
 # -- pivot quality (Sec. 3.4, Table 1) ------------------------------------------------------
 
 def test_pivot_quality_learned_beats_random_uniform():
