@@ -7,8 +7,9 @@
  * prefix-summed and scattered; large buckets recurse, buckets whose keys are
  * all equal stop (Sec. 2.2 homogeneity check; Sec. 2.4 equality buckets) and
  * small ones get a base-case sort (Sec. 4).  The model is a monotone
- * two-level linear RMI (Sec. 2.1; monotone constraint of Sec. 4), an optional
- * monotone FP32 MLP, or -- when the input is small or duplicate-heavy (Alg. 5)
+ * two-level linear RMI (Sec. 2.1; monotone constraint of Sec. 4), optionally
+ * with a monotone FP32 MLP as its root, or -- when the input is small or
+ * duplicate-heavy (Alg. 5)
  * and whenever a bucket comes out more than twice its expected size -- a
  * splitter tree (Sec. 2.4).
  *
@@ -54,7 +55,9 @@ typedef enum {
 typedef enum {
     LS_MODEL_AUTO = 0,     /* RMI if n >= 1e5 and <= 10% sample duplicates, else splitter tree */
     LS_MODEL_RMI = 1,      /* same as AUTO (the policy may still pick the tree) */
-    LS_MODEL_MLP = 2,      /* monotone 1-16-16-1 FP32 MLP CDF trained on the GPU (single-array sort only) */
+    LS_MODEL_MLP = 2,      /* first level: two-level model whose root is a monotone 1-16-16-1 FP32 MLP
+                              trained on the GPU, with linear leaves; deeper levels as AUTO.  Single
+                              arrays of n >= 1e5 keys (smaller ones sort as AUTO) */
     LS_MODEL_SPLITTER = 3  /* classic SampleSort: splitter tree at every level */
 } ls_model;
 
@@ -80,9 +83,10 @@ typedef struct {
     double sample_frac;      /* sample size as a fraction of n; default 0.01 (Sec. 2.2) */
     double fallback_ratio;   /* oversized bucket threshold, x expected; default 2.0 */
     uint64_t seed;           /* sampling seed; default 0x5EED */
-    uint32_t mlp_steps;      /* MLP Adam steps; default 200 */
-    uint32_t mlp_sample;     /* MLP training sample; default 1e6 (capped at n) */
-    float mlp_lr;            /* MLP Adam learning rate; default 1e-2 */
+    uint32_t mlp_steps;      /* MLP Adam steps; default 200; at most 100000 */
+    uint32_t mlp_sample;     /* MLP training-set size: every k-th point of the sorted sample so that at
+                                most this many remain; default 1e6 */
+    float mlp_lr;            /* MLP Adam learning rate; default 3e-3 */
     uint32_t reserved[5];
 } ls_options;
 
@@ -233,33 +237,62 @@ ls_status ls_partition_splitters(const void *keys, const uint32_t *payload, uint
                                  void *out_keys, uint32_t *out_payload, uint64_t *counts, void *stream);
 
 /* ---- Monotone MLP CDF (1-16-16-1, FP32) ----------------------------------- */
-/* Parameter vector: 321 floats V1[16] b1[16] V2[16x16] b2[16] V3[16] b3[1];
- * effective weights |V|; hidden units 0..7 use max(z,0), 8..15 use min(z,0);
- * so the network is non-decreasing in its input (Sec. 3.1 monotone CDF).
- * Input t = clamp((x - lo) * inv, 0, 1) in fp64 rounded to fp32. */
+/* Parameter vector: 321 floats V1[16] b1[16] V2[16x16] (row = output unit)
+ * b2[16] V3[16] b3[1]; effective weights |V|; hidden units 0..7 use
+ * max(z,0), 8..15 use min(z,0); so the network is non-decreasing in its
+ * input (Sec. 3.1 monotone CDF).  Input t = clamp((x - lo) * inv, 0, 1) in
+ * fp64 rounded to fp32, with lo_inv = {lo, inv} (device double[2]) taken
+ * from a sorted sample: lo = smallest key, inv = 1 / (largest - smallest).
+ * Every function here runs on the GPU; all pointers are device pointers. */
 
 /* Mean squared error of the unclamped output against targets y and its
- * gradient over the 321 parameters, on the GPU in FP32 with a fixed-order
- * two-stage reduction.  t, y: device float[S].  params: device float[321].
- * grad: device float[321].  loss: device float[1]. */
+ * gradient over the 321 parameters, in FP32: per-sample terms summed in
+ * sample order within each of up to 256 workgroups, then the workgroup
+ * partials in workgroup order (deterministic).  t, y: float[S].  params:
+ * float[321].  grad: float[321] (nullable).  loss: float[1] (nullable; one
+ * of grad / loss required).  Errors: LS_EINVAL. */
 ls_status ls_mlp_loss_grad(const float *params, const float *t, const float *y, uint64_t S,
                            float *grad, float *loss, void *stream);
 
-/* Train on a SORTED sample (device, S keys): targets i/S, full-batch Adam
- * (Kingma & Ba 2015) for `steps` steps with learning rate lr, betas (0.9,
- * 0.999), eps 1e-8, from params_init (device float[321]) or, if NULL, a
- * seeded initialisation.  Writes the trained parameters to params_out
- * (device float[321]), lo and inv (device double[2]) and the loss after each
- * step to losses (device float[steps], nullable). */
+/* Train on a SORTED sample of S keys: t from the sample's own lo_inv
+ * (written to lo_inv), targets y_i = i / S, full-batch Adam (Kingma & Ba
+ * 2015; betas 0.9 / 0.999, eps 1e-8, learning rate lr) for `steps` steps
+ * from params_init (float[321]) or, if NULL, the start point that makes the
+ * network the piecewise-linear interpolant of the sample CDF through its
+ * octiles.  Adam runs on q = p / s: s = 1 / max(1, |V1_k| + |b1_k|) (at the
+ * start point) for the layer-2 weights of input unit k, 1 otherwise, so that
+ * no step moves a pre-activation by much more than lr.  The loss is evaluated at the start of every step; params_out
+ * (float[321]) receives the parameters with the lowest of those losses (the
+ * start point when steps == 0) and losses (float[steps], nullable) the
+ * losses.
+ * Errors: LS_EINVAL (S < 2, lr <= 0, steps > 100000, missing output). */
 ls_status ls_mlp_train(const void *sorted_sample, uint64_t S, ls_dtype dtype, const float *params_init,
-                       uint32_t steps, float lr, uint64_t seed, float *params_out, double *lo_inv,
-                       float *losses, void *stream);
+                       uint32_t steps, float lr, float *params_out, double *lo_inv, float *losses,
+                       void *stream);
 
-/* Bucket ids under a trained MLP: g = min(floor(F * R), R - 1) in fp32 with
- * F = clamp(net(t), 0, 1) evaluated as fmaf chains in index order.
- * lo_inv: device double[2].  out: device uint32[n]. */
+/* The network alone as a CDF: g = min(floor(F * R), R - 1) in fp32 with
+ * F = clamp(net(t), 0, 1), every product-sum an fmaf chain in index order;
+ * non-finite keys go to 0 (negative) or R - 1.  out: uint32[n].
+ * Errors: LS_EINVAL (R outside [1, 2^24]). */
 ls_status ls_mlp_buckets(const void *keys, uint64_t n, ls_dtype dtype, const float *params,
                          const double *lo_inv, uint32_t R, uint32_t *out, void *stream);
+
+/* Two-level model with the MLP as its root (Sec. 2.1 stages; the model
+ * LS_MODEL_MLP uses): leaf j = min(floor(F * L), L - 1) in fp32; leaves are
+ * the RMI's monotone least-squares lines (Sec. 2.1, Sec. 4).  Fits the L
+ * leaves on a SORTED sample and writes them pre-scaled by R as
+ * leaves[4L] = (alpha_j, beta_j, gamma_j, delta_j) (device doubles).
+ * Errors: LS_EINVAL. */
+ls_status ls_mlp_rmi_fit(const void *sorted_sample, uint64_t S, ls_dtype dtype, const float *params,
+                         const double *lo_inv, uint32_t L, double R, double *leaves, void *stream);
+
+/* Bucket ids at total resolution R under that model:
+ * g = clamp(floor(clamp(fma(alpha_j, x, beta_j), gamma_j, delta_j)), 0, R-1)
+ * with j from the network; non-finite keys as for the RMI.  out: uint32[n].
+ * Errors: LS_EINVAL. */
+ls_status ls_mlp_rmi_buckets(const void *keys, uint64_t n, ls_dtype dtype, const float *params,
+                             const double *lo_inv, const double *leaves, uint32_t L, double R,
+                             uint32_t *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -331,18 +331,46 @@ def effective(params: np.ndarray) -> np.ndarray:
     return p.astype(np.float32)
 
 
-def mlp_train(t: np.ndarray, y: np.ndarray, p0: np.ndarray, steps: int, lr: float):
-    """Full-batch Adam on the mean squared error, fp64: returns the
-    parameters after `steps` steps and the loss before each step."""
+def mlp_step_scale(p0: np.ndarray) -> np.ndarray:
+    """Optimiser step scale of each parameter: for a layer-2 weight of input
+    unit k, 1 / max(1, |V1_k| + |b1_k|) -- the bound of unit k's activation
+    on t in [0, 1] at the start point p0; 1 for every other parameter."""
+    p0 = np.asarray(p0, dtype=np.float64)
+    s = np.ones(MLP_NP)
+    bound = np.maximum(1.0, np.abs(p0[0:16]) + np.abs(p0[16:32]))
+    s[32:288] = np.tile(1.0 / bound, 16)
+    return s
+
+
+def mlp_train(t: np.ndarray, y: np.ndarray, p0: np.ndarray, steps: int, lr: float, final: bool = False):
+    """Full-batch training on the mean squared error, fp64: Adam (the pinned
+    adam_step) on q = p / s with s = mlp_step_scale(p0), so that p moves by
+    s times Adam's step.  The loss is taken at the start of each step;
+    returns the parameters with the lowest of those losses (the start point
+    if steps == 0) -- or, with final=True, the parameters after the last
+    step -- and the losses."""
     p = np.array(p0, dtype=np.float64)
+    sc = mlp_step_scale(p)
     m = np.zeros(MLP_NP)
     v = np.zeros(MLP_NP)
     losses = []
+    best, best_loss = p.copy(), np.inf
     for k in range(1, steps + 1):
         loss, g = mlp_loss_grad(p, t, y)
         losses.append(loss)
-        p, m, v = adam_step(p, m, v, g, k, lr=lr)
-    return p, np.array(losses)
+        if loss < best_loss:
+            best, best_loss = p.copy(), loss
+        q, m, v = adam_step(p / sc, m, v, g * sc, k, lr=lr)
+        p = q * sc
+    return (p if final else best), np.array(losses)
+
+
+def mlp_forward_full(params: np.ndarray, t: float):
+    """(output, z1, h1, z2, h2) of the fp64 forward pass."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    z1, h1, z2, h2 = (np.empty(16) for _ in range(4))
+    out = lib().orc_mlp_forward(_p(p), float(t), _p(z1), _p(h1), _p(z2), _p(h2))
+    return out, z1, h1, z2, h2
 
 
 def mlp_leaf(w: np.ndarray, lo: float, inv: float, L: int, x: float) -> int:

@@ -53,7 +53,7 @@ struct Opts {
 static ls_status normalize(const ls_options* o, Opts& r) {
     r.model = LS_MODEL_AUTO; r.buckets = 1000; r.leaves = 1000; r.tree_buckets = 256; r.cutoff = 512;
     r.max_levels = 16; r.flags = LS_FLAG_SYNC_LEVELS; r.sample_frac = 0.01; r.fallback_ratio = 2.0; r.seed = 0x5EED;
-    r.mlp_steps = 200; r.mlp_sample = 1000000; r.mlp_lr = 1e-2f;
+    r.mlp_steps = 200; r.mlp_sample = 1000000; r.mlp_lr = 3e-3f;
     if (!o) return LS_OK;
     if (o->struct_size != sizeof(ls_options)) return fail(LS_EINVAL, "ls_options.struct_size mismatch");
     if (o->model > LS_MODEL_SPLITTER) return fail(LS_EINVAL, "unknown model");
@@ -77,6 +77,7 @@ static ls_status normalize(const ls_options* o, Opts& r) {
     if (r.cutoff < 1 || r.cutoff > C_MAX) return fail(LS_EINVAL, "cutoff must be in [1, 4096]");
     if (r.max_levels < 1 || r.max_levels > MAXL - 9) return fail(LS_EINVAL, "max_levels must be in [1, 23]");
     if (r.sample_frac > 1.0) return fail(LS_EINVAL, "sample_frac must be in (0, 1]");
+    if (r.mlp_steps > 100000) return fail(LS_EINVAL, "mlp_steps must be at most 100000");
     return LS_OK;
 }
 
@@ -90,16 +91,49 @@ struct Layout {
     int has_pay;
     uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap;
     uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_bigs, o_counts, o_status,
-        o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested;
+        o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested, o_mlp, o_mlp_t, o_mlp_y;
     uint64_t S_big;       // large-path sample size (0: none)
+    uint64_t mlp_S;       // MLP training-set size (0: no MLP training)
+    uint64_t mlp_stride;  // training set = every mlp_stride-th point of the sorted sample
     uint64_t bytes;
     std::vector<Layout> nested;  // sorting the large-path sample
 };
 
+// The MLP-rooted model is built only on the large-array path, and there for
+// any array the policy could give a learned model (n >= 1e5).
+static bool mlp_first_level(uint64_t n, uint64_t m, const Opts& o) {
+    return o.model == LS_MODEL_MLP && m == 1 && n >= 100000;
+}
+
 static uint64_t big_sample_size(uint64_t n, uint64_t m, const Opts& o) {
     if (m != 1) return 0;
     uint64_t S = (uint64_t)std::ceil(o.sample_frac * (double)n);
+    if (mlp_first_level(n, m, o)) return std::min<uint64_t>(n, std::max<uint64_t>(S, 4096));
     return S > (uint64_t)S_LDS ? S : 0;
+}
+
+// Optimiser state of MLP training inside the workspace area o_mlp.
+struct MlpState {
+    float *p, *m, *v, *best, *scale, *partial, *best_loss;
+    unsigned int* done;
+    double* lo_inv;
+};
+constexpr uint64_t MLP_VEC_BYTES = 4ull * (MLP_NP + 3);  // 324 floats: 16-byte multiple
+constexpr uint64_t MLP_STATE_BYTES = 5 * MLP_VEC_BYTES + 4ull * MLP_G * MLP_ACC + 64;
+static MlpState mlp_state(uint8_t* base, const Layout& L) {
+    uint8_t* b = base + L.o_mlp;
+    const uint64_t tail = 5 * MLP_VEC_BYTES + 4ull * MLP_G * MLP_ACC;  // 8-byte aligned
+    MlpState s;
+    s.p = (float*)b;
+    s.m = (float*)(b + MLP_VEC_BYTES);
+    s.v = (float*)(b + 2 * MLP_VEC_BYTES);
+    s.best = (float*)(b + 3 * MLP_VEC_BYTES);
+    s.scale = (float*)(b + 4 * MLP_VEC_BYTES);
+    s.partial = (float*)(b + 5 * MLP_VEC_BYTES);
+    s.done = (unsigned int*)(b + tail);
+    s.best_loss = (float*)(b + tail + 4);
+    s.lo_inv = (double*)(b + tail + 16);
+    return s;
 }
 
 // Options of the engine run that sorts a large first level's sample.  The
@@ -144,15 +178,23 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.o_status = take(L.status_cap * 8);
     L.o_arena[0] = take(L.arena_cap);
     L.o_arena[1] = take(L.arena_cap);
-    L.o_bigmodel = take(8ull * MODEL_WORDS + 64);
+    L.o_bigmodel = take(8ull * std::max(MODEL_WORDS, MLP_MODEL_WORDS) + 64);
     L.o_part = take(FIT_G * 8 * 8);
     L.o_leaf = take(L_MAX * 8 * 8 + (L_MAX + 1) * 8);  // leaf lines, then leaf boundaries
     L.o_flag = take(256);
+    L.o_mlp = take(MLP_STATE_BYTES);
     L.S_big = big_sample_size(n, m, o);
     if (L.S_big) {
         L.o_sample = take(L.S_big * 8);
         L.nested.push_back(plan(L.S_big, 1, 0, nested_opts(o)));
         L.o_nested = take(L.nested[0].bytes);
+    }
+    if (L.S_big && mlp_first_level(n, m, o)) {
+        L.mlp_stride = std::max<uint64_t>(1, (L.S_big + o.mlp_sample - 1) / o.mlp_sample);
+        L.mlp_S = (L.S_big + L.mlp_stride - 1) / L.mlp_stride;
+        L.o_mlp_t = take(L.mlp_S * 4);
+        L.o_mlp_y = take(L.mlp_S * 4);
+        L.o_ids = take(n * 2);
     }
     L.bytes = o_;
     return L;
@@ -186,9 +228,12 @@ static thread_local LastCall g_last;
 // ---------------------------------------------------------------------------
 // optional kernel timing: an event pair around each launch
 // ---------------------------------------------------------------------------
-enum KernelId { KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_BASE_BIG, KI_GATHER, KI_FIT, KI_N };
+enum KernelId {
+    KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_BASE_BIG, KI_GATHER, KI_FIT, KI_MLP_TRAIN,
+    KI_MLP_IDS, KI_N
+};
 static const char* KNAME[KI_N] = {"k_reset", "k_seed", "k_model", "k_hist", "k_scan", "k_scatter", "k_base_small",
-                                  "k_base_big", "k_gather", "k_fit"};
+                                  "k_base_big", "k_gather", "k_fit", "k_mlp_step", "k_mlp_ids"};
 struct TRec {
     int kid;
     hipEvent_t a, b;
@@ -328,7 +373,7 @@ static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
     P.bigs = (uint64_t*)(base + L.o_bigs);
     P.counts = (unsigned long long*)(base + L.o_counts);
     P.status = (unsigned long long*)(base + L.o_status);
-    P.ids = nullptr;
+    P.ids = L.o_ids ? (uint16_t*)(base + L.o_ids) : nullptr;
     P.seg_cap = L.seg_cap; P.tile_cap = L.tile_cap; P.item_cap = L.item_cap; P.big_cap = L.big_cap; P.counts_cap = L.counts_cap;
     P.status_cap = L.status_cap; P.arena_cap = L.arena_cap;
     P.persist = (const uint64_t*)(base + L.o_persist);
@@ -373,8 +418,8 @@ static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPoo
     FitArgs A{};
     A.s = smp; A.S = L.S_big; A.n = c.n; A.u64 = c.u64;
     A.mode = c.o.model == LS_MODEL_SPLITTER ? 2 : 0;
-    A.mlp = 0;
-    A.L = c.o.leaves;
+    A.mlp = L.mlp_S ? 1 : 0;
+    A.L = std::min<uint32_t>(c.o.leaves, std::max<uint32_t>(2, (uint32_t)std::min<uint64_t>(L.S_big / 8, L_MAX)));
     const uint64_t half = std::max<uint32_t>(1, c.o.cutoff / 2);
     uint64_t B1 = std::min<uint64_t>(c.o.buckets, std::max<uint64_t>(2, (c.n + half - 1) / half));
     B1 = std::min<uint64_t>(B1, std::max<uint64_t>(2, c.n / 4));
@@ -395,9 +440,32 @@ static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPoo
     A.model = (uint64_t*)(base + L.o_bigmodel);
     A.flag = (uint32_t*)(base + L.o_flag);
     A.seg = P.segs[1];
+    A.first_mlp = &P.ctl->first_mlp;
     TIMED(KI_FIT, c.st, launch_fit1(A, c.st));
     TIMED(KI_FIT, c.st, launch_fit2(A, c.st));
     TIMED(KI_FIT, c.st, launch_fit_root(A, c.st));
+    if (A.mlp) {
+        // train the MLP root on (every stride-th point of) the sorted sample;
+        // every kernel is gated on the policy's decision in A.flag
+        const MlpState ms = mlp_state(base, L);
+        float* t = (float*)(base + L.o_mlp_t);
+        float* y = (float*)(base + L.o_mlp_y);
+        TIMED(KI_FIT, c.st, launch_mlp_prep(smp, L.S_big, L.mlp_stride, c.u64, t, y, ms.lo_inv, A.flag, c.st));
+        TIMED(KI_FIT, c.st, launch_mlp_setup(t, L.mlp_S, nullptr, 1e-3, ms.p, ms.m, ms.v, ms.best, ms.scale,
+                                             ms.best_loss, ms.done, A.flag, c.st));
+        for (uint32_t k = 1; k <= c.o.mlp_steps; k++) {
+            MlpStep S{};
+            S.t = t; S.y = y; S.S = L.mlp_S; S.p = ms.p; S.m = ms.m; S.v = ms.v; S.partial = ms.partial;
+            S.done = ms.done; S.loss_pair = P.ctl->mlp_loss; S.gate = A.flag; S.step = k; S.update = 1;
+            S.best = ms.best; S.best_loss = ms.best_loss; S.scale = ms.scale;
+            S.lr = c.o.mlp_lr; S.b1 = 0.9f; S.b2 = 0.999f; S.eps = 1e-8f;
+            S.c1 = (float)(1.0 - std::pow(0.9, (double)k));
+            S.c2 = (float)(1.0 - std::pow(0.999, (double)k));
+            TIMED(KI_MLP_TRAIN, c.st, launch_mlp_step(S, c.st));
+        }
+        TIMED(KI_FIT, c.st, launch_mlp_install(ms.best, ms.lo_inv, A.L, A.B1, A.log2B2, A.R, nullptr, A.flag, nullptr,
+                                               A.model, c.st));
+    }
     TIMED(KI_FIT, c.st, launch_fit_leaves(A, c.st));
     TIMED(KI_FIT, c.st, launch_fit_finish(A, c.st));
     return LS_OK;
@@ -426,6 +494,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         const size_t rec0 = g_trec.size();
         const uint32_t g0 = lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024;
         TIMED(KI_MODEL, c.st, launch_model(P, g0, c.st));
+        if (P.ids && lvl <= 1) TIMED(KI_MLP_IDS, c.st, launch_mlp_ids(P, cus * 4, c.st));
         TIMED(KI_HIST, c.st, launch_hist(P, cus * 4, c.st));
         TIMED(KI_SCAN, c.st, launch_scan(P, g0, c.st));
         TIMED(KI_SCATTER, c.st, launch_scatter(P, cus, c.st));
@@ -501,7 +570,8 @@ static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, ui
     if (s) return s;
     Opts o;
     if ((s = normalize(opt, o))) return s;
-    if (o.model == LS_MODEL_MLP) return fail(LS_EUNSUPPORTED, "the MLP model is not available in this build");
+    if (o.model == LS_MODEL_MLP && offsets)
+        return fail(LS_EUNSUPPORTED, "the MLP model is available for single arrays (ls_sort) only");
     if (n <= 1 || m == 0) return LS_OK;
     std::lock_guard<std::mutex> lk(g_mu);
     Layout L = plan(n, m, payload != nullptr, o);
@@ -520,10 +590,16 @@ static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, ui
 }
 
 // Small scratch for the single-step entry points (model, fit partials).
-static ls_status step_scratch(uint8_t*& base, DevPool*& pool, Layout& L) {
+static ls_status step_scratch(uint8_t*& base, DevPool*& pool, Layout& L, uint64_t mlp_S = 0) {
     Opts o;
     normalize(nullptr, o);
     L = plan(16, 1, 0, o);
+    if (mlp_S) {  // training set of the single-step MLP entry points
+        L.mlp_S = mlp_S;
+        L.o_mlp_t = L.bytes;
+        L.o_mlp_y = L.o_mlp_t + align256(mlp_S * 4);
+        L.bytes = L.o_mlp_y + align256(mlp_S * 4);
+    }
     ls_status s = acquire(L.bytes, L, pool, base);
     if (!s) pool->sig = 0;  // this scratch may overlap another layout's look-back words
     return s;
@@ -599,7 +675,8 @@ ls_status ls_get_stats(ls_stats* out) {
         if (s.segments) levels = l + 1;
     }
     out->levels = levels;
-    out->first_model = c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
+    out->first_model = c.first_mlp ? LS_MODEL_MLP
+                       : c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
     out->base_items = c.nitems + c.nbig - c.ncopy;
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
@@ -817,17 +894,116 @@ ls_status ls_partition_splitters(const void* keys, const uint32_t* payload, uint
                          counts, stream);
 }
 
-ls_status ls_mlp_loss_grad(const float*, const float*, const float*, uint64_t, float*, float*, void*) {
-    return fail(LS_EUNSUPPORTED, "the MLP kernels are not available in this build");
+ls_status ls_mlp_loss_grad(const float* params, const float* t, const float* y, uint64_t S, float* grad, float* loss,
+                           void* stream) {
+    if (!params || !t || !y || S == 0 || (!grad && !loss))
+        return fail(LS_EINVAL, "ls_mlp_loss_grad needs params, t, y, S >= 1 and an output");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    ls_status s = step_scratch(base, pool, Lo);
+    if (s) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    const MlpState ms = mlp_state(base, Lo);
+    HIP_TRY(launch_mlp_setup(t, S, params, 0.0, ms.p, ms.m, ms.v, ms.best, ms.scale, ms.best_loss, ms.done, nullptr,
+                             st));
+    MlpStep A{};
+    A.t = t; A.y = y; A.S = S; A.p = ms.p; A.m = ms.m; A.v = ms.v; A.partial = ms.partial; A.done = ms.done;
+    A.grad_out = grad; A.loss_out = loss; A.step = 1; A.update = 0;
+    HIP_TRY(launch_mlp_step(A, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
 }
 
-ls_status ls_mlp_train(const void*, uint64_t, ls_dtype, const float*, uint32_t, float, uint64_t, float*, double*, float*,
-                       void*) {
-    return fail(LS_EUNSUPPORTED, "the MLP kernels are not available in this build");
+ls_status ls_mlp_train(const void* sorted_sample, uint64_t S, ls_dtype dtype, const float* params_init, uint32_t steps,
+                       float lr, float* params_out, double* lo_inv, float* losses, void* stream) {
+    ls_status s = check_keys(sorted_sample, S, dtype, nullptr);
+    if (s) return s;
+    if (S < 2 || !params_out || !lo_inv || !(lr > 0.0f) || steps > 100000)
+        return fail(LS_EINVAL, "ls_mlp_train needs S >= 2, lr > 0, steps <= 100000, params_out and lo_inv");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    if ((s = step_scratch(base, pool, Lo, S))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    const MlpState ms = mlp_state(base, Lo);
+    float* t = (float*)(base + Lo.o_mlp_t);
+    float* y = (float*)(base + Lo.o_mlp_y);
+    HIP_TRY(launch_mlp_prep((const uint64_t*)sorted_sample, S, 1, dtype == LS_U64, t, y, lo_inv, nullptr, st));
+    HIP_TRY(launch_mlp_setup(t, S, params_init, 1e-3, ms.p, ms.m, ms.v, ms.best, ms.scale, ms.best_loss, ms.done,
+                             nullptr, st));
+    for (uint32_t k = 1; k <= steps; k++) {
+        MlpStep A{};
+        A.t = t; A.y = y; A.S = S; A.p = ms.p; A.m = ms.m; A.v = ms.v; A.partial = ms.partial; A.done = ms.done;
+        A.losses = losses; A.step = k; A.update = 1; A.lr = lr; A.b1 = 0.9f; A.b2 = 0.999f; A.eps = 1e-8f;
+        A.best = ms.best; A.best_loss = ms.best_loss; A.scale = ms.scale;
+        A.c1 = (float)(1.0 - std::pow(0.9, (double)k));
+        A.c2 = (float)(1.0 - std::pow(0.999, (double)k));
+        HIP_TRY(launch_mlp_step(A, st));
+    }
+    HIP_TRY(hipMemcpyAsync(params_out, ms.best, 4 * MLP_NP, hipMemcpyDeviceToDevice, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
 }
 
-ls_status ls_mlp_buckets(const void*, uint64_t, ls_dtype, const float*, const double*, uint32_t, uint32_t*, void*) {
-    return fail(LS_EUNSUPPORTED, "the MLP kernels are not available in this build");
+ls_status ls_mlp_buckets(const void* keys, uint64_t n, ls_dtype dtype, const float* params, const double* lo_inv,
+                         uint32_t R, uint32_t* out, void* stream) {
+    ls_status s = check_keys(keys, n, dtype, nullptr);
+    if (s) return s;
+    if (!params || !lo_inv || R < 1 || R > (1u << 24) || (n && !out))
+        return fail(LS_EINVAL, "ls_mlp_buckets needs params, lo_inv, 1 <= R <= 2^24 and out");
+    if (n == 0) return LS_OK;
+    HIP_TRY(launch_mlp_buckets(params, lo_inv, R, (const uint64_t*)keys, n, dtype == LS_U64, out, (hipStream_t)stream));
+    return LS_OK;
+}
+
+ls_status ls_mlp_rmi_fit(const void* sorted_sample, uint64_t S, ls_dtype dtype, const float* params,
+                         const double* lo_inv, uint32_t L, double R, double* leaves, void* stream) {
+    ls_status s = check_keys(sorted_sample, S, dtype, nullptr);
+    if (s) return s;
+    if (S < 2 || L < 2 || L > L_MAX || !params || !lo_inv || !leaves || !(R >= 1.0) || R > 4294967296.0)
+        return fail(LS_EINVAL, "ls_mlp_rmi_fit needs S >= 2, 2 <= L <= 1024, 1 <= R <= 2^32 and all pointers");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    if ((s = step_scratch(base, pool, Lo))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    FitArgs A{};
+    A.s = (const uint64_t*)sorted_sample; A.S = S; A.n = S; A.u64 = dtype == LS_U64; A.mode = 1; A.mlp = 1;
+    A.L = L; A.B1 = 1; A.log2B2 = 0; A.R = R; A.Bt = 2; A.G = FIT_G;
+    A.part = (double*)(base + Lo.o_part);
+    A.leaf = (double*)(base + Lo.o_leaf);
+    A.model = (uint64_t*)(base + Lo.o_bigmodel);
+    A.flag = (uint32_t*)(base + Lo.o_flag);
+    HIP_TRY(launch_mlp_install(params, lo_inv, L, 1, 0, R, nullptr, nullptr, A.flag, A.model, st));
+    HIP_TRY(launch_fit_leaves(A, st));
+    HIP_TRY(launch_fit_finish(A, st));
+    HIP_TRY(launch_copy_words(A.model + MLP_LEAF_WORD, (uint64_t*)leaves, 4ull * L, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
+ls_status ls_mlp_rmi_buckets(const void* keys, uint64_t n, ls_dtype dtype, const float* params, const double* lo_inv,
+                             const double* leaves, uint32_t L, double R, uint32_t* out, void* stream) {
+    ls_status s = check_keys(keys, n, dtype, nullptr);
+    if (s) return s;
+    if (L < 2 || L > L_MAX || !params || !lo_inv || !leaves || !(R >= 1.0) || R > 4294967296.0 || (n && !out))
+        return fail(LS_EINVAL, "ls_mlp_rmi_buckets needs 2 <= L <= 1024, 1 <= R <= 2^32 and all pointers");
+    if (n == 0) return LS_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    if ((s = step_scratch(base, pool, Lo))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    uint64_t* mdl = (uint64_t*)(base + Lo.o_bigmodel);
+    HIP_TRY(launch_mlp_install(params, lo_inv, L, 1, 0, R, leaves, nullptr, nullptr, mdl, st));
+    HIP_TRY(launch_mlp_rmi_buckets(mdl, (const uint64_t*)keys, n, dtype == LS_U64, out, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
 }
 
 }  // extern "C"

@@ -127,15 +127,104 @@ __device__ __forceinline__ float mlp_input(double x, double lo, double inv) {
     return (float)t;
 }
 
-__device__ __forceinline__ uint32_t mlp_bucket(const float* w, double lo, double inv, float Rf, uint64_t raw, int u64) {
-    double x;
-    int nf = key_x(raw, u64, x);
-    if (nf) return nf < 0 ? 0u : (uint32_t)(Rf - 1.0f);
-    float F = mlp_eval(w, mlp_input(x, lo, inv));
-    float g = floorf(F * Rf);
-    g = fminf(g, Rf - 1.0f);
-    return (uint32_t)g;
+// K keys per thread through the network at once: the same operation
+// sequence per key as mlp_eval, with each weight read from LDS once for all
+// K keys (the weights are uniform across the wave, so their reads are
+// broadcasts; K amortises them against the ~300 FMAs per key).
+template <int K>
+__device__ __forceinline__ void mlp_eval_multi(const float* w, const float (&t)[K], float (&F)[K]) {
+    float h1[K][MLP_H];
+#pragma unroll
+    for (int i = 0; i < MLP_H; i++) {
+        const float v = w[OFF_V1 + i], b = w[OFF_B1 + i];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const float z = __builtin_fmaf(v, t[k], b);
+            h1[k][i] = i < MLP_HALF ? fmaxf(z, 0.0f) : fminf(z, 0.0f);
+        }
+    }
+    float out[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) out[k] = w[OFF_B3];
+    // layer 2, max units then min units; not unrolled over units, so that
+    // only one unit's 16 weights are live at a time
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+#pragma unroll 1
+        for (int i = half * MLP_HALF; i < (half + 1) * MLP_HALF; i++) {
+            float z[K];
+#pragma unroll
+            for (int k = 0; k < K; k++) z[k] = w[OFF_B2 + i];
+#pragma unroll
+            for (int j = 0; j < MLP_H; j++) {
+                const float v = w[OFF_V2 + MLP_H * i + j];
+#pragma unroll
+                for (int k = 0; k < K; k++) z[k] = __builtin_fmaf(v, h1[k][j], z[k]);
+            }
+            const float v3 = w[OFF_V3 + i];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const float h = half == 0 ? fmaxf(z[k], 0.0f) : fminf(z[k], 0.0f);
+                out[k] = __builtin_fmaf(v3, h, out[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) F[k] = fminf(fmaxf(out[k], 0.0f), 1.0f);
 }
+
+// Two-level model with the MLP as its root (Sec. 2.1 stages): the leaf is
+// j = min(floor(F * L), L - 1) in fp32 from the clamped network output F,
+// then leaf j's clamped line at total resolution R as in rmi_eval.  F is
+// non-decreasing in x, so j is, and the clamp chain keeps g monotone.
+// Non-finite keys go to 0 (negative) or R - 1.
+template <int K>
+__device__ __forceinline__ void mlp_root_buckets(const float* w, const double* leaves, double lo, double inv, float Lf,
+                                                 double Rm1, const uint64_t (&raw)[K], int u64, uint32_t (&g)[K]) {
+    double x[K];
+    int nf[K];
+    float t[K], F[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        nf[k] = key_x(raw[k], u64, x[k]);
+        t[k] = nf[k] ? 0.0f : mlp_input(x[k], lo, inv);
+    }
+    mlp_eval_multi<K>(w, t, F);
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const float j = fminf(floorf(F[k] * Lf), Lf - 1.0f);
+        const double* q = leaves + 4 * (int)j;
+        double u = __builtin_fma(q[0], x[k], q[1]);
+        u = fmin(fmax(u, q[2]), q[3]);
+        double gg = floor(u);
+        gg = fmin(fmax(gg, 0.0), Rm1);
+        g[k] = nf[k] ? (nf[k] < 0 ? 0u : (uint32_t)Rm1) : (uint32_t)gg;
+    }
+}
+
+// The network alone as a CDF at resolution R (fp32).
+template <int K>
+__device__ __forceinline__ void mlp_buckets_multi(const float* w, double lo, double inv, float Rf,
+                                                  const uint64_t (&raw)[K], int u64, uint32_t (&g)[K]) {
+    double x[K];
+    int nf[K];
+    float t[K], F[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        nf[k] = key_x(raw[k], u64, x[k]);
+        t[k] = nf[k] ? 0.0f : mlp_input(x[k], lo, inv);
+    }
+    mlp_eval_multi<K>(w, t, F);
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const float gg = fminf(floorf(F[k] * Rf), Rf - 1.0f);
+        g[k] = nf[k] ? (nf[k] < 0 ? 0u : (uint32_t)(Rf - 1.0f)) : (uint32_t)gg;
+    }
+}
+
+// Keeps the compiler from hoisting LDS weight reads out of a loop (which
+// would pin all 321 weights in registers and leave one wave per SIMD).
+__device__ __forceinline__ void lds_reload_fence() { __asm__ volatile("" ::: "memory"); }
 
 // ---------------------------------------------------------------------------
 // Wave-level helpers (wave64)
@@ -440,9 +529,9 @@ struct View {
     uint32_t shift;
 };
 
-// Partition models evaluated inside the partition kernels.  The MLP is not
-// among them: an MLP level first stores every key's bucket id (K_STASH) so
-// that its 288 FMAs per key are paid once, not twice.
+// Partition models evaluated inside the partition kernels.  The MLP-rooted
+// model is not among them: k_mlp_ids first stores every key's bucket id of
+// such a level, so that its ~300 FMAs per key are paid once, not twice.
 __device__ __forceinline__ View make_view(const uint64_t* mdl, uint32_t kind, uint32_t nb, uint32_t win) {
     View v{};
     v.kind = kind; v.nb = nb; v.win = win;

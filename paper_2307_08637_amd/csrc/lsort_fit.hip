@@ -98,7 +98,13 @@ __global__ __launch_bounds__(M_THREADS) void k_fit_root(FitArgs A) {
     else learned = (double)A.n >= 1e5 && dup <= 0.10 * (Sd - 1.0) && nf == 0 && !nf0 && !nf1 && x1 > x0;
     uint64_t* dst = A.model;
     uint32_t nb, words, kind;
-    if (learned) {
+    if (learned && A.mlp) {
+        // the MLP root is trained next; its header, weights and leaves are
+        // written by the MLP kernels and the leaf fit
+        nb = A.B1;
+        words = 0;  // per-key ids are stored by k_mlp_ids: nothing to load
+        kind = K_MLP;
+    } else if (learned) {
         double mx = sx / Sd, my = (Sd - 1.0) / (2.0 * Sd);
         double a = sxx > 0 ? sxy / sxx : 0.0;
         if (a < 0) a = 0;
@@ -112,7 +118,7 @@ __global__ __launch_bounds__(M_THREADS) void k_fit_root(FitArgs A) {
         }
         nb = A.B1;
         words = rmi_words(A.L);
-        kind = A.mlp ? K_MLP : K_RMI;
+        kind = K_RMI;
     } else {
         const uint64_t* s = A.s;
         const int u64 = A.u64;
@@ -123,6 +129,7 @@ __global__ __launch_bounds__(M_THREADS) void k_fit_root(FitArgs A) {
     }
     if (threadIdx.x == 0) {
         A.flag[0] = learned ? 1u : 0u;
+        if (A.first_mlp) A.first_mlp[0] = learned && A.mlp ? 1u : 0u;
         if (A.seg) {
             Seg sg{};
             sg.kind = kind; sg.nb = nb; sg.model = (uint64_t)dst;
@@ -144,17 +151,47 @@ __device__ __forceinline__ uint32_t root_leaf(double ar, double br, double Lm1, 
 // Leaf boundaries: the root's leaf index is non-decreasing along the sorted
 // sample, so leaf j covers [bounds[j], bounds[j+1]).  Each sample point
 // writes the starts of the leaves that begin at it.
+__device__ __forceinline__ void write_bounds(const FitArgs& A, uint64_t i, uint32_t j, int64_t jp) {
+    uint64_t* bounds = (uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
+    for (int64_t q = jp + 1; q <= (int64_t)j; q++) bounds[q] = i;
+    if (i == A.S - 1)
+        for (uint32_t q = j + 1; q <= A.L; q++) bounds[q] = A.S;
+}
+
 __global__ __launch_bounds__(FIT_T) void k_fit_bounds(FitArgs A) {
     if (A.flag[0] == 0) return;
     const double ar = ((const double*)A.model)[4], br = ((const double*)A.model)[5];
     const double Lm1 = (double)A.L - 1.0;
-    uint64_t* bounds = (uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
     for (uint64_t i = (uint64_t)blockIdx.x * FIT_T + threadIdx.x; i < A.S; i += (uint64_t)gridDim.x * FIT_T) {
         const uint32_t j = root_leaf(ar, br, Lm1, A.s[i], A.u64);
         const int64_t jp = i > 0 ? (int64_t)root_leaf(ar, br, Lm1, A.s[i - 1], A.u64) : -1;
-        for (int64_t q = jp + 1; q <= (int64_t)j; q++) bounds[q] = i;
-        if (i == A.S - 1)
-            for (uint32_t q = j + 1; q <= A.L; q++) bounds[q] = A.S;
+        write_bounds(A, i, j, jp);
+    }
+}
+
+// The same for the MLP root: leaf = min(floor(F L), L - 1) in fp32 (the
+// sample is finite: the policy admits no learned model otherwise).
+__global__ __launch_bounds__(FIT_T) void k_fit_bounds_mlp(FitArgs A) {
+    __shared__ float w[MLP_NP];
+    if (A.flag[0] == 0) return;
+    const float* ws = (const float*)(A.model + MLP_W_WORD);
+    for (int i = threadIdx.x; i < MLP_NP; i += FIT_T) w[i] = ws[i];
+    __syncthreads();
+    const MlpModel* h = (const MlpModel*)A.model;
+    const double lo = h->lo, inv = h->inv;
+    const float Lf = (float)A.L;
+    for (uint64_t i = (uint64_t)blockIdx.x * FIT_T + threadIdx.x; i < A.S; i += (uint64_t)gridDim.x * FIT_T) {
+        lds_reload_fence();
+        float t[2], F[2];
+        double x;
+        key_x(A.s[i], A.u64, x);
+        t[0] = mlp_input(x, lo, inv);
+        key_x(A.s[i > 0 ? i - 1 : 0], A.u64, x);
+        t[1] = mlp_input(x, lo, inv);
+        mlp_eval_multi<2>(w, t, F);
+        const uint32_t j = (uint32_t)fminf(floorf(F[0] * Lf), Lf - 1.0f);
+        const int64_t jp = i > 0 ? (int64_t)fminf(floorf(F[1] * Lf), Lf - 1.0f) : -1;
+        write_bounds(A, i, j, jp);
     }
 }
 
@@ -222,7 +259,7 @@ __global__ __launch_bounds__(M_THREADS) void k_fit_finish(FitArgs A) {
         } else {
             a = 0; b = dprev; c = dprev; d = dprev;
         }
-        double* o = (double*)A.model + 6 + 4 * tid;
+        double* o = (double*)A.model + (A.mlp ? MLP_LEAF_WORD : 6) + 4 * tid;
         o[0] = A.R * a; o[1] = A.R * b; o[2] = A.R * c; o[3] = A.R * d;
     }
 }
@@ -236,7 +273,7 @@ __global__ __launch_bounds__(256) void k_model_buckets(const uint64_t* model, ui
                                                        uint32_t win, const uint64_t* keys, uint64_t n, int u64,
                                                        uint32_t* out) {
     __shared__ uint64_t mdl[MODEL_WORDS];
-    for (uint32_t i = threadIdx.x; i < words; i += 256) mdl[i] = model[i];
+    for (uint32_t i = threadIdx.x; i < words && i < (uint32_t)MODEL_WORDS; i += 256) mdl[i] = model[i];
     __syncthreads();
     const View v = make_view(mdl, kind, nb, win);
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
@@ -311,7 +348,8 @@ hipError_t launch_fit2(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit2, A.G, F
 hipError_t launch_fit_root(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_root, 1, M_THREADS, st, A); }
 hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st) {
     const uint32_t grid = (uint32_t)std::min<uint64_t>((A.S + FIT_T - 1) / FIT_T, 2048ull);
-    hipLaunchKernelGGL(k_fit_bounds, dim3(grid ? grid : 1), dim3(FIT_T), 0, st, A);
+    if (A.mlp) hipLaunchKernelGGL(k_fit_bounds_mlp, dim3(grid ? grid : 1), dim3(FIT_T), 0, st, A);
+    else hipLaunchKernelGGL(k_fit_bounds, dim3(grid ? grid : 1), dim3(FIT_T), 0, st, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     LAUNCH(k_fit_leaves, A.L, FIT_T, st, A);

@@ -57,12 +57,20 @@ struct RadixModel {
     uint32_t shift, nb;
 };
 static_assert(sizeof(RadixModel) == 16, "radix model is two words");
-struct MlpModel {     // 32 bytes, followed by float w[321] (effective weights |V|, biases)
-    uint32_t B1, log2B2;
-    double lo, inv;
-    double R;
+// Two-level model whose root is the monotone MLP: 48-byte header, the
+// network's effective weights (|V|, biases) as float w[321] from model word
+// MLP_W_WORD, then the pre-scaled leaves (alpha, beta, gamma, delta) x L as
+// doubles from model word MLP_LEAF_WORD.
+struct MlpModel {
+    uint32_t L, B1, log2B2, pad;
+    double lo, inv;   // model input t = clamp((x - lo) * inv, 0, 1)
+    double R;         // B1 << log2B2
+    uint64_t pad2;
 };
-static_assert(sizeof(MlpModel) == 32, "MLP weights start at model word 4");
+static_assert(sizeof(MlpModel) == 48, "MLP weights start at model word 6");
+constexpr int MLP_W_WORD = 6;
+constexpr int MLP_LEAF_WORD = MLP_W_WORD + (MLP_NP + 1) / 2;  // 167
+constexpr int MLP_MODEL_WORDS = MLP_LEAF_WORD + 4 * L_MAX;
 
 // One sub-array partitioned at some level.
 struct Seg {
@@ -114,9 +122,8 @@ struct Ctl {
     unsigned long long status_used;
     unsigned long long arena_used[2];
     uint32_t overflow;              // OVF_* bits
-    uint32_t big_learned;           // first-level policy result of the large path (1 RMI/MLP, 0 tree)
-    double big_stats[8];            // large-path fit scratch
-    double mlp_loss[2];
+    uint32_t first_mlp;             // the first level's model is the MLP-rooted one
+    double mlp_loss[2];             // MLP training loss at the first and the last step
     LevelStats lv[MAXL];
 };
 constexpr uint32_t OVF_SEG = 1, OVF_TILE = 2, OVF_ITEM = 4, OVF_COUNTS = 8, OVF_STATUS = 16, OVF_ARENA = 32,

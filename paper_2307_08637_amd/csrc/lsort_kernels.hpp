@@ -22,6 +22,34 @@ struct FitArgs {
     uint64_t* model;     // model destination (device)
     uint32_t* flag;      // [0] = 1 when the learned model was chosen
     Seg* seg;            // descriptor of the prebuilt first level (nullable)
+    uint32_t* first_mlp; // set to 1 when the MLP-rooted model was chosen (nullable)
+};
+
+// MLP training (lsort_mlp.hip)
+constexpr int MLP_G = 256;           // workgroups of a training step (gradient partials)
+constexpr int MLP_ACC = MLP_NP + 1;  // gradient entries + the squared error per partial
+
+struct MlpStep {
+    const float* t;       // model inputs of the training set
+    const float* y;       // targets (rank fractions)
+    uint64_t S;
+    float* p;             // parameters V / biases
+    float* m;             // Adam first moment
+    float* v;             // Adam second moment
+    float* partial;       // MLP_G * MLP_ACC workgroup partials
+    unsigned int* done;   // workgroups finished in this step; zero between steps
+    float* grad_out;      // nullable: gradient w.r.t. p
+    float* loss_out;      // nullable: loss (mean squared error) at p
+    float* losses;        // nullable: loss of step `step` at losses[step - 1]
+    double* loss_pair;    // nullable: [0] loss at step 1, [1] lowest loss so far
+    float* best;          // nullable: parameters with the lowest loss seen (set up by k_mlp_setup)
+    const float* scale;   // nullable: per-parameter optimiser step scale (set up by k_mlp_setup)
+    float* best_loss;     // that loss (with best)
+    const uint32_t* gate; // nullable: do nothing when gate[0] == 0
+    uint32_t step;        // 1-based Adam step number
+    uint32_t update;      // 1: apply Adam; 0: gradient only
+    float lr, b1, b2, eps;
+    float c1, c2;         // bias corrections 1 - b1^step, 1 - b2^step
 };
 
 // level kernels (lsort_kernels.hip)
@@ -50,5 +78,22 @@ hipError_t launch_install_tree(const uint64_t* u, const uint8_t* eq, uint32_t m,
 hipError_t launch_splitters(const uint64_t* s, uint64_t S, int u64, uint32_t B, uint64_t* scratch, uint64_t* u_out,
                             uint8_t* eq_out, uint32_t* m_out, hipStream_t st);
 hipError_t launch_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t st);
+
+// MLP CDF (lsort_mlp.hip)
+hipError_t launch_mlp_prep(const uint64_t* s, uint64_t S, uint64_t stride, int u64, float* t, float* y, double* lo_inv,
+                           const uint32_t* gate, hipStream_t st);
+hipError_t launch_mlp_setup(const float* t, uint64_t S, const float* init, double eps, float* p, float* m, float* v,
+                            float* best, float* scale, float* best_loss, unsigned int* done, const uint32_t* gate,
+                            hipStream_t st);
+uint32_t mlp_step_grid(uint64_t S);
+hipError_t launch_mlp_step(const MlpStep& A, hipStream_t st);
+hipError_t launch_mlp_install(const float* p, const double* lo_inv, uint32_t L, uint32_t B1, uint32_t log2B2, double R,
+                              const double* leaves, const uint32_t* gate, uint32_t* set, uint64_t* dst,
+                              hipStream_t st);
+hipError_t launch_mlp_ids(const Params& P, uint32_t grid, hipStream_t st);
+hipError_t launch_mlp_rmi_buckets(const uint64_t* mdl, const uint64_t* keys, uint64_t n, int u64, uint32_t* out,
+                                  hipStream_t st);
+hipError_t launch_mlp_buckets(const float* p, const double* lo_inv, uint32_t R, const uint64_t* keys, uint64_t n,
+                              int u64, uint32_t* out, hipStream_t st);
 
 }  // namespace ls

@@ -1,0 +1,471 @@
+// lsort_mlp.hip -- the monotone FP32 MLP CDF: training on the GPU (start
+// point, forward, backward, Adam), the MLP-rooted two-level model, and the
+// per-key bucket ids of levels partitioned by it.
+//
+// Network (a CDF model must be non-decreasing, Sec. 3.1): 1-16-16-1 with
+// effective weights |V| >= 0; in each hidden layer units 0..7 use max(z, 0)
+// and units 8..15 use min(z, 0), both non-decreasing.  Input
+// t = clamp((x - lo) * inv, 0, 1) rounded to fp32; output clamped to [0, 1]
+// when used as a CDF.  Training fits the unclamped output to the rank
+// fractions of a sorted sample by mean squared error with full-batch Adam
+// (Kingma & Ba 2015).  Parameter layout (321 floats): V1[16] b1[16]
+// V2[16x16] (row = output unit) b2[16] V3[16] b3[1].
+//
+// As a partition model the network is the root of a two-level model
+// (Sec. 2.1): it picks one of L linear leaves, fitted exactly as the RMI's.
+#include <algorithm>
+
+#include "lsort_dev.hpp"
+#include "lsort_kernels.hpp"
+
+namespace ls {
+
+__host__ __device__ constexpr bool mlp_is_weight(int p) {
+    return p < OFF_B1 || (p >= OFF_V2 && p < OFF_B2) || (p >= OFF_V3 && p < OFF_B3);
+}
+
+// ---------------------------------------------------------------------------
+// Training set from a sorted sample s[0..S) of raw keys: every stride-th
+// point, t = model input, y = its rank fraction i / S.  lo = smallest key,
+// inv = 1 / (largest - smallest) (0 when all keys are equal or not finite).
+// ---------------------------------------------------------------------------
+__global__ void k_mlp_prep(const uint64_t* s, uint64_t S, uint64_t stride, int u64, float* t, float* y, double* lo_inv,
+                           const uint32_t* gate) {
+    if (gate && gate[0] == 0) return;
+    double x0, x1;
+    const int nf0 = key_x(s[0], u64, x0), nf1 = key_x(s[S - 1], u64, x1);
+    const bool ok = !nf0 && !nf1 && x1 > x0;
+    const double inv = ok ? 1.0 / (x1 - x0) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        lo_inv[0] = ok ? x0 : 0.0;
+        lo_inv[1] = inv;
+    }
+    const uint64_t Sp = (S + stride - 1) / stride;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Sp; i += (uint64_t)gridDim.x * blockDim.x) {
+        double x;
+        key_x(s[i * stride], u64, x);
+        t[i] = ok ? mlp_input(x, x0, inv) : 0.0f;
+        y[i] = (float)((double)(i * stride) / (double)S);
+    }
+}
+
+// Start point (or the caller's parameters) and zeroed optimiser state.  The
+// start point is the piecewise-linear interpolant of the sample CDF through
+// its octiles: knots k_m = t[floor(m S / 8)], k_8 = t[S - 1], widths
+// w_m = max(k_{m+1} - k_m, 1e-6); layer-1 max units ramp from k_m over w_m,
+// layer-2 min units cap each ramp at 1 (V = 1, b = -1), the output averages
+// the eight capped ramps (V3 = 1/8, b3 = 1).  Every other weight is
+// eps / max(1, |V1_k| + |b1_k|) (column k) so that it stays trainable; the
+// layer-1 min units start as unit-slope hinges at (m + 0.5) / 8.  Computed
+// in fp64, rounded once to fp32.
+constexpr int MLP_SETUP_T = 512;
+
+__global__ __launch_bounds__(MLP_SETUP_T) void k_mlp_setup(const float* t, uint64_t S, const float* init, double eps,
+                                                           float* p, float* m, float* v, float* best, float* scale,
+                                                           float* best_loss, unsigned int* done,
+                                                           const uint32_t* gate) {
+    if (gate && gate[0] == 0) return;
+    __shared__ double v1[MLP_H], b1[MLP_H];
+    const int tid = threadIdx.x;
+    if (init && tid < MLP_H) {
+        v1[tid] = (double)init[OFF_V1 + tid];
+        b1[tid] = (double)init[OFF_B1 + tid];
+    }
+    if (!init && tid < MLP_HALF) {
+        const int q = tid;
+        const double k = (double)t[(uint64_t)q * S / 8];
+        const double kn = q == MLP_HALF - 1 ? (double)t[S - 1] : (double)t[(uint64_t)(q + 1) * S / 8];
+        double w = kn - k;
+        if (w < 1e-6) w = 1e-6;
+        v1[q] = 1.0 / w;
+        b1[q] = -k / w;
+        v1[MLP_HALF + q] = 1.0;
+        b1[MLP_HALF + q] = -((double)q + 0.5) / 8.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < MLP_NP; i += MLP_SETUP_T) {
+        double val;
+        if (init) {
+            val = 0.0;
+        } else if (i < OFF_B1) {
+            val = v1[i - OFF_V1];
+        } else if (i < OFF_V2) {
+            val = b1[i - OFF_B1];
+        } else if (i < OFF_B2) {
+            const int r = (i - OFF_V2) / MLP_H, c = (i - OFF_V2) % MLP_H;
+            const double bound = fabs(v1[c]) + fabs(b1[c]);
+            val = (r >= MLP_HALF && c == r - MLP_HALF) ? 1.0 : eps / (bound > 1.0 ? bound : 1.0);
+        } else if (i < OFF_V3) {
+            val = i - OFF_B2 < MLP_HALF ? 0.0 : -1.0;
+        } else if (i < OFF_B3) {
+            val = i - OFF_V3 < MLP_HALF ? eps : 1.0 / 8.0;
+        } else {
+            val = 1.0;
+        }
+        p[i] = init ? init[i] : (float)val;
+        best[i] = p[i];
+        m[i] = 0.0f;
+        v[i] = 0.0f;
+        // optimiser step scale: 1 / (bound of the input activation on [0, 1])
+        // for layer-2 weights, 1 elsewhere
+        double sc = 1.0;
+        if (i >= OFF_V2 && i < OFF_B2) {
+            const int c = (i - OFF_V2) % MLP_H;
+            const double bound = fabs(v1[c]) + fabs(b1[c]);
+            sc = 1.0 / (bound > 1.0 ? bound : 1.0);
+        }
+        scale[i] = (float)sc;
+    }
+    if (tid == 0) {
+        *done = 0;
+        *best_loss = INFINITY;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One full-batch training step.
+//
+// Optimiser: Adam (Kingma & Ba 2015) on q = p / scale, with scale = 1 except
+// for layer-2 weights, where it is 1 / max(1, |V1_k| + |b1_k|) of their input
+// unit k at the start point -- the bound of that unit's activation on
+// t in [0, 1].  Adam moves every q by about lr per step whatever the size of
+// its gradient; the scale keeps a layer-2 weight that multiplies a steep
+// first-layer ramp from moving its pre-activation by more than about lr.
+//
+// Each workgroup takes a contiguous chunk of the samples, 256 at a time: a
+// thread runs forward and backward for one sample and leaves the per-sample
+// factors in an LDS record; then thread j sums, in sample order, the product
+// of the two record fields that make gradient entry j (and entry j + 256):
+//   V1[k]: dz1_k * t     b1[k]: dz1_k       V2[i][k]: dz2_i * h1_k
+//   b2[i]: dz2_i         V3[k]: dout * h2_k b3: dout    loss: e * e
+// (gradients with respect to the effective weights; dout = 2 e / S).  The
+// workgroup partials go to global memory; the last workgroup to finish adds
+// them in workgroup order (so the result does not depend on scheduling),
+// applies d|V|/dV = sign(V) and, if asked, the Adam update.
+// ---------------------------------------------------------------------------
+constexpr int MLP_T = 256;
+constexpr int REC = 69;  // LDS record per sample (odd stride: no bank conflicts)
+enum : int { R_H1 = 0, R_DZ2 = 16, R_DZ1 = 32, R_H2 = 48, R_DOUT = 64, R_T = 65, R_E = 66, R_ONE = 67 };
+
+__device__ __forceinline__ void acc_fields(int j, int& fa, int& fb) {
+    if (j < OFF_B1) { fa = R_DZ1 + j; fb = R_T; }
+    else if (j < OFF_V2) { fa = R_DZ1 + (j - OFF_B1); fb = R_ONE; }
+    else if (j < OFF_B2) { fa = R_DZ2 + (j - OFF_V2) / MLP_H; fb = R_H1 + (j - OFF_V2) % MLP_H; }
+    else if (j < OFF_V3) { fa = R_DZ2 + (j - OFF_B2); fb = R_ONE; }
+    else if (j < OFF_B3) { fa = R_DOUT; fb = R_H2 + (j - OFF_V3); }
+    else if (j == OFF_B3) { fa = R_DOUT; fb = R_ONE; }
+    else { fa = R_E; fb = R_E; }
+}
+
+__global__ __launch_bounds__(MLP_T) void k_mlp_step(MlpStep A) {
+    if (A.gate && A.gate[0] == 0) return;
+    __shared__ float w[MLP_NP];
+    __shared__ float rec[MLP_T * REC];
+    __shared__ int last;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < MLP_NP; i += MLP_T) w[i] = mlp_is_weight(i) ? fabsf(A.p[i]) : A.p[i];
+    int fa0, fb0, fa1 = 0, fb1 = 0;
+    acc_fields(tid, fa0, fb0);
+    const bool two = tid + MLP_T < MLP_ACC;
+    if (two) acc_fields(tid + MLP_T, fa1, fb1);
+    __syncthreads();
+    const float inv_s = 1.0f / (float)A.S;
+    const uint64_t chunk = (A.S + gridDim.x - 1) / gridDim.x;
+    const uint64_t lo = (uint64_t)blockIdx.x * chunk, hi = min(A.S, lo + chunk);
+    float acc0 = 0.0f, acc1 = 0.0f;
+    float* r = rec + tid * REC;
+    for (uint64_t base = lo; base < hi; base += MLP_T) {
+        lds_reload_fence();
+        const uint64_t s = base + tid;
+        if (s < hi) {
+            // forward; a hidden unit is active (derivative 1) exactly when its
+            // output is non-zero, so the activations double as the masks
+            const float tt = A.t[s];
+            float h1[MLP_H];
+#pragma unroll
+            for (int k = 0; k < MLP_H; k++) {
+                const float z = __builtin_fmaf(w[OFF_V1 + k], tt, w[OFF_B1 + k]);
+                h1[k] = k < MLP_HALF ? fmaxf(z, 0.0f) : fminf(z, 0.0f);
+                r[R_H1 + k] = h1[k];
+            }
+            float out = w[OFF_B3];
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+#pragma unroll 1
+                for (int i = half * MLP_HALF; i < (half + 1) * MLP_HALF; i++) {
+                    float z = w[OFF_B2 + i];
+#pragma unroll
+                    for (int k = 0; k < MLP_H; k++) z = __builtin_fmaf(w[OFF_V2 + MLP_H * i + k], h1[k], z);
+                    const float h = half == 0 ? fmaxf(z, 0.0f) : fminf(z, 0.0f);
+                    r[R_H2 + i] = h;
+                    out = __builtin_fmaf(w[OFF_V3 + i], h, out);
+                }
+            }
+            // backward
+            const float e = out - A.y[s];
+            const float dout = 2.0f * e * inv_s;
+            float dh1[MLP_H];
+#pragma unroll
+            for (int k = 0; k < MLP_H; k++) dh1[k] = 0.0f;
+#pragma unroll 1
+            for (int i = 0; i < MLP_H; i++) {
+                const float dz2 = r[R_H2 + i] != 0.0f ? dout * w[OFF_V3 + i] : 0.0f;
+                r[R_DZ2 + i] = dz2;
+#pragma unroll
+                for (int k = 0; k < MLP_H; k++) dh1[k] = __builtin_fmaf(dz2, w[OFF_V2 + MLP_H * i + k], dh1[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < MLP_H; k++) r[R_DZ1 + k] = h1[k] != 0.0f ? dh1[k] : 0.0f;
+            r[R_DOUT] = dout;
+            r[R_T] = tt;
+            r[R_E] = e;
+        } else {
+#pragma unroll
+            for (int f = 0; f < R_ONE; f++) r[f] = 0.0f;
+        }
+        r[R_ONE] = 1.0f;
+        __syncthreads();
+        const int cnt = (int)min<uint64_t>(MLP_T, hi - base);
+        for (int q = 0; q < cnt; q++) {
+            const float* rq = rec + q * REC;
+            acc0 = __builtin_fmaf(rq[fa0], rq[fb0], acc0);
+            if (two) acc1 = __builtin_fmaf(rq[fa1], rq[fb1], acc1);
+        }
+        __syncthreads();
+    }
+    float* part = A.partial + (uint64_t)blockIdx.x * MLP_ACC;
+    part[tid] = acc0;
+    if (two) part[tid + MLP_T] = acc1;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(A.done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // totals in workgroup order: entries tid and tid + 256
+    __shared__ float sh_loss;
+    float gt[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int i = tid + q * MLP_T;
+        if (i >= MLP_ACC) continue;
+        float g = 0.0f;
+        for (uint32_t b = 0; b < gridDim.x; b++)
+            g += __hip_atomic_load(&A.partial[(uint64_t)b * MLP_ACC + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        gt[q] = g;
+        if (i == MLP_NP) sh_loss = g * inv_s;
+    }
+    __syncthreads();
+    const float loss = sh_loss;
+    // keep the parameters with the lowest loss seen so far (those the loss was
+    // just computed at, before this step's update)
+    const bool better = A.best && loss < *A.best_loss;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int i = tid + q * MLP_T;
+        if (i >= MLP_NP) continue;
+        float g = gt[q];
+        const float pv = A.p[i];
+        if (better) A.best[i] = pv;
+        if (mlp_is_weight(i)) g *= pv > 0.0f ? 1.0f : (pv < 0.0f ? -1.0f : 0.0f);  // d|V|/dV
+        if (A.grad_out) A.grad_out[i] = g;
+        if (A.update) {
+            // Adam on q = p / scale: its gradient is scale * g and p moves by scale * (q's step)
+            const float sc = A.scale ? A.scale[i] : 1.0f;
+            const float gs = sc * g;
+            const float mm = A.b1 * A.m[i] + (1.0f - A.b1) * gs;
+            const float vv = A.b2 * A.v[i] + (1.0f - A.b2) * gs * gs;
+            A.m[i] = mm;
+            A.v[i] = vv;
+            A.p[i] = pv - sc * (A.lr * (mm / A.c1) / (sqrtf(vv / A.c2) + A.eps));
+        }
+    }
+    if (tid == 0) {
+        if (better) *A.best_loss = loss;
+        if (A.loss_out) *A.loss_out = loss;
+        if (A.losses) A.losses[A.step - 1] = loss;
+        if (A.loss_pair) {
+            if (A.step == 1) A.loss_pair[0] = loss;
+            A.loss_pair[1] = A.best ? fminf(*A.best_loss, loss) : loss;
+        }
+    }
+    if (tid == 0) *A.done = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Model record of the MLP-rooted model: header, effective weights and
+// (optionally) the caller's pre-scaled leaves.
+// ---------------------------------------------------------------------------
+__global__ void k_mlp_install(const float* p, const double* lo_inv, uint32_t L, uint32_t B1, uint32_t log2B2, double R,
+                              const double* leaves, const uint32_t* gate, uint32_t* set, uint64_t* dst) {
+    if (gate && gate[0] == 0) return;
+    float* w = (float*)(dst + MLP_W_WORD);
+    for (int i = threadIdx.x; i < MLP_NP + 1; i += blockDim.x)
+        w[i] = i == MLP_NP ? 0.0f : (mlp_is_weight(i) ? fabsf(p[i]) : p[i]);
+    if (leaves)
+        for (uint32_t i = threadIdx.x; i < 4 * L; i += blockDim.x) ((double*)dst)[MLP_LEAF_WORD + i] = leaves[i];
+    if (threadIdx.x == 0) {
+        MlpModel* h = (MlpModel*)dst;
+        h->L = L; h->B1 = B1; h->log2B2 = log2B2; h->pad = 0;
+        h->lo = lo_inv[0]; h->inv = lo_inv[1]; h->R = R; h->pad2 = 0;
+        if (set) set[0] = 1;
+    }
+}
+
+// Model record -> LDS (weights and leaves) for the per-key kernels.
+__device__ __forceinline__ void load_mlp_model(const uint64_t* mdl, float* w, double* leaves, int tid, int nt) {
+    const MlpModel* h = (const MlpModel*)mdl;
+    const float* ws = (const float*)(mdl + MLP_W_WORD);
+    for (int i = tid; i < MLP_NP; i += nt) w[i] = ws[i];
+    for (uint32_t i = tid; i < 4 * h->L; i += nt) leaves[i] = ((const double*)mdl)[MLP_LEAF_WORD + i];
+}
+
+// Bucket ids of every key of the level's MLP-rooted segments, stored at the
+// key's absolute position so that the histogram and scatter passes read
+// them instead of evaluating the network twice.  K_MLP: level bucket
+// g >> log2(B2); K_MLP_FINE: g - win inside the parent's fine window.
+constexpr int IDS_T = 256;
+constexpr int IDS_K = 4;  // keys per thread per network pass
+
+__global__ __launch_bounds__(IDS_T) void k_mlp_ids(Params P) {
+    __shared__ float w[MLP_NP];
+    __shared__ double leaves[4 * L_MAX];
+    const int tid = threadIdx.x;
+    const int lvl = P.level;
+    const uint32_t nunit = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
+    const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
+    const uint64_t* src = P.keys[lvl & 1];
+    uint64_t cur = 0;
+    for (uint32_t t = blockIdx.x; t < nunit; t += gridDim.x) {
+        const Tile td = P.tiles[lvl & 1][t];
+        if (td.seg >= nseg) continue;
+        const Seg sg = P.segs[lvl & 1][td.seg];
+        if ((sg.kind != K_MLP && sg.kind != K_MLP_FINE) || (sg.flags & SEG_FAILED)) continue;
+        const uint64_t* mdl = (const uint64_t*)sg.model;
+        if (sg.model != cur) {
+            __syncthreads();
+            load_mlp_model(mdl, w, leaves, tid, IDS_T);
+            __syncthreads();
+            cur = sg.model;
+        }
+        const MlpModel* h = (const MlpModel*)mdl;
+        const double lo = h->lo, inv = h->inv, Rm1 = h->R - 1.0;
+        const float Lf = (float)h->L;
+        const uint32_t shift = sg.kind == K_MLP ? h->log2B2 : 0u;
+        const uint32_t win = sg.kind == K_MLP ? 0u : sg.win;
+        const uint64_t base = sg.off + (uint64_t)td.idx * UNIT;
+        const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
+        for (uint32_t i0 = 0; i0 < un; i0 += IDS_T * IDS_K) {
+            lds_reload_fence();
+            uint64_t raw[IDS_K];
+            uint32_t g[IDS_K];
+#pragma unroll
+            for (int k = 0; k < IDS_K; k++) {
+                const uint32_t i = i0 + k * IDS_T + tid;
+                raw[k] = i < un ? src[base + i] : 0;
+            }
+            mlp_root_buckets<IDS_K>(w, leaves, lo, inv, Lf, Rm1, raw, P.u64, g);
+#pragma unroll
+            for (int k = 0; k < IDS_K; k++) {
+                const uint32_t i = i0 + k * IDS_T + tid;
+                if (i < un) P.ids[base + i] = (uint16_t)((g[k] >> shift) - win);
+            }
+        }
+    }
+}
+
+// Bucket ids at total resolution under an MLP-rooted model record.
+__global__ __launch_bounds__(IDS_T) void k_mlp_rmi_buckets(const uint64_t* mdl, const uint64_t* keys, uint64_t n,
+                                                           int u64, uint32_t* out) {
+    __shared__ float w[MLP_NP];
+    __shared__ double leaves[4 * L_MAX];
+    load_mlp_model(mdl, w, leaves, threadIdx.x, IDS_T);
+    __syncthreads();
+    const MlpModel* h = (const MlpModel*)mdl;
+    const double lo = h->lo, inv = h->inv, Rm1 = h->R - 1.0;
+    const float Lf = (float)h->L;
+    const uint64_t step = (uint64_t)gridDim.x * IDS_T * IDS_K;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * IDS_T * IDS_K; i0 < n; i0 += step) {
+        lds_reload_fence();
+        uint64_t raw[IDS_K];
+        uint32_t g[IDS_K];
+#pragma unroll
+        for (int k = 0; k < IDS_K; k++) {
+            const uint64_t i = i0 + k * IDS_T + threadIdx.x;
+            raw[k] = i < n ? keys[i] : 0;
+        }
+        mlp_root_buckets<IDS_K>(w, leaves, lo, inv, Lf, Rm1, raw, u64, g);
+#pragma unroll
+        for (int k = 0; k < IDS_K; k++) {
+            const uint64_t i = i0 + k * IDS_T + threadIdx.x;
+            if (i < n) out[i] = g[k];
+        }
+    }
+}
+
+// The network alone as a CDF: g = min(floor(F * R), R - 1) in fp32.
+__global__ __launch_bounds__(IDS_T) void k_mlp_buckets(const float* p, const double* lo_inv, uint32_t R,
+                                                       const uint64_t* keys, uint64_t n, int u64, uint32_t* out) {
+    __shared__ float w[MLP_NP];
+    for (int i = threadIdx.x; i < MLP_NP; i += IDS_T) w[i] = mlp_is_weight(i) ? fabsf(p[i]) : p[i];
+    __syncthreads();
+    const double lo = lo_inv[0], inv = lo_inv[1];
+    const uint64_t step = (uint64_t)gridDim.x * IDS_T * IDS_K;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * IDS_T * IDS_K; i0 < n; i0 += step) {
+        lds_reload_fence();
+        uint64_t raw[IDS_K];
+        uint32_t g[IDS_K];
+#pragma unroll
+        for (int k = 0; k < IDS_K; k++) {
+            const uint64_t i = i0 + k * IDS_T + threadIdx.x;
+            raw[k] = i < n ? keys[i] : 0;
+        }
+        mlp_buckets_multi<IDS_K>(w, lo, inv, (float)R, raw, u64, g);
+#pragma unroll
+        for (int k = 0; k < IDS_K; k++) {
+            const uint64_t i = i0 + k * IDS_T + threadIdx.x;
+            if (i < n) out[i] = g[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+#define LAUNCH(kernel, grid, block, stream, ...)                                     \
+    do {                                                                             \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
+        return hipGetLastError();                                                    \
+    } while (0)
+
+static uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap) {
+    const uint64_t g = std::min<uint64_t>((n + threads - 1) / threads, cap);
+    return g ? (uint32_t)g : 1u;
+}
+
+hipError_t launch_mlp_prep(const uint64_t* s, uint64_t S, uint64_t stride, int u64, float* t, float* y, double* lo_inv,
+                           const uint32_t* gate, hipStream_t st) {
+    LAUNCH(k_mlp_prep, grid_for((S + stride - 1) / stride, 256, 2048), 256, st, s, S, stride, u64, t, y, lo_inv, gate);
+}
+hipError_t launch_mlp_setup(const float* t, uint64_t S, const float* init, double eps, float* p, float* m, float* v,
+                            float* best, float* scale, float* best_loss, unsigned int* done, const uint32_t* gate,
+                            hipStream_t st) {
+    LAUNCH(k_mlp_setup, 1, MLP_SETUP_T, st, t, S, init, eps, p, m, v, best, scale, best_loss, done, gate);
+}
+uint32_t mlp_step_grid(uint64_t S) { return grid_for(S, MLP_T, MLP_G); }
+hipError_t launch_mlp_step(const MlpStep& A, hipStream_t st) { LAUNCH(k_mlp_step, mlp_step_grid(A.S), MLP_T, st, A); }
+hipError_t launch_mlp_install(const float* p, const double* lo_inv, uint32_t L, uint32_t B1, uint32_t log2B2, double R,
+                              const double* leaves, const uint32_t* gate, uint32_t* set, uint64_t* dst,
+                              hipStream_t st) {
+    LAUNCH(k_mlp_install, 1, 512, st, p, lo_inv, L, B1, log2B2, R, leaves, gate, set, dst);
+}
+hipError_t launch_mlp_ids(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_mlp_ids, grid, IDS_T, st, P); }
+hipError_t launch_mlp_rmi_buckets(const uint64_t* mdl, const uint64_t* keys, uint64_t n, int u64, uint32_t* out,
+                                  hipStream_t st) {
+    LAUNCH(k_mlp_rmi_buckets, grid_for(n, IDS_T * IDS_K, 2048), IDS_T, st, mdl, keys, n, u64, out);
+}
+hipError_t launch_mlp_buckets(const float* p, const double* lo_inv, uint32_t R, const uint64_t* keys, uint64_t n,
+                              int u64, uint32_t* out, hipStream_t st) {
+    LAUNCH(k_mlp_buckets, grid_for(n, IDS_T * IDS_K, 2048), IDS_T, st, p, lo_inv, R, keys, n, u64, out);
+}
+
+}  // namespace ls

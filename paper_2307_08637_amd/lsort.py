@@ -74,8 +74,10 @@ def lib():
             "ls_partition_rmi": [vp, vp, u64, i32, vp, u32, dbl, u32, vp, vp, vp, vp],
             "ls_partition_splitters": [vp, vp, u64, i32, vp, vp, u32, vp, vp, vp, vp],
             "ls_mlp_loss_grad": [vp, vp, vp, u64, vp, vp, vp],
-            "ls_mlp_train": [vp, u64, i32, vp, u32, C.c_float, u64, vp, vp, vp, vp],
+            "ls_mlp_train": [vp, u64, i32, vp, u32, C.c_float, vp, vp, vp, vp],
             "ls_mlp_buckets": [vp, u64, i32, vp, vp, u32, vp, vp],
+            "ls_mlp_rmi_fit": [vp, u64, i32, vp, vp, u32, dbl, vp, vp],
+            "ls_mlp_rmi_buckets": [vp, u64, i32, vp, vp, vp, u32, dbl, vp, vp],
             "ls_timing": [i32],
             "ls_timing_read": [vp, u32, vp],
         }
@@ -258,6 +260,62 @@ def partition_splitters(keys, u, eq, payload=None):
                                         u.numel(), _ptr(ok), _ptr(op), _ptr(counts), _stream()))
     return ok, op, counts
 
+
+# -- MLP CDF ---------------------------------------------------------------------------
+
+MLP_NP = 321
+
+
+def mlp_loss_grad(params: torch.Tensor, t: torch.Tensor, y: torch.Tensor):
+    """(loss, grad) of the mean squared error at params (float32[321]) over
+    inputs t and targets y (float32, device)."""
+    for a, nm in ((params, "params"), (t, "t"), (y, "y")):
+        _dev(a, nm)
+        if a.dtype != torch.float32:
+            raise ValueError(f"{nm} must be float32")
+    grad = torch.empty(MLP_NP, dtype=torch.float32, device=t.device)
+    loss = torch.empty(1, dtype=torch.float32, device=t.device)
+    _check(lib().ls_mlp_loss_grad(_ptr(params), _ptr(t), _ptr(y), t.numel(), _ptr(grad), _ptr(loss), _stream()))
+    return loss, grad
+
+
+def mlp_train(sorted_sample: torch.Tensor, steps: int, lr: float, params_init: torch.Tensor | None = None):
+    """Train on a sorted sample: returns (params float32[321], lo_inv float64[2],
+    losses float32[steps])."""
+    _dev(sorted_sample, "sorted_sample")
+    dev = sorted_sample.device
+    params = torch.empty(MLP_NP, dtype=torch.float32, device=dev)
+    lo_inv = torch.empty(2, dtype=torch.float64, device=dev)
+    losses = torch.empty(max(steps, 1), dtype=torch.float32, device=dev)
+    _check(lib().ls_mlp_train(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), _ptr(params_init),
+                              steps, float(lr), _ptr(params), _ptr(lo_inv), _ptr(losses), _stream()))
+    return params, lo_inv, losses[:steps]
+
+
+def mlp_buckets(keys: torch.Tensor, params: torch.Tensor, lo_inv: torch.Tensor, R: int) -> torch.Tensor:
+    _dev(keys, "keys")
+    out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
+    _check(lib().ls_mlp_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(params), _ptr(lo_inv), R, _ptr(out),
+                                _stream()))
+    return out
+
+
+def mlp_rmi_fit(sorted_sample: torch.Tensor, params: torch.Tensor, lo_inv: torch.Tensor, L: int,
+                R: float) -> torch.Tensor:
+    _dev(sorted_sample, "sorted_sample")
+    leaves = torch.empty(4 * L, dtype=torch.float64, device=sorted_sample.device)
+    _check(lib().ls_mlp_rmi_fit(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), _ptr(params),
+                                _ptr(lo_inv), L, float(R), _ptr(leaves), _stream()))
+    return leaves
+
+
+def mlp_rmi_buckets(keys: torch.Tensor, params: torch.Tensor, lo_inv: torch.Tensor, leaves: torch.Tensor, L: int,
+                    R: float) -> torch.Tensor:
+    _dev(keys, "keys")
+    out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
+    _check(lib().ls_mlp_rmi_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(params), _ptr(lo_inv), _ptr(leaves),
+                                    L, float(R), _ptr(out), _stream()))
+    return out
 
 def timing(enable: bool) -> None:
     """Start (clearing earlier records) or stop per-kernel event timing."""

@@ -381,6 +381,37 @@ def test_mlp_init_is_the_octile_interpolant(law):
         assert abs(oracle.mlp_forward(pe, float(q)) - oracle.mlp_forward(p, float(q))) < 0.02
 
 
+@pytest.mark.parametrize("law", ["lognormal", "piecewise"])
+def test_mlp_step_scale_bounds_preactivation_change(law):
+    """One training step from the start point changes every layer-2
+    pre-activation, anywhere on t in [0, 1], by at most
+    lr * (1 + sum_k (s_k (B_k + 2 lr) + |V2_ik| 2 lr)) with B_k the activation
+    bound of unit k -- about 17 lr -- because the step of a layer-2 weight is
+    scaled by 1 / B_k.  (Unscaled, a weight feeding a first-layer ramp of
+    width 1e-4 would move its pre-activation by ~1e4 lr.)  Also pins the
+    composition: the first bias-corrected step of each parameter is exactly
+    s * lr * g_s / (|g_s| + eps) with g_s = s g."""
+    S, lr = 4096, 1e-2
+    s = oracle.sort(inputs.generate(law, S, seed=9))[0]
+    lo, inv = oracle.mlp_lo_inv(s)
+    t = oracle.mlp_inputs(s, lo, inv).astype(np.float64)
+    y = np.arange(S) / S
+    p0 = oracle.mlp_init(t)
+    sc = oracle.mlp_step_scale(p0)
+    p1, _ = oracle.mlp_train(t, y, p0, 1, lr, final=True)
+    _, g = oracle.mlp_loss_grad(p0, t, y)
+    gs = sc * g
+    want = -sc * lr * gs / (np.abs(gs) + 1e-8)
+    assert np.all(np.abs((p1 - p0) - want) <= 1e-9 * np.abs(want) + 1e-15 * np.maximum(1.0, np.abs(p0)))
+    bound = np.maximum(1.0, np.abs(p0[0:16]) + np.abs(p0[16:32]))
+    assert bound.max() > 10  # the case the scale is for: steep first-layer ramps
+    V2 = np.abs(p0[32:288]).reshape(16, 16)
+    limit = lr * (1 + (sc[32:48] * (bound + 2 * lr)).sum() + 2 * lr * V2.sum(axis=1) / lr)
+    for q in np.unique(np.concatenate([t[::64], np.linspace(0, 1, 257)])):
+        z0 = oracle.mlp_forward_full(p0, q)[3]
+        z1 = oracle.mlp_forward_full(p1, q)[3]
+        assert np.all(np.abs(z1 - z0) <= limit * (1 + 1e-9) + 1e-12), q
+
 def mlp_root_case(law, S=20_000, L=200, seed=3, steps=0):
     s = oracle.sort(inputs.generate(law, S, seed=seed))[0]
     x = oracle.model_x(s)
