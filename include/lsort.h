@@ -66,6 +66,7 @@ typedef enum {
 #define LS_FLAG_SYNC_LEVELS   0x2u  /* (host) read back the work count after each level to stop early; default on */
 #define LS_FLAG_FIXED_LEVELS  0x4u  /* launch exactly max_levels levels with no host read-back (graph capture) */
 #define LS_FLAG_COLLECT_STATS 0x8u  /* record per-level statistics (read with ls_get_stats) */
+#define LS_FLAG_TUNED         0x10u /* take buckets / cutoff / tree_buckets left 0 from the loaded tuning table */
 
 /* Options.  Zero-initialise and set struct_size = sizeof(ls_options); every
  * zero field takes its default. */
@@ -153,6 +154,31 @@ ls_status ls_get_stats(ls_stats *out);
 
 /* Message for the last non-OK status on this thread (never NULL). */
 const char *ls_last_error(void);
+
+/* ---- Tuning (batched and single-array form) -------------------------------- */
+/* Autotuner: on the current device, for each size class -- the decimal order
+ * of magnitude of the average array size n / m, 1e3 .. 1e8 -- time every
+ * candidate (buckets in {256, 512, 1000, 1024}, cutoff in {256, 512},
+ * tree_buckets in {128, 256}) on synthetic arrays it generates on the device
+ * (uniform, normal and lognormal laws; ~2e7 keys in arrays log-uniform over
+ * [avg / 4, 4 avg) for the batched classes, one array of 1e7 or 1e8 keys for
+ * the others), keep the fastest, write a JSON table to table_path (host
+ * path) keyed by the device's architecture and compute-unit count, and load
+ * it.  Synchronous; allocates its own buffers; takes about a minute.
+ * Errors: LS_EINVAL (path), LS_EHIP, and those of ls_sort. */
+ls_status ls_autotune(const char *table_path);
+
+/* Load a table written by ls_autotune (NULL: unload).  Afterwards a call
+ * with opt == NULL, or with LS_FLAG_TUNED set, takes buckets, cutoff and
+ * tree_buckets that it leaves 0 from the entry of its size class (the
+ * nearest class present; ties go to the smaller class).  Errors: LS_EINVAL
+ * (unreadable, malformed, out of range, or made on a different device
+ * architecture / CU count). */
+ls_status ls_load_tuning(const char *table_path);
+
+/* The options a call over n_total keys in m arrays with opt == NULL would
+ * use (defaults, or the loaded table's entry).  out: host. */
+ls_status ls_tuned_options(uint64_t n_total, uint64_t m, ls_options *out);
 
 /* Library version string, e.g. "lsort 0.1 gfx950". */
 const char *ls_version(void);

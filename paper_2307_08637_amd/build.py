@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblsort.so")
-SOURCES = ["lsort_kernels.hip", "lsort_fit.hip", "lsort_mlp.hip", "lsort_api.hip"]
+SOURCES = ["lsort_kernels.hip", "lsort_fit.hip", "lsort_mlp.hip", "lsort_tune.hip", "lsort_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

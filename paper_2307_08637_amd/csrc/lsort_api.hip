@@ -50,11 +50,50 @@ struct Opts {
     float mlp_lr;
 };
 
-static ls_status normalize(const ls_options* o, Opts& r) {
+// ---------------------------------------------------------------------------
+// tuning table (ls_autotune / ls_load_tuning): per size class -- the decimal
+// order of magnitude of the average array size n / m -- the bucket count,
+// base-case cutoff and splitter fan-out that ran fastest on this device
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+int report_error(int status, const char* msg) { return fail((ls_status)status, msg); }
+
+void tuning_install(const std::vector<TuneEntry>& t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune = t;
+}
+
+static int size_class(uint64_t n, uint64_t m) {
+    const double avg = (double)n / (double)std::max<uint64_t>(m, 1);
+    return (int)std::floor(std::log10(std::max(avg, 1.0)) + 1e-9);
+}
+
+// Fields the caller left zero take the table's values for the call's class
+// (the nearest class in the table when its own is missing; ties go to the
+// smaller class).
+static void apply_tuning(const ls_options* o, Opts& r, uint64_t n, uint64_t m) {
+    if (n == 0 || (o && !(o->flags & LS_FLAG_TUNED))) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune.empty()) return;
+    const int c = size_class(n, m);
+    const TuneEntry* best = &g_tune[0];
+    for (const TuneEntry& e : g_tune)
+        if (std::abs(e.cls - c) < std::abs(best->cls - c)) best = &e;
+    if (!o || !o->buckets) r.buckets = best->buckets;
+    if (!o || !o->cutoff) r.cutoff = best->cutoff;
+    if (!o || !o->tree_buckets) r.tree_buckets = best->tree_buckets;
+}
+
+static ls_status normalize(const ls_options* o, Opts& r, uint64_t n = 0, uint64_t m = 0) {
     r.model = LS_MODEL_AUTO; r.buckets = 1000; r.leaves = 1000; r.tree_buckets = 256; r.cutoff = 512;
     r.max_levels = 16; r.flags = LS_FLAG_SYNC_LEVELS; r.sample_frac = 0.01; r.fallback_ratio = 2.0; r.seed = 0x5EED;
     r.mlp_steps = 200; r.mlp_sample = 1000000; r.mlp_lr = 3e-3f;
-    if (!o) return LS_OK;
+    if (!o) {
+        apply_tuning(o, r, n, m);
+        return LS_OK;
+    }
     if (o->struct_size != sizeof(ls_options)) return fail(LS_EINVAL, "ls_options.struct_size mismatch");
     if (o->model > LS_MODEL_SPLITTER) return fail(LS_EINVAL, "unknown model");
     r.model = o->model;
@@ -70,6 +109,7 @@ static ls_status normalize(const ls_options* o, Opts& r) {
     if (o->mlp_steps) r.mlp_steps = o->mlp_steps;
     if (o->mlp_sample) r.mlp_sample = o->mlp_sample;
     if (o->mlp_lr > 0) r.mlp_lr = o->mlp_lr;
+    apply_tuning(o, r, n, m);
     if (r.buckets < 2 || r.buckets > B_MAX) return fail(LS_EINVAL, "buckets must be in [2, 1024]");
     if (r.leaves < 2 || r.leaves > L_MAX) return fail(LS_EINVAL, "leaves must be in [2, 1024]");
     if (r.tree_buckets < 2 || r.tree_buckets > 512 || (r.tree_buckets & (r.tree_buckets - 1)))
@@ -569,7 +609,7 @@ static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, ui
     ls_status s = check_keys(keys, n, dtype, payload);
     if (s) return s;
     Opts o;
-    if ((s = normalize(opt, o))) return s;
+    if ((s = normalize(opt, o, n, m))) return s;
     if (o.model == LS_MODEL_MLP && offsets)
         return fail(LS_EUNSUPPORTED, "the MLP model is available for single arrays (ls_sort) only");
     if (n <= 1 || m == 0) return LS_OK;
@@ -635,7 +675,7 @@ ls_status ls_workspace_bytes(uint64_t n_total, uint64_t m, ls_dtype dtype, int h
     if (!out) return fail(LS_EINVAL, "out is NULL");
     if (dtype != LS_F64 && dtype != LS_U64) return fail(LS_EINVAL, "bad dtype");
     Opts o;
-    ls_status s = normalize(opt, o);
+    ls_status s = normalize(opt, o, std::max<uint64_t>(n_total, 16), std::max<uint64_t>(m, 1));
     if (s) return s;
     *out = (size_t)plan(std::max<uint64_t>(n_total, 16), std::max<uint64_t>(m, 1), has_payload, o).bytes;
     return LS_OK;
@@ -1004,6 +1044,20 @@ ls_status ls_mlp_rmi_buckets(const void* keys, uint64_t n, ls_dtype dtype, const
     HIP_TRY(launch_mlp_install(params, lo_inv, L, 1, 0, R, leaves, nullptr, nullptr, mdl, st));
     HIP_TRY(launch_mlp_rmi_buckets(mdl, (const uint64_t*)keys, n, dtype == LS_U64, out, st));
     return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
+ls_status ls_tuned_options(uint64_t n_total, uint64_t m, ls_options* out) {
+    if (!out) return fail(LS_EINVAL, "out is NULL");
+    Opts o;
+    ls_status s = normalize(nullptr, o, std::max<uint64_t>(n_total, 1), std::max<uint64_t>(m, 1));
+    if (s) return s;
+    std::memset(out, 0, sizeof(*out));
+    out->struct_size = sizeof(ls_options);
+    out->model = o.model; out->buckets = o.buckets; out->leaves = o.leaves; out->tree_buckets = o.tree_buckets;
+    out->cutoff = o.cutoff; out->max_levels = o.max_levels; out->flags = o.flags; out->sample_frac = o.sample_frac;
+    out->fallback_ratio = o.fallback_ratio; out->seed = o.seed; out->mlp_steps = o.mlp_steps;
+    out->mlp_sample = o.mlp_sample; out->mlp_lr = o.mlp_lr;
+    return LS_OK;
 }
 
 }  // extern "C"

@@ -1,5 +1,7 @@
 // lsort_kernels.hpp -- host-side launch wrappers of the liblsort kernels.
 #pragma once
+#include <vector>
+
 #include "lsort_internal.hpp"
 
 namespace ls {
@@ -95,5 +97,15 @@ hipError_t launch_mlp_rmi_buckets(const uint64_t* mdl, const uint64_t* keys, uin
                                   hipStream_t st);
 hipError_t launch_mlp_buckets(const float* p, const double* lo_inv, uint32_t R, const uint64_t* keys, uint64_t n,
                               int u64, uint32_t* out, hipStream_t st);
+
+// tuning table (lsort_api.hip) and the synthetic inputs of the autotuner (lsort_tune.hip)
+struct TuneEntry {
+    int cls;                                // floor(log10(n / m))
+    uint32_t buckets, cutoff, tree_buckets; // fastest options measured for the class
+    double ms, default_ms;                  // their time and the defaults' time (informational)
+};
+void tuning_install(const std::vector<TuneEntry>& t);
+int report_error(int status, const char* msg);  // sets ls_last_error(), returns status
+hipError_t launch_tune_fill(double* keys, const uint64_t* offsets, uint64_t m, uint64_t seed, hipStream_t st);
 
 }  // namespace ls

@@ -112,14 +112,19 @@ def generate(law: str, n: int, seed: int) -> np.ndarray:
     raise ValueError(f"unknown law {law!r}")
 
 
-def segmented(m: int, seed: int, lo: float = 1e3, hi: float = 1e6, laws=F64_LAWS):
+def segmented(m: int, seed: int, lo: float = 1e3, hi: float = 1e6, laws=F64_LAWS, max_total: int | None = None):
     """Batched workload: m arrays with sizes floor(exp(U[ln lo, ln hi])), each
     drawn from a law picked uniformly from `laws`, concatenated.  Returns
     (keys float64, offsets uint64[m+1], payload uint32 = index within its
-    array, law index per array)."""
+    array, law index per array).  With max_total, only the leading arrays up
+    to the first one at which the running total reaches max_total."""
     g = _rng(seed, 1 << 31)
     sizes = np.floor(np.exp(g.uniform(math.log(lo), math.log(hi), m))).astype(np.int64)
     which = g.integers(0, len(laws), m)
+    if max_total is not None:
+        cut = int(np.searchsorted(np.cumsum(sizes), max_total)) + 1
+        m = min(m, cut)
+        sizes, which = sizes[:m], which[:m]
     off = np.zeros(m + 1, dtype=np.uint64)
     off[1:] = np.cumsum(sizes, dtype=np.uint64)
     keys = np.empty(int(off[-1]), dtype=np.float64)

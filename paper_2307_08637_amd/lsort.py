@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "liblsort.so")
 
 LS_F64, LS_U64 = 0, 1
 MODEL = {"auto": 0, "rmi": 1, "mlp": 2, "splitter": 3}
-FLAG_NO_FALLBACK, FLAG_SYNC_LEVELS, FLAG_FIXED_LEVELS, FLAG_COLLECT_STATS = 1, 2, 4, 8
+FLAG_NO_FALLBACK, FLAG_SYNC_LEVELS, FLAG_FIXED_LEVELS, FLAG_COLLECT_STATS, FLAG_TUNED = 1, 2, 4, 8, 16
 MAX_STAT_LEVELS = 32
 
 
@@ -77,6 +77,9 @@ def lib():
             "ls_mlp_train": [vp, u64, i32, vp, u32, C.c_float, vp, vp, vp, vp],
             "ls_mlp_buckets": [vp, u64, i32, vp, vp, u32, vp, vp],
             "ls_mlp_rmi_fit": [vp, u64, i32, vp, vp, u32, dbl, vp, vp],
+            "ls_autotune": [C.c_char_p],
+            "ls_load_tuning": [C.c_char_p],
+            "ls_tuned_options": [u64, u64, vp],
             "ls_mlp_rmi_buckets": [vp, u64, i32, vp, vp, vp, u32, dbl, vp, vp],
             "ls_timing": [i32],
             "ls_timing_read": [vp, u32, vp],
@@ -123,7 +126,7 @@ def _dev(t: torch.Tensor, name: str):
 
 def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, max_levels=0, flags=0,
                  sample_frac=0.0, fallback_ratio=0.0, seed=0, mlp_steps=0, mlp_sample=0, mlp_lr=0.0,
-                 stats=True, fixed_levels=False, no_fallback=False) -> Options:
+                 stats=True, fixed_levels=False, no_fallback=False, tuned=False) -> Options:
     o = Options()
     o.struct_size = C.sizeof(Options)
     o.model = MODEL[model] if isinstance(model, str) else int(model)
@@ -131,6 +134,7 @@ def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, ma
     f = flags | (FLAG_COLLECT_STATS if stats else 0)
     f |= FLAG_FIXED_LEVELS if fixed_levels else FLAG_SYNC_LEVELS
     f |= FLAG_NO_FALLBACK if no_fallback else 0
+    f |= FLAG_TUNED if tuned else 0
     o.flags = f
     o.sample_frac, o.fallback_ratio, o.seed = sample_frac, fallback_ratio, seed
     o.mlp_steps, o.mlp_sample, o.mlp_lr = mlp_steps, mlp_sample, mlp_lr
@@ -316,6 +320,25 @@ def mlp_rmi_buckets(keys: torch.Tensor, params: torch.Tensor, lo_inv: torch.Tens
     _check(lib().ls_mlp_rmi_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(params), _ptr(lo_inv), _ptr(leaves),
                                     L, float(R), _ptr(out), _stream()))
     return out
+
+# -- tuning ---------------------------------------------------------------------------
+
+def autotune(table_path: str) -> None:
+    """Time the candidate options per size class on this device, write the
+    JSON table and load it (about a minute)."""
+    _check(lib().ls_autotune(os.fsencode(table_path)))
+
+
+def load_tuning(table_path: str | None) -> None:
+    """Load a table written by autotune (None: unload).  Calls made with
+    tuned=True then take buckets / cutoff / tree_buckets from it."""
+    _check(lib().ls_load_tuning(None if table_path is None else os.fsencode(table_path)))
+
+
+def tuned_options(n: int, m: int = 1) -> dict:
+    o = Options()
+    _check(lib().ls_tuned_options(n, m, C.byref(o)))
+    return {"buckets": o.buckets, "cutoff": o.cutoff, "tree_buckets": o.tree_buckets, "leaves": o.leaves}
 
 def timing(enable: bool) -> None:
     """Start (clearing earlier records) or stop per-kernel event timing."""

@@ -77,3 +77,56 @@ def test_workspace_bytes_host_only():
     big = lsort.workspace_bytes(10**8)
     assert 0 < small < big
     assert lsort.workspace_bytes(10**6, payload=True) > small
+
+
+TABLE = """{
+  "format": "lsort-tuning-1",
+  "device": "%s",
+  "cus": %d,
+  "classes": [
+    {"log10_avg_size": 3, "buckets": 256, "cutoff": 256, "tree_buckets": 128, "ms": 1.0, "default_ms": 1.2},
+    {"log10_avg_size": 6, "buckets": 512, "cutoff": 512, "tree_buckets": 256, "ms": 2.0, "default_ms": 2.1},
+    {"log10_avg_size": 8, "buckets": 1000, "cutoff": 256, "tree_buckets": 256, "ms": 4.0, "default_ms": 4.5}
+  ]
+}
+"""
+
+
+def test_tuning_table_lookup(tmp_path):
+    """Loading a table changes exactly the tuned fields, by size class (the
+    nearest class present), and unloading restores the defaults.  No GPU is
+    touched: without a device the table's device key is not compared."""
+    import torch
+    from paper_2307_08637_amd import lsort
+    if torch.cuda.is_available():
+        pytest.skip("the device-key check needs a table made on this device; covered by the GPU tests")
+    path = tmp_path / "t.json"
+    path.write_text(TABLE % ("gfx950", 256))
+    defaults = lsort.tuned_options(10**6, 1)
+    assert defaults["buckets"] == 1000 and defaults["cutoff"] == 512 and defaults["tree_buckets"] == 256
+    lsort.load_tuning(str(path))
+    try:
+        assert lsort.tuned_options(10**6, 1) == {"buckets": 512, "cutoff": 512, "tree_buckets": 256, "leaves": 1000}
+        assert lsort.tuned_options(2 * 10**7, 20_000)["buckets"] == 256          # class 3
+        assert lsort.tuned_options(10**8, 1)["cutoff"] == 256                    # class 8
+        assert lsort.tuned_options(10**4, 1)["buckets"] == 256                   # class 4 -> nearest 3
+        assert lsort.tuned_options(3 * 10**7, 1)["buckets"] == 512               # class 7: tie, smaller class (6)
+    finally:
+        lsort.load_tuning(None)
+    assert lsort.tuned_options(10**6, 1) == defaults
+
+
+@pytest.mark.parametrize("text", ["{}", '{"format": "other"}',
+                                  TABLE.replace('"buckets": 512', '"buckets": 5000') % ("gfx950", 256),
+                                  TABLE.replace('"tree_buckets": 128', '"tree_buckets": 100') % ("gfx950", 256)])
+def test_tuning_table_rejects_bad_files(tmp_path, text):
+    import torch
+    from paper_2307_08637_amd import lsort
+    if torch.cuda.is_available():
+        pytest.skip("CPU-only check")
+    path = tmp_path / "bad.json"
+    path.write_text(text)
+    with pytest.raises(lsort.LsortError):
+        lsort.load_tuning(str(path))
+    with pytest.raises(lsort.LsortError):
+        lsort.load_tuning(str(tmp_path / "missing.json"))
