@@ -7,8 +7,15 @@ model fit, every partition level and the base case).  The keys of every
 timed step are already in HBM: K unsorted copies are made before the timed
 region and step k sorts copy k in place.
 
+Besides the headline line it reports, in extra fields of the same JSON
+object: the same sort per input law, the batched form (sort_segmented over
+the 10,000-array workload's first 2e8 keys, with payload), and the learned
+parts on the 70/20/10 piecewise law (RMI root vs MLP root vs splitter
+tree: first-level max/mean bucket ratio and Gkeys/s).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--law normal]
                        [--n 100000000] [--no-cpu-baseline] [--no-laws]
+                       [--no-batched] [--no-mlp] [--no-splitter]
 """
 from __future__ import annotations
 
@@ -50,6 +57,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-laws", action="store_true", help="skip the per-law table")
     p.add_argument("--cpu-keys", type=int, default=50_000_000, help="keys in the oracle's timed sample")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    p.add_argument("--no-mlp", action="store_true", help="skip the learned-parts comparison")
+    p.add_argument("--no-splitter", action="store_true", help="time the learned sort only (for profiling)")
+    p.add_argument("--mlp-n", type=int, default=100_000_000, help="keys of the piecewise-law comparison")
     return p.parse_args()
 
 
@@ -80,7 +91,7 @@ def main():
     def run(model, steps, timed_bufs):
         for _ in range(a.warmup):
             warm.copy_(base)
-            lsort.sort(warm, model=model)
+            lsort.sort(warm, model=model, stats=False)
         for b in timed_bufs[:steps]:
             b.copy_(base)
         torch.cuda.synchronize()
@@ -90,12 +101,14 @@ def main():
         t0 = time.perf_counter()
         e0.record()
         for b in timed_bufs[:steps]:
-            lsort.sort(b, model=model)
+            lsort.sort(b, model=model, stats=False)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kern = lsort.timing_read()
         lsort.timing(False)
+        warm.copy_(base)  # one more (untimed) sort for the per-level statistics
+        lsort.sort(warm, model=model)
         st = lsort.stats()
         # the result must be a sorted permutation (cheap properties on the GPU)
         k = timed_bufs[0].view(torch.int64)
@@ -107,8 +120,10 @@ def main():
 
     log("learned", a.steps, "steps")
     L = run("auto", a.steps, bufs)
-    log("splitter", a.steps, "steps")
-    S = run("splitter", a.steps, bufs)
+    S = None
+    if not a.no_splitter:
+        log("splitter", a.steps, "steps")
+        S = run("splitter", a.steps, bufs)
 
     gk = lambda r: a.n / (r["ms_per_step"] * 1e-3) / 1e9  # noqa: E731
     kern = L["kernels"]
@@ -131,7 +146,7 @@ def main():
                  "fallback": lv["fallback"]} for lv in st["levels"]]
 
     laws = {}
-    if not a.no_laws:
+    if not a.no_laws and S is not None:
         for law in ("uniform", "normal", "lognormal", "exponential", "chisquared", "mixgauss", "u64"):
             if law == a.law:
                 laws[law] = {"learned": round(gk(L), 3), "splitter": round(gk(S), 3)}
@@ -145,6 +160,16 @@ def main():
             rs = run_on(src, bb, "splitter", lsort, torch)
             laws[law] = {"learned": round(a.n / (rl * 1e-3) / 1e9, 3), "splitter": round(a.n / (rs * 1e-3) / 1e9, 3)}
             del src, h
+
+    batched = None
+    if not a.no_batched:
+        bufs = warm = None
+        torch.cuda.empty_cache()
+        batched = run_batched(inputs, lsort, torch, np, dev, log)
+    mlp = None
+    if not a.no_mlp:
+        torch.cuda.empty_cache()
+        mlp = run_learned_parts(inputs, lsort, torch, np, dev, log, a.mlp_n, a.seed)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -179,30 +204,103 @@ def main():
                      "bytes_per_key": BYTES_PER_KEY[dom], "avg_launch_ms": round(avg_ms, 4),
                      "launches": dk["launches"]},
         "cpu_baseline": cpu,
-        "splitter": {"value": round(gk(S), 4), "ms_per_step": round(S["ms_per_step"], 4),
-                     "levels": level_summary(S["stats"])},
-        "learned_over_splitter": round(gk(L) / gk(S), 4),
+        "splitter": None if S is None else {"value": round(gk(S), 4), "ms_per_step": round(S["ms_per_step"], 4),
+                                            "levels": level_summary(S["stats"])},
+        "learned_over_splitter": None if S is None else round(gk(L) / gk(S), 4),
         "levels": level_summary(L["stats"]),
         "kernels": {k: {"launches": v["launches"], "ms_per_step": round(v["ms"] / a.steps, 4),
                         "keys_per_step": v["keys"] / a.steps} for k, v in kern.items()},
         "wall_ms_per_step": round(L["wall_ms_per_step"], 4),
         "laws": laws,
+        "batched": batched,
+        "learned_parts": mlp,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_batched(inputs, lsort, torch, np, dev, log):
+    """sort_segmented over the 10,000-array workload (sizes log-uniform in
+    [1e3, 1e6], five float64 laws, uint32 payload) up to its first 2e8
+    keys; restore copies are outside the timed region."""
+    log("batched: generating")
+    keys, off, pay, _ = inputs.segmented(10_000, seed=41, max_total=200_000_000)
+    k0 = torch.from_numpy(keys).to(dev)
+    p0 = torch.from_numpy(pay.view(np.int32)).to(dev).view(torch.uint32)
+    o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+    k, p = torch.empty_like(k0), torch.empty_like(p0)
+    del keys, pay
+    res = {}
+    for name, opts in (("learned", {}), ("splitter", {"model": "splitter"})):
+        log("batched:", name)
+        tot = 0.0
+        reps = 3
+        for r in range(reps + 1):
+            k.copy_(k0)
+            p.view(torch.int32).copy_(p0.view(torch.int32))
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lsort.sort_segmented(k, o, p, stats=False, **opts)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                tot += e0.elapsed_time(e1)
+        ms = tot / reps
+        res[name] = {"ms": round(ms, 3), "Gkeys/s": round(k0.numel() / (ms * 1e-3) / 1e9, 3)}
+    return {"workload": f"{off.size - 1} arrays (sizes log-uniform in [1e3, 1e6], five float64 laws) = "
+                        f"{int(off[-1])} keys + uint32 payload, stable", **res}
+
+
+def run_learned_parts(inputs, lsort, torch, np, dev, log, n, seed):
+    """The piecewise law (70% LogNormal(0, 2), 20% 1e6 + U[0, 1), 10% N(-5e3, 1)):
+    the RMI, the MLP-rooted model (200 Adam steps) and the splitter tree as
+    the first level; first-level max/mean bucket ratio and Gkeys/s."""
+    log("learned parts: generating", n)
+    h = inputs.generate("piecewise", n, seed=seed + 30)
+    src = torch.from_numpy(h).to(dev)
+    del h
+    buf = torch.empty_like(src)
+    res = {"workload": f"sort {n} float64 keys, piecewise law 70/20/10"}
+    for name, model in (("rmi", "auto"), ("mlp", "mlp"), ("splitter", "splitter")):
+        log("learned parts:", name)
+        tot = 0.0
+        reps = 3
+        for r in range(reps + 1):
+            buf.copy_(src)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lsort.sort(buf, model=model, stats=False)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                tot += e0.elapsed_time(e1)
+        buf.copy_(src)  # one more (untimed) sort for the statistics
+        lsort.sort(buf, model=model)
+        st = lsort.stats()
+        lv0 = st["levels"][0]
+        ms = tot / reps
+        res[name] = {"ms": round(ms, 3), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3),
+                     "first_level_max_over_mean": lv0["max_bucket_x1000_over_mean"] / 1000.0,
+                     "first_level_fallbacks": lv0["fallback"], "levels": len(st["levels"])}
+        if name == "mlp":
+            res[name]["loss_first"] = st["mlp_loss_first"]
+            res[name]["loss_best"] = st["mlp_loss_last"]
+    return res
 
 
 def run_on(src, bufs, model, lsort, torch):
     """ms per sort of `src` (K = len(bufs) copies, after one warm-up)."""
     tmp = bufs[0]
     tmp.copy_(src)
-    lsort.sort(tmp, model=model)
+    lsort.sort(tmp, model=model, stats=False)
     for b in bufs:
         b.copy_(src)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for b in bufs:
-        lsort.sort(b, model=model)
+        lsort.sort(b, model=model, stats=False)
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / len(bufs)

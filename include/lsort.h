@@ -205,6 +205,11 @@ ls_status ls_timing(int enable);
  * of names written.  Waits for the recorded work to finish. */
 ls_status ls_timing_read(ls_kernel_timing *out, uint32_t cap, uint32_t *count);
 
+/* The recorded launches one by one, in launch order (launches = 1 each;
+ * keys = the keys of the level the launch belongs to).  Host array of cap
+ * entries; *count gets the number written. */
+ls_status ls_timing_records(ls_kernel_timing *out, uint32_t cap, uint32_t *count);
+
 /* ---- Single steps (exposed so each step can be checked on its own) -------- */
 
 /* Random sample with replacement (Sec. 2.2: the model is trained on a ~1%

@@ -270,10 +270,10 @@ static thread_local LastCall g_last;
 // ---------------------------------------------------------------------------
 enum KernelId {
     KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_BASE_BIG, KI_GATHER, KI_FIT, KI_MLP_TRAIN,
-    KI_MLP_IDS, KI_N
+    KI_MLP_IDS, KI_RESIDENT, KI_N
 };
 static const char* KNAME[KI_N] = {"k_reset", "k_seed", "k_model", "k_hist", "k_scan", "k_scatter", "k_base_small",
-                                  "k_base_big", "k_gather", "k_fit", "k_mlp_step", "k_mlp_ids"};
+                                  "k_base_big", "k_gather", "k_fit", "k_mlp_step", "k_mlp_ids", "k_resident"};
 struct TRec {
     int kid;
     hipEvent_t a, b;
@@ -534,6 +534,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         const size_t rec0 = g_trec.size();
         const uint32_t g0 = lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024;
         TIMED(KI_MODEL, c.st, launch_model(P, g0, c.st));
+        if (!c.one_level) TIMED(KI_RESIDENT, c.st, launch_resident(P, cus * (c.pay ? 2 : 3), c.st));
         if (P.ids && lvl <= 1) TIMED(KI_MLP_IDS, c.st, launch_mlp_ids(P, cus * 4, c.st));
         TIMED(KI_HIST, c.st, launch_hist(P, cus * 4, c.st));
         TIMED(KI_SCAN, c.st, launch_scan(P, g0, c.st));
@@ -755,6 +756,28 @@ ls_status ls_timing_read(ls_kernel_timing* out, uint32_t cap, uint32_t* count) {
         if (!agg[i].launches) continue;
         out[k] = agg[i];
         std::snprintf(out[k].name, sizeof(out[k].name), "%s", KNAME[i]);
+        k++;
+    }
+    *count = k;
+    return LS_OK;
+}
+
+ls_status ls_timing_records(ls_kernel_timing* out, uint32_t cap, uint32_t* count) {
+    if (!out || !count) return fail(LS_EINVAL, "out / count is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint32_t k = 0;
+    for (const TRec& r : g_trec) {
+        if (k >= cap) break;
+        float ms = 0;
+        if (r.a && r.b) {
+            HIP_TRY(hipEventSynchronize(r.b));
+            HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        }
+        std::memset(&out[k], 0, sizeof(out[k]));
+        out[k].launches = 1;
+        out[k].ms = ms;
+        out[k].keys = r.keys;
+        std::snprintf(out[k].name, sizeof(out[k].name), "%s", KNAME[r.kid]);
         k++;
     }
     *count = k;

@@ -233,6 +233,36 @@ __device__ __forceinline__ uint32_t lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
+// Value of lane (lane ^ s) for s in {1, 2, 4, 8, 16, 32}, without LDS: DPP
+// quad permutes for 1 and 2, row rotates for 4 and 8 (16-lane rows), and the
+// gfx950 permlane swaps for 16 and 32.  Every lane must be active.  s must
+// be a compile-time constant after unrolling.
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t v, int s, uint32_t lane) {
+    switch (s) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    case 4: {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12C, 0xF, 0xF, false);  // row_ror 12: lane+4
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x124, 0xF, 0xF, false);  // row_ror 4: lane-4
+        return (lane & 4) ? dn : up;
+    }
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror 8
+    case 16: {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    }
+    default: {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
+    }
+}
+
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v, int s, uint32_t lane) {
+    const uint32_t lo = xor_lane32((uint32_t)v, s, lane), hi = xor_lane32((uint32_t)(v >> 32), s, lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Number of set bits of `mask` below this lane.
 __device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -407,7 +437,7 @@ __device__ void bitonic_pairs(uint64_t* a, uint16_t* ix, uint32_t P) {
 // Bitonic sort of 64*E (key, index) pairs held by one wavefront, lane l
 // holding elements l*E .. l*E+E-1 in registers.  Compare-exchanges between
 // elements of one lane stay in registers; those between lanes exchange
-// through cross-lane shuffles.  No LDS, no barriers.  Pairs are ordered by
+// through DPP / permlane lane exchanges.  No LDS, no barriers.  Pairs are ordered by
 // key, then index (indices are distinct), so the result is the stable order.
 template <int E, bool PAIRS>
 __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E], int lane) {
@@ -431,14 +461,16 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E]
                 }
             } else {
                 const int s = j / E;
-                const bool keep_min = (((lane * E) & kk) == 0) == ((lane & s) == 0);
+                // keep the smaller of the pair on one side, the larger on the
+                // other: take the partner's element iff (partner < mine) differs
+                // from "keep the larger" (equal elements are interchangeable)
+                const bool keep_max = (((lane * E) & kk) == 0) != ((lane & s) == 0);
 #pragma unroll
                 for (int e = 0; e < E; e++) {
-                    const uint64_t y = __shfl_xor(k[e], s);
-                    const uint32_t iy = PAIRS ? __shfl_xor(ix[e], s) : 0u;
+                    const uint64_t y = xor_lane64(k[e], s, (uint32_t)lane);
+                    const uint32_t iy = PAIRS ? xor_lane32(ix[e], s, (uint32_t)lane) : 0u;
                     const bool lt = y < k[e] || (PAIRS && y == k[e] && iy < ix[e]);
-                    const bool gt = y > k[e] || (PAIRS && y == k[e] && iy > ix[e]);
-                    if (keep_min ? lt : gt) {
+                    if (lt != keep_max) {
                         k[e] = y;
                         if (PAIRS) ix[e] = iy;
                     }
@@ -468,14 +500,13 @@ __device__ void block_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E], uint64_t* exk
                 if (PAIRS) exi[e * NT + t] = ix[e];
             }
             __syncthreads();
-            const bool keep_min = (((t * E) & kk) == 0) == ((t & s) == 0);
+            const bool keep_max = (((t * E) & kk) == 0) != ((t & s) == 0);
 #pragma unroll
             for (int e = 0; e < E; e++) {
                 const uint64_t y = exk[e * NT + (t ^ s)];
                 const uint32_t iy = PAIRS ? exi[e * NT + (t ^ s)] : 0u;
                 const bool lt = y < k[e] || (PAIRS && y == k[e] && iy < ix[e]);
-                const bool gt = y > k[e] || (PAIRS && y == k[e] && iy > ix[e]);
-                if (keep_min ? lt : gt) {
+                if (lt != keep_max) {
                     k[e] = y;
                     if (PAIRS) ix[e] = iy;
                 }
@@ -483,14 +514,13 @@ __device__ void block_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E], uint64_t* exk
         }
         for (; j >= E; j >>= 1) {  // partner in the same wavefront: shuffle
             const int s = j / E;
-            const bool keep_min = (((t * E) & kk) == 0) == ((t & s) == 0);
+            const bool keep_max = (((t * E) & kk) == 0) != ((t & s) == 0);
 #pragma unroll
             for (int e = 0; e < E; e++) {
                 const uint64_t y = __shfl_xor(k[e], s);
                 const uint32_t iy = PAIRS ? __shfl_xor(ix[e], s) : 0u;
                 const bool lt = y < k[e] || (PAIRS && y == k[e] && iy < ix[e]);
-                const bool gt = y > k[e] || (PAIRS && y == k[e] && iy > ix[e]);
-                if (keep_min ? lt : gt) {
+                if (lt != keep_max) {
                     k[e] = y;
                     if (PAIRS) ix[e] = iy;
                 }

@@ -87,8 +87,11 @@ struct Seg {
     uint32_t flags;   // SEG_* bits; model size in 8-byte words in bits 16..31
 };
 static_assert(sizeof(Seg) == 64, "segment descriptor is 64 bytes");
+constexpr uint32_t FLAG_STATS = 0x8u;   // LS_FLAG_COLLECT_STATS: per-level statistics wanted
 constexpr uint32_t SEG_PREBUILT = 1u;  // model already built (large first level)
 constexpr uint32_t SEG_FAILED = 2u;    // capacity exceeded; not partitioned
+constexpr uint32_t SEG_RESIDENT = 4u;  // sorted by one workgroup (k_resident): no work units
+constexpr uint64_t RES_MAX = 32768;    // largest segment a single workgroup takes (one work unit)
 
 struct Tile {          // one work unit of UNIT keys
     uint32_t seg;     // index in the level's segment list
@@ -112,6 +115,7 @@ struct Ctl {
     uint32_t nseg[MAXL + 1];        // segments at each level
     uint32_t ntile[MAXL + 1];       // tiles at each level
     uint32_t ticket[MAXL + 1];      // scatter unit tickets
+    uint32_t rticket[MAXL + 1];     // k_resident segment tickets
     uint32_t pad0;
     unsigned long long nitems;      // small base-case items (<= SMALL_MAX keys)
     unsigned long long nbig;        // large base-case items and copy items

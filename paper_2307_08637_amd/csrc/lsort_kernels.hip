@@ -58,7 +58,9 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
         const bool item = s < m && !prebuilt && n >= 2 && n <= P.cutoff;
         const bool small = item && n <= SMALL_MAX;
         const bool seg = s < m && (prebuilt ? n >= 1 : n > P.cutoff);
-        const uint32_t nt = seg ? (uint32_t)((n + UNIT - 1) / UNIT) : 0;
+        // an array small enough for one workgroup is sorted whole by k_resident
+        const bool resident = seg && !prebuilt && n <= RES_MAX;
+        const uint32_t nt = seg && !resident ? (uint32_t)((n + UNIT - 1) / UNIT) : 0;
         uint64_t itot, btot, stot, ttot;
         const uint64_t iex = block_excl_scan<256, uint64_t>(small ? 1 : 0, red64, &itot);
         const uint64_t bex = block_excl_scan<256, uint64_t>(item && !small ? 1 : 0, red64, &btot);
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
             } else {
                 Seg sg{};
                 sg.off = lo; sg.n = n; sg.kind = K_FRESH; sg.tile0 = (uint32_t)t0; sg.ntiles = nt;
-                sg.flags = prebuilt ? SEG_PREBUILT : 0;
+                sg.flags = prebuilt ? SEG_PREBUILT : (resident ? SEG_RESIDENT : 0);
                 if (t0 + nt > P.tile_cap) { atomicOr(&P.ctl->overflow, OVF_TILE); sg.flags |= SEG_FAILED; }
                 if (prebuilt) {  // the first level's model and kind were written into segs[1][0]
                     Seg pb = P.segs[1][0];
@@ -354,12 +356,14 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             Seg& o = P.segs[lvl & 1][s];
             o.kind = kind; o.nb = nb; o.model = model; o.cbase = cb; o.sbase = sb; o.flags = fl;
             LevelStats& st = P.ctl->lv[lvl];
-            if (kind == K_RMI || kind == K_RMI_FINE || kind == K_MLP || kind == K_MLP_FINE) atomicAdd(&st.learned, 1ull);
-            else if (kind == K_RADIX) atomicAdd(&st.radix, 1ull);
-            else atomicAdd(&st.tree, 1ull);
+            if (P.flags & FLAG_STATS) {
+                if (kind == K_RMI || kind == K_RMI_FINE || kind == K_MLP || kind == K_MLP_FINE) atomicAdd(&st.learned, 1ull);
+                else if (kind == K_RADIX) atomicAdd(&st.radix, 1ull);
+                else atomicAdd(&st.tree, 1ull);
+            }
         }
         __syncthreads();
-        if (!(shv[2] & SEG_FAILED))
+        if (!(shv[2] & (SEG_FAILED | SEG_RESIDENT)))  // k_resident writes its counts whole
             for (uint32_t b = tid; b < nb; b += M_THREADS) P.counts[shv[0] + b] = 0;
         // this segment's tile descriptors (every reserved slot below capacity)
         for (uint32_t i = tid; i < sg.ntiles; i += M_THREADS)
@@ -381,6 +385,8 @@ __device__ __forceinline__ uint64_t st_load(const unsigned long long* p) {
 __device__ __forceinline__ void st_store(unsigned long long* p, uint64_t v) {
     __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+constexpr int HK = 8;  // keys per thread in flight in k_hist
 
 __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
     __shared__ uint64_t mdl[MODEL_WORDS];
@@ -410,20 +416,35 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
         const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
         const bool aggregate = v.kind == K_TREE || v.kind == K_TREE_FORCED || v.kind == K_RADIX;
         const int bits = ceil_log2(sg.nb);
-#pragma unroll 8
-        for (uint32_t i = tid; i < un; i += P_THREADS) {
-            const uint32_t b = view_bucket(v, mdl, src[base + i], u64, P.ids, base + i);
-            if (aggregate) {
-                // wave-aggregated: one LDS add per distinct bucket in the wave
-                const uint64_t peers = match_peers(b, bits);
-                if (mask_rank(peers) == 0) atomicAdd(&h[b], (uint32_t)__popcll(peers));
-            } else {
-                const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
-                const uint64_t act = __ballot(1), same = __ballot(b == b0);
-                if (same == act) {
-                    if (mask_rank(act) == 0) atomicAdd(&h[b0], (uint32_t)__popcll(act));
-                } else {
-                    atomicAdd(&h[b], 1u);
+        // HK keys per thread are loaded before any is used, so that every wave
+        // keeps HK loads in flight (the unit is read exactly once)
+        for (uint32_t i0 = 0; i0 < un; i0 += P_THREADS * HK) {
+            uint64_t kk[HK];
+#pragma unroll
+            for (int r = 0; r < HK; r++) {
+                const uint32_t i = i0 + r * P_THREADS + tid;
+                kk[r] = i < un ? src[base + i] : 0;
+            }
+#pragma unroll
+            for (int r = 0; r < HK; r++) {
+                const uint32_t i = i0 + r * P_THREADS + tid;
+                if (i0 + r * P_THREADS >= un) break;  // uniform: no key of this round in range
+                const bool in = i < un;
+                const uint32_t b = in ? view_bucket(v, mdl, kk[r], u64, P.ids, base + i) : 0u;
+                if (aggregate) {
+                    // wave-aggregated: one LDS add per distinct bucket in the wave
+                    if (in) {
+                        const uint64_t peers = match_peers(b, bits);
+                        if (mask_rank(peers) == 0) atomicAdd(&h[b], (uint32_t)__popcll(peers));
+                    }
+                } else if (in) {
+                    const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
+                    const uint64_t act = __ballot(1), same = __ballot(b == b0);
+                    if (same == act) {
+                        if (mask_rank(act) == 0) atomicAdd(&h[b0], (uint32_t)__popcll(act));
+                    } else {
+                        atomicAdd(&h[b], 1u);
+                    }
                 }
             }
         }
@@ -447,6 +468,13 @@ constexpr int S_BPT = B_MAX / S_THREADS;  // buckets per thread
 // Per-bucket decision (Sec. 2.2 homogeneity check, Sec. 4 base case, the 2x
 // fallback rule): 0 nothing, 1 copy run, 2 base case, 3 range radix child,
 // 4 fine child (same model), 5 splitter-tree child (fallback), 6 fresh child.
+// A child segment small enough for one workgroup goes to k_resident (no
+// work units); children of the MLP-rooted model stay on the unit path, whose
+// k_mlp_ids supplies their bucket ids.
+__device__ __forceinline__ bool child_resident(uint32_t parent_kind, uint32_t act, uint64_t n) {
+    return n <= RES_MAX && !(act == 4 && parent_kind == K_MLP);
+}
+
 struct Decision {
     uint32_t act;
     uint64_t stat;  // 12-bit fields: empty, equality, base, recurse
@@ -465,11 +493,11 @@ __device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q,
     const bool oversized = (double)c > P.fallback_ratio * expected;
     const bool fine = fine_ok && !oversized && (4ull << log2B2) <= c && (uint32_t)lvl + 1 < P.max_levels;
     // The base case takes a bucket at or below the cutoff, and any bucket it
-    // can hold (C_MAX) that would otherwise need a newly sampled model:
-    // sorting it directly is one pass, a new level is a sample plus a
-    // partition pass.  At the depth cap this leaves range radix (8 bits per
-    // level) only buckets of more than C_MAX keys.
-    if (c <= P.cutoff || (!fine && c <= (uint64_t)C_MAX)) { d.stat = 1ull << 24; d.act = 2; return d; }
+    // can hold (C_MAX): sorting it directly is one pass, another level is at
+    // least a partition pass plus the fixed work of a segment.  At the depth
+    // cap this leaves range radix (8 bits per level) only buckets of more
+    // than C_MAX keys.
+    if (c <= P.cutoff || c <= (uint64_t)C_MAX) { d.stat = 1ull << 24; d.act = 2; return d; }
     d.stat = 1ull << 36;
     if ((uint32_t)lvl + 1 >= P.max_levels) d.act = 3;
     else if (fine) d.act = 4;
@@ -552,7 +580,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             lstat += d.stat;
             const uint64_t nsm = d.act == 2 && c[i] <= SMALL_MAX ? 1 : 0;
             const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && c[i] > SMALL_MAX ? 1 : 0);
-            const uint64_t ntl = d.act >= 3 ? (c[i] + UNIT - 1) / UNIT : 0;
+            const uint64_t ntl = d.act >= 3 && !child_resident(sg.kind, d.act, c[i]) ? (c[i] + UNIT - 1) / UNIT : 0;
             // packed counters: small items | children << 16 | large items << 32, units | fallbacks << 32
             la += nsm | ((uint64_t)(d.act >= 3) << 16) | (nbg << 32);
             lb += ntl | ((uint64_t)(d.act == 5) << 32);
@@ -579,16 +607,18 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             if (sk) atomicAdd(&P.ctl->small_keys, (unsigned long long)sk);
             if (gk) atomicAdd(&P.ctl->big_keys, (unsigned long long)gk);
             const uint64_t m12 = 4095;
-            atomicAdd(&st.segments, 1ull);
-            atomicAdd(&st.keys, (unsigned long long)sg.n);
-            atomicAdd(&st.buckets, (unsigned long long)nb);
-            atomicMax(&st.max_bucket, (unsigned long long)mx);
-            atomicMax(&st.max_ratio_x1000, (unsigned long long)(1000.0 * (double)mx / expected));
-            atomicAdd(&st.empty, (unsigned long long)(sc & m12));
-            atomicAdd(&st.equality, (unsigned long long)((sc >> 12) & m12));
-            atomicAdd(&st.base, (unsigned long long)((sc >> 24) & m12));
-            atomicAdd(&st.recurse, (unsigned long long)((sc >> 36) & m12));
-            atomicAdd(&st.fallback, (unsigned long long)(tb >> 32));
+            atomicAdd(&st.keys, (unsigned long long)sg.n);  // always: per-level kernel timing reads it
+            if (P.flags & FLAG_STATS) {
+                atomicAdd(&st.segments, 1ull);
+                atomicAdd(&st.buckets, (unsigned long long)nb);
+                atomicMax(&st.max_bucket, (unsigned long long)mx);
+                atomicMax(&st.max_ratio_x1000, (unsigned long long)(1000.0 * (double)mx / expected));
+                atomicAdd(&st.empty, (unsigned long long)(sc & m12));
+                atomicAdd(&st.equality, (unsigned long long)((sc >> 12) & m12));
+                atomicAdd(&st.base, (unsigned long long)((sc >> 24) & m12));
+                atomicAdd(&st.recurse, (unsigned long long)((sc >> 36) & m12));
+                atomicAdd(&st.fallback, (unsigned long long)(tb >> 32));
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -598,7 +628,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const uint64_t ci = c[i];
             const uint64_t nsm = a == 2 && ci <= SMALL_MAX ? 1 : 0;
             const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && ci > SMALL_MAX ? 1 : 0);
-            const uint64_t ntl = a >= 3 ? (ci + UNIT - 1) / UNIT : 0;
+            const uint64_t ntl = a >= 3 && !child_resident(sg.kind, a, ci) ? (ci + UNIT - 1) / UNIT : 0;
             const uint64_t iex = xa & 0xffff, cex = (xa >> 16) & 0xffff, gex = xa >> 32, tex = xb & 0xffffffffull;
             if (nsm) {
                 const uint64_t it = resv[0] + iex;
@@ -618,11 +648,12 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                     ch.off = start[i]; ch.n = ci; ch.ntiles = (uint32_t)ntl; ch.tile0 = (uint32_t)t0;
                     ch.kind = a == 3 ? K_RADIX : a == 4 ? (sg.kind == K_RMI ? K_RMI_FINE : K_MLP_FINE)
                             : a == 5 ? K_TREE_FORCED : K_FRESH;
+                    if (child_resident(sg.kind, a, ci)) ch.flags = SEG_RESIDENT;
                     if (a == 4) {
                         ch.model = sg.model;
                         ch.nb = 1u << log2B2;
                         ch.win = b << log2B2;
-                        ch.flags = sg.flags & 0xffff0000u;  // model words
+                        ch.flags |= sg.flags & 0xffff0000u;  // model words
                     }
                     if (t0 + ntl > P.tile_cap) { atomicOr(&P.ctl->overflow, OVF_TILE); ch.flags |= SEG_FAILED; }
                     P.segs[q][si] = ch;  // k_model of the next level writes its unit descriptors
@@ -660,17 +691,22 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
 // Barrier for LDS hand-offs only: global loads in flight stay in flight.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <bool PAY>
-__global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
+template <bool PAY, int NT>
+__global__ __launch_bounds__(NT) void k_scatter(Params P) {
+    constexpr int SW = NT / WAVE;        // waves
+    constexpr int SK = TILE / NT;        // keys per thread per tile
+    constexpr int SWK = WAVE * SK;       // keys per wave per tile
+    constexpr int SB = B_MAX / NT;       // buckets per thread in the tile scan
+    static_assert(SK * NT == TILE && SB * NT == B_MAX, "tile and bucket range split evenly");
     __shared__ uint64_t mdl[MODEL_WORDS];
     __shared__ uint64_t stage[TILE];
     __shared__ uint16_t sbid[TILE];
-    __shared__ uint16_t wcnt[PAY ? P_WAVES : 1][PAY ? B_MAX : 1];
+    __shared__ uint16_t wcnt[PAY ? SW : 1][PAY ? B_MAX : 1];
     __shared__ uint32_t tcnt[B_MAX];
     __shared__ uint16_t tstart[B_MAX];
     __shared__ uint64_t run[B_MAX];
     __shared__ uint32_t sh_t;
-    __shared__ uint64_t red64[P_THREADS / 64];
+    __shared__ uint64_t red64[SW];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lvl = P.level;
     const uint32_t nunit = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
@@ -693,7 +729,7 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
         const Seg sg = P.segs[lvl & 1][td.seg];
         if (sg.flags & SEG_FAILED) { __syncthreads(); continue; }
         if (sg.model != cur_model) {
-            load_model(mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, P_THREADS);
+            load_model(mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, NT);
             cur_model = sg.model;
         }
         const uint32_t nb = sg.nb;
@@ -701,7 +737,7 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
         {
             unsigned long long* row = P.status + sg.sbase + (uint64_t)td.idx * nb;
             uint32_t bad = 0;
-            for (uint32_t j = tid; j < nb; j += P_THREADS) {
+            for (uint32_t j = tid; j < nb; j += NT) {
                 const uint64_t own = st_load(row + j);
                 uint64_t excl = 0;
                 for (int64_t pk = (int64_t)td.idx - 1; pk >= 0; pk--) {
@@ -727,11 +763,11 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
         const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
         const uint32_t ntl = (un + TILE - 1) / TILE;
         // wave w owns keys [w*1024, (w+1)*1024) of a tile, 64 per round
-        uint64_t k[KPT], kn[KPT];
-        uint32_t pl[KPT], pn[KPT];
+        uint64_t k[SK], kn[SK];
+        uint32_t pl[SK], pn[SK];
 #pragma unroll
-        for (int r = 0; r < KPT; r++) {
-            const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+        for (int r = 0; r < SK; r++) {
+            const uint32_t i = w * SWK + r * WAVE + lane;
             k[r] = i < un ? src[ubase + i] : 0;
             pl[r] = (has_pay && i < un) ? psrc[ubase + i] : 0;
         }
@@ -741,29 +777,29 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
             if (tt + 1 < ntl) {  // prefetch the next tile
                 const uint32_t nn = min<uint32_t>(TILE, un - (tt + 1) * TILE);
 #pragma unroll
-                for (int r = 0; r < KPT; r++) {
-                    const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+                for (int r = 0; r < SK; r++) {
+                    const uint32_t i = w * SWK + r * WAVE + lane;
                     kn[r] = i < nn ? src[base + TILE + i] : 0;
                     pn[r] = (has_pay && i < nn) ? psrc[base + TILE + i] : 0;
                 }
             }
-            uint32_t b[KPT], rk[KPT];
+            uint32_t b[SK], rk[SK];
             if (PAY) {
                 for (uint32_t j = lane; j < nb; j += WAVE) wcnt[w][j] = 0;
             } else {
-                for (uint32_t j = tid; j < nb; j += P_THREADS) tcnt[j] = 0;
+                for (uint32_t j = tid; j < nb; j += NT) tcnt[j] = 0;
                 lds_barrier();
             }
 #pragma unroll
-            for (int r = 0; r < KPT; r++) {
-                const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+            for (int r = 0; r < SK; r++) {
+                const uint32_t i = w * SWK + r * WAVE + lane;
                 b[r] = i < tn ? view_bucket(v, mdl, k[r], u64, P.ids, base + i) : 0;
             }
             if (PAY) {
                 // stable rank within the wave: rounds in key order, lanes in key order
 #pragma unroll
-                for (int r = 0; r < KPT; r++) {
-                    const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+                for (int r = 0; r < SK; r++) {
+                    const uint32_t i = w * SWK + r * WAVE + lane;
                     rk[r] = 0;
                     if (i < tn) {
                         const uint64_t peers = match_peers(b[r], bits);
@@ -775,10 +811,10 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
                 }
                 lds_barrier();
                 // per bucket: exclusive prefix over waves (in place) and tile count
-                for (uint32_t j = tid; j < nb; j += P_THREADS) {
+                for (uint32_t j = tid; j < nb; j += NT) {
                     uint32_t acc = 0;
 #pragma unroll
-                    for (int x = 0; x < P_WAVES; x++) {
+                    for (int x = 0; x < SW; x++) {
                         const uint32_t c = wcnt[x][j];
                         wcnt[x][j] = (uint16_t)acc;
                         acc += c;
@@ -789,8 +825,8 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
                 // any order inside a bucket: one LDS atomic per key (one per wave
                 // when the whole wave falls into a single bucket)
 #pragma unroll
-                for (int r = 0; r < KPT; r++) {
-                    const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+                for (int r = 0; r < SK; r++) {
+                    const uint32_t i = w * SWK + r * WAVE + lane;
                     rk[r] = 0;
                     if (i < tn) {
                         const uint32_t b0 = __builtin_amdgcn_readfirstlane(b[r]);
@@ -806,10 +842,14 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
                 }
             }
             lds_barrier();
-            {  // tile-local bucket starts: exclusive scan over buckets, 2 per thread
-                const uint32_t j0 = 2 * tid, j1 = 2 * tid + 1;
-                const uint32_t c0 = j0 < nb ? tcnt[j0] : 0u, c1 = j1 < nb ? tcnt[j1] : 0u;
-                const uint32_t lane_sum = c0 + c1;
+            {  // tile-local bucket starts: exclusive scan over buckets, SB per thread
+                uint32_t c[SB], lane_sum = 0;
+#pragma unroll
+                for (int q = 0; q < SB; q++) {
+                    const uint32_t j = SB * tid + q;
+                    c[q] = j < nb ? tcnt[j] : 0u;
+                    lane_sum += c[q];
+                }
                 uint32_t x = lane_sum;
 #pragma unroll
                 for (int o = 1; o < 64; o <<= 1) {
@@ -818,19 +858,22 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
                 }
                 if (lane == 63) red64[w] = x;
                 lds_barrier();
-                uint32_t before = 0;
+                uint32_t ex = x - lane_sum;
 #pragma unroll
-                for (int q = 0; q < P_WAVES; q++) before += q < w ? (uint32_t)red64[q] : 0u;
-                const uint32_t ex = before + x - lane_sum;
-                if (j0 < nb) tstart[j0] = (uint16_t)ex;
-                if (j1 < nb) tstart[j1] = (uint16_t)(ex + c0);
+                for (int q = 0; q < SW; q++) ex += q < w ? (uint32_t)red64[q] : 0u;
+#pragma unroll
+                for (int q = 0; q < SB; q++) {
+                    const uint32_t j = SB * tid + q;
+                    if (j < nb) tstart[j] = (uint16_t)ex;
+                    ex += c[q];
+                }
             }
             lds_barrier();
             // stage keys grouped by bucket (stable positions)
-            uint32_t pos[KPT];
+            uint32_t pos[SK];
 #pragma unroll
-            for (int r = 0; r < KPT; r++) {
-                const uint32_t i = w * WAVE_KEYS + r * WAVE + lane;
+            for (int r = 0; r < SK; r++) {
+                const uint32_t i = w * SWK + r * WAVE + lane;
                 pos[r] = 0xffffffffu;
                 if (i < tn) {
                     const uint32_t p = tstart[b[r]] + (PAY ? (uint32_t)wcnt[w][b[r]] : 0u) + rk[r];
@@ -840,7 +883,7 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
                 }
             }
             lds_barrier();
-            for (uint32_t p = tid; p < tn; p += P_THREADS) {
+            for (uint32_t p = tid; p < tn; p += NT) {
                 const uint32_t bb = sbid[p];
                 dst[run[bb] + (p - tstart[bb])] = stage[p];
             }
@@ -848,19 +891,19 @@ __global__ __launch_bounds__(P_THREADS) void k_scatter(Params P) {
                 lds_barrier();
                 uint32_t* st32 = (uint32_t*)stage;
 #pragma unroll
-                for (int r = 0; r < KPT; r++)
+                for (int r = 0; r < SK; r++)
                     if (pos[r] != 0xffffffffu) st32[pos[r]] = pl[r];
                 lds_barrier();
-                for (uint32_t p = tid; p < tn; p += P_THREADS) {
+                for (uint32_t p = tid; p < tn; p += NT) {
                     const uint32_t bb = sbid[p];
                     pdst[run[bb] + (p - tstart[bb])] = st32[p];
                 }
             }
             lds_barrier();
-            for (uint32_t j = tid; j < nb; j += P_THREADS) run[j] += tcnt[j];
+            for (uint32_t j = tid; j < nb; j += NT) run[j] += tcnt[j];
             lds_barrier();
 #pragma unroll
-            for (int r = 0; r < KPT; r++) { k[r] = kn[r]; pl[r] = pn[r]; }
+            for (int r = 0; r < SK; r++) { k[r] = kn[r]; pl[r] = pn[r]; }
         }
         __syncthreads();
     }
@@ -920,6 +963,185 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
         else if (size <= 128) base_small_item<2, PAY>(P, off, size, srcb, lane);
         else if (size <= 256) base_small_item<4, PAY>(P, off, size, srcb, lane);
         else base_small_item<8, PAY>(P, off, size, srcb, lane);
+    }
+}
+
+// ===========================================================================
+// k_resident: one workgroup partitions a whole segment of at most RES_MAX
+// keys (one work unit), with no look-back: it histograms the segment with
+// its model, finds the bucket starts in LDS, scatters the keys into the
+// other buffer, and writes the counts for k_scan, which classifies the
+// buckets exactly as for any other segment.  The second read of the segment
+// comes from the cache.
+//   PAY: the scatter is stable (wave-match ranks and per-wave bucket
+//   positions, tile by tile in key order), so a payload keeps the input
+//   order of equal keys; without a payload one LDS atomic per key places it.
+// ===========================================================================
+
+constexpr int R_THREADS = 512;
+constexpr int R_WAVES = R_THREADS / WAVE;
+constexpr int RK = 8;                        // keys per thread per tile
+constexpr int R_TILE = R_THREADS * RK;       // 4096 keys
+constexpr int R_WKEYS = WAVE * RK;           // keys per wave per tile
+
+template <int KIND>
+__device__ __forceinline__ uint32_t rbucket(const View& v, const uint64_t* mdl, uint64_t raw, int u64) {
+    if constexpr (KIND == K_RMI)
+        return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) >> v.log2B2;
+    else if constexpr (KIND == K_RMI_FINE)
+        return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) - v.win;
+    else if constexpr (KIND == K_TREE)
+        return tree_bucket(mdl + 2, (const uint16_t*)(mdl + 2 + v.m), v.m, v.top, key_ord(raw, u64));
+    else
+        return radix_bucket(v.lo, v.shift, key_ord(raw, u64));
+}
+
+template <bool PAY>
+struct ResLds {
+    uint64_t mdl[MODEL_WORDS];
+    uint32_t cnt[B_MAX];
+    uint32_t start[B_MAX];
+    uint32_t cur[B_MAX];
+    uint32_t wpos[PAY ? R_WAVES : 1][PAY ? B_MAX : 1];
+    uint64_t red[R_WAVES];
+    uint32_t seg;
+};
+
+// Histogram, bucket starts and the scatter of one resident segment.
+template <int KIND, bool PAY>
+__device__ void res_partition(const Params& P, const Seg& sg, const View& v, ResLds<PAY>& L, int lvl) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint64_t* src = P.keys[lvl & 1];
+    uint64_t* dst = P.keys[(lvl + 1) & 1];
+    const uint32_t* psrc = P.pay[lvl & 1];
+    uint32_t* pdst = P.pay[(lvl + 1) & 1];
+    const int u64 = P.u64;
+    const uint32_t n = (uint32_t)sg.n, nb = sg.nb;
+    const uint64_t off = sg.off;
+    for (uint32_t b = tid; b < B_MAX; b += R_THREADS) L.cnt[b] = 0;
+    __syncthreads();
+    // histogram
+    for (uint32_t t0 = 0; t0 < n; t0 += R_TILE) {
+        uint64_t k[RK];
+#pragma unroll
+        for (int r = 0; r < RK; r++) {
+            const uint32_t i = t0 + w * R_WKEYS + r * WAVE + lane;
+            k[r] = i < n ? src[off + i] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < RK; r++) {
+            const uint32_t i = t0 + w * R_WKEYS + r * WAVE + lane;
+            if (i < n) atomicAdd(&L.cnt[rbucket<KIND>(v, L.mdl, k[r], u64)], 1u);
+        }
+    }
+    __syncthreads();
+    // bucket starts: exclusive scan, 2 buckets per thread
+    {
+        const uint32_t j0 = 2 * tid, j1 = 2 * tid + 1;
+        const uint32_t c0 = j0 < nb ? L.cnt[j0] : 0u, c1 = j1 < nb ? L.cnt[j1] : 0u;
+        uint64_t tot;
+        const uint32_t ex = (uint32_t)block_excl_scan<R_THREADS, uint64_t>((uint64_t)(c0 + c1), L.red, &tot);
+        if (j0 < nb) { L.start[j0] = ex; L.cur[j0] = ex; }
+        if (j1 < nb) { L.start[j1] = ex + c0; L.cur[j1] = ex + c0; }
+    }
+    __syncthreads();
+    // scatter into the other buffer
+    const int bits = ceil_log2(nb);
+    for (uint32_t t0 = 0; t0 < n; t0 += R_TILE) {
+        uint64_t k[RK];
+        uint32_t pl[RK], b[RK];
+#pragma unroll
+        for (int r = 0; r < RK; r++) {
+            const uint32_t i = t0 + w * R_WKEYS + r * WAVE + lane;
+            k[r] = i < n ? src[off + i] : 0;
+            pl[r] = (PAY && i < n) ? psrc[off + i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < RK; r++) {
+            const uint32_t i = t0 + w * R_WKEYS + r * WAVE + lane;
+            b[r] = i < n ? rbucket<KIND>(v, L.mdl, k[r], u64) : 0u;
+        }
+        if constexpr (!PAY) {
+#pragma unroll
+            for (int r = 0; r < RK; r++) {
+                const uint32_t i = t0 + w * R_WKEYS + r * WAVE + lane;
+                if (i < n) dst[off + atomicAdd(&L.cur[b[r]], 1u)] = k[r];
+            }
+        } else {
+            // stable: ranks within the wave in key order, then positions per
+            // (wave, bucket) from the running cursors
+            for (uint32_t j = lane; j < nb; j += WAVE) L.wpos[w][j] = 0;
+            uint32_t rk[RK];
+#pragma unroll
+            for (int r = 0; r < RK; r++) {
+                const uint32_t i = t0 + w * R_WKEYS + r * WAVE + lane;
+                rk[r] = 0;
+                if (i < n) {
+                    const uint64_t peers = match_peers(b[r], bits);
+                    const uint32_t below = mask_rank(peers);
+                    const uint32_t before = L.wpos[w][b[r]];
+                    if (below == 0) L.wpos[w][b[r]] = before + (uint32_t)__popcll(peers);
+                    rk[r] = before + below;
+                }
+            }
+            __syncthreads();
+            for (uint32_t j = tid; j < nb; j += R_THREADS) {
+                uint32_t acc = L.cur[j];
+#pragma unroll
+                for (int x = 0; x < R_WAVES; x++) {
+                    const uint32_t c = L.wpos[x][j];
+                    L.wpos[x][j] = acc;
+                    acc += c;
+                }
+                L.cur[j] = acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < RK; r++) {
+                const uint32_t i = t0 + w * R_WKEYS + r * WAVE + lane;
+                if (i < n) {
+                    const uint32_t pos = L.wpos[w][b[r]] + rk[r];
+                    dst[off + pos] = k[r];
+                    pdst[off + pos] = pl[r];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <bool PAY>
+__global__ __launch_bounds__(R_THREADS) void k_resident(Params P) {
+    __shared__ ResLds<PAY> L;
+    const int tid = threadIdx.x;
+    const int lvl = P.level;
+    const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
+    uint64_t cur_model = 0;
+    for (;;) {
+        if (tid == 0) L.seg = atomicAdd(&P.ctl->rticket[lvl], 1u);
+        __syncthreads();
+        const uint32_t s = L.seg;
+        if (s >= nseg) break;
+        const Seg sg = P.segs[lvl & 1][s];
+        if (!(sg.flags & SEG_RESIDENT) || (sg.flags & SEG_FAILED)) {
+            __syncthreads();
+            continue;
+        }
+        if (sg.model != cur_model) {
+            load_model(L.mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, R_THREADS);
+            cur_model = sg.model;
+        }
+        __syncthreads();
+        const View v = make_view(L.mdl, sg.kind, sg.nb, sg.win);
+        switch (sg.kind) {
+        case K_RMI: res_partition<K_RMI, PAY>(P, sg, v, L, lvl); break;
+        case K_RMI_FINE: res_partition<K_RMI_FINE, PAY>(P, sg, v, L, lvl); break;
+        case K_TREE:
+        case K_TREE_FORCED: res_partition<K_TREE, PAY>(P, sg, v, L, lvl); break;
+        default: res_partition<K_RADIX, PAY>(P, sg, v, L, lvl); break;
+        }
+        for (uint32_t b = tid; b < sg.nb; b += R_THREADS) P.counts[sg.cbase + b] = L.cnt[b];
+        __syncthreads();
     }
 }
 
@@ -1008,14 +1230,21 @@ hipError_t launch_seed(const Params& P, const uint64_t* offsets, uint64_t m, uin
 hipError_t launch_model(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_model, grid, M_THREADS, st, P); }
 hipError_t launch_hist(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_hist, grid, P_THREADS, st, P); }
 hipError_t launch_scan(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_scan, grid, S_THREADS, st, P); }
+constexpr int SC_THREADS = 1024;  // threads of a scatter workgroup (16 waves, 8 keys each per tile)
+
 hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st) {
-    if (P.has_pay) LAUNCH(k_scatter<true>, grid, P_THREADS, st, P);
-    LAUNCH(k_scatter<false>, grid, P_THREADS, st, P);
+    if (P.has_pay) LAUNCH((k_scatter<true, SC_THREADS>), grid, SC_THREADS, st, P);
+    LAUNCH((k_scatter<false, SC_THREADS>), grid, SC_THREADS, st, P);
 }
 hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st) {
     if (P.has_pay) LAUNCH(k_base_small<true>, grid, BASE_THREADS, st, P);
     LAUNCH(k_base_small<false>, grid, BASE_THREADS, st, P);
 }
+hipError_t launch_resident(const Params& P, uint32_t grid, hipStream_t st) {
+    if (P.has_pay) LAUNCH(k_resident<true>, grid, R_THREADS, st, P);
+    LAUNCH(k_resident<false>, grid, R_THREADS, st, P);
+}
 hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_base_big, grid, BIG_THREADS, st, P); }
+
 
 }  // namespace ls

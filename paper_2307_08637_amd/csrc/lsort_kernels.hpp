@@ -64,6 +64,7 @@ hipError_t launch_scan(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st);
+hipError_t launch_resident(const Params& P, uint32_t grid, hipStream_t st);
 
 // sample fit and single steps (lsort_fit.hip)
 hipError_t launch_gather(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t S, uint64_t* out, hipStream_t st);

@@ -83,6 +83,7 @@ def lib():
             "ls_mlp_rmi_buckets": [vp, u64, i32, vp, vp, vp, u32, dbl, vp, vp],
             "ls_timing": [i32],
             "ls_timing_read": [vp, u32, vp],
+            "ls_timing_records": [vp, u32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -352,6 +353,14 @@ def timing_read() -> dict:
     _check(lib().ls_timing_read(buf, 32, C.byref(cnt)))
     return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "keys": buf[i].keys}
             for i in range(cnt.value)}
+
+
+def timing_records(cap: int = 4096) -> list:
+    """The recorded launches in order: [(kernel name, ms, level keys)]."""
+    buf = (KernelTiming * cap)()
+    cnt = C.c_uint32()
+    _check(lib().ls_timing_records(buf, cap, C.byref(cnt)))
+    return [(buf[i].name.decode(), buf[i].ms, buf[i].keys) for i in range(cnt.value)]
 
 
 def version() -> str:
