@@ -9,7 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblsort.so")
-SOURCES = ["lsort_kernels.hip", "lsort_fit.hip", "lsort_mlp.hip", "lsort_tune.hip", "lsort_api.hip"]
+SOURCES = ["lsort_kernels.hip", "lsort_base.hip", "lsort_fit.hip", "lsort_mlp.hip", "lsort_tune.hip", "lsort_api.hip"]
+# per-file flags: the base case's only floating-point operations are binary64
+# comparators on operands checked NaN-free beforehand
+EXTRA_FLAGS = {"lsort_base.hip": ["-fno-honor-nans"]}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -31,7 +34,7 @@ def build(verbose: bool = False) -> str:
             continue
         obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
         os.makedirs(os.path.dirname(obj), exist_ok=True)
-        cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", path, "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-I", os.path.join(ROOT, "include"), "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True), src))

@@ -434,6 +434,105 @@ __device__ void bitonic_pairs(uint64_t* a, uint16_t* ix, uint32_t P) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Group sort (keys only): one wavefront sorts 64/G independent sub-arrays at
+// once, G = 2^LG lanes each (G <= 16: one DPP row), E = 2^LE keys per lane.
+// Element i of a sub-array sits in lane (group base + i / E), register i % E:
+// the low LE index bits are register bits, so most comparators of the
+// network join two registers of one lane.  The network is the bitonic sort
+// in its flip form: phase p merges sorted runs of 2^(p-1) by comparing i with
+// i ^ (2^p - 1), then half-cleans with i ^ 2^c for c = p-2 .. 0; every
+// comparator puts the smaller key at the lower index, so there are no
+// direction bits.  Lane partners come from DPP: the flip's partner lane is a
+// mirror (quad_perm [1,0,3,2] / [3,2,1,0], row_half_mirror, row_mirror), a
+// half-cleaner's is lane ^ 1, ^ 2, ^ 4 (half-mirror then quad reversal) or
+// ^ 8 (row_ror 8).
+//   T = double: finite or infinite binary64 keys without NaN and without
+//   -0.0 (callers check), compared as numbers (v_min_f64 / v_max_f64);
+//   T = uint64_t: ordered keys compared as integers.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T dpp_t(T v, int op) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    switch (op) {  // constant after unrolling
+    case 0: u = dpp_u64<0xB1>(u); break;                  // lane ^ 1
+    case 1: u = dpp_u64<0x4E>(u); break;                  // lane ^ 2
+    case 2: u = dpp_u64<0x1B>(dpp_u64<0x141>(u)); break;  // lane ^ 4 = (lane ^ 7) ^ 3
+    case 3: u = dpp_u64<0x128>(u); break;                 // lane ^ 8
+    case 4: u = dpp_u64<0xB1>(u); break;                  // lane ^ 1  (mirror of 2 lanes)
+    case 5: u = dpp_u64<0x1B>(u); break;                  // lane ^ 3  (mirror of 4)
+    case 6: u = dpp_u64<0x141>(u); break;                 // lane ^ 7  (mirror of 8)
+    default: u = dpp_u64<0x140>(u); break;                // lane ^ 15 (mirror of 16)
+    }
+    return __builtin_bit_cast(T, u);
+}
+
+// Comparator inside a lane: a <- min, b <- max.
+__device__ __forceinline__ void cx_reg(double& a, double& b) {
+    const double lo = __builtin_fmin(a, b), hi = __builtin_fmax(a, b);
+    a = lo;
+    b = hi;
+}
+__device__ __forceinline__ void cx_reg(uint64_t& a, uint64_t& b) {
+    const bool lt = a < b;
+    const uint64_t lo = lt ? a : b, hi = lt ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// Lane-pair comparator: the lane holding the higher index (keep_max) keeps
+// the larger key of the pair, its partner the smaller.
+template <typename T>
+__device__ __forceinline__ T cx_lane(T mine, T other, bool keep_max) {
+    return ((other < mine) != keep_max) ? other : mine;
+}
+
+template <typename T, int LE, int LG>
+__device__ __forceinline__ void group_bitonic(T (&k)[1 << LE], int lane) {
+    constexpr int E = 1 << LE;
+    static_assert(LG <= 4, "lane groups stay inside one DPP row");
+#pragma unroll
+    for (int p = 1; p <= LE + LG; p++) {
+        const int b = p - 1;
+        if (b < LE) {  // flip inside the lane
+#pragma unroll
+            for (int r = 0; r < E; r++) {
+                if (!((r >> b) & 1)) cx_reg(k[r], k[r ^ ((2 << b) - 1)]);
+            }
+        } else {  // flip across lanes: partner lane ^ (2^(s+1) - 1), register E-1-r
+            const int s = b - LE;
+            const bool km = (lane >> s) & 1;
+#pragma unroll
+            for (int r = 0; r < E / 2; r++) {
+                const T y0 = dpp_t(k[E - 1 - r], 4 + s), y1 = dpp_t(k[r], 4 + s);
+                k[r] = cx_lane(k[r], y0, km);
+                k[E - 1 - r] = cx_lane(k[E - 1 - r], y1, km);
+            }
+        }
+#pragma unroll
+        for (int c = b - 1; c >= 0; c--) {
+            if (c < LE) {
+#pragma unroll
+                for (int r = 0; r < E; r++) {
+                    if (!((r >> c) & 1)) cx_reg(k[r], k[r | (1 << c)]);
+                }
+            } else {
+                const int s = c - LE;
+                const bool km = (lane >> s) & 1;
+#pragma unroll
+                for (int r = 0; r < E; r++) k[r] = cx_lane(k[r], dpp_t(k[r], s), km);
+            }
+        }
+    }
+}
+
 // Bitonic sort of 64*E (key, index) pairs held by one wavefront, lane l
 // holding elements l*E .. l*E+E-1 in registers.  Compare-exchanges between
 // elements of one lane stay in registers; those between lanes exchange

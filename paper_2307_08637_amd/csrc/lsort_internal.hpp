@@ -21,6 +21,8 @@ constexpr int L_MAX = 1024;                    // RMI leaves
 constexpr int S_LDS = 16384;                   // largest sample one workgroup sorts in LDS
 constexpr int C_MAX = 4096;                    // largest base-case sub-array
 constexpr int SMALL_MAX = 512;                 // largest sub-array one wavefront sorts in registers
+constexpr int GROUP_MAX = 256;                 // largest sub-array a lane group sorts (4 per wavefront)
+constexpr int GROUP_SMALL_MAX = 128;           // ... sorted by a smaller lane group (8 per wavefront)
 constexpr int MAXL = 32;                       // partition levels (arrays)
 constexpr int MODEL_WORDS = 4 + 2 + 4 * L_MAX; // 8-byte words of the largest model (RMI, L_MAX leaves)
 constexpr uint64_t COPY_CHUNK = 65536;         // keys per copy item
@@ -117,7 +119,9 @@ struct Ctl {
     uint32_t ticket[MAXL + 1];      // scatter unit tickets
     uint32_t rticket[MAXL + 1];     // k_resident segment tickets
     uint32_t pad0;
-    unsigned long long nitems;      // small base-case items (<= SMALL_MAX keys)
+    unsigned long long nitems;      // small base-case items of <= GROUP_SMALL_MAX keys (front of items)
+    unsigned long long nitems_w;    // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)
+    unsigned long long nitems_b;    // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys (items_b)
     unsigned long long nbig;        // large base-case items and copy items
     unsigned long long ncopy;
     unsigned long long small_keys;  // keys in small base-case items
@@ -148,13 +152,15 @@ struct Params {
     Ctl* ctl;
     Seg* segs[2];
     Tile* tiles[2];
-    uint64_t* items;                // small base-case items
+    uint64_t* items;                // small base-case items: <= GROUP_SMALL_MAX keys from the front,
+                                    // GROUP_MAX+1 .. SMALL_MAX keys from the back
+    uint64_t* items_b;              // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys
     uint64_t* bigs;                 // large base-case items and copy items
     unsigned long long* counts;
     unsigned long long* status;
     uint8_t* arena[2];
     uint16_t* ids;                  // per-key bucket ids of MLP levels (absolute positions)
-    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap;
+    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap;
     const uint64_t* persist;        // [0] call epoch, [1] clear-status request (survives calls)
     int level;
 };

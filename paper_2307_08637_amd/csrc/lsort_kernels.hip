@@ -2,7 +2,8 @@
 //
 // One partition level over a list of sub-arrays ("segments") runs as
 //   k_model   -> k_hist -> k_scan -> k_scatter
-// and after the last level k_base sorts every small bucket in LDS.  Segments
+// and after the last level the base-case kernels (lsort_base.hip) sort every
+// small bucket.  Segments
 // of one level share every launch (the batched form is the same code with
 // more segments).  Buffers ping-pong between the caller's keys (index 0) and
 // a temporary (index 1): level l reads buffer l&1 and writes buffer (l+1)&1;
@@ -40,7 +41,7 @@ __global__ void k_reset(Params P, uint64_t* persist) {
 __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets, uint64_t m, uint64_t n_single,
                                               uint32_t prebuilt, const uint64_t* persist) {
     __shared__ uint64_t red64[256 / 64];
-    __shared__ uint64_t base[4];
+    __shared__ uint64_t base[6];
     if (persist[1]) {
         for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.status_cap;
              i += (uint64_t)gridDim.x * blockDim.x)
@@ -57,12 +58,15 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
         // prebuilt: the caller supplied the first level's model; always partition
         const bool item = s < m && !prebuilt && n >= 2 && n <= P.cutoff;
         const bool small = item && n <= SMALL_MAX;
+        const int cls = !small ? 3 : n <= GROUP_SMALL_MAX ? 0 : n <= GROUP_MAX ? 1 : 2;  // item list
         const bool seg = s < m && (prebuilt ? n >= 1 : n > P.cutoff);
         // an array small enough for one workgroup is sorted whole by k_resident
         const bool resident = seg && !prebuilt && n <= RES_MAX;
         const uint32_t nt = seg && !resident ? (uint32_t)((n + UNIT - 1) / UNIT) : 0;
-        uint64_t itot, btot, stot, ttot;
-        const uint64_t iex = block_excl_scan<256, uint64_t>(small ? 1 : 0, red64, &itot);
+        uint64_t itot, wtot, gtot, btot, stot, ttot;
+        const uint64_t iex = block_excl_scan<256, uint64_t>(item && cls == 0 ? 1 : 0, red64, &itot);
+        const uint64_t gex = block_excl_scan<256, uint64_t>(item && cls == 1 ? 1 : 0, red64, &gtot);
+        const uint64_t wex = block_excl_scan<256, uint64_t>(item && cls == 2 ? 1 : 0, red64, &wtot);
         const uint64_t bex = block_excl_scan<256, uint64_t>(item && !small ? 1 : 0, red64, &btot);
         const uint64_t sex = block_excl_scan<256, uint64_t>(seg ? 1 : 0, red64, &stot);
         const uint64_t tex = block_excl_scan<256, uint64_t>(nt, red64, &ttot);
@@ -73,13 +77,17 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
             base[1] = stot ? atomicAdd(&P.ctl->nseg[0], (uint32_t)stot) : 0;
             base[2] = ttot ? atomicAdd(&P.ctl->ntile[0], (uint32_t)ttot) : 0;
             base[3] = btot ? atomicAdd(&P.ctl->nbig, (unsigned long long)btot) : 0;
+            base[4] = wtot ? atomicAdd(&P.ctl->nitems_w, (unsigned long long)wtot) : 0;
+            base[5] = gtot ? atomicAdd(&P.ctl->nitems_b, (unsigned long long)gtot) : 0;
             if (sk) atomicAdd(&P.ctl->small_keys, (unsigned long long)sk);
             if (gk) atomicAdd(&P.ctl->big_keys, (unsigned long long)gk);
         }
         __syncthreads();
         if (item) {
-            const uint64_t it = small ? base[0] + iex : base[3] + bex;
-            if (it < (small ? P.item_cap : P.big_cap)) (small ? P.items : P.bigs)[it] = item_pack(lo, 0, 0, (uint32_t)n);
+            const uint64_t it = cls == 0 ? base[0] + iex : cls == 1 ? base[5] + gex : cls == 2 ? base[4] + wex : base[3] + bex;
+            const uint64_t cap = cls == 1 ? P.item_b_cap : cls == 3 ? P.big_cap : P.item_cap;
+            uint64_t* list = cls == 1 ? P.items_b : cls == 3 ? P.bigs : P.items;
+            if (it < cap) list[cls == 2 ? cap - 1 - it : it] = item_pack(lo, 0, 0, (uint32_t)n);
             else atomicOr(&P.ctl->overflow, OVF_ITEM);
         }
         if (seg) {
@@ -509,7 +517,7 @@ __device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q,
 __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
     __shared__ uint64_t red64[S_THREADS / 64];
     __shared__ uint8_t eqb[B_MAX];
-    __shared__ uint64_t resv[4];
+    __shared__ uint64_t resv[6];
     const int tid = threadIdx.x;
     const int lvl = P.level;
     if (blockIdx.x == 0 && tid == 0) {  // pools of the next level (this level's data stays readable)
@@ -569,7 +577,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         __syncthreads();
         const double expected = (double)sg.n / (double)nb;
         uint32_t act[S_BPT];
-        uint64_t la = 0, lb = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0;
+        uint64_t la = 0, lb = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0, lfb = 0;
 #pragma unroll
         for (int i = 0; i < S_BPT; i++) {
             const uint32_t b = S_BPT * tid + i;
@@ -579,11 +587,15 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             act[i] = d.act;
             lstat += d.stat;
             const uint64_t nsm = d.act == 2 && c[i] <= SMALL_MAX ? 1 : 0;
+            const uint64_t ng0 = nsm && c[i] <= GROUP_SMALL_MAX ? 1 : 0;
+            const uint64_t ng1 = nsm && !ng0 && c[i] <= GROUP_MAX ? 1 : 0;
             const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && c[i] > SMALL_MAX ? 1 : 0);
             const uint64_t ntl = d.act >= 3 && !child_resident(sg.kind, d.act, c[i]) ? (c[i] + UNIT - 1) / UNIT : 0;
-            // packed counters: small items | children << 16 | large items << 32, units | fallbacks << 32
-            la += nsm | ((uint64_t)(d.act >= 3) << 16) | (nbg << 32);
-            lb += ntl | ((uint64_t)(d.act == 5) << 32);
+            // packed counters: items <= 128 keys | children << 16 | large items << 32,
+            // units | items of 129..256 keys << 32 | items of 257..512 keys << 48
+            la += ng0 | ((uint64_t)(d.act >= 3) << 16) | (nbg << 32);
+            lb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1) << 48);
+            lfb += d.act == 5 ? 1 : 0;
             lsk += nsm ? c[i] : 0;
             lgk += nbg ? c[i] : 0;
             lcp += d.act == 1 ? nbg : 0;
@@ -596,10 +608,14 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         const uint64_t gk = block_sum<S_THREADS, uint64_t>(lgk, red64);
         const uint64_t ncp = block_sum<S_THREADS, uint64_t>(lcp, red64);
         const uint64_t sc = block_sum<S_THREADS, uint64_t>(lstat, red64);
+        const uint64_t nfb = block_sum<S_THREADS, uint64_t>(lfb, red64);
         const uint64_t mx = block_max<S_THREADS, uint64_t>(cmax, red64);
         if (tid == 0) {
             const uint64_t itot = ta & 0xffff, ctot = (ta >> 16) & 0xffff, gtot = ta >> 32, ttot = tb & 0xffffffffull;
+            const uint64_t btot = (tb >> 32) & 0xffff, wtot = tb >> 48;
             resv[0] = itot ? atomicAdd(&P.ctl->nitems, (unsigned long long)itot) : 0;
+            resv[4] = wtot ? atomicAdd(&P.ctl->nitems_w, (unsigned long long)wtot) : 0;
+            resv[5] = btot ? atomicAdd(&P.ctl->nitems_b, (unsigned long long)btot) : 0;
             resv[1] = ctot ? atomicAdd(&P.ctl->nseg[lvl + 1], (uint32_t)ctot) : 0;
             resv[2] = ttot ? atomicAdd(&P.ctl->ntile[lvl + 1], (uint32_t)ttot) : 0;
             resv[3] = gtot ? atomicAdd(&P.ctl->nbig, (unsigned long long)gtot) : 0;
@@ -617,7 +633,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                 atomicAdd(&st.equality, (unsigned long long)((sc >> 12) & m12));
                 atomicAdd(&st.base, (unsigned long long)((sc >> 24) & m12));
                 atomicAdd(&st.recurse, (unsigned long long)((sc >> 36) & m12));
-                atomicAdd(&st.fallback, (unsigned long long)(tb >> 32));
+                atomicAdd(&st.fallback, (unsigned long long)nfb);
             }
         }
         __syncthreads();
@@ -630,9 +646,13 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && ci > SMALL_MAX ? 1 : 0);
             const uint64_t ntl = a >= 3 && !child_resident(sg.kind, a, ci) ? (ci + UNIT - 1) / UNIT : 0;
             const uint64_t iex = xa & 0xffff, cex = (xa >> 16) & 0xffff, gex = xa >> 32, tex = xb & 0xffffffffull;
+            const uint64_t bex = (xb >> 32) & 0xffff, wex = xb >> 48;
+            const uint64_t ng0 = nsm && ci <= GROUP_SMALL_MAX ? 1 : 0;
+            const uint64_t ng1 = nsm && !ng0 && ci <= GROUP_MAX ? 1 : 0;
             if (nsm) {
-                const uint64_t it = resv[0] + iex;
-                if (it < P.item_cap) P.items[it] = item_pack(start[i], q, 0u, (uint32_t)ci);
+                const uint64_t it = ng0 ? resv[0] + iex : ng1 ? resv[5] + bex : resv[4] + wex;
+                const uint64_t cap = ng1 ? P.item_b_cap : P.item_cap;
+                if (it < cap) (ng1 ? P.items_b : P.items)[ng0 || ng1 ? it : cap - 1 - it] = item_pack(start[i], q, 0u, (uint32_t)ci);
                 else atomicOr(&P.ctl->overflow, OVF_ITEM);
             }
             for (uint64_t k = 0; k < nbg; k++) {
@@ -663,8 +683,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                         if (t0 + u < P.tile_cap) P.tiles[q][t0 + u] = Tile{0xffffffffu, 0};
                 }
             }
-            xa += nsm | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
-            xb += ntl | ((uint64_t)(a == 5) << 32);
+            xa += ng0 | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
+            xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1) << 48);
         }
         __syncthreads();
     }
@@ -910,63 +930,6 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
 }
 
 // ===========================================================================
-// Base case (Sec. 4: sub-arrays below the cutoff are sorted directly).
-// k_base_small: one wavefront per sub-array of at most 512 keys, sorted in
-// registers (wave_bitonic); k_base_big: one workgroup per larger sub-array
-// (up to 4096) sorted in LDS, and the copies of finished runs.
-// ===========================================================================
-
-constexpr int BASE_THREADS = 256;
-
-template <int E, bool PAY>
-__device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, int lane) {
-    const uint64_t* in = P.keys[srcb];
-    uint64_t* out = P.keys[0];
-    const int u64 = P.u64;
-    uint64_t k[E];
-    uint32_t ix[E];
-#pragma unroll
-    for (int e = 0; e < E; e++) {
-        const uint32_t i = lane * E + e;
-        k[e] = i < size ? key_ord(in[off + i], u64) : ~0ull;
-        ix[e] = i;
-    }
-    if (PAY) {
-        wave_bitonic<E, true>(k, ix, lane);
-        const uint32_t* pin = P.pay[srcb];
-        uint32_t* pout = P.pay[0];
-        uint32_t pv[E];
-#pragma unroll
-        for (int e = 0; e < E; e++) pv[e] = (lane * E + e < (int)size) ? pin[off + ix[e]] : 0u;
-#pragma unroll
-        for (int e = 0; e < E; e++)
-            if (lane * E + e < (int)size) pout[off + lane * E + e] = pv[e];
-    } else {
-        wave_bitonic<E, false>(k, ix, lane);
-    }
-#pragma unroll
-    for (int e = 0; e < E; e++)
-        if (lane * E + e < (int)size) out[off + lane * E + e] = key_unord(k[e], u64);
-}
-
-template <bool PAY>
-__global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t waves = (uint64_t)gridDim.x * (BASE_THREADS / 64);
-    const uint64_t nitems = min<unsigned long long>(P.ctl->nitems, P.item_cap);
-    for (uint64_t it = (uint64_t)blockIdx.x * (BASE_THREADS / 64) + (threadIdx.x >> 6); it < nitems; it += waves) {
-        const uint64_t wd = P.items[it];
-        const uint64_t off = wd >> 18;
-        const uint32_t srcb = (wd >> 17) & 1u;
-        const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
-        if (size <= 64) base_small_item<1, PAY>(P, off, size, srcb, lane);
-        else if (size <= 128) base_small_item<2, PAY>(P, off, size, srcb, lane);
-        else if (size <= 256) base_small_item<4, PAY>(P, off, size, srcb, lane);
-        else base_small_item<8, PAY>(P, off, size, srcb, lane);
-    }
-}
-
-// ===========================================================================
 // k_resident: one workgroup partitions a whole segment of at most RES_MAX
 // keys (one work unit), with no look-back: it histograms the segment with
 // its model, finds the bucket starts in LDS, scatters the keys into the
@@ -1145,73 +1108,6 @@ __global__ __launch_bounds__(R_THREADS) void k_resident(Params P) {
     }
 }
 
-constexpr int BIG_THREADS = 512;
-
-// One sub-array of 513..4096 keys: gather into registers (BIG_THREADS * E
-// elements, padded with the largest key), block_bitonic, write back.  The
-// payload follows through the sorted local index, read before any write.
-template <int E>
-__device__ void base_big_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, uint64_t* sk, uint32_t* si) {
-    const uint64_t* in = P.keys[srcb];
-    uint64_t* out = P.keys[0];
-    const int t = threadIdx.x, u64 = P.u64;
-    uint64_t k[E];
-    uint32_t ix[E];
-#pragma unroll
-    for (int e = 0; e < E; e++) {
-        const uint32_t i = t * E + e;
-        k[e] = i < size ? key_ord(in[off + i], u64) : ~0ull;
-        ix[e] = i;
-    }
-    if (P.has_pay) {
-        block_bitonic<BIG_THREADS, E, true>(k, ix, sk, si);
-        const uint32_t* pin = P.pay[srcb];
-        uint32_t* pout = P.pay[0];
-        uint32_t pv[E];
-#pragma unroll
-        for (int e = 0; e < E; e++) pv[e] = t * E + e < size ? pin[off + ix[e]] : 0u;
-        __syncthreads();  // every payload read of this sub-array happens before any write
-#pragma unroll
-        for (int e = 0; e < E; e++)
-            if (t * E + e < size) pout[off + t * E + e] = pv[e];
-    } else {
-        block_bitonic<BIG_THREADS, E, false>(k, ix, sk, si);
-    }
-#pragma unroll
-    for (int e = 0; e < E; e++)
-        if (t * E + e < size) out[off + t * E + e] = key_unord(k[e], u64);
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(BIG_THREADS) void k_base_big(Params P) {
-    __shared__ uint64_t sk[C_MAX];
-    __shared__ uint32_t si[C_MAX];
-    const int tid = threadIdx.x;
-    const uint64_t nitems = min<unsigned long long>(P.ctl->nbig, P.big_cap);
-    const int has_pay = P.has_pay;
-    uint64_t* out = P.keys[0];
-    uint32_t* pout = P.pay[0];
-    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint64_t wd = P.bigs[it];
-        const uint64_t off = wd >> 18;
-        const uint32_t srcb = (wd >> 17) & 1u, copy = (wd >> 16) & 1u;
-        const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
-        const uint64_t* in = P.keys[srcb];
-        const uint32_t* pin = P.pay[srcb];
-        if (copy) {
-            if (srcb)
-                for (uint32_t i = tid; i < size; i += BIG_THREADS) {
-                    out[off + i] = in[off + i];
-                    if (has_pay) pout[off + i] = pin[off + i];
-                }
-            continue;
-        }
-        if (size <= 1024) base_big_item<2>(P, off, size, srcb, sk, si);
-        else if (size <= 2048) base_big_item<4>(P, off, size, srcb, sk, si);
-        else base_big_item<8>(P, off, size, srcb, sk, si);
-    }
-}
-
 }  // namespace ls
 
 namespace ls {
@@ -1236,15 +1132,10 @@ hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st) {
     if (P.has_pay) LAUNCH((k_scatter<true, SC_THREADS>), grid, SC_THREADS, st, P);
     LAUNCH((k_scatter<false, SC_THREADS>), grid, SC_THREADS, st, P);
 }
-hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st) {
-    if (P.has_pay) LAUNCH(k_base_small<true>, grid, BASE_THREADS, st, P);
-    LAUNCH(k_base_small<false>, grid, BASE_THREADS, st, P);
-}
 hipError_t launch_resident(const Params& P, uint32_t grid, hipStream_t st) {
     if (P.has_pay) LAUNCH(k_resident<true>, grid, R_THREADS, st, P);
     LAUNCH(k_resident<false>, grid, R_THREADS, st, P);
 }
-hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_base_big, grid, BIG_THREADS, st, P); }
 
 
 }  // namespace ls

@@ -173,9 +173,25 @@ def adversarial(kind: str, n: int, seed: int = 0) -> np.ndarray:
         return (np.uint64(2**60) + g.integers(0, 2**20, n, dtype=np.uint64))
     if kind == "few_distinct":
         return g.integers(0, 7, n).astype(np.float64)
+    if kind == "subnormal_mix":
+        # subnormals and the smallest normals of both signs, no -0.0 or NaN:
+        # bit patterns with a biased exponent of 0..3 and a random mantissa
+        bits = g.integers(1, 1 << 52, n, dtype=np.uint64) | (g.integers(0, 4, n, dtype=np.uint64) << np.uint64(52))
+        bits |= g.integers(0, 2, n, dtype=np.uint64) << np.uint64(63)
+        return bits.view(np.float64)
+    if kind == "sparse_specials":
+        # normal keys with rare NaNs (both signs), -0.0 and +0.0
+        a = g.normal(0, 1, n)
+        pos_nan = np.frombuffer(np.uint64(0x7ff0000000000123).tobytes(), dtype=np.float64)[0]
+        neg_nan = np.frombuffer(np.uint64(0xfff8000000000000).tobytes(), dtype=np.float64)[0]
+        u = g.random(n)
+        a = np.where(u < 1e-4, pos_nan, a)
+        a = np.where((u >= 1e-4) & (u < 2e-4), neg_nan, a)
+        a = np.where((u >= 2e-4) & (u < 3e-4), -0.0, a)
+        return np.where((u >= 3e-4) & (u < 4e-4), 0.0, a)
     raise ValueError(kind)
 
 
 ADVERSARIAL_F64 = ("all_equal", "sorted", "reversed", "organ_pipe", "two_values", "signed_zeros",
-                   "extremes", "with_nan", "few_distinct")
+                   "extremes", "with_nan", "few_distinct", "subnormal_mix", "sparse_specials")
 ADVERSARIAL_U64 = ("u64_extremes", "u64_collide")

@@ -93,6 +93,43 @@ def test_adversarial(dev, kind, n):
     assert np.array_equal(gp, wp)
 
 
+@pytest.mark.parametrize("kind", inputs.ADVERSARIAL_F64 + inputs.ADVERSARIAL_U64)
+@pytest.mark.parametrize("n", [100, 5000, 200_000, 1_000_003])
+def test_adversarial_keys_only(dev, kind, n):
+    """Keys only: the base case's lane-group sort (binary64 comparators when
+    a wavefront's sub-arrays hold no NaN and no -0.0, ordered integers
+    otherwise) against the oracle."""
+    keys = inputs.adversarial(kind, n, seed=6)
+    got, _ = gpu_sort(keys, dev)
+    assert_same_bits(got, oracle.sort(keys)[0])
+
+
+def test_group_items_every_size(dev):
+    """Segments of every size 1..600 (sorted directly by the base case:
+    lane groups up to 128 keys, whole wavefronts above), keys only, with and
+    without special values."""
+    sizes = np.tile(np.arange(1, 601, dtype=np.int64), 3)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    parts = [inputs.generate("normal", n, seed=7), inputs.adversarial("sparse_specials", n, seed=8),
+             inputs.adversarial("subnormal_mix", n, seed=9)]
+    for keys in parts:
+        t = to_dev(keys, dev)
+        o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+        print(f"[case] group items n={n}", flush=True)
+        lsort.sort_segmented(t, o, cutoff=600)
+        torch.cuda.synchronize()
+        want, _ = oracle.sort_segmented(keys, off)
+        assert_same_bits(to_host(t), want)
+    keys = inputs.generate("u64", n, seed=10)
+    t = to_dev(keys, dev)
+    o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+    lsort.sort_segmented(t, o, cutoff=600)
+    torch.cuda.synchronize()
+    assert_same_bits(to_host(t), oracle.sort_segmented(keys, off)[0])
+
+
 @pytest.mark.parametrize("law", ["uniform", "normal", "rootdups", "u64"])
 def test_splitter_model(dev, law):
     keys = inputs.generate(law, 400_000, seed=41)
