@@ -721,7 +721,7 @@ ls_status ls_get_stats(ls_stats* out) {
     out->levels = levels;
     out->first_model = c.first_mlp ? LS_MODEL_MLP
                        : c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
-    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nbig - c.ncopy;
+    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nbig - c.ncopy - c.nmoved;
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
     out->mlp_loss_last = c.mlp_loss[1];

@@ -12,10 +12,9 @@ namespace ls {
 
 // ===========================================================================
 // Base case (Sec. 4: sub-arrays below the cutoff are sorted directly).
-// k_base_small: sub-arrays of at most 512 keys sorted in registers -- up to
-// 256 keys by a group of 8 or 16 lanes (group_bitonic, 8 or 4 sub-arrays per
-// wavefront), larger ones (and all of them with a payload) by a whole
-// wavefront (wave_bitonic); k_base_big: one workgroup per larger sub-array
+// k_base_small: sub-arrays of at most 512 keys sorted in registers by groups
+// of 4, 8 or 16 lanes (group_bitonic, 16, 8 or 4 sub-arrays per wavefront);
+// with a payload, one sub-array per wavefront (wave_bitonic); k_base_big: one workgroup per larger sub-array
 // (up to 4096) sorted in LDS, and the copies of finished runs.
 // ===========================================================================
 
@@ -52,17 +51,19 @@ __device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, u
         if (lane * E + e < (int)size) out[off + lane * E + e] = key_unord(k[e], u64);
 }
 
-// Group items: GPW = 64 / G sub-arrays per wavefront, G lanes and E keys per
-// lane each (group_bitonic): items of up to 128 keys on 8 lanes, of 129..256
-// keys on 16 lanes, 16 keys per lane.  Loads read key j of a sub-array into
-// lane j % G, register j / G (consecutive lanes, consecutive keys: any
-// placement of unsorted input is valid); the sorted keys go out through LDS,
-// each wave in its own region, so that stores are contiguous too.  binary64
-// keys are sorted as numbers unless the wavefront holds a NaN or a -0.0
-// (whose order is the bit pattern's), else as ordered integers.
-constexpr int GLE = 4, GE = 1 << GLE;
-constexpr int G_SLOTS = WAVE * GE + WAVE * GE / 16;  // LDS slots per wave: one pad slot after every 16
-static_assert(GE * 8 == GROUP_SMALL_MAX && GE * 16 == GROUP_MAX, "lane groups of 8 and 16 lanes");
+// Group items: 64 / G sub-arrays per wavefront, G lanes and E = 32 keys per
+// lane each (group_bitonic): items of up to 128 keys on 4 lanes, 129..256 on
+// 8 lanes, 257..512 on 16 lanes.  Loads read key j of a sub-array into lane
+// j % G, register j / G (consecutive lanes, consecutive keys: any placement
+// of unsorted input is valid).  The sorted keys leave through LDS in phases
+// of 16 registers, each wave in its own 8.5 KB region, so that stores are
+// contiguous too.  binary64 keys are sorted as numbers unless the task holds
+// a NaN or a -0.0 (whose order is the bit pattern's), else as ordered
+// integers.
+constexpr int GLE = 5, GE = 1 << GLE;
+constexpr int GPH = 16;                              // registers per LDS phase
+constexpr int G_SLOTS = WAVE * GPH + WAVE * GPH / 16; // LDS slots per wave: one pad slot after every 16
+static_assert(GE * 4 == GROUP_SMALL_MAX && GE * 8 == GROUP_MAX && GE * 16 == SMALL_MAX, "lane groups of 4, 8, 16");
 
 __device__ __forceinline__ uint32_t gslot(uint32_t i) { return i + (i >> 4); }
 
@@ -74,63 +75,86 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Items [lo, hi) of a list, each sorted by the whole wavefront.  Not inlined:
-// the group tasks call it only for the rare task holding a NaN or a -0.0, and
-// its registers then stay out of the group code's.
-__attribute__((noinline)) __device__ void base_items_one_by_one(const Params& P, const uint64_t* items, uint64_t lo,
-                                                                uint64_t hi, int lane) {
-    for (uint64_t it = lo; it < hi; it++) {
-        const uint64_t w = items[it];
-        const uint32_t sz = (uint32_t)(w & 0xffffu) + 1;
-        if (sz <= 64) base_small_item<1, false>(P, w >> 18, sz, (w >> 17) & 1u, lane);
-        else if (sz <= 128) base_small_item<2, false>(P, w >> 18, sz, (w >> 17) & 1u, lane);
-        else base_small_item<4, false>(P, w >> 18, sz, (w >> 17) & 1u, lane);
-    }
+// A value the compiler cannot see through: lane offsets derived from it are
+// formed where they are used instead of being kept in registers across the
+// sort (or hoisted out of the task loops).
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
-// One task: GPW items of the group's list.  U64: ordered-integer network.
-// binary64: the numeric network, unless the task holds a NaN or a -0.0; then
-// its items go one by one through the whole-wavefront sort instead (rare, and
-// it keeps the integer network's registers out of this kernel).
+// Loads and stores of the keys through global (not flat) instructions.
+__device__ __forceinline__ uint64_t gload(const uint64_t* p) {
+    return *(const __attribute__((address_space(1))) uint64_t*)p;
+}
+__device__ __forceinline__ void gstore(uint64_t* p, uint64_t v) { *(__attribute__((address_space(1))) uint64_t*)p = v; }
+
+// One task: 64 / G items, entries [task * GPW, ...) of a list (read from the
+// back when REV).  U64: ordered-integer network.  binary64: the numeric
+// network, unless the task holds a NaN or a -0.0; then (rarely) its items are
+// handed to k_base_big, which runs after this kernel and orders by the
+// totalOrder image (a one-key item is only moved).  Keeping the integer
+// network out of this kernel keeps its register count down.
+// The descriptor of this lane's item in a task.  Every load is in bounds
+// without a branch: an idle group (past the last item) reads the last item
+// and gets size 0 from base_group_task.
+template <int LG, bool REV>
+__device__ __forceinline__ uint64_t group_desc(const uint64_t* items, uint64_t cap, uint64_t task, uint64_t nitem,
+                                               int lane) {
+    const uint64_t e = min<uint64_t>(task * (WAVE >> LG) + (opaque(lane) >> LG), nitem - 1);
+    return items[REV ? cap - 1 - e : e];
+}
+
 template <int LG, bool U64>
-__device__ __forceinline__ void base_group_task(const Params& P, const uint64_t* items, uint64_t task, uint64_t nitem,
-                                                uint64_t* lds, int lane) {
-    constexpr int G = 1 << LG, GPW = WAVE / G, N = GE * G;
-    // per-task copy of the lane id: the sixteen lane offsets r * G + gl are
-    // cheap to form again each task, and hoisted out of the task loop they
-    // would hold sixteen registers for the whole kernel
-    int ln = lane;
-    asm volatile("" : "+v"(ln));
-    const int g = ln >> LG, gl = ln & (G - 1);
+__device__ __forceinline__ void base_group_task(const Params& P, const uint64_t* k0, const uint64_t* k1, uint64_t wd,
+                                                uint64_t task, uint64_t nitem, uint64_t* lds, int lane) {
+    constexpr int G = 1 << LG, GPW = WAVE / G;
+    // per-task copy of the lane id: the lane offsets r * G + gl are cheap to
+    // form again each task, and hoisted out of the task loop they would hold
+    // registers for the whole kernel
+    const int g = opaque(lane) >> LG, gl = opaque(lane) & (G - 1);
     const uint64_t idx = task * GPW + g;
-    // every load is in bounds without a branch: an idle group (past the last
-    // item) reads the last item and keeps size 0; indices clamp to size - 1
-    const uint64_t wd = items[min<uint64_t>(idx, nitem - 1)];
+    // indices clamp to size - 1, so every key load is in bounds too
     const uint64_t off = wd >> 18;
     const uint32_t size = idx < nitem ? (uint32_t)(wd & 0xffffu) + 1 : 0u;
-    const uint64_t* src = (((wd >> 17) & 1u) ? P.keys[1] : P.keys[0]) + off;
-    uint64_t* dst = P.keys[0] + off;
+    const uint64_t* src = (((wd >> 17) & 1u) ? k1 : k0) + off;
+    uint64_t* dst = const_cast<uint64_t*>(k0) + off;
     const uint32_t last = size ? size - 1 : 0u;
     uint64_t raw[GE];
 #pragma unroll
-    for (int r = 0; r < GE; r++) raw[r] = src[min<uint32_t>(r * G + gl, last)];
-    uint64_t* mine = lds + g * (N + N / 16);
+    for (int r = 0; r < GE; r++) {
+        raw[r] = gload(src + min<uint32_t>(r * G + gl, last));
+        // each address formed next to its load: all of them up front would
+        // hold a register pair each until the last load is issued
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const int gp = opaque(lane) & (G - 1);  // fresh copy: the offsets below are formed again, not kept
+    bool special = U64;
+    if (!U64) {
+#pragma unroll
+        for (int r = 0; r < GE; r++) {
+            if ((uint32_t)(r * G + gp) >= size) raw[r] = 0x7ff0000000000000ull;  // +inf pads
+            // NaN (signalling, quiet) or -0.0
+            special |= __builtin_amdgcn_class(__builtin_bit_cast(double, raw[r]), 0x001 | 0x002 | 0x020);
+        }
+    }
+    if (!U64 && __ballot(special) != 0) {
+        if (gp == 0 && size == 1) {
+            if (src != dst) gstore(dst, gload(src));
+        } else if (gp == 0 && size > 1) {
+            const uint64_t b = atomicAdd(&P.ctl->nbig, 1ull);
+            atomicAdd(&P.ctl->nmoved, 1ull);
+            if (b < P.big_cap) P.bigs[b] = wd;
+            else atomicOr(&P.ctl->overflow, OVF_ITEM);
+        }
+        return;
+    }
     if (U64) {
 #pragma unroll
         for (int r = 0; r < GE; r++)
-            if ((uint32_t)(r * G + gl) >= size) raw[r] = ~0ull;
+            if ((uint32_t)(r * G + gp) >= size) raw[r] = ~0ull;
         group_bitonic<uint64_t, GLE, LG>(raw, lane);
     } else {
-        bool special = false;
-#pragma unroll
-        for (int r = 0; r < GE; r++) {
-            if ((uint32_t)(r * G + gl) >= size) raw[r] = 0x7ff0000000000000ull;  // +inf pads
-            special |= (raw[r] << 1) > 0xffe0000000000000ull || raw[r] == 0x8000000000000000ull;  // NaN, -0.0
-        }
-        if (__ballot(special) != 0) {
-            base_items_one_by_one(P, items, task * GPW, min<uint64_t>(nitem, task * GPW + GPW), lane);
-            return;
-        }
         double k[GE];
 #pragma unroll
         for (int r = 0; r < GE; r++) k[r] = __builtin_bit_cast(double, raw[r]);
@@ -138,23 +162,52 @@ __device__ __forceinline__ void base_group_task(const Params& P, const uint64_t*
 #pragma unroll
         for (int r = 0; r < GE; r++) raw[r] = __builtin_bit_cast(uint64_t, k[r]);
     }
+    // Element i of the sub-array is lane i / E, register i % E.  Phase h moves
+    // registers 16h .. 16h+15 of every lane: lane c's run lands at LDS slots
+    // c*16 .. c*16+15 of the group's region, and is read back as
+    // u = rr * G + gl, i.e. element (u / 16) * E + 16h + u % 16, so the G
+    // lanes of a store write G consecutive keys.
+    const int gs = opaque(lane) & (G - 1);
+    uint64_t* mine = lds + (opaque(lane) >> LG) * (G * GPH + G * GPH / 16);
 #pragma unroll
-    for (int r = 0; r < GE; r++) mine[gslot(gl * GE + r)] = raw[r];
-    wave_lds_sync();
-    uint64_t o[GE];
+    for (int h = 0; h < GE / GPH; h++) {
 #pragma unroll
-    for (int r = 0; r < GE; r++) o[r] = mine[gslot(r * G + gl)];
+        for (int rr = 0; rr < GPH; rr++) mine[gslot(gs * GPH + rr)] = raw[h * GPH + rr];
+        wave_lds_sync();
+        uint64_t o[GPH];
 #pragma unroll
-    for (int r = 0; r < GE; r++)
-        if ((uint32_t)(r * G + gl) < size) dst[r * G + gl] = o[r];
-    wave_lds_sync();  // the next task rewrites the region
+        for (int rr = 0; rr < GPH; rr++) o[rr] = mine[gslot(rr * G + gs)];
+#pragma unroll
+        for (int rr = 0; rr < GPH; rr++) {
+            const uint32_t u = rr * G + gs, pos = (u / GPH) * GE + h * GPH + u % GPH;
+            if (pos < size) gstore(dst + pos, o[rr]);
+        }
+        wave_lds_sync();  // the next phase (or task) rewrites the region
+    }
 }
 
-// Three loops, each grid-strided over every wavefront (so each class is spread
-// evenly), largest items first: whole-wave items (257..512 keys), tasks of 4
-// items of 129..256 keys, tasks of 8 items of up to 128 keys.  Separate loops
-// keep each class's loop-invariant registers out of the others'.  With a
-// payload every item is one wave task (the stable pair sort, wave_bitonic).
+// The tasks of one class, grid-strided over every wavefront; the next task's
+// descriptors are loaded before the current task is sorted.
+template <int LG, bool U64, bool REV>
+__device__ __forceinline__ void group_loop(const Params& P, const uint64_t* items, uint64_t cap, uint64_t nitem,
+                                           uint64_t wid, uint64_t waves, uint64_t* lds, int lane) {
+    const uint64_t ntask = (nitem + (WAVE >> LG) - 1) / (WAVE >> LG);
+    if (wid >= ntask) return;
+    const uint64_t* k0 = P.keys[0];
+    const uint64_t* k1 = P.keys[1];
+    uint64_t wd = group_desc<LG, REV>(items, cap, wid, nitem, lane);
+    for (uint64_t t = wid; t < ntask; t += waves) {
+        const uint64_t wn = group_desc<LG, REV>(items, cap, min(t + waves, ntask - 1), nitem, lane);
+        base_group_task<LG, U64>(P, k0, k1, wd, t, nitem, lds, lane);
+        wd = wn;
+    }
+}
+
+// Three loops over the group classes, each grid-strided over every wavefront
+// (so each class is spread evenly), largest items first: tasks of 4 items of
+// 257..512 keys, of 8 items of 129..256, of 16 items of up to 128.  Separate
+// loops keep each class's loop-invariant registers out of the others'.  With
+// a payload every item is one wave task (the stable pair sort, wave_bitonic).
 template <bool PAY, bool U64>
 __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
     constexpr int W = BASE_THREADS / 64;
@@ -164,20 +217,22 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
     const uint64_t n0 = min<unsigned long long>(P.ctl->nitems, P.item_cap);
     const uint64_t n1 = min<unsigned long long>(P.ctl->nitems_b, P.item_b_cap);
     const uint64_t nw = min<unsigned long long>(P.ctl->nitems_w, P.item_cap);
-    const uint64_t nall = PAY ? nw + n1 + n0 : nw;
-    for (uint64_t t = wid; t < nall; t += waves) {
-        const uint64_t wd = t < nw ? P.items[P.item_cap - 1 - t] : t < nw + n1 ? P.items_b[t - nw] : P.items[t - nw - n1];
-        const uint64_t off = wd >> 18;
-        const uint32_t srcb = (wd >> 17) & 1u;
-        const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
-        if (size <= 64) base_small_item<1, PAY>(P, off, size, srcb, lane);
-        else if (size <= 128) base_small_item<2, PAY>(P, off, size, srcb, lane);
-        else if (size <= 256) base_small_item<4, PAY>(P, off, size, srcb, lane);
-        else base_small_item<8, PAY>(P, off, size, srcb, lane);
+    if (PAY) {
+        for (uint64_t t = wid; t < nw + n1 + n0; t += waves) {
+            const uint64_t wd = t < nw ? P.items[P.item_cap - 1 - t] : t < nw + n1 ? P.items_b[t - nw] : P.items[t - nw - n1];
+            const uint64_t off = wd >> 18;
+            const uint32_t srcb = (wd >> 17) & 1u;
+            const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
+            if (size <= 64) base_small_item<1, PAY>(P, off, size, srcb, lane);
+            else if (size <= 128) base_small_item<2, PAY>(P, off, size, srcb, lane);
+            else if (size <= 256) base_small_item<4, PAY>(P, off, size, srcb, lane);
+            else base_small_item<8, PAY>(P, off, size, srcb, lane);
+        }
+        return;
     }
-    if (PAY) return;
-    for (uint64_t t = wid; t < (n1 + 3) / 4; t += waves) base_group_task<4, U64>(P, P.items_b, t, n1, glds[wv], lane);
-    for (uint64_t t = wid; t < (n0 + 7) / 8; t += waves) base_group_task<3, U64>(P, P.items, t, n0, glds[wv], lane);
+    group_loop<4, U64, true>(P, P.items, P.item_cap, nw, wid, waves, glds[wv], lane);
+    group_loop<3, U64, false>(P, P.items_b, P.item_b_cap, n1, wid, waves, glds[wv], lane);
+    group_loop<2, U64, false>(P, P.items, P.item_cap, n0, wid, waves, glds[wv], lane);
 }
 
 constexpr int BIG_THREADS = 512;

@@ -494,6 +494,17 @@ __device__ __forceinline__ T cx_lane(T mine, T other, bool keep_max) {
     return ((other < mine) != keep_max) ? other : mine;
 }
 
+// Index with a 0 bit inserted at position c: the q-th register whose bit c is 0.
+__device__ __forceinline__ constexpr int ins0(int q, int c) { return ((q >> c) << (c + 1)) | (q & ((1 << c) - 1)); }
+
+// Scheduling window: a fence every GW comparators keeps the scheduler from
+// overlapping a whole stage's comparators, each of which holds a temporary
+// register pair while in flight.
+constexpr int GW = 4;
+__device__ __forceinline__ void cx_window(int q) {
+    if ((q % GW) == GW - 1) __builtin_amdgcn_sched_barrier(0);
+}
+
 template <typename T, int LE, int LG>
 __device__ __forceinline__ void group_bitonic(T (&k)[1 << LE], int lane) {
     constexpr int E = 1 << LE;
@@ -503,8 +514,10 @@ __device__ __forceinline__ void group_bitonic(T (&k)[1 << LE], int lane) {
         const int b = p - 1;
         if (b < LE) {  // flip inside the lane
 #pragma unroll
-            for (int r = 0; r < E; r++) {
-                if (!((r >> b) & 1)) cx_reg(k[r], k[r ^ ((2 << b) - 1)]);
+            for (int q = 0; q < E / 2; q++) {
+                const int r = ins0(q, b);
+                cx_reg(k[r], k[r ^ ((2 << b) - 1)]);
+                cx_window(q);
             }
         } else {  // flip across lanes: partner lane ^ (2^(s+1) - 1), register E-1-r
             const int s = b - LE;
@@ -514,20 +527,26 @@ __device__ __forceinline__ void group_bitonic(T (&k)[1 << LE], int lane) {
                 const T y0 = dpp_t(k[E - 1 - r], 4 + s), y1 = dpp_t(k[r], 4 + s);
                 k[r] = cx_lane(k[r], y0, km);
                 k[E - 1 - r] = cx_lane(k[E - 1 - r], y1, km);
+                cx_window(r);
             }
         }
 #pragma unroll
         for (int c = b - 1; c >= 0; c--) {
             if (c < LE) {
 #pragma unroll
-                for (int r = 0; r < E; r++) {
-                    if (!((r >> c) & 1)) cx_reg(k[r], k[r | (1 << c)]);
+                for (int q = 0; q < E / 2; q++) {
+                    const int r = ins0(q, c);
+                    cx_reg(k[r], k[r | (1 << c)]);
+                    cx_window(q);
                 }
             } else {
                 const int s = c - LE;
                 const bool km = (lane >> s) & 1;
 #pragma unroll
-                for (int r = 0; r < E; r++) k[r] = cx_lane(k[r], dpp_t(k[r], s), km);
+                for (int r = 0; r < E; r++) {
+                    k[r] = cx_lane(k[r], dpp_t(k[r], s), km);
+                    cx_window(r);
+                }
             }
         }
     }

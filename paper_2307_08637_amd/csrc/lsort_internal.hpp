@@ -123,6 +123,7 @@ struct Ctl {
     unsigned long long nitems_w;    // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)
     unsigned long long nitems_b;    // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys (items_b)
     unsigned long long nbig;        // large base-case items and copy items
+    unsigned long long nmoved;      // small items handed on to the large list (NaN / -0.0 tasks)
     unsigned long long ncopy;
     unsigned long long small_keys;  // keys in small base-case items
     unsigned long long big_keys;    // keys in large base-case items and copy runs
