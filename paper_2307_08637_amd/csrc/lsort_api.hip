@@ -195,7 +195,7 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.tile_cap = n / UNIT + L.seg_cap + 16;
     L.item_cap = n + m + 64;        // small items hold >= 1 key
     L.big_cap = n / 2 + m + 64;     // large items > 512 keys, copy runs >= 2 keys
-    L.item_b_cap = n / (GROUP_SMALL_MAX + 1) + m + 64;  // items of 129..256 keys
+    L.item_b_cap = n / (GROUP_SMALL_MAX + 1) + m + 64;  // items of 129..256 keys and of 513..1024
     // Bucket counts per level: a segment gets at most n_seg / 4 buckets (at
     // least 2), except one first-level segment whose model the caller gives
     // (up to B_MAX).  Look-back words: tiles x buckets of each segment.
@@ -721,7 +721,7 @@ ls_status ls_get_stats(ls_stats* out) {
     out->levels = levels;
     out->first_model = c.first_mlp ? LS_MODEL_MLP
                        : c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
-    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nbig - c.ncopy - c.nmoved;
+    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nitems_k + c.nbig - c.ncopy - c.nmoved;
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
     out->mlp_loss_last = c.mlp_loss[1];

@@ -12,9 +12,10 @@ namespace ls {
 
 // ===========================================================================
 // Base case (Sec. 4: sub-arrays below the cutoff are sorted directly).
-// k_base_small: sub-arrays of at most 512 keys sorted in registers by groups
-// of 4, 8 or 16 lanes (group_bitonic, 16, 8 or 4 sub-arrays per wavefront);
-// with a payload, one sub-array per wavefront (wave_bitonic); k_base_big: one workgroup per larger sub-array
+// k_base_small: sub-arrays of at most 1024 keys sorted in registers by groups
+// of 4, 8, 16 or 32 lanes (group_bitonic, 16, 8, 4 or 2 sub-arrays per
+// wavefront); with a payload, sub-arrays of at most 512 keys, one per
+// wavefront (wave_bitonic); k_base_big: one workgroup per larger sub-array
 // (up to 4096) sorted in LDS, and the copies of finished runs.
 // ===========================================================================
 
@@ -53,7 +54,7 @@ __device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, u
 
 // Group items: 64 / G sub-arrays per wavefront, G lanes and E = 32 keys per
 // lane each (group_bitonic): items of up to 128 keys on 4 lanes, 129..256 on
-// 8 lanes, 257..512 on 16 lanes.  Loads read key j of a sub-array into lane
+// 8 lanes, 257..512 on 16 lanes, 513..1024 on 32 lanes.  Loads read key j of a sub-array into lane
 // j % G, register j / G (consecutive lanes, consecutive keys: any placement
 // of unsorted input is valid).  The sorted keys leave through LDS in phases
 // of 16 registers, each wave in its own 8.5 KB region, so that stores are
@@ -63,7 +64,8 @@ __device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, u
 constexpr int GLE = 5, GE = 1 << GLE;
 constexpr int GPH = 16;                              // registers per LDS phase
 constexpr int G_SLOTS = WAVE * GPH + WAVE * GPH / 16; // LDS slots per wave: one pad slot after every 16
-static_assert(GE * 4 == GROUP_SMALL_MAX && GE * 8 == GROUP_MAX && GE * 16 == SMALL_MAX, "lane groups of 4, 8, 16");
+static_assert(GE * 4 == GROUP_SMALL_MAX && GE * 8 == GROUP_MAX && GE * 16 == SMALL_MAX && GE * 32 == GROUP_LARGE_MAX,
+              "lane groups of 4, 8, 16, 32");
 
 __device__ __forceinline__ uint32_t gslot(uint32_t i) { return i + (i >> 4); }
 
@@ -203,11 +205,12 @@ __device__ __forceinline__ void group_loop(const Params& P, const uint64_t* item
     }
 }
 
-// Three loops over the group classes, each grid-strided over every wavefront
-// (so each class is spread evenly), largest items first: tasks of 4 items of
-// 257..512 keys, of 8 items of 129..256, of 16 items of up to 128.  Separate
-// loops keep each class's loop-invariant registers out of the others'.  With
-// a payload every item is one wave task (the stable pair sort, wave_bitonic).
+// One loop per group class, each grid-strided over every wavefront (so each
+// class is spread evenly), largest items first: tasks of 2 items of
+// 513..1024 keys (keys only), of 4 items of 257..512, of 8 of 129..256, of 16
+// of up to 128.  Separate loops keep each class's loop-invariant registers
+// out of the others'.  With a payload every item is one wave task (the
+// stable pair sort, wave_bitonic).
 template <bool PAY, bool U64>
 __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
     constexpr int W = BASE_THREADS / 64;
@@ -230,6 +233,8 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
         }
         return;
     }
+    const uint64_t nk = min<unsigned long long>(P.ctl->nitems_k, P.item_b_cap);
+    group_loop<5, U64, true>(P, P.items_b, P.item_b_cap, nk, wid, waves, glds[wv], lane);
     group_loop<4, U64, true>(P, P.items, P.item_cap, nw, wid, waves, glds[wv], lane);
     group_loop<3, U64, false>(P, P.items_b, P.item_b_cap, n1, wid, waves, glds[wv], lane);
     group_loop<2, U64, false>(P, P.items, P.item_cap, n0, wid, waves, glds[wv], lane);

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lsort_internal.hpp"
 
 namespace ls {
@@ -436,17 +438,15 @@ __device__ void bitonic_pairs(uint64_t* a, uint16_t* ix, uint32_t P) {
 
 // ---------------------------------------------------------------------------
 // Group sort (keys only): one wavefront sorts 64/G independent sub-arrays at
-// once, G = 2^LG lanes each (G <= 16: one DPP row), E = 2^LE keys per lane.
+// once, G = 2^LG lanes each (G <= 64), E = 2^LE keys per lane.
 // Element i of a sub-array sits in lane (group base + i / E), register i % E:
 // the low LE index bits are register bits, so most comparators of the
 // network join two registers of one lane.  The network is the bitonic sort
 // in its flip form: phase p merges sorted runs of 2^(p-1) by comparing i with
 // i ^ (2^p - 1), then half-cleans with i ^ 2^c for c = p-2 .. 0; every
 // comparator puts the smaller key at the lower index, so there are no
-// direction bits.  Lane partners come from DPP: the flip's partner lane is a
-// mirror (quad_perm [1,0,3,2] / [3,2,1,0], row_half_mirror, row_mirror), a
-// half-cleaner's is lane ^ 1, ^ 2, ^ 4 (half-mirror then quad reversal) or
-// ^ 8 (row_ror 8).
+// direction bits.  Lane partners come from dpp_t: the flip's partner lane is
+// a mirror, a half-cleaner's a lane xor.
 //   T = double: finite or infinite binary64 keys without NaN and without
 //   -0.0 (callers check), compared as numbers (v_min_f64 / v_max_f64);
 //   T = uint64_t: ordered keys compared as integers.
@@ -458,19 +458,25 @@ __device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename T>
-__device__ __forceinline__ T dpp_t(T v, int op) {
+// Partner value across lanes: OP s (0..5) is lane ^ 2^s, OP 8 + s is the
+// mirror lane ^ (2^(s+1) - 1).  Inside a row of 16 lanes DPP does it (one
+// move per word, two for lane ^ 4); lane bits 4 and 5 go through the
+// permlane swaps (xor_lane64).
+template <int OP, typename T>
+__device__ __forceinline__ T dpp_t(T v, uint32_t lane) {
     uint64_t u = __builtin_bit_cast(uint64_t, v);
-    switch (op) {  // constant after unrolling
-    case 0: u = dpp_u64<0xB1>(u); break;                  // lane ^ 1
-    case 1: u = dpp_u64<0x4E>(u); break;                  // lane ^ 2
-    case 2: u = dpp_u64<0x1B>(dpp_u64<0x141>(u)); break;  // lane ^ 4 = (lane ^ 7) ^ 3
-    case 3: u = dpp_u64<0x128>(u); break;                 // lane ^ 8
-    case 4: u = dpp_u64<0xB1>(u); break;                  // lane ^ 1  (mirror of 2 lanes)
-    case 5: u = dpp_u64<0x1B>(u); break;                  // lane ^ 3  (mirror of 4)
-    case 6: u = dpp_u64<0x141>(u); break;                 // lane ^ 7  (mirror of 8)
-    default: u = dpp_u64<0x140>(u); break;                // lane ^ 15 (mirror of 16)
-    }
+    if constexpr (OP == 0) u = dpp_u64<0xB1>(u);                  // lane ^ 1
+    else if constexpr (OP == 1) u = dpp_u64<0x4E>(u);             // lane ^ 2
+    else if constexpr (OP == 2) u = dpp_u64<0x1B>(dpp_u64<0x141>(u));  // lane ^ 4 = (lane ^ 7) ^ 3
+    else if constexpr (OP == 3) u = dpp_u64<0x128>(u);            // lane ^ 8
+    else if constexpr (OP == 4) u = xor_lane64(u, 16, lane);      // lane ^ 16
+    else if constexpr (OP == 5) u = xor_lane64(u, 32, lane);      // lane ^ 32
+    else if constexpr (OP == 8) u = dpp_u64<0xB1>(u);             // lane ^ 1  (mirror of 2 lanes)
+    else if constexpr (OP == 9) u = dpp_u64<0x1B>(u);             // lane ^ 3  (mirror of 4)
+    else if constexpr (OP == 10) u = dpp_u64<0x141>(u);           // lane ^ 7  (mirror of 8)
+    else if constexpr (OP == 11) u = dpp_u64<0x140>(u);           // lane ^ 15 (mirror of 16)
+    else if constexpr (OP == 12) u = xor_lane64(dpp_u64<0x140>(u), 16, lane);                       // lane ^ 31
+    else u = xor_lane64(xor_lane64(dpp_u64<0x140>(u), 16, lane), 32, lane);                         // lane ^ 63
     return __builtin_bit_cast(T, u);
 }
 
@@ -505,51 +511,62 @@ __device__ __forceinline__ void cx_window(int q) {
     if ((q % GW) == GW - 1) __builtin_amdgcn_sched_barrier(0);
 }
 
-template <typename T, int LE, int LG>
-__device__ __forceinline__ void group_bitonic(T (&k)[1 << LE], int lane) {
+// One stage of the network, B the index bit it compares across; FLIP: the
+// merge's first stage (partner i ^ (2^(B+1) - 1)), else a half-cleaner
+// (partner i ^ 2^B).  Stages and phases are unrolled by template recursion,
+// so every register index and lane exchange is a compile-time constant.
+template <typename T, int LE, int B, bool FLIP>
+__device__ __forceinline__ void group_stage(T (&k)[1 << LE], int lane) {
     constexpr int E = 1 << LE;
-    static_assert(LG <= 4, "lane groups stay inside one DPP row");
+    if constexpr (B < LE) {  // inside the lane
 #pragma unroll
-    for (int p = 1; p <= LE + LG; p++) {
-        const int b = p - 1;
-        if (b < LE) {  // flip inside the lane
-#pragma unroll
-            for (int q = 0; q < E / 2; q++) {
-                const int r = ins0(q, b);
-                cx_reg(k[r], k[r ^ ((2 << b) - 1)]);
-                cx_window(q);
-            }
-        } else {  // flip across lanes: partner lane ^ (2^(s+1) - 1), register E-1-r
-            const int s = b - LE;
-            const bool km = (lane >> s) & 1;
-#pragma unroll
-            for (int r = 0; r < E / 2; r++) {
-                const T y0 = dpp_t(k[E - 1 - r], 4 + s), y1 = dpp_t(k[r], 4 + s);
-                k[r] = cx_lane(k[r], y0, km);
-                k[E - 1 - r] = cx_lane(k[E - 1 - r], y1, km);
-                cx_window(r);
-            }
+        for (int q = 0; q < E / 2; q++) {
+            const int r = ins0(q, B);
+            cx_reg(k[r], k[FLIP ? r ^ ((2 << B) - 1) : r | (1 << B)]);
+            cx_window(q);
         }
+    } else if constexpr (FLIP) {  // partner lane ^ (2^(s+1) - 1), register E-1-r
+        constexpr int S = B - LE;
+        const bool km = (lane >> S) & 1;
 #pragma unroll
-        for (int c = b - 1; c >= 0; c--) {
-            if (c < LE) {
+        for (int r = 0; r < E / 2; r++) {
+            const T y0 = dpp_t<8 + S>(k[E - 1 - r], (uint32_t)lane), y1 = dpp_t<8 + S>(k[r], (uint32_t)lane);
+            k[r] = cx_lane(k[r], y0, km);
+            k[E - 1 - r] = cx_lane(k[E - 1 - r], y1, km);
+            cx_window(r);
+        }
+    } else {
+        constexpr int S = B - LE;
+        const bool km = (lane >> S) & 1;
 #pragma unroll
-                for (int q = 0; q < E / 2; q++) {
-                    const int r = ins0(q, c);
-                    cx_reg(k[r], k[r | (1 << c)]);
-                    cx_window(q);
-                }
-            } else {
-                const int s = c - LE;
-                const bool km = (lane >> s) & 1;
-#pragma unroll
-                for (int r = 0; r < E; r++) {
-                    k[r] = cx_lane(k[r], dpp_t(k[r], s), km);
-                    cx_window(r);
-                }
-            }
+        for (int r = 0; r < E; r++) {
+            k[r] = cx_lane(k[r], dpp_t<S>(k[r], (uint32_t)lane), km);
+            cx_window(r);
         }
     }
+}
+
+template <typename T, int LE, int C>
+__device__ __forceinline__ void group_clean(T (&k)[1 << LE], int lane) {
+    if constexpr (C >= 0) {
+        group_stage<T, LE, C, false>(k, lane);
+        group_clean<T, LE, C - 1>(k, lane);
+    }
+}
+
+template <typename T, int LE, int LG, int PH>
+__device__ __forceinline__ void group_phases(T (&k)[1 << LE], int lane) {
+    if constexpr (PH <= LE + LG) {
+        group_stage<T, LE, PH - 1, true>(k, lane);
+        group_clean<T, LE, PH - 2>(k, lane);
+        group_phases<T, LE, LG, PH + 1>(k, lane);
+    }
+}
+
+template <typename T, int LE, int LG>
+__device__ __forceinline__ void group_bitonic(T (&k)[1 << LE], int lane) {
+    static_assert(LG <= 6, "lane groups within one wavefront");
+    group_phases<T, LE, LG, 1>(k, lane);
 }
 
 // Bitonic sort of 64*E (key, index) pairs held by one wavefront, lane l
@@ -707,6 +724,40 @@ __device__ __forceinline__ uint32_t view_bucket(const View& v, const uint64_t* m
         return tree_bucket(mdl + 2, (const uint16_t*)(mdl + 2 + v.m), v.m, v.top, key_ord(raw, u64));
     case K_RADIX: return radix_bucket(v.lo, v.shift, key_ord(raw, u64));
     default: return ids[pos];  // K_MLP, K_MLP_FINE: ids stored by k_mlp_ids
+    }
+}
+
+// view_bucket with the kind fixed at compile time (KIND: K_RMI, K_RMI_FINE,
+// K_TREE for both tree kinds, K_RADIX, K_MLP for both stored-id kinds), so
+// that a loop over keys carries no per-key dispatch; KIND 0 dispatches at run
+// time (one copy of the loop).
+template <int KIND>
+__device__ __forceinline__ uint32_t kind_bucket(const View& v, const uint64_t* mdl, uint64_t raw, int u64,
+                                                const uint16_t* ids, uint64_t pos) {
+    if constexpr (KIND == 0) return view_bucket(v, mdl, raw, u64, ids, pos);
+    else if constexpr (KIND == K_RMI) return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) >> v.log2B2;
+    else if constexpr (KIND == K_RMI_FINE) return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) - v.win;
+    else if constexpr (KIND == K_TREE)
+        return tree_bucket(mdl + 2, (const uint16_t*)(mdl + 2 + v.m), v.m, v.top, key_ord(raw, u64));
+    else if constexpr (KIND == K_RADIX) return radix_bucket(v.lo, v.shift, key_ord(raw, u64));
+    else return ids[pos];
+}
+
+// Calls f(std::integral_constant<int, KIND>) for the kind of a view (with
+// KIND 0, the run-time dispatch, when SPECIALISE is false).
+template <bool SPECIALISE = true, typename F>
+__device__ __forceinline__ void with_kind(uint32_t kind, F&& f) {
+    if (!SPECIALISE) {
+        f(std::integral_constant<int, 0>{});
+        return;
+    }
+    switch (kind) {
+    case K_RMI: f(std::integral_constant<int, K_RMI>{}); break;
+    case K_RMI_FINE: f(std::integral_constant<int, K_RMI_FINE>{}); break;
+    case K_TREE:
+    case K_TREE_FORCED: f(std::integral_constant<int, K_TREE>{}); break;
+    case K_RADIX: f(std::integral_constant<int, K_RADIX>{}); break;
+    default: f(std::integral_constant<int, K_MLP>{}); break;
     }
 }
 

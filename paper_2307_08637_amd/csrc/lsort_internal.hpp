@@ -23,6 +23,7 @@ constexpr int C_MAX = 4096;                    // largest base-case sub-array
 constexpr int SMALL_MAX = 512;                 // largest sub-array one wavefront sorts in registers
 constexpr int GROUP_MAX = 256;                 // largest sub-array a lane group sorts (4 per wavefront)
 constexpr int GROUP_SMALL_MAX = 128;           // ... sorted by a smaller lane group (8 per wavefront)
+constexpr int GROUP_LARGE_MAX = 1024;          // largest keys-only sub-array one wavefront sorts in registers
 constexpr int MAXL = 32;                       // partition levels (arrays)
 constexpr int MODEL_WORDS = 4 + 2 + 4 * L_MAX; // 8-byte words of the largest model (RMI, L_MAX leaves)
 constexpr uint64_t COPY_CHUNK = 65536;         // keys per copy item
@@ -122,6 +123,7 @@ struct Ctl {
     unsigned long long nitems;      // small base-case items of <= GROUP_SMALL_MAX keys (front of items)
     unsigned long long nitems_w;    // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)
     unsigned long long nitems_b;    // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys (items_b)
+    unsigned long long nitems_k;    // keys only: items of SMALL_MAX+1 .. GROUP_LARGE_MAX keys (back of items_b)
     unsigned long long nbig;        // large base-case items and copy items
     unsigned long long nmoved;      // small items handed on to the large list (NaN / -0.0 tasks)
     unsigned long long ncopy;
@@ -155,7 +157,8 @@ struct Params {
     Tile* tiles[2];
     uint64_t* items;                // small base-case items: <= GROUP_SMALL_MAX keys from the front,
                                     // GROUP_MAX+1 .. SMALL_MAX keys from the back
-    uint64_t* items_b;              // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys
+    uint64_t* items_b;              // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys from the
+                                    // front, keys only SMALL_MAX+1 .. GROUP_LARGE_MAX from the back
     uint64_t* bigs;                 // large base-case items and copy items
     unsigned long long* counts;
     unsigned long long* status;

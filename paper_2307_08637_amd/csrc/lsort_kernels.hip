@@ -41,7 +41,7 @@ __global__ void k_reset(Params P, uint64_t* persist) {
 __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets, uint64_t m, uint64_t n_single,
                                               uint32_t prebuilt, const uint64_t* persist) {
     __shared__ uint64_t red64[256 / 64];
-    __shared__ uint64_t base[6];
+    __shared__ uint64_t base[7];
     if (persist[1]) {
         for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.status_cap;
              i += (uint64_t)gridDim.x * blockDim.x)
@@ -57,16 +57,18 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
         }
         // prebuilt: the caller supplied the first level's model; always partition
         const bool item = s < m && !prebuilt && n >= 2 && n <= P.cutoff;
-        const bool small = item && n <= SMALL_MAX;
-        const int cls = !small ? 3 : n <= GROUP_SMALL_MAX ? 0 : n <= GROUP_MAX ? 1 : 2;  // item list
+        // keys only: up to GROUP_LARGE_MAX keys still go to k_base_small
+        const bool small = item && (n <= SMALL_MAX || (n <= GROUP_LARGE_MAX && !P.has_pay));
+        const int cls = !small ? 3 : n <= GROUP_SMALL_MAX ? 0 : n <= GROUP_MAX ? 1 : n <= SMALL_MAX ? 2 : 4;
         const bool seg = s < m && (prebuilt ? n >= 1 : n > P.cutoff);
         // an array small enough for one workgroup is sorted whole by k_resident
         const bool resident = seg && !prebuilt && n <= RES_MAX;
         const uint32_t nt = seg && !resident ? (uint32_t)((n + UNIT - 1) / UNIT) : 0;
-        uint64_t itot, wtot, gtot, btot, stot, ttot;
+        uint64_t itot, wtot, gtot, ktot, btot, stot, ttot;
         const uint64_t iex = block_excl_scan<256, uint64_t>(item && cls == 0 ? 1 : 0, red64, &itot);
         const uint64_t gex = block_excl_scan<256, uint64_t>(item && cls == 1 ? 1 : 0, red64, &gtot);
         const uint64_t wex = block_excl_scan<256, uint64_t>(item && cls == 2 ? 1 : 0, red64, &wtot);
+        const uint64_t kex = block_excl_scan<256, uint64_t>(item && cls == 4 ? 1 : 0, red64, &ktot);
         const uint64_t bex = block_excl_scan<256, uint64_t>(item && !small ? 1 : 0, red64, &btot);
         const uint64_t sex = block_excl_scan<256, uint64_t>(seg ? 1 : 0, red64, &stot);
         const uint64_t tex = block_excl_scan<256, uint64_t>(nt, red64, &ttot);
@@ -79,15 +81,18 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
             base[3] = btot ? atomicAdd(&P.ctl->nbig, (unsigned long long)btot) : 0;
             base[4] = wtot ? atomicAdd(&P.ctl->nitems_w, (unsigned long long)wtot) : 0;
             base[5] = gtot ? atomicAdd(&P.ctl->nitems_b, (unsigned long long)gtot) : 0;
+            base[6] = ktot ? atomicAdd(&P.ctl->nitems_k, (unsigned long long)ktot) : 0;
             if (sk) atomicAdd(&P.ctl->small_keys, (unsigned long long)sk);
             if (gk) atomicAdd(&P.ctl->big_keys, (unsigned long long)gk);
         }
         __syncthreads();
         if (item) {
-            const uint64_t it = cls == 0 ? base[0] + iex : cls == 1 ? base[5] + gex : cls == 2 ? base[4] + wex : base[3] + bex;
-            const uint64_t cap = cls == 1 ? P.item_b_cap : cls == 3 ? P.big_cap : P.item_cap;
-            uint64_t* list = cls == 1 ? P.items_b : cls == 3 ? P.bigs : P.items;
-            if (it < cap) list[cls == 2 ? cap - 1 - it : it] = item_pack(lo, 0, 0, (uint32_t)n);
+            const uint64_t it = cls == 0 ? base[0] + iex : cls == 1 ? base[5] + gex : cls == 2 ? base[4] + wex
+                              : cls == 4 ? base[6] + kex : base[3] + bex;
+            const uint64_t cap = cls == 1 || cls == 4 ? P.item_b_cap : cls == 3 ? P.big_cap : P.item_cap;
+            uint64_t* list = cls == 1 || cls == 4 ? P.items_b : cls == 3 ? P.bigs : P.items;
+            // lists 2 and 4 fill their arrays from the back
+            if (it < cap) list[cls == 2 || cls == 4 ? cap - 1 - it : it] = item_pack(lo, 0, 0, (uint32_t)n);
             else atomicOr(&P.ctl->overflow, OVF_ITEM);
         }
         if (seg) {
@@ -422,40 +427,44 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
         const View v = make_view(mdl, sg.kind, sg.nb, sg.win);
         const uint64_t base = sg.off + (uint64_t)td.idx * UNIT;
         const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
-        const bool aggregate = v.kind == K_TREE || v.kind == K_TREE_FORCED || v.kind == K_RADIX;
         const int bits = ceil_log2(sg.nb);
-        // HK keys per thread are loaded before any is used, so that every wave
-        // keeps HK loads in flight (the unit is read exactly once)
-        for (uint32_t i0 = 0; i0 < un; i0 += P_THREADS * HK) {
-            uint64_t kk[HK];
+        with_kind(v.kind, [&](auto kc) {
+            constexpr int KIND = decltype(kc)::value;
+            // trees and radix put runs of equal keys into one bucket: add per
+            // distinct bucket of the wave
+            constexpr bool aggregate = KIND == K_TREE || KIND == K_RADIX;
+            // HK keys per thread are loaded before any is used, so that every
+            // wave keeps HK loads in flight (the unit is read exactly once)
+            for (uint32_t i0 = 0; i0 < un; i0 += P_THREADS * HK) {
+                uint64_t kk[HK];
 #pragma unroll
-            for (int r = 0; r < HK; r++) {
-                const uint32_t i = i0 + r * P_THREADS + tid;
-                kk[r] = i < un ? src[base + i] : 0;
-            }
+                for (int r = 0; r < HK; r++) {
+                    const uint32_t i = i0 + r * P_THREADS + tid;
+                    kk[r] = i < un ? src[base + i] : 0;
+                }
 #pragma unroll
-            for (int r = 0; r < HK; r++) {
-                const uint32_t i = i0 + r * P_THREADS + tid;
-                if (i0 + r * P_THREADS >= un) break;  // uniform: no key of this round in range
-                const bool in = i < un;
-                const uint32_t b = in ? view_bucket(v, mdl, kk[r], u64, P.ids, base + i) : 0u;
-                if (aggregate) {
-                    // wave-aggregated: one LDS add per distinct bucket in the wave
-                    if (in) {
-                        const uint64_t peers = match_peers(b, bits);
-                        if (mask_rank(peers) == 0) atomicAdd(&h[b], (uint32_t)__popcll(peers));
-                    }
-                } else if (in) {
-                    const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
-                    const uint64_t act = __ballot(1), same = __ballot(b == b0);
-                    if (same == act) {
-                        if (mask_rank(act) == 0) atomicAdd(&h[b0], (uint32_t)__popcll(act));
-                    } else {
-                        atomicAdd(&h[b], 1u);
+                for (int r = 0; r < HK; r++) {
+                    const uint32_t i = i0 + r * P_THREADS + tid;
+                    if (i0 + r * P_THREADS >= un) break;  // uniform: no key of this round in range
+                    const bool in = i < un;
+                    const uint32_t b = in ? kind_bucket<KIND>(v, mdl, kk[r], u64, P.ids, base + i) : 0u;
+                    if (aggregate) {
+                        if (in) {
+                            const uint64_t peers = match_peers(b, bits);
+                            if (mask_rank(peers) == 0) atomicAdd(&h[b], (uint32_t)__popcll(peers));
+                        }
+                    } else if (in) {
+                        const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
+                        const uint64_t act = __ballot(1), same = __ballot(b == b0);
+                        if (same == act) {
+                            if (mask_rank(act) == 0) atomicAdd(&h[b0], (uint32_t)__popcll(act));
+                        } else {
+                            atomicAdd(&h[b], 1u);
+                        }
                     }
                 }
             }
-        }
+        });
         __syncthreads();
         unsigned long long* row = P.status + sg.sbase + (uint64_t)td.idx * sg.nb;
         for (uint32_t b = tid; b < sg.nb; b += P_THREADS) {
@@ -517,7 +526,7 @@ __device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q,
 __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
     __shared__ uint64_t red64[S_THREADS / 64];
     __shared__ uint8_t eqb[B_MAX];
-    __shared__ uint64_t resv[6];
+    __shared__ uint64_t resv[7];
     const int tid = threadIdx.x;
     const int lvl = P.level;
     if (blockIdx.x == 0 && tid == 0) {  // pools of the next level (this level's data stays readable)
@@ -577,7 +586,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         __syncthreads();
         const double expected = (double)sg.n / (double)nb;
         uint32_t act[S_BPT];
-        uint64_t la = 0, lb = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0, lfb = 0;
+        uint64_t la = 0, lb = 0, lc = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0, lfb = 0;
 #pragma unroll
         for (int i = 0; i < S_BPT; i++) {
             const uint32_t b = S_BPT * tid + i;
@@ -586,15 +595,17 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const Decision d = decide(P, lvl, q, c[i], eqb[b] != 0, fine_ok, log2B2, expected);
             act[i] = d.act;
             lstat += d.stat;
-            const uint64_t nsm = d.act == 2 && c[i] <= SMALL_MAX ? 1 : 0;
+            const uint64_t nsm = d.act == 2 && (c[i] <= SMALL_MAX || (c[i] <= GROUP_LARGE_MAX && !P.has_pay)) ? 1 : 0;
             const uint64_t ng0 = nsm && c[i] <= GROUP_SMALL_MAX ? 1 : 0;
             const uint64_t ng1 = nsm && !ng0 && c[i] <= GROUP_MAX ? 1 : 0;
-            const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && c[i] > SMALL_MAX ? 1 : 0);
+            const uint64_t ng3 = nsm && c[i] > SMALL_MAX ? 1 : 0;
+            const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && !nsm ? 1 : 0);
             const uint64_t ntl = d.act >= 3 && !child_resident(sg.kind, d.act, c[i]) ? (c[i] + UNIT - 1) / UNIT : 0;
             // packed counters: items <= 128 keys | children << 16 | large items << 32,
             // units | items of 129..256 keys << 32 | items of 257..512 keys << 48
             la += ng0 | ((uint64_t)(d.act >= 3) << 16) | (nbg << 32);
-            lb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1) << 48);
+            lb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3) << 48);
+            lc += ng3;
             lfb += d.act == 5 ? 1 : 0;
             lsk += nsm ? c[i] : 0;
             lgk += nbg ? c[i] : 0;
@@ -604,6 +615,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         uint64_t ta, tb;
         uint64_t xa = block_excl_scan<S_THREADS, uint64_t>(la, red64, &ta);
         uint64_t xb = block_excl_scan<S_THREADS, uint64_t>(lb, red64, &tb);
+        uint64_t tc;
+        uint64_t xc = block_excl_scan<S_THREADS, uint64_t>(lc, red64, &tc);
         const uint64_t sk = block_sum<S_THREADS, uint64_t>(lsk, red64);
         const uint64_t gk = block_sum<S_THREADS, uint64_t>(lgk, red64);
         const uint64_t ncp = block_sum<S_THREADS, uint64_t>(lcp, red64);
@@ -616,6 +629,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             resv[0] = itot ? atomicAdd(&P.ctl->nitems, (unsigned long long)itot) : 0;
             resv[4] = wtot ? atomicAdd(&P.ctl->nitems_w, (unsigned long long)wtot) : 0;
             resv[5] = btot ? atomicAdd(&P.ctl->nitems_b, (unsigned long long)btot) : 0;
+            resv[6] = tc ? atomicAdd(&P.ctl->nitems_k, (unsigned long long)tc) : 0;
             resv[1] = ctot ? atomicAdd(&P.ctl->nseg[lvl + 1], (uint32_t)ctot) : 0;
             resv[2] = ttot ? atomicAdd(&P.ctl->ntile[lvl + 1], (uint32_t)ttot) : 0;
             resv[3] = gtot ? atomicAdd(&P.ctl->nbig, (unsigned long long)gtot) : 0;
@@ -642,17 +656,21 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const uint32_t b = S_BPT * tid + i;
             const uint32_t a = act[i];
             const uint64_t ci = c[i];
-            const uint64_t nsm = a == 2 && ci <= SMALL_MAX ? 1 : 0;
-            const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && ci > SMALL_MAX ? 1 : 0);
+            const uint64_t nsm = a == 2 && (ci <= SMALL_MAX || (ci <= GROUP_LARGE_MAX && !P.has_pay)) ? 1 : 0;
+            const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && !nsm ? 1 : 0);
             const uint64_t ntl = a >= 3 && !child_resident(sg.kind, a, ci) ? (ci + UNIT - 1) / UNIT : 0;
             const uint64_t iex = xa & 0xffff, cex = (xa >> 16) & 0xffff, gex = xa >> 32, tex = xb & 0xffffffffull;
             const uint64_t bex = (xb >> 32) & 0xffff, wex = xb >> 48;
             const uint64_t ng0 = nsm && ci <= GROUP_SMALL_MAX ? 1 : 0;
             const uint64_t ng1 = nsm && !ng0 && ci <= GROUP_MAX ? 1 : 0;
+            const uint64_t ng3 = nsm && ci > SMALL_MAX ? 1 : 0;
             if (nsm) {
-                const uint64_t it = ng0 ? resv[0] + iex : ng1 ? resv[5] + bex : resv[4] + wex;
-                const uint64_t cap = ng1 ? P.item_b_cap : P.item_cap;
-                if (it < cap) (ng1 ? P.items_b : P.items)[ng0 || ng1 ? it : cap - 1 - it] = item_pack(start[i], q, 0u, (uint32_t)ci);
+                // lists: <= 128 front of items, 129..256 front of items_b,
+                // 257..512 back of items, 513..1024 back of items_b
+                const uint64_t it = ng0 ? resv[0] + iex : ng1 ? resv[5] + bex : ng3 ? resv[6] + xc : resv[4] + wex;
+                const bool inb = ng1 || ng3;
+                const uint64_t cap = inb ? P.item_b_cap : P.item_cap;
+                if (it < cap) (inb ? P.items_b : P.items)[ng0 || ng1 ? it : cap - 1 - it] = item_pack(start[i], q, 0u, (uint32_t)ci);
                 else atomicOr(&P.ctl->overflow, OVF_ITEM);
             }
             for (uint64_t k = 0; k < nbg; k++) {
@@ -684,7 +702,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                 }
             }
             xa += ng0 | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
-            xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1) << 48);
+            xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3) << 48);
+            xc += ng3;
         }
         __syncthreads();
     }
@@ -725,6 +744,7 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
     __shared__ uint32_t tcnt[B_MAX];
     __shared__ uint16_t tstart[B_MAX];
     __shared__ uint64_t run[B_MAX];
+    __shared__ uint64_t delta[PAY ? 1 : B_MAX];  // run[b] - tstart[b] of the current tile (keys only)
     __shared__ uint32_t sh_t;
     __shared__ uint64_t red64[SW];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -782,25 +802,40 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
         const uint64_t ubase = sg.off + (uint64_t)td.idx * UNIT;
         const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
         const uint32_t ntl = (un + TILE - 1) / TILE;
-        // wave w owns keys [w*1024, (w+1)*1024) of a tile, 64 per round
+        // the payload variant keeps one copy of the tile loop (registers)
+        with_kind<!PAY>(v.kind, [&](auto kc) {
+        constexpr int KIND = decltype(kc)::value;
+        // wave w owns keys [w*1024, (w+1)*1024) of a tile, 64 per round.
+        // Keys only: every global load and store of the tile loop is issued
+        // unconditionally (indices clamp into the tile; a lane past the end
+        // repeats the tile's last load or store, same address and value), so
+        // the compiler's vector-memory wait counts stay exact and the next
+        // tile's loads stay in flight across this tile's stores.
         uint64_t k[SK], kn[SK];
         uint32_t pl[SK], pn[SK];
 #pragma unroll
         for (int r = 0; r < SK; r++) {
             const uint32_t i = w * SWK + r * WAVE + lane;
-            k[r] = i < un ? src[ubase + i] : 0;
-            pl[r] = (has_pay && i < un) ? psrc[ubase + i] : 0;
+            if (PAY) {
+                k[r] = i < un ? src[ubase + i] : 0;
+                pl[r] = i < un ? psrc[ubase + i] : 0;
+            } else {
+                k[r] = src[ubase + min(i, un - 1)];
+            }
         }
+        // the first tile's keys have arrived before the loop, so that inside
+        // it only the prefetched keys are waited for, never this tile's stores
+        if (!PAY) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         for (uint32_t tt = 0; tt < ntl; tt++) {
             const uint64_t base = ubase + (uint64_t)tt * TILE;
             const uint32_t tn = min<uint32_t>(TILE, un - tt * TILE);
-            if (tt + 1 < ntl) {  // prefetch the next tile
+            if (PAY && tt + 1 < ntl) {  // prefetch the next tile
                 const uint32_t nn = min<uint32_t>(TILE, un - (tt + 1) * TILE);
 #pragma unroll
                 for (int r = 0; r < SK; r++) {
                     const uint32_t i = w * SWK + r * WAVE + lane;
                     kn[r] = i < nn ? src[base + TILE + i] : 0;
-                    pn[r] = (has_pay && i < nn) ? psrc[base + TILE + i] : 0;
+                    pn[r] = i < nn ? psrc[base + TILE + i] : 0;
                 }
             }
             uint32_t b[SK], rk[SK];
@@ -813,7 +848,19 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
 #pragma unroll
             for (int r = 0; r < SK; r++) {
                 const uint32_t i = w * SWK + r * WAVE + lane;
-                b[r] = i < tn ? view_bucket(v, mdl, k[r], u64, P.ids, base + i) : 0;
+                if (PAY) {
+                    b[r] = i < tn ? kind_bucket<KIND>(v, mdl, k[r], u64, P.ids, base + i) : 0;
+                } else {
+                    const uint32_t bk = kind_bucket<KIND>(v, mdl, k[r], u64, P.ids, base + min(i, tn - 1));
+                    b[r] = i < tn ? bk : 0;
+                }
+            }
+            if (!PAY) {  // prefetch the next tile (or reload this one: in bounds, no branch)
+                const bool more = tt + 1 < ntl;
+                const uint64_t nbase = more ? base + TILE : base;
+                const uint32_t nn = more ? min<uint32_t>(TILE, un - (tt + 1) * TILE) : tn;
+#pragma unroll
+                for (int r = 0; r < SK; r++) kn[r] = src[nbase + min<uint32_t>(w * SWK + r * WAVE + lane, nn - 1)];
             }
             if (PAY) {
                 // stable rank within the wave: rounds in key order, lanes in key order
@@ -884,7 +931,14 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
 #pragma unroll
                 for (int q = 0; q < SB; q++) {
                     const uint32_t j = SB * tid + q;
-                    if (j < nb) tstart[j] = (uint16_t)ex;
+                    if (j < nb) {
+                        tstart[j] = (uint16_t)ex;
+                        if (!PAY) {
+                            const uint64_t rj = run[j];
+                            delta[j] = rj - ex;  // staging slot p of bucket j goes to position p + delta[j]
+                            run[j] = rj + c[q];  // the next tile's start of bucket j
+                        }
+                    }
                     ex += c[q];
                 }
             }
@@ -903,11 +957,25 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                 }
             }
             lds_barrier();
-            for (uint32_t p = tid; p < tn; p += NT) {
-                const uint32_t bb = sbid[p];
-                dst[run[bb] + (p - tstart[bb])] = stage[p];
-            }
-            if (has_pay) {
+            if (!PAY) {
+                uint32_t bq[SK];
+                uint64_t vq[SK];
+#pragma unroll
+                for (int q = 0; q < SK; q++) {
+                    const uint32_t p = min<uint32_t>(tid + q * NT, tn - 1);
+                    bq[q] = sbid[p];
+                    vq[q] = stage[p];
+                }
+#pragma unroll
+                for (int q = 0; q < SK; q++) {
+                    const uint32_t p = min<uint32_t>(tid + q * NT, tn - 1);
+                    dst[delta[bq[q]] + p] = vq[q];
+                }
+            } else {
+                for (uint32_t p = tid; p < tn; p += NT) {
+                    const uint32_t bb = sbid[p];
+                    dst[run[bb] + (p - tstart[bb])] = stage[p];
+                }
                 lds_barrier();
                 uint32_t* st32 = (uint32_t*)stage;
 #pragma unroll
@@ -918,13 +986,17 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                     const uint32_t bb = sbid[p];
                     pdst[run[bb] + (p - tstart[bb])] = st32[p];
                 }
+                lds_barrier();
+                for (uint32_t j = tid; j < nb; j += NT) run[j] += tcnt[j];
+                lds_barrier();
             }
-            lds_barrier();
-            for (uint32_t j = tid; j < nb; j += NT) run[j] += tcnt[j];
-            lds_barrier();
+            // keys only: no barrier here; the next tile's first LDS writes
+            // (its bucket counters) are not read by this write-out, and the
+            // barrier after them orders everything else
 #pragma unroll
             for (int r = 0; r < SK; r++) { k[r] = kn[r]; pl[r] = pn[r]; }
         }
+        });
         __syncthreads();
     }
 }
