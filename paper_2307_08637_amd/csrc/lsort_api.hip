@@ -129,8 +129,8 @@ static inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 struct Layout {
     uint64_t n, m;
     int has_pay;
-    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap;
-    uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_bigs, o_items_b, o_counts, o_status,
+    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
+    uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_bigs, o_items_b, o_items_c, o_counts, o_status,
         o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested, o_mlp, o_mlp_t, o_mlp_y;
     uint64_t S_big;       // large-path sample size (0: none)
     uint64_t mlp_S;       // MLP training-set size (0: no MLP training)
@@ -196,6 +196,7 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.item_cap = n + m + 64;        // small items hold >= 1 key
     L.big_cap = n / 2 + m + 64;     // large items > 512 keys, copy runs >= 2 keys
     L.item_b_cap = n / (GROUP_SMALL_MAX + 1) + m + 64;  // items of 129..256 keys and of 513..1024
+    L.item_c_cap = n / (GROUP_LARGE_MAX + 1) + m + 64;  // items of 1025..2048 keys
     // Bucket counts per level: a segment gets at most n_seg / 4 buckets (at
     // least 2), except one first-level segment whose model the caller gives
     // (up to B_MAX).  Look-back words: tiles x buckets of each segment.
@@ -216,6 +217,7 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.o_items = take(L.item_cap * 8);
     L.o_bigs = take(L.big_cap * 8);
     L.o_items_b = take(L.item_b_cap * 8);
+    L.o_items_c = take(L.item_c_cap * 8);
     L.o_counts = take(L.counts_cap * 8);
     L.o_status = take(L.status_cap * 8);
     L.o_arena[0] = take(L.arena_cap);
@@ -414,11 +416,12 @@ static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
     P.items = (uint64_t*)(base + L.o_items);
     P.bigs = (uint64_t*)(base + L.o_bigs);
     P.items_b = (uint64_t*)(base + L.o_items_b);
+    P.items_c = (uint64_t*)(base + L.o_items_c);
     P.counts = (unsigned long long*)(base + L.o_counts);
     P.status = (unsigned long long*)(base + L.o_status);
     P.ids = L.o_ids ? (uint16_t*)(base + L.o_ids) : nullptr;
     P.seg_cap = L.seg_cap; P.tile_cap = L.tile_cap; P.item_cap = L.item_cap; P.big_cap = L.big_cap; P.counts_cap = L.counts_cap;
-    P.status_cap = L.status_cap; P.arena_cap = L.arena_cap; P.item_b_cap = L.item_b_cap;
+    P.status_cap = L.status_cap; P.arena_cap = L.arena_cap; P.item_b_cap = L.item_b_cap; P.item_c_cap = L.item_c_cap;
     P.persist = (const uint64_t*)(base + L.o_persist);
     P.level = 0;
     return P;
@@ -721,7 +724,7 @@ ls_status ls_get_stats(ls_stats* out) {
     out->levels = levels;
     out->first_model = c.first_mlp ? LS_MODEL_MLP
                        : c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
-    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nitems_k + c.nbig - c.ncopy - c.nmoved;
+    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nitems_k + c.nitems_c + c.nbig - c.ncopy - c.nmoved;
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
     out->mlp_loss_last = c.mlp_loss[1];

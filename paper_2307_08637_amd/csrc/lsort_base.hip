@@ -12,11 +12,11 @@ namespace ls {
 
 // ===========================================================================
 // Base case (Sec. 4: sub-arrays below the cutoff are sorted directly).
-// k_base_small: sub-arrays of at most 1024 keys sorted in registers by groups
-// of 4, 8, 16 or 32 lanes (group_bitonic, 16, 8, 4 or 2 sub-arrays per
+// k_base_small: sub-arrays of at most 2048 keys sorted in registers by groups
+// of 4, 8, 16, 32 or 64 lanes (group_bitonic, 16 .. 1 sub-arrays per
 // wavefront); with a payload, sub-arrays of at most 512 keys, one per
 // wavefront (wave_bitonic); k_base_big: one workgroup per larger sub-array
-// (up to 4096) sorted in LDS, and the copies of finished runs.
+// (up to 8192) sorted in LDS, and the copies of finished runs.
 // ===========================================================================
 
 constexpr int BASE_THREADS = 256;
@@ -54,7 +54,7 @@ __device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, u
 
 // Group items: 64 / G sub-arrays per wavefront, G lanes and E = 32 keys per
 // lane each (group_bitonic): items of up to 128 keys on 4 lanes, 129..256 on
-// 8 lanes, 257..512 on 16 lanes, 513..1024 on 32 lanes.  Loads read key j of a sub-array into lane
+// 8 lanes, 257..512 on 16 lanes, 513..1024 on 32, 1025..2048 on 64.  Loads read key j of a sub-array into lane
 // j % G, register j / G (consecutive lanes, consecutive keys: any placement
 // of unsorted input is valid).  The sorted keys leave through LDS in phases
 // of 16 registers, each wave in its own 8.5 KB region, so that stores are
@@ -64,8 +64,9 @@ __device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, u
 constexpr int GLE = 5, GE = 1 << GLE;
 constexpr int GPH = 16;                              // registers per LDS phase
 constexpr int G_SLOTS = WAVE * GPH + WAVE * GPH / 16; // LDS slots per wave: one pad slot after every 16
-static_assert(GE * 4 == GROUP_SMALL_MAX && GE * 8 == GROUP_MAX && GE * 16 == SMALL_MAX && GE * 32 == GROUP_LARGE_MAX,
-              "lane groups of 4, 8, 16, 32");
+static_assert(GE * 4 == GROUP_SMALL_MAX && GE * 8 == GROUP_MAX && GE * 16 == SMALL_MAX && GE * 32 == GROUP_LARGE_MAX &&
+                  GE * 64 == GROUP_WAVE_MAX,
+              "lane groups of 4, 8, 16, 32, 64");
 
 __device__ __forceinline__ uint32_t gslot(uint32_t i) { return i + (i >> 4); }
 
@@ -206,9 +207,9 @@ __device__ __forceinline__ void group_loop(const Params& P, const uint64_t* item
 }
 
 // One loop per group class, each grid-strided over every wavefront (so each
-// class is spread evenly), largest items first: tasks of 2 items of
-// 513..1024 keys (keys only), of 4 items of 257..512, of 8 of 129..256, of 16
-// of up to 128.  Separate loops keep each class's loop-invariant registers
+// class is spread evenly), largest items first: tasks of 1 item of
+// 1025..2048 keys and of 2 items of 513..1024 (keys only), of 4 items of
+// 257..512, of 8 of 129..256, of 16 of up to 128.  Separate loops keep each class's loop-invariant registers
 // out of the others'.  With a payload every item is one wave task (the
 // stable pair sort, wave_bitonic).
 template <bool PAY, bool U64>
@@ -234,6 +235,8 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
         return;
     }
     const uint64_t nk = min<unsigned long long>(P.ctl->nitems_k, P.item_b_cap);
+    const uint64_t nc = min<unsigned long long>(P.ctl->nitems_c, P.item_c_cap);
+    group_loop<6, U64, false>(P, P.items_c, P.item_c_cap, nc, wid, waves, glds[wv], lane);
     group_loop<5, U64, true>(P, P.items_b, P.item_b_cap, nk, wid, waves, glds[wv], lane);
     group_loop<4, U64, true>(P, P.items, P.item_cap, nw, wid, waves, glds[wv], lane);
     group_loop<3, U64, false>(P, P.items_b, P.item_b_cap, n1, wid, waves, glds[wv], lane);
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
 
 constexpr int BIG_THREADS = 512;
 
-// One sub-array of 513..4096 keys: gather into registers (BIG_THREADS * E
+// One sub-array of up to BIG_MAX keys: gather into registers (BIG_THREADS * E
 // elements, padded with the largest key), block_bitonic, write back.  The
 // payload follows through the sorted local index, read before any write.
 template <int E>
@@ -278,9 +281,13 @@ __device__ void base_big_item(const Params& P, uint64_t off, uint32_t size, uint
     __syncthreads();
 }
 
+// CAP: the largest item this instantiation sorts (its LDS); the 4096-key one
+// also does the copies, the 8192-key one (one workgroup per CU) only the
+// few items above 4096 keys.
+template <int CAP>
 __global__ __launch_bounds__(BIG_THREADS) void k_base_big(Params P) {
-    __shared__ uint64_t sk[C_MAX];
-    __shared__ uint32_t si[C_MAX];
+    __shared__ uint64_t sk[CAP];
+    __shared__ uint32_t si[CAP];
     const int tid = threadIdx.x;
     const uint64_t nitems = min<unsigned long long>(P.ctl->nbig, P.big_cap);
     const int has_pay = P.has_pay;
@@ -293,6 +300,10 @@ __global__ __launch_bounds__(BIG_THREADS) void k_base_big(Params P) {
         const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
         const uint64_t* in = P.keys[srcb];
         const uint32_t* pin = P.pay[srcb];
+        if (CAP > C_MAX) {  // only the large sorts
+            if (!copy && size > C_MAX) base_big_item<16>(P, off, size, srcb, sk, si);
+            continue;
+        }
         if (copy) {
             if (srcb)
                 for (uint32_t i = tid; i < size; i += BIG_THREADS) {
@@ -303,10 +314,9 @@ __global__ __launch_bounds__(BIG_THREADS) void k_base_big(Params P) {
         }
         if (size <= 1024) base_big_item<2>(P, off, size, srcb, sk, si);
         else if (size <= 2048) base_big_item<4>(P, off, size, srcb, sk, si);
-        else base_big_item<8>(P, off, size, srcb, sk, si);
+        else if (size <= 4096) base_big_item<8>(P, off, size, srcb, sk, si);
     }
 }
-
 
 #define LAUNCH(kernel, grid, block, stream, ...)                                     \
     do {                                                                             \
@@ -319,6 +329,9 @@ hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st) {
     if (P.u64) LAUNCH((k_base_small<false, true>), grid, BASE_THREADS, st, P);
     LAUNCH((k_base_small<false, false>), grid, BASE_THREADS, st, P);
 }
-hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_base_big, grid, BIG_THREADS, st, P); }
+hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_base_big<C_MAX>, dim3(grid), dim3(BIG_THREADS), 0, st, P);
+    LAUNCH(k_base_big<BIG_MAX>, grid / 2 ? grid / 2 : 1, BIG_THREADS, st, P);
+}
 
 }  // namespace ls

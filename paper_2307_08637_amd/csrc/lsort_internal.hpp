@@ -19,11 +19,13 @@ constexpr int WAVE_KEYS = WAVE * KPT;          // 1024 keys per wave per tile
 constexpr int B_MAX = 1024;                    // buckets of one partition
 constexpr int L_MAX = 1024;                    // RMI leaves
 constexpr int S_LDS = 16384;                   // largest sample one workgroup sorts in LDS
-constexpr int C_MAX = 4096;                    // largest base-case sub-array
+constexpr int C_MAX = 4096;                    // largest base-case cutoff an option may set
+constexpr int BIG_MAX = 8192;                  // largest sub-array the base case takes (k_base_big)
 constexpr int SMALL_MAX = 512;                 // largest sub-array one wavefront sorts in registers
 constexpr int GROUP_MAX = 256;                 // largest sub-array a lane group sorts (4 per wavefront)
 constexpr int GROUP_SMALL_MAX = 128;           // ... sorted by a smaller lane group (8 per wavefront)
-constexpr int GROUP_LARGE_MAX = 1024;          // largest keys-only sub-array one wavefront sorts in registers
+constexpr int GROUP_LARGE_MAX = 1024;          // keys only: largest sub-array two per wavefront are sorted
+constexpr int GROUP_WAVE_MAX = 2048;           // keys only: largest sub-array one wavefront sorts in registers
 constexpr int MAXL = 32;                       // partition levels (arrays)
 constexpr int MODEL_WORDS = 4 + 2 + 4 * L_MAX; // 8-byte words of the largest model (RMI, L_MAX leaves)
 constexpr uint64_t COPY_CHUNK = 65536;         // keys per copy item
@@ -94,7 +96,7 @@ constexpr uint32_t FLAG_STATS = 0x8u;   // LS_FLAG_COLLECT_STATS: per-level stat
 constexpr uint32_t SEG_PREBUILT = 1u;  // model already built (large first level)
 constexpr uint32_t SEG_FAILED = 2u;    // capacity exceeded; not partitioned
 constexpr uint32_t SEG_RESIDENT = 4u;  // sorted by one workgroup (k_resident): no work units
-constexpr uint64_t RES_MAX = 32768;    // largest segment a single workgroup takes (one work unit)
+constexpr uint64_t RES_MAX = 8192;     // largest segment a single workgroup takes (one work unit)
 
 struct Tile {          // one work unit of UNIT keys
     uint32_t seg;     // index in the level's segment list
@@ -124,6 +126,7 @@ struct Ctl {
     unsigned long long nitems_w;    // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)
     unsigned long long nitems_b;    // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys (items_b)
     unsigned long long nitems_k;    // keys only: items of SMALL_MAX+1 .. GROUP_LARGE_MAX keys (back of items_b)
+    unsigned long long nitems_c;    // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys (items_c)
     unsigned long long nbig;        // large base-case items and copy items
     unsigned long long nmoved;      // small items handed on to the large list (NaN / -0.0 tasks)
     unsigned long long ncopy;
@@ -164,7 +167,8 @@ struct Params {
     unsigned long long* status;
     uint8_t* arena[2];
     uint16_t* ids;                  // per-key bucket ids of MLP levels (absolute positions)
-    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap;
+    uint64_t* items_c;              // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys
+    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
     const uint64_t* persist;        // [0] call epoch, [1] clear-status request (survives calls)
     int level;
 };

@@ -41,7 +41,7 @@ __global__ void k_reset(Params P, uint64_t* persist) {
 __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets, uint64_t m, uint64_t n_single,
                                               uint32_t prebuilt, const uint64_t* persist) {
     __shared__ uint64_t red64[256 / 64];
-    __shared__ uint64_t base[7];
+    __shared__ uint64_t base[8];
     if (persist[1]) {
         for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.status_cap;
              i += (uint64_t)gridDim.x * blockDim.x)
@@ -58,17 +58,19 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
         // prebuilt: the caller supplied the first level's model; always partition
         const bool item = s < m && !prebuilt && n >= 2 && n <= P.cutoff;
         // keys only: up to GROUP_LARGE_MAX keys still go to k_base_small
-        const bool small = item && (n <= SMALL_MAX || (n <= GROUP_LARGE_MAX && !P.has_pay));
-        const int cls = !small ? 3 : n <= GROUP_SMALL_MAX ? 0 : n <= GROUP_MAX ? 1 : n <= SMALL_MAX ? 2 : 4;
+        const bool small = item && (n <= SMALL_MAX || (n <= GROUP_WAVE_MAX && !P.has_pay));
+        const int cls = !small ? 3 : n <= GROUP_SMALL_MAX ? 0 : n <= GROUP_MAX ? 1 : n <= SMALL_MAX ? 2
+                      : n <= GROUP_LARGE_MAX ? 4 : 5;
         const bool seg = s < m && (prebuilt ? n >= 1 : n > P.cutoff);
         // an array small enough for one workgroup is sorted whole by k_resident
         const bool resident = seg && !prebuilt && n <= RES_MAX;
         const uint32_t nt = seg && !resident ? (uint32_t)((n + UNIT - 1) / UNIT) : 0;
-        uint64_t itot, wtot, gtot, ktot, btot, stot, ttot;
+        uint64_t itot, wtot, gtot, ktot, ctot, btot, stot, ttot;
         const uint64_t iex = block_excl_scan<256, uint64_t>(item && cls == 0 ? 1 : 0, red64, &itot);
         const uint64_t gex = block_excl_scan<256, uint64_t>(item && cls == 1 ? 1 : 0, red64, &gtot);
         const uint64_t wex = block_excl_scan<256, uint64_t>(item && cls == 2 ? 1 : 0, red64, &wtot);
         const uint64_t kex = block_excl_scan<256, uint64_t>(item && cls == 4 ? 1 : 0, red64, &ktot);
+        const uint64_t cex = block_excl_scan<256, uint64_t>(item && cls == 5 ? 1 : 0, red64, &ctot);
         const uint64_t bex = block_excl_scan<256, uint64_t>(item && !small ? 1 : 0, red64, &btot);
         const uint64_t sex = block_excl_scan<256, uint64_t>(seg ? 1 : 0, red64, &stot);
         const uint64_t tex = block_excl_scan<256, uint64_t>(nt, red64, &ttot);
@@ -82,15 +84,17 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
             base[4] = wtot ? atomicAdd(&P.ctl->nitems_w, (unsigned long long)wtot) : 0;
             base[5] = gtot ? atomicAdd(&P.ctl->nitems_b, (unsigned long long)gtot) : 0;
             base[6] = ktot ? atomicAdd(&P.ctl->nitems_k, (unsigned long long)ktot) : 0;
+            base[7] = ctot ? atomicAdd(&P.ctl->nitems_c, (unsigned long long)ctot) : 0;
             if (sk) atomicAdd(&P.ctl->small_keys, (unsigned long long)sk);
             if (gk) atomicAdd(&P.ctl->big_keys, (unsigned long long)gk);
         }
         __syncthreads();
         if (item) {
             const uint64_t it = cls == 0 ? base[0] + iex : cls == 1 ? base[5] + gex : cls == 2 ? base[4] + wex
-                              : cls == 4 ? base[6] + kex : base[3] + bex;
-            const uint64_t cap = cls == 1 || cls == 4 ? P.item_b_cap : cls == 3 ? P.big_cap : P.item_cap;
-            uint64_t* list = cls == 1 || cls == 4 ? P.items_b : cls == 3 ? P.bigs : P.items;
+                              : cls == 4 ? base[6] + kex : cls == 5 ? base[7] + cex : base[3] + bex;
+            const uint64_t cap = cls == 1 || cls == 4 ? P.item_b_cap : cls == 3 ? P.big_cap
+                               : cls == 5 ? P.item_c_cap : P.item_cap;
+            uint64_t* list = cls == 1 || cls == 4 ? P.items_b : cls == 3 ? P.bigs : cls == 5 ? P.items_c : P.items;
             // lists 2 and 4 fill their arrays from the back
             if (it < cap) list[cls == 2 || cls == 4 ? cap - 1 - it : it] = item_pack(lo, 0, 0, (uint32_t)n);
             else atomicOr(&P.ctl->overflow, OVF_ITEM);
@@ -510,11 +514,11 @@ __device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q,
     const bool oversized = (double)c > P.fallback_ratio * expected;
     const bool fine = fine_ok && !oversized && (4ull << log2B2) <= c && (uint32_t)lvl + 1 < P.max_levels;
     // The base case takes a bucket at or below the cutoff, and any bucket it
-    // can hold (C_MAX): sorting it directly is one pass, another level is at
+    // can hold (BIG_MAX): sorting it directly is one pass, another level is at
     // least a partition pass plus the fixed work of a segment.  At the depth
     // cap this leaves range radix (8 bits per level) only buckets of more
-    // than C_MAX keys.
-    if (c <= P.cutoff || c <= (uint64_t)C_MAX) { d.stat = 1ull << 24; d.act = 2; return d; }
+    // than BIG_MAX keys.
+    if (c <= P.cutoff || c <= (uint64_t)BIG_MAX) { d.stat = 1ull << 24; d.act = 2; return d; }
     d.stat = 1ull << 36;
     if ((uint32_t)lvl + 1 >= P.max_levels) d.act = 3;
     else if (fine) d.act = 4;
@@ -526,7 +530,7 @@ __device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q,
 __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
     __shared__ uint64_t red64[S_THREADS / 64];
     __shared__ uint8_t eqb[B_MAX];
-    __shared__ uint64_t resv[7];
+    __shared__ uint64_t resv[8];
     const int tid = threadIdx.x;
     const int lvl = P.level;
     if (blockIdx.x == 0 && tid == 0) {  // pools of the next level (this level's data stays readable)
@@ -595,17 +599,18 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const Decision d = decide(P, lvl, q, c[i], eqb[b] != 0, fine_ok, log2B2, expected);
             act[i] = d.act;
             lstat += d.stat;
-            const uint64_t nsm = d.act == 2 && (c[i] <= SMALL_MAX || (c[i] <= GROUP_LARGE_MAX && !P.has_pay)) ? 1 : 0;
+            const uint64_t nsm = d.act == 2 && (c[i] <= SMALL_MAX || (c[i] <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
             const uint64_t ng0 = nsm && c[i] <= GROUP_SMALL_MAX ? 1 : 0;
             const uint64_t ng1 = nsm && !ng0 && c[i] <= GROUP_MAX ? 1 : 0;
-            const uint64_t ng3 = nsm && c[i] > SMALL_MAX ? 1 : 0;
+            const uint64_t ng3 = nsm && c[i] > SMALL_MAX && c[i] <= GROUP_LARGE_MAX ? 1 : 0;
+            const uint64_t ng4 = nsm && c[i] > GROUP_LARGE_MAX ? 1 : 0;
             const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && !nsm ? 1 : 0);
             const uint64_t ntl = d.act >= 3 && !child_resident(sg.kind, d.act, c[i]) ? (c[i] + UNIT - 1) / UNIT : 0;
             // packed counters: items <= 128 keys | children << 16 | large items << 32,
             // units | items of 129..256 keys << 32 | items of 257..512 keys << 48
             la += ng0 | ((uint64_t)(d.act >= 3) << 16) | (nbg << 32);
-            lb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3) << 48);
-            lc += ng3;
+            lb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
+            lc += ng3 | (ng4 << 32);
             lfb += d.act == 5 ? 1 : 0;
             lsk += nsm ? c[i] : 0;
             lgk += nbg ? c[i] : 0;
@@ -629,7 +634,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             resv[0] = itot ? atomicAdd(&P.ctl->nitems, (unsigned long long)itot) : 0;
             resv[4] = wtot ? atomicAdd(&P.ctl->nitems_w, (unsigned long long)wtot) : 0;
             resv[5] = btot ? atomicAdd(&P.ctl->nitems_b, (unsigned long long)btot) : 0;
-            resv[6] = tc ? atomicAdd(&P.ctl->nitems_k, (unsigned long long)tc) : 0;
+            resv[6] = (tc & 0xffffffffull) ? atomicAdd(&P.ctl->nitems_k, (unsigned long long)(tc & 0xffffffffull)) : 0;
+            resv[7] = (tc >> 32) ? atomicAdd(&P.ctl->nitems_c, (unsigned long long)(tc >> 32)) : 0;
             resv[1] = ctot ? atomicAdd(&P.ctl->nseg[lvl + 1], (uint32_t)ctot) : 0;
             resv[2] = ttot ? atomicAdd(&P.ctl->ntile[lvl + 1], (uint32_t)ttot) : 0;
             resv[3] = gtot ? atomicAdd(&P.ctl->nbig, (unsigned long long)gtot) : 0;
@@ -656,21 +662,25 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const uint32_t b = S_BPT * tid + i;
             const uint32_t a = act[i];
             const uint64_t ci = c[i];
-            const uint64_t nsm = a == 2 && (ci <= SMALL_MAX || (ci <= GROUP_LARGE_MAX && !P.has_pay)) ? 1 : 0;
+            const uint64_t nsm = a == 2 && (ci <= SMALL_MAX || (ci <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
             const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && !nsm ? 1 : 0);
             const uint64_t ntl = a >= 3 && !child_resident(sg.kind, a, ci) ? (ci + UNIT - 1) / UNIT : 0;
             const uint64_t iex = xa & 0xffff, cex = (xa >> 16) & 0xffff, gex = xa >> 32, tex = xb & 0xffffffffull;
             const uint64_t bex = (xb >> 32) & 0xffff, wex = xb >> 48;
             const uint64_t ng0 = nsm && ci <= GROUP_SMALL_MAX ? 1 : 0;
             const uint64_t ng1 = nsm && !ng0 && ci <= GROUP_MAX ? 1 : 0;
-            const uint64_t ng3 = nsm && ci > SMALL_MAX ? 1 : 0;
+            const uint64_t ng3 = nsm && ci > SMALL_MAX && ci <= GROUP_LARGE_MAX ? 1 : 0;
+            const uint64_t ng4 = nsm && ci > GROUP_LARGE_MAX ? 1 : 0;
             if (nsm) {
                 // lists: <= 128 front of items, 129..256 front of items_b,
-                // 257..512 back of items, 513..1024 back of items_b
-                const uint64_t it = ng0 ? resv[0] + iex : ng1 ? resv[5] + bex : ng3 ? resv[6] + xc : resv[4] + wex;
+                // 257..512 back of items, 513..1024 back of items_b,
+                // 1025..2048 items_c
+                const uint64_t it = ng0 ? resv[0] + iex : ng1 ? resv[5] + bex : ng3 ? resv[6] + (xc & 0xffffffffull)
+                                  : ng4 ? resv[7] + (xc >> 32) : resv[4] + wex;
                 const bool inb = ng1 || ng3;
-                const uint64_t cap = inb ? P.item_b_cap : P.item_cap;
-                if (it < cap) (inb ? P.items_b : P.items)[ng0 || ng1 ? it : cap - 1 - it] = item_pack(start[i], q, 0u, (uint32_t)ci);
+                const uint64_t cap = inb ? P.item_b_cap : ng4 ? P.item_c_cap : P.item_cap;
+                uint64_t* list = inb ? P.items_b : ng4 ? P.items_c : P.items;
+                if (it < cap) list[ng0 || ng1 || ng4 ? it : cap - 1 - it] = item_pack(start[i], q, 0u, (uint32_t)ci);
                 else atomicOr(&P.ctl->overflow, OVF_ITEM);
             }
             for (uint64_t k = 0; k < nbg; k++) {
@@ -702,8 +712,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                 }
             }
             xa += ng0 | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
-            xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3) << 48);
-            xc += ng3;
+            xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
+            xc += ng3 | (ng4 << 32);
         }
         __syncthreads();
     }

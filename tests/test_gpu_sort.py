@@ -105,10 +105,10 @@ def test_adversarial_keys_only(dev, kind, n):
 
 
 def test_group_items_every_size(dev):
-    """Segments of every size 1..1100 (sorted directly by the base case:
-    lane groups of 4..32 lanes up to 1024 keys, the workgroup sort above),
+    """Segments of every size 1..2100 (sorted directly by the base case:
+    lane groups of 4..64 lanes up to 2048 keys, the workgroup sort above),
     keys only, with and without special values."""
-    sizes = np.tile(np.arange(1, 1101, dtype=np.int64), 2)
+    sizes = np.tile(np.arange(1, 2101, dtype=np.int64), 2)
     off = np.zeros(sizes.size + 1, dtype=np.uint64)
     off[1:] = np.cumsum(sizes)
     n = int(off[-1])
@@ -118,14 +118,14 @@ def test_group_items_every_size(dev):
         t = to_dev(keys, dev)
         o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
         print(f"[case] group items n={n}", flush=True)
-        lsort.sort_segmented(t, o, cutoff=1100)
+        lsort.sort_segmented(t, o, cutoff=2100)
         torch.cuda.synchronize()
         want, _ = oracle.sort_segmented(keys, off)
         assert_same_bits(to_host(t), want)
     keys = inputs.generate("u64", n, seed=10)
     t = to_dev(keys, dev)
     o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
-    lsort.sort_segmented(t, o, cutoff=1100)
+    lsort.sort_segmented(t, o, cutoff=2100)
     torch.cuda.synchronize()
     assert_same_bits(to_host(t), oracle.sort_segmented(keys, off)[0])
 
