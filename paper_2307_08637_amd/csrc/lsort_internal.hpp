@@ -121,6 +121,7 @@ struct Ctl {
     uint32_t ntile[MAXL + 1];       // tiles at each level
     uint32_t ticket[MAXL + 1];      // scatter unit tickets
     uint32_t rticket[MAXL + 1];     // k_resident segment tickets
+    uint32_t hticket[MAXL + 1];     // k_hist unit tickets
     uint32_t pad0;
     unsigned long long nitems;      // small base-case items of <= GROUP_SMALL_MAX keys (front of items)
     unsigned long long nitems_w;    // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)

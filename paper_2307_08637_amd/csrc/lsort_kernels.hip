@@ -415,13 +415,20 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
     const uint64_t tag = ((uint64_t)(P.persist[0] * MAXL + lvl)) << ST_TAG_SHIFT;
     const uint64_t* src = P.keys[lvl & 1];
     const int u64 = P.u64;
+    __shared__ uint32_t sh_t;
     uint64_t cur_model = 0;
-    for (uint32_t t = blockIdx.x; t < nunit; t += gridDim.x) {
+    // units taken through a ticket: a workgroup that drew slow units (tree
+    // models) takes fewer, so the launch ends evenly
+    for (;;) {
+        __syncthreads();  // the previous unit is done with mdl, h and sh_t
+        if (tid == 0) sh_t = atomicAdd(&P.ctl->hticket[lvl], 1u);
+        __syncthreads();
+        const uint32_t t = sh_t;
+        if (t >= nunit) break;
         const Tile td = P.tiles[lvl & 1][t];
         if (td.seg >= nseg) continue;
         const Seg sg = P.segs[lvl & 1][td.seg];
         if (sg.flags & SEG_FAILED) continue;
-        __syncthreads();  // the previous unit is done with mdl and h
         if (sg.model != cur_model) {
             load_model(mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, P_THREADS);
             cur_model = sg.model;
@@ -437,9 +444,45 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
             // trees and radix put runs of equal keys into one bucket: add per
             // distinct bucket of the wave
             constexpr bool aggregate = KIND == K_TREE || KIND == K_RADIX;
+            auto add = [&](uint32_t b, bool in) {
+                if (aggregate) {
+                    if (in) {
+                        const uint64_t peers = match_peers(b, bits);
+                        if (mask_rank(peers) == 0) atomicAdd(&h[b], (uint32_t)__popcll(peers));
+                    }
+                } else if (in) {
+                    const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
+                    const uint64_t act = __ballot(1), same = __ballot(b == b0);
+                    if (same == act) {
+                        if (mask_rank(act) == 0) atomicAdd(&h[b0], (uint32_t)__popcll(act));
+                    } else {
+                        atomicAdd(&h[b], 1u);
+                    }
+                }
+            };
+            constexpr uint32_t RND = P_THREADS * HK;  // keys per round
+            if (un == UNIT) {
+                // full unit: no bounds checks; the next round's HK keys are
+                // loaded (unconditionally: the last round reloads itself)
+                // while this round's are bucketed
+                uint64_t kk[HK], kn[HK];
+#pragma unroll
+                for (int r = 0; r < HK; r++) kk[r] = src[base + r * P_THREADS + tid];
+                for (uint32_t i0 = 0; i0 < UNIT; i0 += RND) {
+                    const uint32_t nx = i0 + RND < UNIT ? i0 + RND : i0;
+#pragma unroll
+                    for (int r = 0; r < HK; r++) kn[r] = src[base + nx + r * P_THREADS + tid];
+#pragma unroll
+                    for (int r = 0; r < HK; r++)
+                        add(kind_bucket<KIND>(v, mdl, kk[r], u64, P.ids, base + i0 + r * P_THREADS + tid), true);
+#pragma unroll
+                    for (int r = 0; r < HK; r++) kk[r] = kn[r];
+                }
+                return;
+            }
             // HK keys per thread are loaded before any is used, so that every
             // wave keeps HK loads in flight (the unit is read exactly once)
-            for (uint32_t i0 = 0; i0 < un; i0 += P_THREADS * HK) {
+            for (uint32_t i0 = 0; i0 < un; i0 += RND) {
                 uint64_t kk[HK];
 #pragma unroll
                 for (int r = 0; r < HK; r++) {
@@ -451,21 +494,7 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
                     const uint32_t i = i0 + r * P_THREADS + tid;
                     if (i0 + r * P_THREADS >= un) break;  // uniform: no key of this round in range
                     const bool in = i < un;
-                    const uint32_t b = in ? kind_bucket<KIND>(v, mdl, kk[r], u64, P.ids, base + i) : 0u;
-                    if (aggregate) {
-                        if (in) {
-                            const uint64_t peers = match_peers(b, bits);
-                            if (mask_rank(peers) == 0) atomicAdd(&h[b], (uint32_t)__popcll(peers));
-                        }
-                    } else if (in) {
-                        const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
-                        const uint64_t act = __ballot(1), same = __ballot(b == b0);
-                        if (same == act) {
-                            if (mask_rank(act) == 0) atomicAdd(&h[b0], (uint32_t)__popcll(act));
-                        } else {
-                            atomicAdd(&h[b], 1u);
-                        }
-                    }
+                    add(in ? kind_bucket<KIND>(v, mdl, kk[r], u64, P.ids, base + i) : 0u, in);
                 }
             }
         });
