@@ -195,29 +195,35 @@ __global__ __launch_bounds__(FIT_T) void k_fit_bounds_mlp(FitArgs A) {
     }
 }
 
-__global__ __launch_bounds__(FIT_T) void k_fit_leaves(FitArgs A) {
-    __shared__ double red[FIT_T / 64];
+// One workgroup of FIT_LT threads per leaf: the leaves the root clamps the
+// distribution's tails into hold a few per cent of the sample each, and
+// their two passes set the kernel's time.  The rank term i / S is taken as
+// i * (1 / S) (a rounding apart from the quotient).
+constexpr int FIT_LT = 1024;
+
+__global__ __launch_bounds__(FIT_LT) void k_fit_leaves(FitArgs A) {
+    __shared__ double red[FIT_LT / 64];
     if (A.flag[0] == 0) return;
     const uint32_t j = blockIdx.x;
     const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
     const uint64_t range[2] = {bounds[j], bounds[j + 1]};
     const uint64_t lo = range[0], hi = range[1];
-    const double Sd = (double)A.S;
+    const double Sd = (double)A.S, invS = 1.0 / Sd;
     double a = 0, b = 0, pmin = 0, pmax = 0;
     if (hi > lo) {
         const double cnt = (double)(hi - lo);
         double s = 0;
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_T) { double x; key_x(A.s[i], A.u64, x); s += x; }
-        s = block_sum<FIT_T, double>(s, red);
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_LT) { double x; key_x(A.s[i], A.u64, x); s += x; }
+        s = block_sum<FIT_LT, double>(s, red);
         const double mx = s / cnt, my = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
         double sxx = 0, sxy = 0;
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_T) {
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_LT) {
             double x; key_x(A.s[i], A.u64, x);
-            double dx = x - mx, dy = (double)i / Sd - my;
+            double dx = x - mx, dy = (double)i * invS - my;
             sxx += dx * dx; sxy += dx * dy;
         }
-        sxx = block_sum<FIT_T, double>(sxx, red);
-        sxy = block_sum<FIT_T, double>(sxy, red);
+        sxx = block_sum<FIT_LT, double>(sxx, red);
+        sxy = block_sum<FIT_LT, double>(sxy, red);
         a = sxx > 0 ? sxy / sxx : 0.0;
         if (a < 0) a = 0;
         b = my - a * mx;
@@ -352,7 +358,7 @@ hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st) {
     else hipLaunchKernelGGL(k_fit_bounds, dim3(grid ? grid : 1), dim3(FIT_T), 0, st, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    LAUNCH(k_fit_leaves, A.L, FIT_T, st, A);
+    LAUNCH(k_fit_leaves, A.L, FIT_LT, st, A);
 }
 hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_finish, 1, M_THREADS, st, A); }
 hipError_t launch_model_buckets(const uint64_t* model, uint32_t words, uint32_t kind, uint32_t nb, uint32_t win,

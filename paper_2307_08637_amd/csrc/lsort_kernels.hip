@@ -186,30 +186,48 @@ __device__ void fit_rmi_block(const uint64_t* smp, uint32_t S, int u64, uint32_t
             for (uint32_t q = j + 1; q <= L; q++) lstart[q] = S;
     }
     __syncthreads();
-    // per-leaf least squares (thread j)
+    // per-leaf least squares: two threads per leaf (even and odd points, the
+    // partial sums combined through a lane swap), so that a leaf the root
+    // clamps a tail into is walked in half the time; the raw line and its
+    // ends go to the leaf's model slots and are read back below
+    const double invS = 1.0 / Sd;  // i / S as i * (1 / S): no division per point
+    for (uint32_t j0 = 0; j0 < L; j0 += M_THREADS / 2) {
+        const uint32_t j = j0 + ((uint32_t)tid >> 1), half = (uint32_t)tid & 1u;
+        const uint32_t jl = j < L ? j : L - 1;
+        const uint32_t lo = lstart[jl], hi = j < L ? lstart[jl + 1] : lo;
+        const double cnt = (double)(hi - lo);
+        double s = 0;
+        for (uint32_t i = lo + half; i < hi; i += 2) { double x; key_x(key_unord(smp[i], u64), u64, x); s += x; }
+        s += __shfl_xor(s, 1);
+        const double lmx = hi > lo ? s / cnt : 0.0;
+        const double lmy = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
+        double lxx = 0, lxy = 0;
+        for (uint32_t i = lo + half; i < hi; i += 2) {
+            double x; key_x(key_unord(smp[i], u64), u64, x);
+            const double dx = x - lmx, dy = (double)i * invS - lmy;
+            lxx += dx * dx; lxy += dx * dy;
+        }
+        lxx += __shfl_xor(lxx, 1);
+        lxy += __shfl_xor(lxy, 1);
+        if (j < L && hi > lo && half == 0) {
+            double a = lxx > 0 ? lxy / lxx : 0.0;
+            if (a < 0) a = 0;
+            const double b = lmy - a * lmx;
+            double x0, x1;
+            key_x(key_unord(smp[lo], u64), u64, x0);
+            key_x(key_unord(smp[hi - 1], u64), u64, x1);
+            double* q = dst + 4 + 2 + 4 * j;
+            q[0] = a; q[1] = b; q[2] = a * x0 + b; q[3] = a * x1 + b;
+        }
+    }
+    __syncthreads();
     double a = 0, b = 0, pmin = 0, pmax = -INFINITY;
     uint32_t lo = 0, hi = 0;
     if ((uint32_t)tid < L) {
         lo = lstart[tid]; hi = lstart[tid + 1];
         if (hi > lo) {
-            double cnt = (double)(hi - lo), s = 0;
-            for (uint32_t i = lo; i < hi; i++) { double x; key_x(key_unord(smp[i], u64), u64, x); s += x; }
-            double lmx = s / cnt;
-            double lmy = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
-            double lxx = 0, lxy = 0;
-            for (uint32_t i = lo; i < hi; i++) {
-                double x; key_x(key_unord(smp[i], u64), u64, x);
-                double dx = x - lmx, dy = (double)i / Sd - lmy;
-                lxx += dx * dx; lxy += dx * dy;
-            }
-            a = lxx > 0 ? lxy / lxx : 0.0;
-            if (a < 0) a = 0;
-            b = lmy - a * lmx;
-            double x0, x1;
-            key_x(key_unord(smp[lo], u64), u64, x0);
-            key_x(key_unord(smp[hi - 1], u64), u64, x1);
-            pmin = a * x0 + b;
-            pmax = a * x1 + b;
+            const double* q = dst + 4 + 2 + 4 * tid;
+            a = q[0]; b = q[1]; pmin = q[2]; pmax = q[3];
         }
     }
     // d_j = clip01(max(0, prefix max of pmax over non-empty leaves))
@@ -309,7 +327,7 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             const uint64_t n = sg.n;
             uint32_t Bt = min(P.tree_buckets, max(2u, floor_pow2((uint32_t)min<uint64_t>(n / 16, 1u << 30))));
             uint64_t want = (uint64_t)ceil(P.sample_frac * (double)n);
-            uint64_t floor_s = min<uint64_t>(n, 16ull * Bt);
+            uint64_t floor_s = min<uint64_t>(n, 8ull * Bt);  // 8 sample keys per bucket at least
             uint32_t S = (uint32_t)min<uint64_t>(S_LDS, max<uint64_t>(want, max<uint64_t>(floor_s, 2)));
             uint32_t P2 = 1u << ceil_log2(S);
             const uint64_t sseed = splitmix64_at(P.seed, (sg.off << 6) | (uint64_t)lvl);
