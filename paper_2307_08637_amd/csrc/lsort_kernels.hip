@@ -912,12 +912,12 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                     b[r] = i < tn ? bk : 0;
                 }
             }
-            if (!PAY) {  // prefetch the next tile (or reload this one: in bounds, no branch)
+            if (!PAY) {  // prefetch the next tile (after the last one: one line, in bounds, no branch)
                 const bool more = tt + 1 < ntl;
-                const uint64_t nbase = more ? base + TILE : base;
-                const uint32_t nn = more ? min<uint32_t>(TILE, un - (tt + 1) * TILE) : tn;
+                const uint32_t nn = more ? min<uint32_t>(TILE, un - (tt + 1) * TILE) : 1u;
+                const uint32_t lim = more ? nn - 1 : 0u;
 #pragma unroll
-                for (int r = 0; r < SK; r++) kn[r] = src[nbase + min<uint32_t>(w * SWK + r * WAVE + lane, nn - 1)];
+                for (int r = 0; r < SK; r++) kn[r] = src[base + (more ? TILE : 0) + min<uint32_t>(w * SWK + r * WAVE + lane, lim)];
             }
             if (PAY) {
                 // stable rank within the wave: rounds in key order, lanes in key order
