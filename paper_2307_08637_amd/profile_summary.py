@@ -4,10 +4,13 @@
       text table of a --kernel-trace --stats run (name, calls, total ms,
       average us, share)
   python -m paper_2307_08637_amd.profile_summary traffic FETCH_CSV WRITE_CSV KERNEL OUT_JSON
+        [--name NAME] [--command TEXT] [--copy-bytes BYTES]
       HBM bytes per dispatch of KERNEL from two --pmc runs (FETCH_SIZE,
       WRITE_SIZE; KiB per dispatch), each scaled by what the counter reads
       for the runtime's buffer-copy kernel of the same run against the bytes
       that copy moves, written as JSON with the hash of the kernel sources
+      (NAME: the kernel's name in the benchmark's timing table, when it
+      differs from the rocprofv3 name; TEXT: the profiled command)
 
 The copy used for calibration is the largest __amd_rocclr_copyBuffer
 dispatch in each run; its size in bytes is passed as --copy-bytes (default
@@ -39,7 +42,11 @@ def short(name: str) -> str:
     name = name.strip('"')
     for pre in ("void ", "ls::"):
         name = name.replace(pre, "")
-    return name.split("(")[0]
+    name = name.split("(")[0]
+    if name.startswith("at::native::"):  # torch's own kernels (the output check): name and functor
+        parts = [x for x in name.replace("<", " ").replace(">", " ").replace(",", " ").split() if "::" in x]
+        name = "torch " + " ".join(x.split("::")[-1] for x in parts[:2])
+    return name[:34]
 
 
 def kernels(stats_csv: str) -> str:
@@ -86,10 +93,14 @@ def main(argv):
         copy_bytes = 8e8
         if "--copy-bytes" in argv:
             copy_bytes = float(argv[argv.index("--copy-bytes") + 1])
+        name = argv[argv.index("--name") + 1] if "--name" in argv else argv[3]
         t = traffic(argv[1], argv[2], argv[3], copy_bytes)
-        out = {"kernel": argv[3], "source_sha": kernel_source_sha(), "workload": os.environ.get("LSORT_WORKLOAD", ""),
+        out = {"kernel": name, "source_sha": kernel_source_sha(), "workload": os.environ.get("LSORT_WORKLOAD", ""),
                "fetch": t["FETCH_SIZE"], "write": t["WRITE_SIZE"],
-               "bytes_per_launch": t["FETCH_SIZE"]["bytes_per_launch"] + t["WRITE_SIZE"]["bytes_per_launch"]}
+               "bytes_per_launch": t["FETCH_SIZE"]["bytes_per_launch"] + t["WRITE_SIZE"]["bytes_per_launch"],
+               "rocprof_kernel": argv[3]}
+        if "--command" in argv:
+            out["command"] = argv[argv.index("--command") + 1]
         with open(argv[4], "w") as f:
             json.dump(out, f, indent=1)
         print(json.dumps(out))
