@@ -58,24 +58,73 @@ __device__ __forceinline__ uint64_t sample_index(uint64_t seed, uint64_t k, uint
 // ---------------------------------------------------------------------------
 
 // Monotone two-level RMI at total resolution R (Sec. 2.1 formula, Sec. 2.2
-// bucket = floor(B F(x)), Sec. 4 clamp intervals). p: 2 + 4L pre-scaled
-// doubles (alpha_r, beta_r, then alpha_j, beta_j, gamma_j, delta_j).
-__device__ __forceinline__ uint32_t rmi_eval(const double* p, double Lm1, double Rm1, double x) {
-    double r = floor(__builtin_fma(p[0], x, p[1]));
-    r = fmin(fmax(r, 0.0), Lm1);
-    const double* q = p + 2 + 4 * (int)r;
-    double t = __builtin_fma(q[0], x, q[1]);
-    t = fmin(fmax(t, q[2]), q[3]);
-    double g = floor(t);
-    g = fmin(fmax(g, 0.0), Rm1);
-    return (uint32_t)g;
+// bucket = floor(B F(x)), Sec. 4 clamp intervals).  Stored form (model word 4
+// on): 2 + 4L pre-scaled doubles alpha_r, beta_r, then alpha_j, beta_j,
+// gamma_j, delta_j per leaf; the bucket is
+//   j = clamp(floor(fma(alpha_r, x, beta_r)), 0, L-1)
+//   g = clamp(floor(clamp(fma(alpha_j, x, beta_j), gamma_j, delta_j)), 0, R-1).
+//
+// The partition kernels evaluate an LDS image of it (load_model_lds): header
+// and root as stored, the leaf lines as (alpha_j, beta_j) pairs (one 16-byte
+// read), then per leaf the bucket range [lo_j, hi_j] its clamp interval
+// allows, lo_j = G(gamma_j), hi_j = G(delta_j), G(y) = clamp(floor(y), 0, R-1)
+// (lo_j = hi_j = G(delta_j) when gamma_j > delta_j).  G is non-decreasing, so
+// G(clamp(t, gamma, delta)) = clamp(G(t), lo, hi); and a saturating
+// conversion to uint32 (truncation, negative and NaN to 0) agrees with G
+// wherever the bounds do not override it.  Hence
+//   j = min(cvt_u32(fma(alpha_r, x, beta_r)), L-1)
+//   g = med3(cvt_u32(fma(alpha_j, x, beta_j)), lo_j, hi_j)
+// gives the same ids bit for bit with two conversions and two integer clamps
+// in place of two floors and six double min/max, and with no branch per key.
+constexpr int RMI_PAIRS = 6;  // LDS image: word of the first (alpha_j, beta_j) pair
+
+__device__ __forceinline__ uint32_t cvt_sat_u32(double d) {
+    uint32_t r;
+    asm("v_cvt_u32_f64 %0, %1" : "=v"(r) : "v"(d));  // saturates; NaN -> 0
+    return r;
 }
 
-__device__ __forceinline__ uint32_t rmi_bucket(const double* p, double Lm1, double Rm1, uint64_t raw, int u64) {
-    double x;
-    int nf = key_x(raw, u64, x);
-    if (nf) return nf < 0 ? 0u : (uint32_t)Rm1;
-    return rmi_eval(p, Lm1, Rm1, x);
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t lo, uint32_t hi) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(lo), "v"(hi));
+    return r;
+}
+
+// LDS image of the leaf table of a stored RMI at src (header first) into dst:
+// one leaf per thread of [tid, L) step nt.
+__device__ __forceinline__ void rmi_to_lds(uint64_t* dst, const uint64_t* src, int tid, int nt) {
+    const RmiModel* h = (const RmiModel*)src;
+    const uint32_t L = h->L;
+    const double Rm1 = h->R - 1.0;
+    for (int i = tid; i < RMI_PAIRS; i += nt) dst[i] = src[i];
+    const double* q = (const double*)(src + RMI_PAIRS);
+    for (uint32_t j = tid; j < L; j += nt) {
+        dst[RMI_PAIRS + 2 * j] = __double_as_longlong(q[4 * j]);
+        dst[RMI_PAIRS + 2 * j + 1] = __double_as_longlong(q[4 * j + 1]);
+        double c = q[4 * j + 2], d = q[4 * j + 3];
+        if (c != c) c = -INFINITY;  // a NaN bound clamps nothing
+        if (d != d) d = INFINITY;
+        const uint32_t lo = (uint32_t)fmin(fmax(floor(c), 0.0), Rm1);
+        const uint32_t hi = (uint32_t)fmin(fmax(floor(d), 0.0), Rm1);
+        dst[RMI_PAIRS + 2 * L + j] = (uint64_t)(lo < hi ? lo : hi) | ((uint64_t)hi << 32);
+    }
+}
+
+// Bucket of a key under the LDS image m of an RMI with L leaves (lm1 = L-1,
+// rm1 = R-1).  Non-finite binary64 keys go to the first / last bucket by sign.
+template <bool U64>
+__device__ __forceinline__ uint32_t rmi_lds_bucket(const uint64_t* m, uint32_t L, uint32_t lm1, uint32_t rm1,
+                                                   uint64_t raw) {
+    const double* p = (const double*)(m + 4);
+    const double x = U64 ? (double)raw : __longlong_as_double((long long)raw);
+    const uint32_t j = min(cvt_sat_u32(__builtin_fma(p[0], x, p[1])), lm1);
+    const double2 ab = *(const double2*)(m + RMI_PAIRS + 2 * j);
+    const uint2 lh = *(const uint2*)(m + RMI_PAIRS + 2 * L + j);
+    const uint32_t g = med3_u32(cvt_sat_u32(__builtin_fma(ab.x, x, ab.y)), lh.x, lh.y);
+    if (U64) return g;
+    const bool nf = __builtin_amdgcn_class(x, 0x003 | 0x004 | 0x200);  // NaN, -inf, +inf
+    const uint32_t edge = (int32_t)(raw >> 32) < 0 ? 0u : rm1;
+    return nf ? edge : g;
 }
 
 // Splitter tree (Sec. 2.4): k = #{u_i <= o} by branch-free binary lifting over
@@ -688,7 +737,7 @@ __device__ void block_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E], uint64_t* exk
 
 struct View {
     uint32_t kind, nb, win, log2B2;
-    double Lm1, Rm1;     // RMI
+    uint32_t L, lm1, rm1;  // RMI: leaves, L - 1, R - 1
     uint32_t m, top;     // tree
     uint64_t lo;         // radix
     uint32_t shift;
@@ -702,7 +751,7 @@ __device__ __forceinline__ View make_view(const uint64_t* mdl, uint32_t kind, ui
     v.kind = kind; v.nb = nb; v.win = win;
     if (kind == K_RMI || kind == K_RMI_FINE) {
         const RmiModel* h = (const RmiModel*)mdl;
-        v.Lm1 = (double)h->L - 1.0; v.Rm1 = h->R - 1.0; v.log2B2 = h->log2B2;
+        v.L = h->L; v.lm1 = h->L - 1; v.rm1 = (uint32_t)(h->R - 1.0); v.log2B2 = h->log2B2;
     } else if (kind == K_TREE || kind == K_TREE_FORCED) {
         const TreeModel* h = (const TreeModel*)mdl;
         v.m = h->m; v.top = h->top;
@@ -713,12 +762,30 @@ __device__ __forceinline__ View make_view(const uint64_t* mdl, uint32_t kind, ui
     return v;
 }
 
-// Bucket of the key at absolute position pos (stash: precomputed id).
+// Model of a segment into the LDS of a partition kernel: the RMI's LDS
+// image, a tree or radix model as stored; nothing for the stored-id kinds
+// (their bucket ids come from k_mlp_ids).
+__device__ __forceinline__ void load_model_lds(uint64_t* dst, const uint64_t* src, uint32_t kind, uint32_t words,
+                                               int tid, int nt) {
+    if (kind == K_RMI || kind == K_RMI_FINE) {
+        rmi_to_lds(dst, src, tid, nt);
+    } else if (kind == K_TREE || kind == K_TREE_FORCED || kind == K_RADIX) {
+        const uint32_t w = words < (uint32_t)LDS_MODEL_WORDS ? words : (uint32_t)LDS_MODEL_WORDS;
+        for (uint32_t i = tid; i < w; i += nt) dst[i] = src[i];
+    }
+}
+
+// Bucket of the key at absolute position pos (stash: precomputed id), the
+// model being in LDS (load_model_lds).
 __device__ __forceinline__ uint32_t view_bucket(const View& v, const uint64_t* mdl, uint64_t raw, int u64,
                                                 const uint16_t* ids, uint64_t pos) {
     switch (v.kind) {
-    case K_RMI: return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) >> v.log2B2;
-    case K_RMI_FINE: return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) - v.win;
+    case K_RMI:
+    case K_RMI_FINE: {
+        const uint32_t g = u64 ? rmi_lds_bucket<true>(mdl, v.L, v.lm1, v.rm1, raw)
+                               : rmi_lds_bucket<false>(mdl, v.L, v.lm1, v.rm1, raw);
+        return v.kind == K_RMI ? g >> v.log2B2 : g - v.win;
+    }
     case K_TREE:
     case K_TREE_FORCED:
         return tree_bucket(mdl + 2, (const uint16_t*)(mdl + 2 + v.m), v.m, v.top, key_ord(raw, u64));
@@ -728,32 +795,42 @@ __device__ __forceinline__ uint32_t view_bucket(const View& v, const uint64_t* m
 }
 
 // view_bucket with the kind fixed at compile time (KIND: K_RMI, K_RMI_FINE,
-// K_TREE for both tree kinds, K_RADIX, K_MLP for both stored-id kinds), so
-// that a loop over keys carries no per-key dispatch; KIND 0 dispatches at run
-// time (one copy of the loop).
+// each with or without KIND_U64 for uint64 keys, K_TREE for both tree kinds,
+// K_RADIX, K_MLP for both stored-id kinds), so that a loop over keys carries
+// no per-key dispatch; KIND 0 dispatches at run time (one copy of the loop).
+constexpr int KIND_U64 = 0x100;
+
 template <int KIND>
 __device__ __forceinline__ uint32_t kind_bucket(const View& v, const uint64_t* mdl, uint64_t raw, int u64,
                                                 const uint16_t* ids, uint64_t pos) {
+    constexpr int K = KIND & 0xff;
+    constexpr bool U = (KIND & KIND_U64) != 0;
     if constexpr (KIND == 0) return view_bucket(v, mdl, raw, u64, ids, pos);
-    else if constexpr (KIND == K_RMI) return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) >> v.log2B2;
-    else if constexpr (KIND == K_RMI_FINE) return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) - v.win;
-    else if constexpr (KIND == K_TREE)
+    else if constexpr (K == K_RMI) return rmi_lds_bucket<U>(mdl, v.L, v.lm1, v.rm1, raw) >> v.log2B2;
+    else if constexpr (K == K_RMI_FINE) return rmi_lds_bucket<U>(mdl, v.L, v.lm1, v.rm1, raw) - v.win;
+    else if constexpr (K == K_TREE)
         return tree_bucket(mdl + 2, (const uint16_t*)(mdl + 2 + v.m), v.m, v.top, key_ord(raw, u64));
-    else if constexpr (KIND == K_RADIX) return radix_bucket(v.lo, v.shift, key_ord(raw, u64));
+    else if constexpr (K == K_RADIX) return radix_bucket(v.lo, v.shift, key_ord(raw, u64));
     else return ids[pos];
 }
 
-// Calls f(std::integral_constant<int, KIND>) for the kind of a view (with
-// KIND 0, the run-time dispatch, when SPECIALISE is false).
+// Calls f(std::integral_constant<int, KIND>) for the kind of a view and the
+// key type (with KIND 0, the run-time dispatch, when SPECIALISE is false).
 template <bool SPECIALISE = true, typename F>
-__device__ __forceinline__ void with_kind(uint32_t kind, F&& f) {
+__device__ __forceinline__ void with_kind(uint32_t kind, int u64, F&& f) {
     if (!SPECIALISE) {
         f(std::integral_constant<int, 0>{});
         return;
     }
     switch (kind) {
-    case K_RMI: f(std::integral_constant<int, K_RMI>{}); break;
-    case K_RMI_FINE: f(std::integral_constant<int, K_RMI_FINE>{}); break;
+    case K_RMI:
+        if (u64) f(std::integral_constant<int, K_RMI | KIND_U64>{});
+        else f(std::integral_constant<int, K_RMI>{});
+        break;
+    case K_RMI_FINE:
+        if (u64) f(std::integral_constant<int, K_RMI_FINE | KIND_U64>{});
+        else f(std::integral_constant<int, K_RMI_FINE>{});
+        break;
     case K_TREE:
     case K_TREE_FORCED: f(std::integral_constant<int, K_TREE>{}); break;
     case K_RADIX: f(std::integral_constant<int, K_RADIX>{}); break;

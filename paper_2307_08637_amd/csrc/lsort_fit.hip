@@ -278,8 +278,8 @@ __global__ __launch_bounds__(M_THREADS) void k_fit_finish(FitArgs A) {
 __global__ __launch_bounds__(256) void k_model_buckets(const uint64_t* model, uint32_t words, uint32_t kind, uint32_t nb,
                                                        uint32_t win, const uint64_t* keys, uint64_t n, int u64,
                                                        uint32_t* out) {
-    __shared__ uint64_t mdl[MODEL_WORDS];
-    for (uint32_t i = threadIdx.x; i < words && i < (uint32_t)MODEL_WORDS; i += 256) mdl[i] = model[i];
+    __shared__ __align__(16) uint64_t mdl[LDS_MODEL_WORDS];
+    load_model_lds(mdl, model, kind, words, threadIdx.x, 256);
     __syncthreads();
     const View v = make_view(mdl, kind, nb, win);
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)

@@ -28,6 +28,7 @@ constexpr int GROUP_LARGE_MAX = 1024;          // keys only: largest sub-array t
 constexpr int GROUP_WAVE_MAX = 2048;           // keys only: largest sub-array one wavefront sorts in registers
 constexpr int MAXL = 32;                       // partition levels (arrays)
 constexpr int MODEL_WORDS = 4 + 2 + 4 * L_MAX; // 8-byte words of the largest model (RMI, L_MAX leaves)
+constexpr int LDS_MODEL_WORDS = 4 + 2 + 3 * L_MAX;  // ... of its LDS image in the partition kernels
 constexpr uint64_t COPY_CHUNK = 65536;         // keys per copy item
 
 // ---- MLP parameter layout (321 floats) -------------------------------------

@@ -13,9 +13,6 @@
 
 namespace ls {
 
-__device__ __forceinline__ void load_model(uint64_t* dst, const uint64_t* src, uint32_t words, int tid, int nt) {
-    for (uint32_t i = tid; i < words; i += nt) dst[i] = src[i];
-}
 
 // ===========================================================================
 // Call set-up
@@ -424,7 +421,7 @@ __device__ __forceinline__ void st_store(unsigned long long* p, uint64_t v) {
 constexpr int HK = 8;  // keys per thread in flight in k_hist
 
 __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
-    __shared__ uint64_t mdl[MODEL_WORDS];
+    __shared__ __align__(16) uint64_t mdl[LDS_MODEL_WORDS];
     __shared__ uint32_t h[B_MAX];
     const int tid = threadIdx.x;
     const int lvl = P.level;
@@ -448,7 +445,7 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
         const Seg sg = P.segs[lvl & 1][td.seg];
         if (sg.flags & SEG_FAILED) continue;
         if (sg.model != cur_model) {
-            load_model(mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, P_THREADS);
+            load_model_lds(mdl, (const uint64_t*)sg.model, sg.kind, sg.flags >> 16, tid, P_THREADS);
             cur_model = sg.model;
         }
         for (uint32_t b = tid; b < B_MAX; b += P_THREADS) h[b] = 0;
@@ -457,7 +454,7 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
         const uint64_t base = sg.off + (uint64_t)td.idx * UNIT;
         const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
         const int bits = ceil_log2(sg.nb);
-        with_kind(v.kind, [&](auto kc) {
+        with_kind(v.kind, u64, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
             // trees and radix put runs of equal keys into one bucket: add per
             // distinct bucket of the wave
@@ -781,8 +778,17 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
 //   per-wave counters), so a payload keeps the input order of equal keys.
 //   PAY = false: keys only.  Order inside a bucket is not observable -- the
 //   bucket is sorted later and equal keys are identical -- so the rank is one
-//   LDS atomic per key.
+//   LDS atomic per key.  A tile writes each bucket's keys only up to the last
+//   64-byte boundary they reach and carries the rest (at most 7 keys, in the
+//   registers of the bucket's thread) into the unit's next tile, which writes
+//   them in front of its own: a tile's run of a bucket is ~8 keys at 1000
+//   buckets, and output segments shared by two tiles written at different
+//   times cost the memory system about twice the bytes of whole ones.
 // ===========================================================================
+
+// Keys only, per bucket: keys held back from one tile for the next (a partial
+// 64-byte output segment has at most 7).
+constexpr int CARRY = 7;
 
 // Barrier for LDS hand-offs only: global loads in flight stay in flight.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
@@ -794,14 +800,17 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
     constexpr int SWK = WAVE * SK;       // keys per wave per tile
     constexpr int SB = B_MAX / NT;       // buckets per thread in the tile scan
     static_assert(SK * NT == TILE && SB * NT == B_MAX, "tile and bucket range split evenly");
-    __shared__ uint64_t mdl[MODEL_WORDS];
+    static_assert(PAY || SB == 1, "keys only: thread j owns bucket j (its carry and output cursor)");
+    __shared__ __align__(16) uint64_t mdl[LDS_MODEL_WORDS];
     __shared__ uint64_t stage[TILE];
     __shared__ uint16_t sbid[TILE];
     __shared__ uint16_t wcnt[PAY ? SW : 1][PAY ? B_MAX : 1];
     __shared__ uint32_t tcnt[B_MAX];
     __shared__ uint16_t tstart[B_MAX];
-    __shared__ uint64_t run[B_MAX];
-    __shared__ uint64_t delta[PAY ? 1 : B_MAX];  // run[b] - tstart[b] of the current tile (keys only)
+    __shared__ uint64_t run[PAY ? B_MAX : 1];    // payload: output position of the tile's run of each bucket
+    // keys only: output position of staging slot 0 for each bucket's slots, in
+    // the low 48 bits; the end of the bucket's slots written this tile, above
+    __shared__ uint64_t delta[PAY ? 1 : B_MAX];
     __shared__ uint32_t sh_t;
     __shared__ uint64_t red64[SW];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -826,10 +835,18 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
         const Seg sg = P.segs[lvl & 1][td.seg];
         if (sg.flags & SEG_FAILED) { __syncthreads(); continue; }
         if (sg.model != cur_model) {
-            load_model(mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, NT);
+            load_model_lds(mdl, (const uint64_t*)sg.model, sg.kind, sg.flags >> 16, tid, NT);
             cur_model = sg.model;
         }
         const uint32_t nb = sg.nb;
+        // keys only, thread j for bucket j: the output cursor and the carry,
+        // the keys of the bucket's last partial 64-byte segment held back for
+        // the unit's next tile (at most CARRY of them)
+        uint64_t acur = 0;
+        uint32_t kcar = 0;
+        uint64_t car[CARRY];
+#pragma unroll
+        for (int c = 0; c < CARRY; c++) car[c] = 0;
         // ---- look-back: exclusive prefix of this unit for every bucket ----
         {
             unsigned long long* row = P.status + sg.sbase + (uint64_t)td.idx * nb;
@@ -846,7 +863,8 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                 }
                 if ((own & ~ST_LOW_MASK) != (tag | ST_AGG) && (own & ~ST_LOW_MASK) != (tag | ST_PREFIX)) bad = 1;
                 st_store(row + j, tag | ST_PREFIX | (excl + (own & ST_VALUE_MASK)));
-                run[j] = P.counts[sg.cbase + nb + j] + excl;
+                if (PAY) run[j] = P.counts[sg.cbase + nb + j] + excl;
+                else acur = P.counts[sg.cbase + nb + j] + excl;
             }
             if (__syncthreads_or(bad)) {  // never expected: refuse to write anything for this unit
                 if (tid == 0) atomicOr(&P.ctl->overflow, OVF_STATE);
@@ -860,7 +878,7 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
         const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
         const uint32_t ntl = (un + TILE - 1) / TILE;
         // the payload variant keeps one copy of the tile loop (registers)
-        with_kind<!PAY>(v.kind, [&](auto kc) {
+        with_kind<!PAY>(v.kind, u64, [&](auto kc) {
         constexpr int KIND = decltype(kc)::value;
         // wave w owns keys [w*1024, (w+1)*1024) of a tile, 64 per round.
         // Keys only: every global load and store of the tile loop is issued
@@ -966,6 +984,10 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                 }
             }
             lds_barrier();
+            // keys only, thread j for bucket j: keys written this tile (twr) of the
+            // carry + this tile's keys of the bucket (tm), and the bucket's
+            // first staging slot (tex)
+            uint32_t twr = 0, tm = 0, tex = 0;
             {  // tile-local bucket starts: exclusive scan over buckets, SB per thread
                 uint32_t c[SB], lane_sum = 0;
 #pragma unroll
@@ -991,9 +1013,23 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                     if (j < nb) {
                         tstart[j] = (uint16_t)ex;
                         if (!PAY) {
-                            const uint64_t rj = run[j];
-                            delta[j] = rj - ex;  // staging slot p of bucket j goes to position p + delta[j]
-                            run[j] = rj + c[q];  // the next tile's start of bucket j
+                            // the carry, then this tile's keys, go out from acur up to
+                            // the last 64-byte boundary they reach (all of them in the
+                            // unit's last tile); the rest is carried.  Once past the
+                            // unit's first write, acur stays on a boundary, so every
+                            // 64-byte segment inside the unit's run of the bucket is
+                            // written whole, by one tile.
+                            const uint32_t m = kcar + c[q];
+                            uint32_t wr = m;
+                            if (tt + 1 < ntl) {
+                                const uint64_t e = (acur + m) & ~7ull;
+                                wr = e > acur ? (uint32_t)(e - acur) : 0u;  // 0, or more than kcar
+                            }
+                            // staging slot p (new keys only) goes to (delta & MASK48) + p
+                            // while p < delta >> 48
+                            const uint32_t wend = ex + (wr > 0 ? wr - kcar : 0u);
+                            delta[j] = (acur + kcar - ex) | ((uint64_t)wend << 48);
+                            twr = wr; tm = m; tex = ex;
                         }
                     }
                     ex += c[q];
@@ -1015,6 +1051,10 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
             }
             lds_barrier();
             if (!PAY) {
+                // the next tile's keys are taken now, before this tile's stores
+                // are issued: the wait for them then never waits for stores
+#pragma unroll
+                for (int r = 0; r < SK; r++) k[r] = kn[r];
                 uint32_t bq[SK];
                 uint64_t vq[SK];
 #pragma unroll
@@ -1026,7 +1066,26 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
 #pragma unroll
                 for (int q = 0; q < SK; q++) {
                     const uint32_t p = min<uint32_t>(tid + q * NT, tn - 1);
-                    dst[delta[bq[q]] + p] = vq[q];
+                    const uint64_t dl = delta[bq[q]];
+                    if (p < (uint32_t)(dl >> 48)) dst[(dl & 0xFFFFFFFFFFFFull) + p] = vq[q];
+                }
+                if ((uint32_t)tid < nb) {
+                    // the carry goes out in front of the bucket's new keys, then the
+                    // keys past the written part become the carry
+                    if (twr > 0) {
+#pragma unroll
+                        for (int c = 0; c < CARRY; c++)
+                            if ((uint32_t)c < kcar) dst[acur + c] = car[c];
+                    }
+                    const uint32_t nk = tm - twr;
+                    const int32_t o0 = twr > 0 ? (int32_t)(twr - kcar) : -(int32_t)kcar;
+#pragma unroll
+                    for (int c = 0; c < CARRY; c++) {
+                        const bool keep = twr == 0 && (uint32_t)c < kcar;
+                        if (!keep && (uint32_t)c < nk) car[c] = stage[(int32_t)tex + o0 + c];
+                    }
+                    acur += twr;
+                    kcar = nk;
                 }
             } else {
                 for (uint32_t p = tid; p < tn; p += NT) {
@@ -1050,8 +1109,10 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
             // keys only: no barrier here; the next tile's first LDS writes
             // (its bucket counters) are not read by this write-out, and the
             // barrier after them orders everything else
+            if (PAY) {
 #pragma unroll
-            for (int r = 0; r < SK; r++) { k[r] = kn[r]; pl[r] = pn[r]; }
+                for (int r = 0; r < SK; r++) { k[r] = kn[r]; pl[r] = pn[r]; }
+            }
         }
         });
         __syncthreads();
@@ -1078,19 +1139,12 @@ constexpr int R_WKEYS = WAVE * RK;           // keys per wave per tile
 
 template <int KIND>
 __device__ __forceinline__ uint32_t rbucket(const View& v, const uint64_t* mdl, uint64_t raw, int u64) {
-    if constexpr (KIND == K_RMI)
-        return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) >> v.log2B2;
-    else if constexpr (KIND == K_RMI_FINE)
-        return rmi_bucket((const double*)(mdl + 4), v.Lm1, v.Rm1, raw, u64) - v.win;
-    else if constexpr (KIND == K_TREE)
-        return tree_bucket(mdl + 2, (const uint16_t*)(mdl + 2 + v.m), v.m, v.top, key_ord(raw, u64));
-    else
-        return radix_bucket(v.lo, v.shift, key_ord(raw, u64));
+    return kind_bucket<KIND>(v, mdl, raw, u64, nullptr, 0);
 }
 
 template <bool PAY>
 struct ResLds {
-    uint64_t mdl[MODEL_WORDS];
+    alignas(16) uint64_t mdl[LDS_MODEL_WORDS];
     uint32_t cnt[B_MAX];
     uint32_t start[B_MAX];
     uint32_t cur[B_MAX];
@@ -1220,14 +1274,20 @@ __global__ __launch_bounds__(R_THREADS) void k_resident(Params P) {
             continue;
         }
         if (sg.model != cur_model) {
-            load_model(L.mdl, (const uint64_t*)sg.model, sg.flags >> 16, tid, R_THREADS);
+            load_model_lds(L.mdl, (const uint64_t*)sg.model, sg.kind, sg.flags >> 16, tid, R_THREADS);
             cur_model = sg.model;
         }
         __syncthreads();
         const View v = make_view(L.mdl, sg.kind, sg.nb, sg.win);
         switch (sg.kind) {
-        case K_RMI: res_partition<K_RMI, PAY>(P, sg, v, L, lvl); break;
-        case K_RMI_FINE: res_partition<K_RMI_FINE, PAY>(P, sg, v, L, lvl); break;
+        case K_RMI:
+            if (P.u64) res_partition<K_RMI | KIND_U64, PAY>(P, sg, v, L, lvl);
+            else res_partition<K_RMI, PAY>(P, sg, v, L, lvl);
+            break;
+        case K_RMI_FINE:
+            if (P.u64) res_partition<K_RMI_FINE | KIND_U64, PAY>(P, sg, v, L, lvl);
+            else res_partition<K_RMI_FINE, PAY>(P, sg, v, L, lvl);
+            break;
         case K_TREE:
         case K_TREE_FORCED: res_partition<K_TREE, PAY>(P, sg, v, L, lvl); break;
         default: res_partition<K_RADIX, PAY>(P, sg, v, L, lvl); break;
