@@ -500,6 +500,19 @@ __device__ void bitonic_pairs(uint64_t* a, uint16_t* ix, uint32_t P) {
 //   -0.0 (callers check), compared as numbers (v_min_f64 / v_max_f64);
 //   T = uint64_t: ordered keys compared as integers.
 // ---------------------------------------------------------------------------
+// Inclusive prefix sum over the 64 lanes of a wavefront in six DPP adds (no
+// LDS): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the last lane
+// of row 0 / 2 added to rows 1 / 3 and that of row 1 to rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr 1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr 2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr 4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr 8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast 15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast 31
+    return x;
+}
+
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, false);

@@ -865,6 +865,7 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                 st_store(row + j, tag | ST_PREFIX | (excl + (own & ST_VALUE_MASK)));
                 if (PAY) run[j] = P.counts[sg.cbase + nb + j] + excl;
                 else acur = P.counts[sg.cbase + nb + j] + excl;
+                if (!PAY) tcnt[j] = 0;  // the first tile's counters (later tiles: in the scan)
             }
             if (__syncthreads_or(bad)) {  // never expected: refuse to write anything for this unit
                 if (tid == 0) atomicOr(&P.ctl->overflow, OVF_STATE);
@@ -916,9 +917,6 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
             uint32_t b[SK], rk[SK];
             if (PAY) {
                 for (uint32_t j = lane; j < nb; j += WAVE) wcnt[w][j] = 0;
-            } else {
-                for (uint32_t j = tid; j < nb; j += NT) tcnt[j] = 0;
-                lds_barrier();
             }
 #pragma unroll
             for (int r = 0; r < SK; r++) {
@@ -994,14 +992,13 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                 for (int q = 0; q < SB; q++) {
                     const uint32_t j = SB * tid + q;
                     c[q] = j < nb ? tcnt[j] : 0u;
+                    // keys only: bucket j's counter is read by thread j alone, so
+                    // it is cleared for the next tile here (the barriers before
+                    // the next tile's atomics order the two)
+                    if (!PAY && j < nb) tcnt[j] = 0;
                     lane_sum += c[q];
                 }
-                uint32_t x = lane_sum;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const uint32_t y = __shfl_up(x, o);
-                    if (lane >= o) x += y;
-                }
+                const uint32_t x = wave_incl_sum(lane_sum);
                 if (lane == 63) red64[w] = x;
                 lds_barrier();
                 uint32_t ex = x - lane_sum;
