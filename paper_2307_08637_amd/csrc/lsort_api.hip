@@ -572,7 +572,8 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         TIMED(KI_BASE, c.st, launch_base_small(P, cus * 8, c.st));
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
         if (g_timing) {  // keys through the base case (both kernels) and the copies
-            HIP_TRY(hipMemcpyAsync(pool->pinned, &P.ctl->small_keys, 16, hipMemcpyDeviceToHost, c.st));
+            HIP_TRY(hipMemcpyAsync(pool->pinned, &P.ctl->small_keys, 8, hipMemcpyDeviceToHost, c.st));
+            HIP_TRY(hipMemcpyAsync(pool->pinned + 1, &P.ctl->big_keys, 8, hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));
             g_trec[g_trec.size() - 2].keys = (double)pool->pinned[0];
             g_trec.back().keys = (double)pool->pinned[1];

@@ -236,11 +236,22 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
     }
     const uint64_t nk = min<unsigned long long>(P.ctl->nitems_k, P.item_b_cap);
     const uint64_t nc = min<unsigned long long>(P.ctl->nitems_c, P.item_c_cap);
-    group_loop<6, U64, false>(P, P.items_c, P.item_c_cap, nc, wid, waves, glds[wv], lane);
-    group_loop<5, U64, true>(P, P.items_b, P.item_b_cap, nk, wid, waves, glds[wv], lane);
-    group_loop<4, U64, true>(P, P.items, P.item_cap, nw, wid, waves, glds[wv], lane);
-    group_loop<3, U64, false>(P, P.items_b, P.item_b_cap, n1, wid, waves, glds[wv], lane);
-    group_loop<2, U64, false>(P, P.items, P.item_cap, n0, wid, waves, glds[wv], lane);
+    // the classes' tasks are dealt out as one list: a class starts at the
+    // wavefront after the one the previous class ended on, so that with fewer
+    // tasks than wavefronts no wavefront sorts two
+    uint64_t o = 0;
+    auto first = [&](uint64_t ntask) {
+        const uint64_t f = (wid + waves - o % waves) % waves;
+        o += ntask;
+        return f;
+    };
+    const uint64_t f6 = first(nc), f5 = first((nk + 1) / 2), f4 = first((nw + 3) / 4), f3 = first((n1 + 7) / 8);
+    const uint64_t f2 = first((n0 + 15) / 16);
+    group_loop<6, U64, false>(P, P.items_c, P.item_c_cap, nc, f6, waves, glds[wv], lane);
+    group_loop<5, U64, true>(P, P.items_b, P.item_b_cap, nk, f5, waves, glds[wv], lane);
+    group_loop<4, U64, true>(P, P.items, P.item_cap, nw, f4, waves, glds[wv], lane);
+    group_loop<3, U64, false>(P, P.items_b, P.item_b_cap, n1, f3, waves, glds[wv], lane);
+    group_loop<2, U64, false>(P, P.items, P.item_cap, n0, f2, waves, glds[wv], lane);
 }
 
 constexpr int BIG_THREADS = 512;

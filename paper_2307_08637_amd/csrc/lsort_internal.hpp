@@ -117,31 +117,37 @@ struct LevelStats {
 };
 
 // Control block at the start of the workspace.
+// Counters that every workgroup of a launch updates with device-scope atomics
+// each sit in a 256-byte slot of their own: atomics on one address are
+// serialised where they are performed, but different lines proceed in
+// parallel (a level of ~1000 segments updates about ten of these counters per
+// segment).
+#define LS_HOT alignas(256)
 struct Ctl {
-    uint32_t nseg[MAXL + 1];        // segments at each level
-    uint32_t ntile[MAXL + 1];       // tiles at each level
-    uint32_t ticket[MAXL + 1];      // scatter unit tickets
-    uint32_t rticket[MAXL + 1];     // k_resident segment tickets
-    uint32_t hticket[MAXL + 1];     // k_hist unit tickets
-    uint32_t pad0;
-    unsigned long long nitems;      // small base-case items of <= GROUP_SMALL_MAX keys (front of items)
-    unsigned long long nitems_w;    // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)
-    unsigned long long nitems_b;    // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys (items_b)
-    unsigned long long nitems_k;    // keys only: items of SMALL_MAX+1 .. GROUP_LARGE_MAX keys (back of items_b)
-    unsigned long long nitems_c;    // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys (items_c)
-    unsigned long long nbig;        // large base-case items and copy items
-    unsigned long long nmoved;      // small items handed on to the large list (NaN / -0.0 tasks)
-    unsigned long long ncopy;
-    unsigned long long small_keys;  // keys in small base-case items
-    unsigned long long big_keys;    // keys in large base-case items and copy runs
-    unsigned long long counts_used; // bump allocators (reset per level)
-    unsigned long long status_used;
-    unsigned long long arena_used[2];
-    uint32_t overflow;              // OVF_* bits
-    uint32_t first_mlp;             // the first level's model is the MLP-rooted one
-    double mlp_loss[2];             // MLP training loss at the first and the last step
-    LevelStats lv[MAXL];
+    LS_HOT uint32_t nseg[MAXL + 1];         // segments at each level
+    LS_HOT uint32_t ntile[MAXL + 1];        // tiles at each level
+    LS_HOT uint32_t ticket[MAXL + 1];       // scatter unit tickets
+    LS_HOT uint32_t rticket[MAXL + 1];      // k_resident segment tickets
+    LS_HOT uint32_t hticket[MAXL + 1];      // k_hist unit tickets
+    LS_HOT unsigned long long nitems;       // small base-case items of <= GROUP_SMALL_MAX keys (front of items)
+    LS_HOT unsigned long long nitems_w;     // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)
+    LS_HOT unsigned long long nitems_b;     // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys (items_b)
+    LS_HOT unsigned long long nitems_k;     // keys only: items of SMALL_MAX+1 .. GROUP_LARGE_MAX keys (back of items_b)
+    LS_HOT unsigned long long nitems_c;     // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys (items_c)
+    LS_HOT unsigned long long nbig;         // large base-case items and copy items
+    LS_HOT unsigned long long nmoved;       // small items handed on to the large list (NaN / -0.0 tasks)
+    LS_HOT unsigned long long ncopy;
+    LS_HOT unsigned long long small_keys;   // keys in small base-case items
+    LS_HOT unsigned long long big_keys;     // keys in large base-case items and copy runs
+    LS_HOT unsigned long long counts_used;  // bump allocators (reset per level)
+    LS_HOT unsigned long long status_used;
+    LS_HOT unsigned long long arena_used[2];
+    LS_HOT uint32_t overflow;               // OVF_* bits
+    uint32_t first_mlp;                     // the first level's model is the MLP-rooted one
+    double mlp_loss[2];                     // MLP training loss at the first and the last step
+    LS_HOT LevelStats lv[MAXL];
 };
+#undef LS_HOT
 constexpr uint32_t OVF_SEG = 1, OVF_TILE = 2, OVF_ITEM = 4, OVF_COUNTS = 8, OVF_STATUS = 16, OVF_ARENA = 32,
                    OVF_STATE = 64;  // a look-back word without this level's tag (never expected)
 

@@ -672,22 +672,34 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         const uint64_t sc = block_sum<S_THREADS, uint64_t>(lstat, red64);
         const uint64_t nfb = block_sum<S_THREADS, uint64_t>(lfb, red64);
         const uint64_t mx = block_max<S_THREADS, uint64_t>(cmax, red64);
-        if (tid == 0) {
+        if (tid < WAVE) {
+            // the reservations: one device-scope atomic per lane, issued as one
+            // instruction per width, so that their round trips overlap
             const uint64_t itot = ta & 0xffff, ctot = (ta >> 16) & 0xffff, gtot = ta >> 32, ttot = tb & 0xffffffffull;
             const uint64_t btot = (tb >> 32) & 0xffff, wtot = tb >> 48;
-            resv[0] = itot ? atomicAdd(&P.ctl->nitems, (unsigned long long)itot) : 0;
-            resv[4] = wtot ? atomicAdd(&P.ctl->nitems_w, (unsigned long long)wtot) : 0;
-            resv[5] = btot ? atomicAdd(&P.ctl->nitems_b, (unsigned long long)btot) : 0;
-            resv[6] = (tc & 0xffffffffull) ? atomicAdd(&P.ctl->nitems_k, (unsigned long long)(tc & 0xffffffffull)) : 0;
-            resv[7] = (tc >> 32) ? atomicAdd(&P.ctl->nitems_c, (unsigned long long)(tc >> 32)) : 0;
-            resv[1] = ctot ? atomicAdd(&P.ctl->nseg[lvl + 1], (uint32_t)ctot) : 0;
-            resv[2] = ttot ? atomicAdd(&P.ctl->ntile[lvl + 1], (uint32_t)ttot) : 0;
-            resv[3] = gtot ? atomicAdd(&P.ctl->nbig, (unsigned long long)gtot) : 0;
-            if (ncp) atomicAdd(&P.ctl->ncopy, (unsigned long long)ncp);
-            if (sk) atomicAdd(&P.ctl->small_keys, (unsigned long long)sk);
-            if (gk) atomicAdd(&P.ctl->big_keys, (unsigned long long)gk);
+            const int l = tid;
+            unsigned long long* p64 = l == 0 ? &P.ctl->nitems : l == 1 ? &P.ctl->nitems_w : l == 2 ? &P.ctl->nitems_b
+                                    : l == 3 ? &P.ctl->nitems_k : l == 4 ? &P.ctl->nitems_c : l == 5 ? &P.ctl->nbig
+                                    : l == 6 ? &P.ctl->ncopy : l == 7 ? &P.ctl->small_keys : l == 8 ? &P.ctl->big_keys
+                                    : &st.keys;
+            const uint64_t v64 = l == 0 ? itot : l == 1 ? wtot : l == 2 ? btot : l == 3 ? (tc & 0xffffffffull)
+                               : l == 4 ? (tc >> 32) : l == 5 ? gtot : l == 6 ? ncp : l == 7 ? sk : l == 8 ? gk
+                               : l == 9 ? sg.n : 0;  // st.keys always: per-level kernel timing reads it
+            if (l < 10 && (v64 || l == 9)) {
+                const uint64_t r = atomicAdd(p64, (unsigned long long)v64);
+                const int slot = l == 0 ? 0 : l == 1 ? 4 : l == 2 ? 5 : l == 3 ? 6 : l == 4 ? 7 : l == 5 ? 3 : -1;
+                if (slot >= 0) resv[slot] = r;
+            } else if (l < 6) {
+                const int slot = l == 0 ? 0 : l == 1 ? 4 : l == 2 ? 5 : l == 3 ? 6 : l == 4 ? 7 : 3;
+                resv[slot] = 0;
+            }
+            const uint32_t v32 = l == 10 ? (uint32_t)ctot : l == 11 ? (uint32_t)ttot : 0u;
+            if (l == 10 || l == 11) {
+                resv[l - 9] = v32 ? atomicAdd(l == 10 ? &P.ctl->nseg[lvl + 1] : &P.ctl->ntile[lvl + 1], v32) : 0u;
+            }
+        }
+        if (tid == 0) {
             const uint64_t m12 = 4095;
-            atomicAdd(&st.keys, (unsigned long long)sg.n);  // always: per-level kernel timing reads it
             if (P.flags & FLAG_STATS) {
                 atomicAdd(&st.segments, 1ull);
                 atomicAdd(&st.buckets, (unsigned long long)nb);
