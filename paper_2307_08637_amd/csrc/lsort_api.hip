@@ -535,12 +535,15 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     const bool fixed = (c.o.flags & LS_FLAG_FIXED_LEVELS) != 0;
     const uint32_t max_run = c.one_level ? 1 : std::min<uint32_t>(MAXL - 1, c.o.max_levels + 9);
     uint32_t levels = 0;
+    uint32_t next_res = 0;  // resident segments of the next level (read back)
     for (uint32_t lvl = 0; lvl < max_run; lvl++) {
         P.level = (int)lvl;
         const size_t rec0 = g_trec.size();
         const uint32_t g0 = lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024;
         TIMED(KI_MODEL, c.st, launch_model(P, g0, c.st));
-        if (!c.one_level) TIMED(KI_RESIDENT, c.st, launch_resident(P, cus * (c.pay ? 2 : 3), c.st));
+        // (after the first level the read-back below says whether any segment is resident)
+        if (!c.one_level && (lvl == 0 || fixed || next_res))
+            TIMED(KI_RESIDENT, c.st, launch_resident(P, cus * (c.pay ? 2 : 3), c.st));
         if (P.ids && lvl <= 1) TIMED(KI_MLP_IDS, c.st, launch_mlp_ids(P, cus * 4, c.st));
         TIMED(KI_HIST, c.st, launch_hist(P, cus * 4, c.st));
         TIMED(KI_SCAN, c.st, launch_scan(P, g0, c.st));
@@ -559,10 +562,12 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         HIP_TRY(hipMemcpyAsync(pool->pinned, &ctl->nseg[lvl + 1], 4, hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 8, &ctl->overflow, 4, hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 16, &ctl->lv[lvl].keys, 8, hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 24, &ctl->nres[lvl + 1], 4, hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
         uint32_t next = ((uint32_t*)pool->pinned)[0];
         uint32_t ovf = ((uint32_t*)pool->pinned)[2];
         double lkeys = (double)((uint64_t*)pool->pinned)[2];
+        next_res = ((uint32_t*)pool->pinned)[6];
         for (size_t i = rec0; i < g_trec.size(); i++) g_trec[i].keys = lkeys;
         if (ovf) return fail(LS_ENOMEM, "workspace capacity exceeded:" + overflow_text(ovf));
         if (next == 0) break;

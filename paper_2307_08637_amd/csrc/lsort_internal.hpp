@@ -129,6 +129,7 @@ struct Ctl {
     LS_HOT uint32_t ticket[MAXL + 1];       // scatter unit tickets
     LS_HOT uint32_t rticket[MAXL + 1];      // k_resident segment tickets
     LS_HOT uint32_t hticket[MAXL + 1];      // k_hist unit tickets
+    LS_HOT uint32_t nres[MAXL + 1];         // segments at each level that k_resident sorts whole
     LS_HOT unsigned long long nitems;       // small base-case items of <= GROUP_SMALL_MAX keys (front of items)
     LS_HOT unsigned long long nitems_w;     // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)
     LS_HOT unsigned long long nitems_b;     // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys (items_b)

@@ -62,6 +62,10 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
         // an array small enough for one workgroup is sorted whole by k_resident
         const bool resident = seg && !prebuilt && n <= RES_MAX;
         const uint32_t nt = seg && !resident ? (uint32_t)((n + UNIT - 1) / UNIT) : 0;
+        {
+            const uint32_t nr = (uint32_t)__popcll(__ballot(resident));
+            if ((threadIdx.x & 63) == 0 && nr) atomicAdd(&P.ctl->nres[0], nr);
+        }
         uint64_t itot, wtot, gtot, ktot, ctot, btot, stot, ttot;
         const uint64_t iex = block_excl_scan<256, uint64_t>(item && cls == 0 ? 1 : 0, red64, &itot);
         const uint64_t gex = block_excl_scan<256, uint64_t>(item && cls == 1 ? 1 : 0, red64, &gtot);
@@ -713,6 +717,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             }
         }
         __syncthreads();
+        uint32_t nresc = 0;
 #pragma unroll
         for (int i = 0; i < S_BPT; i++) {
             const uint32_t b = S_BPT * tid + i;
@@ -745,6 +750,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                 const uint64_t sz = a == 1 ? min<uint64_t>(COPY_CHUNK, ci - k * COPY_CHUNK) : ci;
                 P.bigs[it] = item_pack(start[i] + k * COPY_CHUNK, a == 1 ? 1u : q, a == 1 ? 1u : 0u, (uint32_t)sz);
             }
+            nresc += a >= 3 && child_resident(sg.kind, a, ci) ? 1u : 0u;
             if (a >= 3) {
                 const uint64_t si = resv[1] + cex, t0 = resv[2] + tex;
                 if (si < P.seg_cap) {
@@ -770,6 +776,10 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             xa += ng0 | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
             xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
             xc += ng3 | (ng4 << 32);
+        }
+        {  // resident children, one atomic per wavefront that has any
+            const uint32_t wt = wave_incl_sum(nresc);
+            if ((tid & 63) == 63 && wt) atomicAdd(&P.ctl->nres[lvl + 1], wt);
         }
         __syncthreads();
     }
@@ -1270,6 +1280,7 @@ __global__ __launch_bounds__(R_THREADS) void k_resident(Params P) {
     __shared__ ResLds<PAY> L;
     const int tid = threadIdx.x;
     const int lvl = P.level;
+    if (P.ctl->nres[lvl] == 0) return;  // no segment of this level is resident
     const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
     uint64_t cur_model = 0;
     for (;;) {
