@@ -183,7 +183,7 @@ static Opts nested_opts(const Opts& o) {
     Opts r = o;
     r.flags = (o.flags & LS_FLAG_FIXED_LEVELS) ? o.flags : ((o.flags & ~(uint32_t)LS_FLAG_FIXED_LEVELS) | LS_FLAG_SYNC_LEVELS);
     r.model = o.model == LS_MODEL_SPLITTER ? LS_MODEL_SPLITTER : LS_MODEL_AUTO;
-    r.sample_frac = 0.004;
+    r.sample_frac = 0.002;
     return r;
 }
 
