@@ -423,6 +423,8 @@ static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
     P.seg_cap = L.seg_cap; P.tile_cap = L.tile_cap; P.item_cap = L.item_cap; P.big_cap = L.big_cap; P.counts_cap = L.counts_cap;
     P.status_cap = L.status_cap; P.arena_cap = L.arena_cap; P.item_b_cap = L.item_b_cap; P.item_c_cap = L.item_c_cap;
     P.persist = (const uint64_t*)(base + L.o_persist);
+    P.fsample = L.S_big ? (const uint64_t*)(base + L.o_sample) : nullptr;
+    P.fS = L.S_big;
     P.level = 0;
     return P;
 }

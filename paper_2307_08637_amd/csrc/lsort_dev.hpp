@@ -90,6 +90,17 @@ __device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t lo, uint32_t h
     return r;
 }
 
+// The bucket range [lo, hi] that leaf clamp interval [c, d] allows:
+// G(c), G(d) with G(y) = clamp(floor(y), 0, R-1); a NaN bound clamps nothing;
+// c > d leaves only G(d).
+__device__ __forceinline__ void rmi_leaf_range(double c, double d, double Rm1, uint32_t& lo, uint32_t& hi) {
+    if (c != c) c = -INFINITY;
+    if (d != d) d = INFINITY;
+    lo = (uint32_t)fmin(fmax(floor(c), 0.0), Rm1);
+    hi = (uint32_t)fmin(fmax(floor(d), 0.0), Rm1);
+    if (lo > hi) lo = hi;
+}
+
 // LDS image of the leaf table of a stored RMI at src (header first) into dst:
 // one leaf per thread of [tid, L) step nt.
 __device__ __forceinline__ void rmi_to_lds(uint64_t* dst, const uint64_t* src, int tid, int nt) {
@@ -101,12 +112,9 @@ __device__ __forceinline__ void rmi_to_lds(uint64_t* dst, const uint64_t* src, i
     for (uint32_t j = tid; j < L; j += nt) {
         dst[RMI_PAIRS + 2 * j] = __double_as_longlong(q[4 * j]);
         dst[RMI_PAIRS + 2 * j + 1] = __double_as_longlong(q[4 * j + 1]);
-        double c = q[4 * j + 2], d = q[4 * j + 3];
-        if (c != c) c = -INFINITY;  // a NaN bound clamps nothing
-        if (d != d) d = INFINITY;
-        const uint32_t lo = (uint32_t)fmin(fmax(floor(c), 0.0), Rm1);
-        const uint32_t hi = (uint32_t)fmin(fmax(floor(d), 0.0), Rm1);
-        dst[RMI_PAIRS + 2 * L + j] = (uint64_t)(lo < hi ? lo : hi) | ((uint64_t)hi << 32);
+        uint32_t lo, hi;
+        rmi_leaf_range(q[4 * j + 2], q[4 * j + 3], Rm1, lo, hi);
+        dst[RMI_PAIRS + 2 * L + j] = (uint64_t)lo | ((uint64_t)hi << 32);
     }
 }
 
@@ -125,6 +133,21 @@ __device__ __forceinline__ uint32_t rmi_lds_bucket(const uint64_t* m, uint32_t L
     const bool nf = __builtin_amdgcn_class(x, 0x003 | 0x004 | 0x200);  // NaN, -inf, +inf
     const uint32_t edge = (int32_t)(raw >> 32) < 0 ? 0u : rm1;
     return nf ? edge : g;
+}
+
+// The same bucket (at resolution R) evaluated on the stored form in global
+// memory, for the few keys a search needs.
+__device__ __forceinline__ uint32_t rmi_stored_bucket(const uint64_t* model, uint64_t raw, int u64) {
+    const RmiModel* h = (const RmiModel*)model;
+    const double* p = (const double*)(model + 4);
+    const uint32_t rm1 = (uint32_t)(h->R - 1.0);
+    const double x = u64 ? (double)raw : __longlong_as_double((long long)raw);
+    if (!u64 && __builtin_amdgcn_class(x, 0x003 | 0x004 | 0x200)) return (int32_t)(raw >> 32) < 0 ? 0u : rm1;
+    const uint32_t j = min(cvt_sat_u32(__builtin_fma(p[0], x, p[1])), h->L - 1);
+    const double* q = p + 2 + 4 * j;
+    uint32_t lo, hi;
+    rmi_leaf_range(q[2], q[3], h->R - 1.0, lo, hi);
+    return med3_u32(cvt_sat_u32(__builtin_fma(q[0], x, q[1])), lo, hi);
 }
 
 // Splitter tree (Sec. 2.4): k = #{u_i <= o} by branch-free binary lifting over

@@ -97,6 +97,8 @@ constexpr uint32_t FLAG_STATS = 0x8u;   // LS_FLAG_COLLECT_STATS: per-level stat
 constexpr uint32_t SEG_PREBUILT = 1u;  // model already built (large first level)
 constexpr uint32_t SEG_FAILED = 2u;    // capacity exceeded; not partitioned
 constexpr uint32_t SEG_RESIDENT = 4u;  // sorted by one workgroup (k_resident): no work units
+constexpr uint32_t SEG_FROM_SAMPLE = 8u;  // fallback child of the first level: its tree's sample is the
+                                          // first-level sample's run in its bucket (model = parent's, win = bucket)
 constexpr uint64_t RES_MAX = 8192;     // largest segment a single workgroup takes (one work unit)
 
 struct Tile {          // one work unit of UNIT keys
@@ -179,6 +181,8 @@ struct Params {
     uint64_t* items_c;              // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys
     uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
     const uint64_t* persist;        // [0] call epoch, [1] clear-status request (survives calls)
+    const uint64_t* fsample;        // sorted first-level sample of a large array (raw keys), or null
+    uint64_t fS;                    // its size
     int level;
 };
 

@@ -281,6 +281,46 @@ __device__ void sample_sort(uint64_t* smp, const uint64_t* src, uint64_t off, ui
     __syncthreads();
 }
 
+// First index i in [0, S) with bucket(fs[i]) >= target under the stored RMI
+// pm at the parent's resolution (bucket = g >> log2B2), S if none; the
+// buckets of the sorted sample do not decrease.  Coarse-to-fine: each round
+// the workgroup tests M_THREADS evenly spaced positions of the current range.
+__device__ uint64_t sample_lower_bound(const uint64_t* fs, uint64_t S, const uint64_t* pm, uint32_t target, int u64,
+                                       uint64_t* sh) {
+    const uint32_t sh2 = ((const RmiModel*)pm)->log2B2;
+    uint64_t lo = 0, hi = S;  // answer in [lo, hi]
+    while (hi > lo) {
+        const uint64_t span = hi - lo, step = (span + M_THREADS - 1) / M_THREADS;
+        __syncthreads();
+        if (threadIdx.x == 0) sh[0] = hi;
+        __syncthreads();
+        const uint64_t i = lo + (uint64_t)threadIdx.x * step;
+        if (i < hi && (rmi_stored_bucket(pm, fs[i], u64) >> sh2) >= target) atomicMin((unsigned long long*)&sh[0], i);
+        __syncthreads();
+        const uint64_t f = sh[0];  // first tested position that qualifies (or hi)
+        if (step == 1) return f;
+        // the answer lies after the last tested position below f
+        hi = f;
+        lo = f > lo ? (f - lo - 1) / step * step + lo + 1 : lo;
+        if (f == lo) return f;
+    }
+    return lo;
+}
+
+// The first-level sample's keys in parent bucket b, as ordered keys in smp[]
+// (evenly thinned to S_LDS when more); returns their number.
+__device__ uint32_t sample_slice(uint64_t* smp, const uint64_t* fs, uint64_t S, const uint64_t* pm, uint32_t b, int u64,
+                                 uint64_t* sh) {
+    const uint64_t lo = sample_lower_bound(fs, S, pm, b, u64, sh);
+    const uint64_t hi = sample_lower_bound(fs, S, pm, b + 1, u64, sh);
+    const uint64_t cnt = hi > lo ? hi - lo : 0;
+    const uint32_t m = (uint32_t)min<uint64_t>(cnt, S_LDS);
+    for (uint32_t k = threadIdx.x; k < m; k += M_THREADS)
+        smp[k] = key_ord(fs[lo + (cnt > S_LDS ? (uint64_t)k * cnt / S_LDS : k)], u64);
+    __syncthreads();
+    return m;
+}
+
 __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
     __shared__ uint64_t smp[S_LDS];
     __shared__ uint32_t lstart[L_MAX + 1];
@@ -330,14 +370,24 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             uint64_t want = (uint64_t)ceil(P.sample_frac * (double)n);
             uint64_t floor_s = min<uint64_t>(n, 8ull * Bt);  // 8 sample keys per bucket at least
             uint32_t S = (uint32_t)min<uint64_t>(S_LDS, max<uint64_t>(want, max<uint64_t>(floor_s, 2)));
-            uint32_t P2 = 1u << ceil_log2(S);
-            const uint64_t sseed = splitmix64_at(P.seed, (sg.off << 6) | (uint64_t)lvl);
-            // gather and sort in registers; the sorted sample lands in smp[]
-            if (P2 <= 1024) sample_sort<1>(smp, src, sg.off, n, S, sseed, u64);
-            else if (P2 <= 2048) sample_sort<2>(smp, src, sg.off, n, S, sseed, u64);
-            else if (P2 <= 4096) sample_sort<4>(smp, src, sg.off, n, S, sseed, u64);
-            else if (P2 <= 8192) sample_sort<8>(smp, src, sg.off, n, S, sseed, u64);
-            else sample_sort<16>(smp, src, sg.off, n, S, sseed, u64);
+            // a fallback child of a large array's first level: the first-level
+            // sample's keys in the parent bucket are already a sorted random
+            // sample of this segment (about 1% of it)
+            const uint32_t Sf = (sg.flags & SEG_FROM_SAMPLE) && P.fsample
+                                    ? sample_slice(smp, P.fsample, P.fS, (const uint64_t*)sg.model, sg.win, u64, shv)
+                                    : 0u;
+            if (Sf >= 2) {
+                S = Sf;
+            } else {
+                const uint32_t P2 = 1u << ceil_log2(S);
+                const uint64_t sseed = splitmix64_at(P.seed, (sg.off << 6) | (uint64_t)lvl);
+                // gather and sort in registers; the sorted sample lands in smp[]
+                if (P2 <= 1024) sample_sort<1>(smp, src, sg.off, n, S, sseed, u64);
+                else if (P2 <= 2048) sample_sort<2>(smp, src, sg.off, n, S, sseed, u64);
+                else if (P2 <= 4096) sample_sort<4>(smp, src, sg.off, n, S, sseed, u64);
+                else if (P2 <= 8192) sample_sort<8>(smp, src, sg.off, n, S, sseed, u64);
+                else sample_sort<16>(smp, src, sg.off, n, S, sseed, u64);
+            }
             // duplicates and finiteness (Alg. 5; Sec. 4: more than 10% duplicates -> tree)
             uint64_t dup = 0;
             for (uint32_t j = 1 + tid; j < S; j += M_THREADS) dup += smp[j] == smp[j - 1];
@@ -759,6 +809,11 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                     ch.kind = a == 3 ? K_RADIX : a == 4 ? (sg.kind == K_RMI ? K_RMI_FINE : K_MLP_FINE)
                             : a == 5 ? K_TREE_FORCED : K_FRESH;
                     if (child_resident(sg.kind, a, ci)) ch.flags = SEG_RESIDENT;
+                    if (a == 5 && lvl == 0 && sg.kind == K_RMI && (sg.flags & SEG_PREBUILT) && P.fsample) {
+                        ch.flags |= SEG_FROM_SAMPLE;  // the tree's sample: the first-level sample in bucket b
+                        ch.model = sg.model;
+                        ch.win = b;
+                    }
                     if (a == 4) {
                         ch.model = sg.model;
                         ch.nb = 1u << log2B2;
