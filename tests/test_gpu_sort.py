@@ -169,6 +169,20 @@ def test_large_1e7_oracle(dev, law):
     assert_same_bits(got, oracle.sort(keys)[0])
 
 
+@pytest.mark.parametrize("law", ["normal", "lognormal", "exponential"])
+def test_first_level_fallback_trees(dev, law):
+    """A large array's oversized first-level buckets (above 2x the expected
+    size) get splitter trees whose sample is the sorted first-level sample's
+    run in the bucket: the path must run (fallbacks at level 0, trees at level
+    1) and the output must equal the oracle's bit for bit."""
+    keys = inputs.generate(law, 5_000_000, seed=71)
+    got, _ = gpu_sort(keys, dev, buckets=1000, fallback_ratio=1.5)
+    st = lsort.stats()["levels"]
+    assert st[0]["learned"] == 1 and st[0]["fallback"] > 0, st[0]
+    assert st[1]["tree"] >= st[0]["fallback"], st[1]
+    assert_same_bits(got, oracle.sort(keys)[0])
+
+
 @pytest.mark.parametrize("law", ["uniform", "normal", "lognormal", "exponential", "chisquared", "mixgauss", "u64",
                                  "rootdups", "twodups", "zipf"])
 def test_full_size_1e8_properties(dev, law):
