@@ -134,49 +134,50 @@ __global__ __launch_bounds__(MLP_SETUP_T) void k_mlp_setup(const float* t, uint6
 //
 // Each workgroup takes a contiguous chunk of the samples, 256 at a time: a
 // thread runs forward and backward for one sample and leaves the per-sample
-// factors in an LDS record; then thread j sums, in sample order, the product
-// of the two record fields that make gradient entry j (and entry j + 256):
-//   V1[k]: dz1_k * t     b1[k]: dz1_k       V2[i][k]: dz2_i * h1_k
-//   b2[i]: dz2_i         V3[k]: dout * h2_k b3: dout    loss: e * e
-// (gradients with respect to the effective weights; dout = 2 e / S).  The
+// factors in LDS, field-major (rec[f][sample]).  The gradient is then a set
+// of small products over the samples:
+//   V2[i][k] = sum dz2_i * h1_k (16 x 16)   V1[k] = sum dz1_k * t   b1[k] = sum dz1_k
+//   b2[i] = sum dz2_i   V3[k] = sum dout * h2_k   b3 = sum dout   loss = sum e * e
+// (gradients with respect to the effective weights; dout = 2 e / S).  Thread
+// (tile, group) keeps a 4 x 4 tile of V2 -- and tiles 0..12 one of the
+// vectors above -- in registers for the 16 samples of its group in each
+// batch, reading four samples of a field per 16-byte LDS load; the sixteen
+// groups' sums are added in group order once, at the end of the chunk.  The
 // workgroup partials go to global memory; the last workgroup to finish adds
 // them in workgroup order (so the result does not depend on scheduling),
 // applies d|V|/dV = sign(V) and, if asked, the Adam update.
 // ---------------------------------------------------------------------------
 constexpr int MLP_T = 256;
-constexpr int REC = 69;  // LDS record per sample (odd stride: no bank conflicts)
-enum : int { R_H1 = 0, R_DZ2 = 16, R_DZ1 = 32, R_H2 = 48, R_DOUT = 64, R_T = 65, R_E = 66, R_ONE = 67 };
-
-__device__ __forceinline__ void acc_fields(int j, int& fa, int& fb) {
-    if (j < OFF_B1) { fa = R_DZ1 + j; fb = R_T; }
-    else if (j < OFF_V2) { fa = R_DZ1 + (j - OFF_B1); fb = R_ONE; }
-    else if (j < OFF_B2) { fa = R_DZ2 + (j - OFF_V2) / MLP_H; fb = R_H1 + (j - OFF_V2) % MLP_H; }
-    else if (j < OFF_V3) { fa = R_DZ2 + (j - OFF_B2); fb = R_ONE; }
-    else if (j < OFF_B3) { fa = R_DOUT; fb = R_H2 + (j - OFF_V3); }
-    else if (j == OFF_B3) { fa = R_DOUT; fb = R_ONE; }
-    else { fa = R_E; fb = R_E; }
-}
+constexpr int NREC = 68;  // record fields
+enum : int { R_H1 = 0, R_DZ2 = 16, R_DZ1 = 32, R_H2 = 48, R_DOUT = 64, R_T = 65, R_E = 66 };
+constexpr int MLP_GROUP = 16;  // samples of one thread group per batch
 
 __global__ __launch_bounds__(MLP_T) void k_mlp_step(MlpStep A) {
     if (A.gate && A.gate[0] == 0) return;
     __shared__ float w[MLP_NP];
-    __shared__ float rec[MLP_T * REC];
+    __shared__ __align__(16) float rec[NREC * MLP_T];
     __shared__ int last;
     const int tid = threadIdx.x;
     for (int i = tid; i < MLP_NP; i += MLP_T) w[i] = mlp_is_weight(i) ? fabsf(A.p[i]) : A.p[i];
-    int fa0, fb0, fa1 = 0, fb1 = 0;
-    acc_fields(tid, fa0, fb0);
-    const bool two = tid + MLP_T < MLP_ACC;
-    if (two) acc_fields(tid + MLP_T, fa1, fb1);
     __syncthreads();
     const float inv_s = 1.0f / (float)A.S;
     const uint64_t chunk = (A.S + gridDim.x - 1) / gridDim.x;
     const uint64_t lo = (uint64_t)blockIdx.x * chunk, hi = min(A.S, lo + chunk);
-    float acc0 = 0.0f, acc1 = 0.0f;
-    float* r = rec + tid * REC;
+    // accumulation role: tile of V2 rows i0.., columns k0..; group of samples
+    const int tile = tid & 15, grp = tid >> 4;
+    const int i0 = (tile >> 2) * 4, k0 = (tile & 3) * 4;
+    float a2[4][4], ax[8];
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++) a2[x][y] = 0.0f;
+#pragma unroll
+    for (int x = 0; x < 8; x++) ax[x] = 0.0f;
+    auto rd4 = [&](int f, int s0) { return *(const float4*)&rec[f * MLP_T + s0]; };
     for (uint64_t base = lo; base < hi; base += MLP_T) {
         lds_reload_fence();
         const uint64_t s = base + tid;
+        float r[NREC];
         if (s < hi) {
             // forward; a hidden unit is active (derivative 1) exactly when its
             // output is non-zero, so the activations double as the masks
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(MLP_T) void k_mlp_step(MlpStep A) {
 #pragma unroll
                     for (int k = 0; k < MLP_H; k++) z = __builtin_fmaf(w[OFF_V2 + MLP_H * i + k], h1[k], z);
                     const float h = half == 0 ? fmaxf(z, 0.0f) : fminf(z, 0.0f);
-                    r[R_H2 + i] = h;
+                    rec[(R_H2 + i) * MLP_T + tid] = h;
                     out = __builtin_fmaf(w[OFF_V3 + i], h, out);
                 }
             }
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(MLP_T) void k_mlp_step(MlpStep A) {
             for (int k = 0; k < MLP_H; k++) dh1[k] = 0.0f;
 #pragma unroll 1
             for (int i = 0; i < MLP_H; i++) {
-                const float dz2 = r[R_H2 + i] != 0.0f ? dout * w[OFF_V3 + i] : 0.0f;
+                const float dz2 = rec[(R_H2 + i) * MLP_T + tid] != 0.0f ? dout * w[OFF_V3 + i] : 0.0f;
                 r[R_DZ2 + i] = dz2;
 #pragma unroll
                 for (int k = 0; k < MLP_H; k++) dh1[k] = __builtin_fmaf(dz2, w[OFF_V2 + MLP_H * i + k], dh1[k]);
@@ -221,17 +222,90 @@ __global__ __launch_bounds__(MLP_T) void k_mlp_step(MlpStep A) {
             r[R_E] = e;
         } else {
 #pragma unroll
-            for (int f = 0; f < R_ONE; f++) r[f] = 0.0f;
+            for (int f = 0; f < NREC; f++) r[f] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < MLP_H; i++) rec[(R_H2 + i) * MLP_T + tid] = 0.0f;
         }
-        r[R_ONE] = 1.0f;
+#pragma unroll
+        for (int f = 0; f < NREC; f++)
+            if (f < R_H2 || f >= R_H2 + MLP_H) rec[f * MLP_T + tid] = r[f];
         __syncthreads();
-        const int cnt = (int)min<uint64_t>(MLP_T, hi - base);
-        for (int q = 0; q < cnt; q++) {
-            const float* rq = rec + q * REC;
-            acc0 = __builtin_fmaf(rq[fa0], rq[fb0], acc0);
-            if (two) acc1 = __builtin_fmaf(rq[fa1], rq[fb1], acc1);
+        // this group's 16 samples of the batch, four at a time
+#pragma unroll 1
+        for (int c = 0; c < MLP_GROUP; c += 4) {
+            const int s0 = grp * MLP_GROUP + c;
+            float4 dz[4], hh[4];
+#pragma unroll
+            for (int x = 0; x < 4; x++) { dz[x] = rd4(R_DZ2 + i0 + x, s0); hh[x] = rd4(R_H1 + k0 + x, s0); }
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++) {
+                    a2[x][y] = __builtin_fmaf(dz[x].x, hh[y].x, a2[x][y]);
+                    a2[x][y] = __builtin_fmaf(dz[x].y, hh[y].y, a2[x][y]);
+                    a2[x][y] = __builtin_fmaf(dz[x].z, hh[y].z, a2[x][y]);
+                    a2[x][y] = __builtin_fmaf(dz[x].w, hh[y].w, a2[x][y]);
+                }
+            if (tile < 4) {  // V1[k0..], b1[k0..]
+                const float4 t4 = rd4(R_T, s0);
+#pragma unroll
+                for (int y = 0; y < 4; y++) {
+                    const float4 d = rd4(R_DZ1 + k0 + y, s0);
+                    ax[y] = __builtin_fmaf(d.x, t4.x, ax[y]); ax[y] = __builtin_fmaf(d.y, t4.y, ax[y]);
+                    ax[y] = __builtin_fmaf(d.z, t4.z, ax[y]); ax[y] = __builtin_fmaf(d.w, t4.w, ax[y]);
+                    ax[4 + y] += d.x; ax[4 + y] += d.y; ax[4 + y] += d.z; ax[4 + y] += d.w;
+                }
+            } else if (tile < 8) {  // V3[k0..]
+                const float4 o4 = rd4(R_DOUT, s0);
+#pragma unroll
+                for (int y = 0; y < 4; y++) {
+                    const float4 hv = rd4(R_H2 + k0 + y, s0);
+                    ax[y] = __builtin_fmaf(o4.x, hv.x, ax[y]); ax[y] = __builtin_fmaf(o4.y, hv.y, ax[y]);
+                    ax[y] = __builtin_fmaf(o4.z, hv.z, ax[y]); ax[y] = __builtin_fmaf(o4.w, hv.w, ax[y]);
+                }
+            } else if (tile < 12) {  // b2[k0..]
+#pragma unroll
+                for (int y = 0; y < 4; y++) {
+                    const float4 d = rd4(R_DZ2 + k0 + y, s0);
+                    ax[y] += d.x; ax[y] += d.y; ax[y] += d.z; ax[y] += d.w;
+                }
+            } else if (tile == 12) {  // b3, squared error
+                const float4 o4 = rd4(R_DOUT, s0), e4 = rd4(R_E, s0);
+                ax[0] += o4.x; ax[0] += o4.y; ax[0] += o4.z; ax[0] += o4.w;
+                ax[1] = __builtin_fmaf(e4.x, e4.x, ax[1]); ax[1] = __builtin_fmaf(e4.y, e4.y, ax[1]);
+                ax[1] = __builtin_fmaf(e4.z, e4.z, ax[1]); ax[1] = __builtin_fmaf(e4.w, e4.w, ax[1]);
+            }
         }
         __syncthreads();
+    }
+    // the groups' sums in group order: red[group][entry] in the record area
+    float* red = rec;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++) red[grp * MLP_ACC + OFF_V2 + MLP_H * (i0 + x) + k0 + y] = a2[x][y];
+    if (tile < 4) {
+#pragma unroll
+        for (int y = 0; y < 4; y++) {
+            red[grp * MLP_ACC + OFF_V1 + k0 + y] = ax[y];
+            red[grp * MLP_ACC + OFF_B1 + k0 + y] = ax[4 + y];
+        }
+    } else if (tile < 8) {
+#pragma unroll
+        for (int y = 0; y < 4; y++) red[grp * MLP_ACC + OFF_V3 + k0 + y] = ax[y];
+    } else if (tile < 12) {
+#pragma unroll
+        for (int y = 0; y < 4; y++) red[grp * MLP_ACC + OFF_B2 + k0 + y] = ax[y];
+    } else if (tile == 12) {
+        red[grp * MLP_ACC + OFF_B3] = ax[0];
+        red[grp * MLP_ACC + MLP_NP] = ax[1];
+    }
+    __syncthreads();
+    const bool two = tid + MLP_T < MLP_ACC;
+    float acc0 = 0.0f, acc1 = 0.0f;
+    for (int g = 0; g < MLP_T / MLP_GROUP; g++) {
+        acc0 += red[g * MLP_ACC + tid];
+        if (two) acc1 += red[g * MLP_ACC + tid + MLP_T];
     }
     float* part = A.partial + (uint64_t)blockIdx.x * MLP_ACC;
     part[tid] = acc0;
@@ -250,7 +324,18 @@ __global__ __launch_bounds__(MLP_T) void k_mlp_step(MlpStep A) {
         const int i = tid + q * MLP_T;
         if (i >= MLP_ACC) continue;
         float g = 0.0f;
-        for (uint32_t b = 0; b < gridDim.x; b++)
+        // 64 loads in flight, added in workgroup order
+        uint32_t b = 0;
+        for (; b + 64 <= gridDim.x; b += 64) {
+            float v[64];
+#pragma unroll
+            for (int u = 0; u < 64; u++)
+                v[u] = __hip_atomic_load(&A.partial[(uint64_t)(b + u) * MLP_ACC + i], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int u = 0; u < 64; u++) g += v[u];
+        }
+        for (; b < gridDim.x; b++)
             g += __hip_atomic_load(&A.partial[(uint64_t)b * MLP_ACC + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         gt[q] = g;
         if (i == MLP_NP) sh_loss = g * inv_s;
