@@ -28,7 +28,7 @@ struct FitArgs {
 };
 
 // MLP training (lsort_mlp.hip)
-constexpr int MLP_G = 256;           // workgroups of a training step (gradient partials)
+constexpr int MLP_G = 512;           // workgroups of a training step (gradient partials; two per CU)
 constexpr int MLP_ACC = MLP_NP + 1;  // gradient entries + the squared error per partial
 
 struct MlpStep {
