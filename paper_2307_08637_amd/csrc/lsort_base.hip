@@ -255,11 +255,12 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
 }
 
 constexpr int BIG_THREADS = 512;
+constexpr int MID_THREADS = 256, MID_MAX = 2048;
 
 // One sub-array of up to BIG_MAX keys: gather into registers (BIG_THREADS * E
 // elements, padded with the largest key), block_bitonic, write back.  The
 // payload follows through the sorted local index, read before any write.
-template <int E>
+template <int E, int NT = BIG_THREADS>
 __device__ void base_big_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, uint64_t* sk, uint32_t* si) {
     const uint64_t* in = P.keys[srcb];
     uint64_t* out = P.keys[0];
@@ -273,7 +274,7 @@ __device__ void base_big_item(const Params& P, uint64_t off, uint32_t size, uint
         ix[e] = i;
     }
     if (P.has_pay) {
-        block_bitonic<BIG_THREADS, E, true>(k, ix, sk, si);
+        block_bitonic<NT, E, true>(k, ix, sk, si);
         const uint32_t* pin = P.pay[srcb];
         uint32_t* pout = P.pay[0];
         uint32_t pv[E];
@@ -284,7 +285,7 @@ __device__ void base_big_item(const Params& P, uint64_t off, uint32_t size, uint
         for (int e = 0; e < E; e++)
             if (t * E + e < size) pout[off + t * E + e] = pv[e];
     } else {
-        block_bitonic<BIG_THREADS, E, false>(k, ix, sk, si);
+        block_bitonic<NT, E, false>(k, ix, sk, si);
     }
 #pragma unroll
     for (int e = 0; e < E; e++)
@@ -323,9 +324,27 @@ __global__ __launch_bounds__(BIG_THREADS) void k_base_big(Params P) {
                 }
             continue;
         }
-        if (size <= 1024) base_big_item<2>(P, off, size, srcb, sk, si);
-        else if (size <= 2048) base_big_item<4>(P, off, size, srcb, sk, si);
-        else if (size <= 4096) base_big_item<8>(P, off, size, srcb, sk, si);
+        // items of up to MID_MAX keys: k_base_mid
+        if (size > MID_MAX && size <= 4096) base_big_item<8>(P, off, size, srcb, sk, si);
+    }
+}
+
+// Items of up to MID_MAX keys (with a payload, or keys with NaN / -0): a
+// quarter-size workgroup per item, so that four items are in flight per CU.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_base_mid(Params P) {
+    __shared__ uint64_t sk[MID_MAX];
+    __shared__ uint32_t si[MID_MAX];
+    const uint64_t nitems = min<unsigned long long>(P.ctl->nbig, P.big_cap);
+    for (uint64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint64_t wd = P.bigs[it];
+        const uint32_t copy = (wd >> 16) & 1u;
+        const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
+        if (copy || size > MID_MAX) continue;
+        const uint64_t off = wd >> 18;
+        const uint32_t srcb = (wd >> 17) & 1u;
+        if (size <= NT * 4) base_big_item<4, NT>(P, off, size, srcb, sk, si);
+        else base_big_item<MID_MAX / NT, NT>(P, off, size, srcb, sk, si);
     }
 }
 
@@ -341,6 +360,7 @@ hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st) {
     LAUNCH((k_base_small<false, false>), grid, BASE_THREADS, st, P);
 }
 hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_base_mid<MID_THREADS>, dim3(grid / 2 * 5), dim3(MID_THREADS), 0, st, P);  // 5 per CU
     hipLaunchKernelGGL(k_base_big<C_MAX>, dim3(grid), dim3(BIG_THREADS), 0, st, P);
     LAUNCH(k_base_big<BIG_MAX>, grid / 2 ? grid / 2 : 1, BIG_THREADS, st, P);
 }
