@@ -76,8 +76,9 @@ typedef struct {
     uint32_t buckets;        /* B of a learned level; default 1000 (Sec. 2.1/2.2); 2..1024 */
     uint32_t leaves;         /* RMI leaves L; default 1000 (Sec. 2.1); 2..1024 */
     uint32_t tree_buckets;   /* splitter-tree fan-out; default 256 (Sec. 4); power of two 2..512 */
-    uint32_t cutoff;         /* base case at or below this many keys; default 512 (one wavefront sorts
-                                up to 512 keys in registers; the paper's CPU base case takes 4096, Sec. 4);
+    uint32_t cutoff;         /* base case at or below this many keys (and the fine resolution of a reused
+                                model: sub-buckets of about cutoff/2 keys); default 1024 for a single array,
+                                512 for the segmented form (the paper's CPU base case takes 4096, Sec. 4);
                                 1..4096 */
     uint32_t max_levels;     /* model-based levels before range radix (8 bits per level) takes over; default 16; 1..23 */
     uint32_t flags;          /* LS_FLAG_* */

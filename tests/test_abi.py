@@ -103,7 +103,8 @@ def test_tuning_table_lookup(tmp_path):
     path = tmp_path / "t.json"
     path.write_text(TABLE % ("gfx950", 256))
     defaults = lsort.tuned_options(10**6, 1)
-    assert defaults["buckets"] == 1000 and defaults["cutoff"] == 512 and defaults["tree_buckets"] == 256
+    assert defaults["buckets"] == 1000 and defaults["cutoff"] == 1024 and defaults["tree_buckets"] == 256
+    assert lsort.tuned_options(10**6, 100)["cutoff"] == 512  # the segmented form's default
     lsort.load_tuning(str(path))
     try:
         assert lsort.tuned_options(10**6, 1) == {"buckets": 512, "cutoff": 512, "tree_buckets": 256, "leaves": 1000}
