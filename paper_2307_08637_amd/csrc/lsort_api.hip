@@ -134,7 +134,7 @@ struct Layout {
     int has_pay;
     uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
     uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_bigs, o_items_b, o_items_c, o_counts, o_status,
-        o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested, o_mlp, o_mlp_t, o_mlp_y;
+        o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested, o_mlp, o_mlp_t, o_mlp_y, o_bstart;
     uint64_t S_big;       // large-path sample size (0: none)
     uint64_t mlp_S;       // MLP training-set size (0: no MLP training)
     uint64_t mlp_stride;  // training set = every mlp_stride-th point of the sorted sample
@@ -233,6 +233,7 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.S_big = big_sample_size(n, m, o);
     if (L.S_big) {
         L.o_sample = take(L.S_big * 8);
+        L.o_bstart = take((B_MAX + 1) * 8);
         L.nested.push_back(plan(L.S_big, 1, 0, nested_opts(o)));
         L.o_nested = take(L.nested[0].bytes);
     }
@@ -427,6 +428,7 @@ static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
     P.status_cap = L.status_cap; P.arena_cap = L.arena_cap; P.item_b_cap = L.item_b_cap; P.item_c_cap = L.item_c_cap;
     P.persist = (const uint64_t*)(base + L.o_persist);
     P.fsample = L.S_big ? (const uint64_t*)(base + L.o_sample) : nullptr;
+    P.fbstart = L.S_big ? (const uint64_t*)(base + L.o_bstart) : nullptr;
     P.fS = L.S_big;
     P.level = 0;
     return P;
@@ -519,6 +521,8 @@ static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPoo
     }
     TIMED(KI_FIT, c.st, launch_fit_leaves(A, c.st));
     TIMED(KI_FIT, c.st, launch_fit_finish(A, c.st));
+    A.bstart = (uint64_t*)(base + L.o_bstart);
+    TIMED(KI_FIT, c.st, launch_fit_bstart(A, c.st));
     return LS_OK;
 }
 

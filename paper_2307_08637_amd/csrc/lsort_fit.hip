@@ -239,6 +239,24 @@ __global__ __launch_bounds__(FIT_LT) void k_fit_leaves(FitArgs A) {
     }
 }
 
+// Where each first-level bucket starts in the sorted sample: bstart[b] = the
+// first i with bucket(s[i]) >= b (S if none), for b in [0, B1].  The buckets
+// of the sorted sample do not decrease (monotone model), so each entry is
+// written once, by the sample key at which the bucket sequence passes b.
+// Only for the RMI chosen by the policy (the fallback trees of its buckets
+// take their samples from these runs).
+__global__ __launch_bounds__(FIT_T) void k_fit_bstart(FitArgs A) {
+    if (!A.bstart || A.flag[0] == 0 || (A.first_mlp && *A.first_mlp)) return;
+    const uint32_t sh2 = A.log2B2;
+    for (uint64_t i = (uint64_t)blockIdx.x * FIT_T + threadIdx.x; i < A.S; i += (uint64_t)gridDim.x * FIT_T) {
+        const uint32_t g = rmi_stored_bucket(A.model, A.s[i], A.u64) >> sh2;
+        const int64_t gp = i ? (int64_t)(rmi_stored_bucket(A.model, A.s[i - 1], A.u64) >> sh2) : -1;
+        for (int64_t b = gp + 1; b <= (int64_t)g; b++) A.bstart[b] = i;
+        if (i == A.S - 1)
+            for (uint32_t b = g + 1; b <= A.B1; b++) A.bstart[b] = A.S;
+    }
+}
+
 // Monotone clamp intervals (Sec. 4) via a prefix maximum, then pre-scaling
 // by the total resolution R.  One workgroup of 1024 threads (L <= 1024).
 __global__ __launch_bounds__(M_THREADS) void k_fit_finish(FitArgs A) {
@@ -361,6 +379,10 @@ hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st) {
     LAUNCH(k_fit_leaves, A.L, FIT_LT, st, A);
 }
 hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_finish, 1, M_THREADS, st, A); }
+hipError_t launch_fit_bstart(const FitArgs& A, hipStream_t st) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((A.S + FIT_T - 1) / FIT_T, 2048ull);
+    LAUNCH(k_fit_bstart, grid ? grid : 1, FIT_T, st, A);
+}
 hipError_t launch_model_buckets(const uint64_t* model, uint32_t words, uint32_t kind, uint32_t nb, uint32_t win,
                                 const uint64_t* keys, uint64_t n, int u64, uint32_t* out, hipStream_t st) {
     uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 2048ull);

@@ -182,6 +182,7 @@ struct Params {
     uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
     const uint64_t* persist;        // [0] call epoch, [1] clear-status request (survives calls)
     const uint64_t* fsample;        // sorted first-level sample of a large array (raw keys), or null
+    const uint64_t* fbstart;        // [B1 + 1]: first sample index of each first-level bucket
     uint64_t fS;                    // its size
     int level;
 };

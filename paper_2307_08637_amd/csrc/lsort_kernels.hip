@@ -281,70 +281,12 @@ __device__ void sample_sort(uint64_t* smp, const uint64_t* src, uint64_t off, ui
     __syncthreads();
 }
 
-// First indices A0, A1 of the sorted sample fs[0..S) whose bucket under the
-// stored RMI pm at the parent's resolution (bucket = g >> log2B2) is >= b and
-// >= b + 1 (S if none); the buckets of the sorted sample do not decrease.
-// Coarse-to-fine: each round the workgroup tests M_THREADS evenly spaced
-// positions of each target's current range (one shared set in the first
-// round), so a 1e6-key sample takes two rounds.  The first qualifying probe
-// is the one whose left neighbour does not qualify (pf: M_THREADS flags).
-__device__ void sample_bounds(const uint64_t* fs, uint64_t S, const uint64_t* pm, uint32_t b, int u64, uint64_t* sh,
-                              uint32_t* pf, uint64_t& A0, uint64_t& A1) {
-    const uint32_t sh2 = ((const RmiModel*)pm)->log2B2;
-    const uint32_t t = threadIdx.x;
-    uint64_t lo[2] = {0, 0}, hi[2] = {S, S};  // answer q in [lo[q], hi[q]]
-    bool done[2] = {S == 0, S == 0};
-    A0 = A1 = 0;
-    for (int round = 0; !(done[0] && done[1]); round++) {
-        uint64_t st[2];
-#pragma unroll
-        for (int q = 0; q < 2; q++) st[q] = done[q] ? 1 : (hi[q] - lo[q] + M_THREADS - 1) / M_THREADS;
-        __syncthreads();
-        if (t < 2) sh[t] = hi[t];
-        uint64_t ip[2];
-        uint32_t f = 0;  // bit q: probe t qualifies for target q
-        if (round == 0) {  // both ranges are [0, S]: one evaluation per probe serves both targets
-            ip[0] = ip[1] = (uint64_t)t * st[0];
-            if (ip[0] < S) {
-                const uint32_t g = rmi_stored_bucket(pm, fs[ip[0]], u64) >> sh2;
-                f = (g >= b ? 1u : 0u) | (g >= b + 1 ? 2u : 0u);
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 2; q++) {
-                ip[q] = lo[q] + (uint64_t)t * st[q];
-                if (!done[q] && ip[q] < hi[q] && (rmi_stored_bucket(pm, fs[ip[q]], u64) >> sh2) >= b + q) f |= 1u << q;
-            }
-        }
-        pf[t] = f;
-        __syncthreads();
-        const uint32_t fl = t ? pf[t - 1] : 0u;
-#pragma unroll
-        for (int q = 0; q < 2; q++)
-            if ((f >> q & 1u) && !(fl >> q & 1u)) sh[q] = ip[q];  // at most one thread per target
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 2; q++) {
-            if (done[q]) continue;
-            const uint64_t fq = sh[q];  // first tested position that qualifies (or hi)
-            if (st[q] <= 1 || fq == lo[q]) {
-                (q ? A1 : A0) = fq;
-                done[q] = true;
-            } else {  // after the last tested position below fq
-                lo[q] = (fq - lo[q] - 1) / st[q] * st[q] + lo[q] + 1;
-                hi[q] = fq;
-                if (hi[q] == lo[q]) { (q ? A1 : A0) = fq; done[q] = true; }
-            }
-        }
-    }
-}
-
-// The first-level sample's keys in parent bucket b, as ordered keys in smp[]
+// The first-level sample's keys in parent bucket b (the run
+// [bstart[b], bstart[b+1]) that k_fit_bstart found), as ordered keys in smp[]
 // (evenly thinned to S_LDS when more); returns their number.
-__device__ uint32_t sample_slice(uint64_t* smp, const uint64_t* fs, uint64_t S, const uint64_t* pm, uint32_t b, int u64,
-                                 uint64_t* sh, uint32_t* pf) {
-    uint64_t lo, hi;
-    sample_bounds(fs, S, pm, b, u64, sh, pf, lo, hi);
+__device__ uint32_t sample_slice(uint64_t* smp, const uint64_t* fs, uint64_t S, const uint64_t* bstart, uint32_t b,
+                                 int u64) {
+    const uint64_t lo = min(bstart[b], S), hi = min(bstart[b + 1], S);
     const uint64_t cnt = hi > lo ? hi - lo : 0;
     const uint32_t m = (uint32_t)min<uint64_t>(cnt, S_LDS);
     for (uint32_t k = threadIdx.x; k < m; k += M_THREADS)
@@ -405,8 +347,8 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             // a fallback child of a large array's first level: the first-level
             // sample's keys in the parent bucket are already a sorted random
             // sample of this segment (about 1% of it)
-            const uint32_t Sf = (sg.flags & SEG_FROM_SAMPLE) && P.fsample
-                                    ? sample_slice(smp, P.fsample, P.fS, (const uint64_t*)sg.model, sg.win, u64, shv, lstart)
+            const uint32_t Sf = (sg.flags & SEG_FROM_SAMPLE) && P.fsample && P.fbstart
+                                    ? sample_slice(smp, P.fsample, P.fS, P.fbstart, sg.win, u64)
                                     : 0u;
             if (Sf >= 2) {
                 S = Sf;

@@ -25,6 +25,7 @@ struct FitArgs {
     uint32_t* flag;      // [0] = 1 when the learned model was chosen
     Seg* seg;            // descriptor of the prebuilt first level (nullable)
     uint32_t* first_mlp; // set to 1 when the MLP-rooted model was chosen (nullable)
+    uint64_t* bstart;    // [B1 + 1]: first sample index of each first-level bucket (nullable)
 };
 
 // MLP training (lsort_mlp.hip)
@@ -73,6 +74,7 @@ hipError_t launch_fit2(const FitArgs& A, hipStream_t st);
 hipError_t launch_fit_root(const FitArgs& A, hipStream_t st);
 hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st);
 hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st);
+hipError_t launch_fit_bstart(const FitArgs& A, hipStream_t st);
 hipError_t launch_model_buckets(const uint64_t* model, uint32_t words, uint32_t kind, uint32_t nb, uint32_t win,
                                 const uint64_t* keys, uint64_t n, int u64, uint32_t* out, hipStream_t st);
 hipError_t launch_install_rmi(const double* params, uint32_t L, double R, uint32_t B1, uint32_t log2B2, uint64_t* dst,
