@@ -20,6 +20,11 @@ __global__ void k_gather(const uint64_t* keys, uint64_t n, uint64_t seed, uint64
 // sum (x - mean)^2, centred sum (x - mean)(y - mean y).
 // ---------------------------------------------------------------------------
 
+// In every pass below a thread visits its indices i0, i0 + T, i0 + 2T, ... in
+// that order (T: threads of the workgroup) and adds in that order; FIT_LU of
+// its keys are loaded before any of them is used.
+constexpr int FIT_LU = 8;
+
 __global__ __launch_bounds__(FIT_T) void k_fit1(FitArgs A) {
     __shared__ double red[FIT_T / 64];
     __shared__ uint64_t red64[FIT_T / 64];
@@ -27,12 +32,23 @@ __global__ __launch_bounds__(FIT_T) void k_fit1(FitArgs A) {
     const uint64_t lo = blockIdx.x * chunk, hi = min(A.S, lo + chunk);
     double sx = 0;
     uint64_t dup = 0, nf = 0;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_T) {
-        uint64_t r = A.s[i];
-        double x;
-        if (key_x(r, A.u64, x)) nf++;
-        else sx += x;
-        if (i > 0) dup += key_ord(r, A.u64) == key_ord(A.s[i - 1], A.u64);
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)FIT_T * FIT_LU) {
+        uint64_t r[FIT_LU], rp[FIT_LU];
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++) {
+            const uint64_t i = i0 + (uint64_t)u * FIT_T;
+            r[u] = i < hi ? A.s[i] : 0;
+            rp[u] = i < hi && i > 0 ? A.s[i - 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++) {
+            const uint64_t i = i0 + (uint64_t)u * FIT_T;
+            if (i >= hi) continue;
+            double x;
+            if (key_x(r[u], A.u64, x)) nf++;
+            else sx += x;
+            if (i > 0) dup += key_ord(r[u], A.u64) == key_ord(rp[u], A.u64);
+        }
     }
     sx = block_sum<FIT_T, double>(sx, red);
     dup = block_sum<FIT_T, uint64_t>(dup, red64);
@@ -55,12 +71,19 @@ __global__ __launch_bounds__(FIT_T) void k_fit2(FitArgs A) {
     const uint64_t chunk = (A.S + gridDim.x - 1) / gridDim.x;
     const uint64_t lo = blockIdx.x * chunk, hi = min(A.S, lo + chunk);
     double sxx = 0, sxy = 0;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_T) {
-        double x;
-        if (key_x(A.s[i], A.u64, x)) continue;
-        double dx = x - mx, dy = (double)i / Sd - my;
-        sxx += dx * dx;
-        sxy += dx * dy;
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)FIT_T * FIT_LU) {
+        uint64_t r[FIT_LU];
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++) r[u] = i0 + (uint64_t)u * FIT_T < hi ? A.s[i0 + (uint64_t)u * FIT_T] : 0;
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++) {
+            const uint64_t i = i0 + (uint64_t)u * FIT_T;
+            double x;
+            if (i >= hi || key_x(r[u], A.u64, x)) continue;
+            double dx = x - mx, dy = (double)i / Sd - my;
+            sxx += dx * dx;
+            sxy += dx * dy;
+        }
     }
     sxx = block_sum<FIT_T, double>(sxx, red);
     sxy = block_sum<FIT_T, double>(sxy, red);
@@ -213,14 +236,30 @@ __global__ __launch_bounds__(FIT_LT) void k_fit_leaves(FitArgs A) {
     if (hi > lo) {
         const double cnt = (double)(hi - lo);
         double s = 0;
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_LT) { double x; key_x(A.s[i], A.u64, x); s += x; }
+        for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)FIT_LT * FIT_LU) {
+            uint64_t r[FIT_LU];
+#pragma unroll
+            for (int u = 0; u < FIT_LU; u++) r[u] = i0 + (uint64_t)u * FIT_LT < hi ? A.s[i0 + (uint64_t)u * FIT_LT] : 0;
+#pragma unroll
+            for (int u = 0; u < FIT_LU; u++)
+                if (i0 + (uint64_t)u * FIT_LT < hi) { double x; key_x(r[u], A.u64, x); s += x; }
+        }
         s = block_sum<FIT_LT, double>(s, red);
         const double mx = s / cnt, my = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
         double sxx = 0, sxy = 0;
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += FIT_LT) {
-            double x; key_x(A.s[i], A.u64, x);
-            double dx = x - mx, dy = (double)i * invS - my;
-            sxx += dx * dx; sxy += dx * dy;
+        for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)FIT_LT * FIT_LU) {
+            uint64_t r[FIT_LU];
+#pragma unroll
+            for (int u = 0; u < FIT_LU; u++) r[u] = i0 + (uint64_t)u * FIT_LT < hi ? A.s[i0 + (uint64_t)u * FIT_LT] : 0;
+#pragma unroll
+            for (int u = 0; u < FIT_LU; u++) {
+                const uint64_t i = i0 + (uint64_t)u * FIT_LT;
+                if (i < hi) {
+                    double x; key_x(r[u], A.u64, x);
+                    double dx = x - mx, dy = (double)i * invS - my;
+                    sxx += dx * dx; sxy += dx * dy;
+                }
+            }
         }
         sxx = block_sum<FIT_LT, double>(sxx, red);
         sxy = block_sum<FIT_LT, double>(sxy, red);
