@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # Algorithmic bytes each kernel must move per key it processes (keys only,
-# float64): read + write of the keys; see the design doc.
+# float64): k_hist reads each key once (8 B); the scatter and the base-case
+# sorts read it and write it once (16 B).
 BYTES_PER_KEY = {"k_hist": 8.0, "k_scatter": 16.0, "k_base_small": 16.0, "k_base_big": 16.0}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2307_08637_amd", "csrc", f)
