@@ -34,6 +34,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # float64): k_hist reads each key once (8 B); the scatter and the base-case
 # sorts read it and write it once (16 B).
 BYTES_PER_KEY = {"k_hist": 8.0, "k_scatter": 16.0, "k_base_small": 16.0, "k_base_big": 16.0}
+STREAM_OF = {"k_hist": "read", "k_scatter": "copy", "k_base_small": "copy", "k_base_big": "copy"}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2307_08637_amd", "csrc", f)
                   for f in ("lsort_kernels.hip", "lsort_dev.hpp", "lsort_internal.hpp")]
@@ -130,6 +131,8 @@ def main():
 
     log("learned", a.steps, "steps")
     L = run("auto", a.steps, bufs)
+    log("reference streams")
+    cal = calibrate(base, warm, lsort, torch, a.steps)
     S = None
     if not a.no_splitter:
         log("splitter", a.steps, "steps")
@@ -212,7 +215,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_key": BYTES_PER_KEY[dom], "avg_launch_ms": round(avg_ms, 4),
-                     "launches": dk["launches"]},
+                     "launches": dk["launches"],
+                     # against the reference stream of the same access pattern
+                     "frac_of_stream": round(achieved / cal[STREAM_OF[dom]]["GB/s"], 4)},
+        "streams": cal,
         "cpu_baseline": cpu,
         "splitter": None if S is None else {"value": round(gk(S), 4), "ms_per_step": round(S["ms_per_step"], 4),
                                             "levels": level_summary(S["stats"])},
@@ -226,6 +232,33 @@ def main():
         "learned_parts": mlp,
     }
     print(json.dumps(out), flush=True)
+
+
+def calibrate(src, dst, lsort, torch, reps):
+    """The library's reference streams over the benchmark's key buffer: a
+    copy (read + write of every word) and a read-only sum, timed with HIP
+    events on the stream they run on; the practical ceilings of a scatter /
+    base-case pass and of a histogram pass."""
+    nbytes = src.numel() * 8
+    out = torch.empty(2, dtype=torch.uint64, device=src.device)
+    for _ in range(2):
+        lsort.stream_copy(src, dst)
+        lsort.stream_read(src, out)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        lsort.stream_copy(src, dst)
+    e[1].record()
+    for _ in range(reps):
+        lsort.stream_read(src, out)
+    e[2].record()
+    torch.cuda.synchronize()
+    copy_ms, read_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+    copy_gbs, read_gbs = 2 * nbytes / copy_ms / 1e6, nbytes / read_ms / 1e6
+    return {"bytes": nbytes,
+            "copy": {"ms": round(copy_ms, 4), "GB/s": round(copy_gbs, 1), "frac": round(copy_gbs / HBM_PEAK_GBS, 4)},
+            "read": {"ms": round(read_ms, 4), "GB/s": round(read_gbs, 1), "frac": round(read_gbs / HBM_PEAK_GBS, 4)}}
 
 
 def run_batched(inputs, lsort, torch, np, dev, log):

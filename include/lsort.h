@@ -326,6 +326,18 @@ ls_status ls_mlp_rmi_buckets(const void *keys, uint64_t n, ls_dtype dtype, const
                              const double *lo_inv, const double *leaves, uint32_t L, double R,
                              uint32_t *out, void *stream);
 
+/* Reference streams (not steps of the sort): the practical ceilings that the
+ * sort's passes are measured against.  ls_stream_copy copies n 8-byte words
+ * from src to dst (one read and one write per word, as in a partition
+ * scatter or the base case); ls_stream_read reads n words and writes their
+ * wrapping sum (mod 2^64) to *sum (one read per word, as in the histogram
+ * pass; *sum is 0 when n == 0; a copy of n == 0 words does nothing).
+ * src, dst: device, 8-byte aligned, not overlapping; sum: device uint64.
+ * Asynchronous on `stream`; nothing is allocated.
+ * Errors: LS_EINVAL (NULL pointer with n > 0, misalignment, n >= 2^45). */
+ls_status ls_stream_copy(const void *src, void *dst, uint64_t n, void *stream);
+ls_status ls_stream_read(const void *src, uint64_t n, uint64_t *sum, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

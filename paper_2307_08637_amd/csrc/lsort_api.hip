@@ -1090,6 +1090,35 @@ ls_status ls_mlp_rmi_buckets(const void* keys, uint64_t n, ls_dtype dtype, const
     return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
 }
 
+static ls_status stream_args(const void* a, const void* b, uint64_t n, const char* name, uint32_t& cus) {
+    if (n > 0 && (!a || !b)) return fail(LS_EINVAL, std::string(name) + ": NULL pointer with n > 0");
+    if (((uintptr_t)a | (uintptr_t)b) & 7) return fail(LS_EINVAL, std::string(name) + ": pointers must be 8-byte aligned");
+    if (n >= (1ull << 45)) return fail(LS_EINVAL, std::string(name) + ": n too large");
+    int dev = 0, c = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+    cus = (uint32_t)std::max(c, 1);
+    return LS_OK;
+}
+
+ls_status ls_stream_copy(const void* src, void* dst, uint64_t n, void* stream) {
+    if (n == 0) return LS_OK;
+    uint32_t cus = 0;
+    ls_status s = stream_args(src, dst, n, "ls_stream_copy", cus);
+    if (s) return s;
+    HIP_TRY(launch_stream_copy((const uint64_t*)src, (uint64_t*)dst, n, cus, (hipStream_t)stream));
+    return LS_OK;
+}
+
+ls_status ls_stream_read(const void* src, uint64_t n, uint64_t* sum, void* stream) {
+    uint32_t cus = 0;
+    if (!sum) return fail(LS_EINVAL, "ls_stream_read: sum is NULL");
+    ls_status s = stream_args(n ? src : sum, sum, n, "ls_stream_read", cus);
+    if (s) return s;
+    HIP_TRY(launch_stream_read((const uint64_t*)src, n, sum, cus, (hipStream_t)stream));
+    return LS_OK;
+}
+
 ls_status ls_tuned_options(uint64_t n_total, uint64_t m, ls_options* out) {
     if (!out) return fail(LS_EINVAL, "out is NULL");
     Opts o;

@@ -111,4 +111,8 @@ void tuning_install(const std::vector<TuneEntry>& t);
 int report_error(int status, const char* msg);  // sets ls_last_error(), returns status
 hipError_t launch_tune_fill(double* keys, const uint64_t* offsets, uint64_t m, uint64_t seed, hipStream_t st);
 
+// reference streams (lsort_stream.hip): copy of n words; wrapping sum of n words into *sum
+hipError_t launch_stream_copy(const uint64_t* src, uint64_t* dst, uint64_t n, uint32_t cus, hipStream_t st);
+hipError_t launch_stream_read(const uint64_t* src, uint64_t n, uint64_t* sum, uint32_t cus, hipStream_t st);
+
 }  // namespace ls

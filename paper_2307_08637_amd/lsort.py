@@ -84,6 +84,8 @@ def lib():
             "ls_timing": [i32],
             "ls_timing_read": [vp, u32, vp],
             "ls_timing_records": [vp, u32, vp],
+            "ls_stream_copy": [vp, vp, u64, vp],
+            "ls_stream_read": [vp, u64, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -361,6 +363,27 @@ def timing_records(cap: int = 4096) -> list:
     cnt = C.c_uint32()
     _check(lib().ls_timing_records(buf, cap, C.byref(cnt)))
     return [(buf[i].name.decode(), buf[i].ms, buf[i].keys) for i in range(cnt.value)]
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """Reference copy of src's 8-byte words into dst (same size, 8-byte aligned)."""
+    _dev(src, "src")
+    _dev(dst, "dst")
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size() or src.element_size() != 8:
+        raise ValueError("stream_copy needs two tensors of the same number of 8-byte elements")
+    _check(lib().ls_stream_copy(_ptr(src), _ptr(dst), src.numel(), _stream()))
+
+
+def stream_read(src: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Reference read of src's 8-byte words; returns a one-element uint64
+    device tensor holding their sum mod 2^64."""
+    _dev(src, "src")
+    if src.element_size() != 8:
+        raise ValueError("stream_read needs 8-byte elements")
+    if out is None:
+        out = torch.empty(2, dtype=torch.uint64, device=src.device)
+    _check(lib().ls_stream_read(_ptr(src), src.numel(), _ptr(out), _stream()))
+    return out[:1]
 
 
 def version() -> str:

@@ -71,6 +71,19 @@ def test_argument_errors_without_gpu():
     assert lib.ls_sort(C.c_void_p(64), 1, 1, None, None, None) == 0
 
 
+def test_stream_argument_errors_without_gpu():
+    from paper_2307_08637_amd import lsort
+    lib = lsort.lib()
+    assert lib.ls_stream_copy(None, None, 5, None) == -1
+    assert b"NULL" in lib.ls_last_error()
+    assert lib.ls_stream_copy(C.c_void_p(64), C.c_void_p(68), 5, None) == -1
+    assert b"aligned" in lib.ls_last_error()
+    assert lib.ls_stream_read(C.c_void_p(64), 5, None, None) == -1
+    assert lib.ls_stream_read(C.c_void_p(12), 5, C.c_void_p(64), None) == -1
+    assert b"aligned" in lib.ls_last_error()
+    assert lib.ls_stream_copy(None, None, 0, None) == 0
+
+
 def test_workspace_bytes_host_only():
     from paper_2307_08637_amd import lsort
     small = lsort.workspace_bytes(10**6)
