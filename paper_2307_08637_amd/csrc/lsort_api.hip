@@ -353,7 +353,7 @@ static ls_status acquire(uint64_t bytes, const Layout& L, DevPool*& pool, uint8_
     if (!pool->cus) {
         HIP_TRY(hipDeviceGetAttribute(&pool->cus, hipDeviceAttributeMultiprocessorCount, dev));
         HIP_TRY(hipEventCreateWithFlags(&pool->last, hipEventDisableTiming));
-        HIP_TRY(hipHostMalloc((void**)&pool->pinned, 4096, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&pool->pinned, std::max<size_t>(4096, sizeof(Ctl)), hipHostMallocDefault));
     }
     if (pool->user) {
         if (bytes > pool->user_bytes)
@@ -566,17 +566,16 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
             continue;
         }
         if (fixed) continue;
-        // read back the next level's work, the overflow flags and this level's keys
-        Ctl* ctl = P.ctl;
-        HIP_TRY(hipMemcpyAsync(pool->pinned, &ctl->nseg[lvl + 1], 4, hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 8, &ctl->overflow, 4, hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 16, &ctl->lv[lvl].keys, 8, hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipMemcpyAsync((uint8_t*)pool->pinned + 24, &ctl->nres[lvl + 1], 4, hipMemcpyDeviceToHost, c.st));
+        // read back the next level's work, the overflow flags and this level's
+        // keys: the whole control block in one copy (one copy dispatch instead
+        // of one per field)
+        HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
-        uint32_t next = ((uint32_t*)pool->pinned)[0];
-        uint32_t ovf = ((uint32_t*)pool->pinned)[2];
-        double lkeys = (double)((uint64_t*)pool->pinned)[2];
-        next_res = ((uint32_t*)pool->pinned)[6];
+        const Ctl* hc = (const Ctl*)pool->pinned;
+        uint32_t next = hc->nseg[lvl + 1];
+        uint32_t ovf = hc->overflow;
+        double lkeys = (double)hc->lv[lvl].keys;
+        next_res = hc->nres[lvl + 1];
         for (size_t i = rec0; i < g_trec.size(); i++) g_trec[i].keys = lkeys;
         if (ovf) return fail(LS_ENOMEM, "workspace capacity exceeded:" + overflow_text(ovf));
         if (next == 0) break;
@@ -586,11 +585,11 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         TIMED(KI_BASE, c.st, launch_base_small(P, cus * 8, c.st));
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
         if (g_timing) {  // keys through the base case (both kernels) and the copies
-            HIP_TRY(hipMemcpyAsync(pool->pinned, &P.ctl->small_keys, 8, hipMemcpyDeviceToHost, c.st));
-            HIP_TRY(hipMemcpyAsync(pool->pinned + 1, &P.ctl->big_keys, 8, hipMemcpyDeviceToHost, c.st));
+            HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));
-            g_trec[g_trec.size() - 2].keys = (double)pool->pinned[0];
-            g_trec.back().keys = (double)pool->pinned[1];
+            const Ctl* hc = (const Ctl*)pool->pinned;
+            g_trec[g_trec.size() - 2].keys = (double)hc->small_keys;
+            g_trec.back().keys = (double)hc->big_keys;
         }
     }
     return LS_OK;
