@@ -11,7 +11,7 @@ namespace ls {
 // Random sample with replacement (Sec. 2.2: ~1% sample; Alg. 5 Sample).
 __global__ void k_gather(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t S, uint64_t* out) {
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S; k += (uint64_t)gridDim.x * blockDim.x)
-        out[k] = keys[sample_index(seed, k, n)];
+        out[k] = __builtin_nontemporal_load(keys + sample_index(seed, k, n));
 }
 
 // ---------------------------------------------------------------------------
