@@ -947,7 +947,7 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                 k[r] = i < un ? src[ubase + i] : 0;
                 pl[r] = i < un ? psrc[ubase + i] : 0;
             } else {
-                k[r] = src[ubase + min(i, un - 1)];
+                k[r] = __builtin_nontemporal_load(src + ubase + min(i, un - 1));
             }
         }
         // the first tile's keys have arrived before the loop, so that inside
@@ -984,7 +984,7 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
                 const uint32_t nn = more ? min<uint32_t>(TILE, un - (tt + 1) * TILE) : 1u;
                 const uint32_t lim = more ? nn - 1 : 0u;
 #pragma unroll
-                for (int r = 0; r < SK; r++) kn[r] = src[base + (more ? TILE : 0) + min<uint32_t>(w * SWK + r * WAVE + lane, lim)];
+                for (int r = 0; r < SK; r++) kn[r] = __builtin_nontemporal_load(src + base + (more ? TILE : 0) + min<uint32_t>(w * SWK + r * WAVE + lane, lim));
             }
             if (PAY) {
                 // stable rank within the wave: rounds in key order, lanes in key order
