@@ -64,7 +64,13 @@ typedef enum {
 /* Option flags. */
 #define LS_FLAG_NO_FALLBACK   0x1u  /* never replace an oversized learned bucket's model by a splitter tree */
 #define LS_FLAG_SYNC_LEVELS   0x2u  /* (host) read back the work count after each level to stop early; default on */
-#define LS_FLAG_FIXED_LEVELS  0x4u  /* launch exactly max_levels levels with no host read-back (graph capture) */
+#define LS_FLAG_FIXED_LEVELS  0x4u  /* no host read-back: launch every level the depth cap allows,
+                                       min(max_levels + 9, 31) (max_levels model-based levels, then up to
+                                       8 range-radix levels and one more), each exiting at once when it
+                                       has no work; needed for stream capture.  The host cannot see a
+                                       workspace overflow then: read ls_get_stats().overflow after the
+                                       call (or after a graph replay); nonzero means the output is
+                                       invalid */
 #define LS_FLAG_COLLECT_STATS 0x8u  /* record per-level statistics (read with ls_get_stats) */
 #define LS_FLAG_TUNED         0x10u /* take buckets / cutoff / tree_buckets left 0 from the loaded tuning table */
 
@@ -117,6 +123,11 @@ typedef struct {
     uint64_t copy_items;     /* finished runs copied back to the caller's buffer */
     double mlp_loss_first;   /* MLP training: loss at step 1 and at the last step */
     double mlp_loss_last;
+    uint32_t overflow;       /* nonzero: a workspace capacity was exceeded and some sub-arrays were left
+                                unsorted (the call returned LS_ENOMEM, or with LS_FLAG_FIXED_LEVELS could
+                                not tell); bits: 1 segments, 2 work units, 4 base-case items, 8 bucket
+                                counts, 16 look-back words, 32 model arena, 64 look-back sequence */
+    uint32_t reserved;
     ls_level_stats level[LS_MAX_STAT_LEVELS];
 } ls_stats;
 
@@ -145,12 +156,22 @@ ls_status ls_workspace_bytes(uint64_t n_total, uint64_t m, ls_dtype dtype, int h
 
 /* Use caller memory (device, 256-byte aligned) as the workspace of later
  * calls on this device; dev_ptr = NULL returns to the library's own pool.
+ * The memory is cleared on `stream` (after every earlier call that used the
+ * previous workspace), and later calls on any stream are ordered after that.
  * The library never allocates while a workspace is set: a call that needs
- * more than `bytes` fails with LS_ENOMEM. */
-ls_status ls_set_workspace(void *dev_ptr, size_t bytes);
+ * more than `bytes` fails with LS_ENOMEM.  Required before stream capture: a
+ * call made while its stream is capturing fails with LS_EINVAL unless a
+ * workspace is set (the library's own pool may be reallocated by a later
+ * eager call, which a captured graph would not see).  The caller keeps the
+ * memory alive while any graph captured with it exists; a replay must not
+ * overlap another call that uses the same workspace.  Must itself be called
+ * outside capture.  Errors: LS_EINVAL, LS_EHIP. */
+ls_status ls_set_workspace(void *dev_ptr, size_t bytes, void *stream);
 
-/* Statistics of the last completed call made with LS_FLAG_COLLECT_STATS on
- * this thread.  Waits for that call's stream. out: host. */
+/* Statistics of the last call on this thread (per-level counts only when it
+ * set LS_FLAG_COLLECT_STATS; `overflow` always), read from its workspace, so
+ * after a graph replay they are the replay's.  Waits for that call's stream.
+ * out: host. */
 ls_status ls_get_stats(ls_stats *out);
 
 /* Message for the last non-OK status on this thread (never NULL). */
@@ -232,6 +253,15 @@ ls_status ls_sample(const void *keys, uint64_t n, ls_dtype dtype, uint64_t seed,
  * S >= 2, 2 <= L <= 1024. */
 ls_status ls_rmi_fit(const void *sorted_sample, uint64_t S, ls_dtype dtype, uint32_t L, double R,
                      double *params, void *stream);
+
+/* The same fit (Sec. 2.1 RMI, Sec. 4 monotone clamp) by the one-workgroup
+ * kernel that builds the model of every segment whose sample fits on chip:
+ * the sample is held in LDS, sums run in a workgroup's reduction order.
+ * Same output layout as ls_rmi_fit.  Requires 2 <= S <= 16384, 2 <= L <= 1024
+ * and an integer R in [1, 2^32).  sorted_sample, params: device.
+ * Errors: LS_EINVAL, LS_ENOMEM, LS_EHIP. */
+ls_status ls_rmi_fit_block(const void *sorted_sample, uint64_t S, ls_dtype dtype, uint32_t L, double R,
+                           double *params, void *stream);
 
 /* Bucket ids of keys under RMI params (the layout ls_rmi_fit writes):
  * j = clamp(floor(fma(alpha_r, x, beta_r)), 0, L-1),

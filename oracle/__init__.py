@@ -78,6 +78,11 @@ def lib():
             "orc_radix_buckets": (None, [vp, u32, vp, u64, i32, vp]),
             "orc_mlp_buckets": (None, [vp, dbl, dbl, u32, vp, u64, i32, vp]),
             "orc_mlp_init": (None, [vp, u64, dbl, vp]),
+            "orc_mlp_step_scale": (None, [vp, vp]),
+            "orc_mlp_effective": (None, [vp, vp]),
+            "orc_mlp_lo_inv": (None, [vp, u64, i32, vp]),
+            "orc_model_x_array": (None, [vp, u64, i32, vp]),
+            "orc_mlp_train": (None, [vp, vp, u64, vp, u32, dbl, i32, vp, vp]),
             "orc_mlp_inputs": (None, [vp, u64, i32, dbl, dbl, vp]),
             "orc_mlp_leaf": (u32, [vp, dbl, dbl, u32, dbl]),
             "orc_mlp_rmi_fit": (None, [vp, u64, vp, dbl, dbl, u32, dbl, vp, vp, vp]),
@@ -176,10 +181,11 @@ def policy_learned(n: int, sorted_sample: np.ndarray, large_n: float = 1e5, dup_
 # -- 5. RMI ------------------------------------------------------------------------
 
 def model_x(keys: np.ndarray) -> np.ndarray:
-    """Model input of every key (finite keys only)."""
-    if keys.dtype == np.uint64:
-        return keys.astype(np.float64)
-    return np.ascontiguousarray(keys, dtype=np.float64)
+    """Model input of every key (orc_model_x; NaN for a non-finite key)."""
+    r = raw_bits(keys)
+    out = np.empty(r.size)
+    lib().orc_model_x_array(_p(r), r.size, dtype_code(keys), _p(out))
+    return out
 
 
 def rmi_fit(sorted_x: np.ndarray, L: int, R: float, root=None):
@@ -317,52 +323,41 @@ def mlp_inputs(keys: np.ndarray, lo: float, inv: float) -> np.ndarray:
 
 
 def mlp_lo_inv(sorted_keys: np.ndarray):
-    """(lo, inv) of the model input from a sorted sample: smallest key and
-    1 / (largest - smallest), or inv = 0 when they are equal."""
-    x = model_x(sorted_keys[[0, -1]])
-    return float(x[0]), (1.0 / (x[1] - x[0]) if x[1] > x[0] else 0.0)
+    """(lo, inv) of the model input from a sorted sample (orc_mlp_lo_inv)."""
+    r = raw_bits(sorted_keys)
+    out = np.empty(2)
+    lib().orc_mlp_lo_inv(_p(r), r.size, dtype_code(sorted_keys), _p(out))
+    return float(out[0]), float(out[1])
 
 
 def effective(params: np.ndarray) -> np.ndarray:
-    """fp32 effective weights |V| with the biases as they are."""
-    p = np.array(params, dtype=np.float64)
-    for a, b in ((0, 16), (32, 288), (304, 320)):
-        p[a:b] = np.abs(p[a:b])
-    return p.astype(np.float32)
+    """fp32 effective weights (orc_mlp_effective)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    w = np.empty(MLP_NP, dtype=np.float32)
+    lib().orc_mlp_effective(_p(p), _p(w))
+    return w
 
 
 def mlp_step_scale(p0: np.ndarray) -> np.ndarray:
-    """Optimiser step scale of each parameter: for a layer-2 weight of input
-    unit k, 1 / max(1, |V1_k| + |b1_k|) -- the bound of unit k's activation
-    on t in [0, 1] at the start point p0; 1 for every other parameter."""
-    p0 = np.asarray(p0, dtype=np.float64)
-    s = np.ones(MLP_NP)
-    bound = np.maximum(1.0, np.abs(p0[0:16]) + np.abs(p0[16:32]))
-    s[32:288] = np.tile(1.0 / bound, 16)
+    """Optimiser step scale of each parameter at the start point p0 (see
+    orc_mlp_step_scale)."""
+    p = np.ascontiguousarray(p0, dtype=np.float64)
+    s = np.empty(MLP_NP)
+    lib().orc_mlp_step_scale(_p(p), _p(s))
     return s
 
 
 def mlp_train(t: np.ndarray, y: np.ndarray, p0: np.ndarray, steps: int, lr: float, final: bool = False):
-    """Full-batch training on the mean squared error, fp64: Adam (the pinned
-    adam_step) on q = p / s with s = mlp_step_scale(p0), so that p moves by
-    s times Adam's step.  The loss is taken at the start of each step;
-    returns the parameters with the lowest of those losses (the start point
-    if steps == 0) -- or, with final=True, the parameters after the last
-    step -- and the losses."""
-    p = np.array(p0, dtype=np.float64)
-    sc = mlp_step_scale(p)
-    m = np.zeros(MLP_NP)
-    v = np.zeros(MLP_NP)
-    losses = []
-    best, best_loss = p.copy(), np.inf
-    for k in range(1, steps + 1):
-        loss, g = mlp_loss_grad(p, t, y)
-        losses.append(loss)
-        if loss < best_loss:
-            best, best_loss = p.copy(), loss
-        q, m, v = adam_step(p / sc, m, v, g * sc, k, lr=lr)
-        p = q * sc
-    return (p if final else best), np.array(losses)
+    """Full-batch fp64 training (see orc_mlp_train).  Returns the parameters
+    with the lowest loss seen (or, with final=True, those after the last
+    step) and the losses of every step."""
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    p = np.ascontiguousarray(p0, dtype=np.float64)
+    out = np.empty(MLP_NP)
+    losses = np.empty(steps)
+    lib().orc_mlp_train(_p(tt), _p(yy), tt.size, _p(p), steps, float(lr), 1 if final else 0, _p(out), _p(losses))
+    return out, losses
 
 
 def mlp_forward_full(params: np.ndarray, t: float):

@@ -23,13 +23,18 @@
  *   6. splitter tree with equality buckets (Sec. 2.4 SampleSort, equality buckets)
  *   7. range-radix bucket (depth cap)      (Sec. 2.4 IPS2Ra MSD radix idea)
  *   8. one partition level                 (Sec. 2.2 partitioning into buckets)
- *   9. monotone FP32 MLP CDF: fp64 forward/backward, Adam, start point,
- *      fp32 inference, and the MLP as the root of a two-level model
+ *   9. monotone FP32 MLP CDF: fp64 forward/backward, Adam, the scaled
+ *      training rule with best-loss selection, start point, fp32 inference,
+ *      and the MLP as the root of a two-level model
  *                                          (Sec. 3.1 CDF-model properties;
  *                                           Sec. 2.1 RMI stages)
  *  10. pivot quality and implicit pivots   (Sec. 3.3 Alg. 4; Sec. 3.4 Table 1 metric)
  *
- * parity unpinned: none of the functions below lacks a pin; see the tests.
+ * Every function below is pinned by a CPU test (tests/test_oracle_*.py)
+ * against something other than itself: closed forms, brute force, library
+ * routines, exact rational arithmetic or hand-counted values.  Only the
+ * paper's own Table 1 numbers are parity unpinned: the paper states neither
+ * IPS4o's sample size nor the exact RMI behind them.
  */
 #include <math.h>
 #include <stdint.h>
@@ -550,6 +555,56 @@ void orc_adam_step(double *p, double *m, double *v, const double *g, uint64_t np
     }
 }
 
+/* Per-parameter optimiser step scale at the start point p0: a layer-2 weight
+ * that reads hidden unit k gets s = 1 / max(1, |V1_k| + |b1_k|), the bound of
+ * that unit's activation over t in [0, 1]; every other parameter gets 1.
+ * (The paper trains no network; this is the reading the MLP CDF uses so that
+ * a training step moves no layer-2 pre-activation by much more than the
+ * learning rate, however steep a first-layer ramp is.) */
+void orc_mlp_step_scale(const double *p0, double *s)
+{
+    for (int i = 0; i < MLP_NP; i++) s[i] = 1.0;
+    for (int k = 0; k < MLP_H; k++) {
+        double bound = fabs(p0[OFF_V1 + k]) + fabs(p0[OFF_B1 + k]);
+        if (bound < 1.0) bound = 1.0;
+        for (int i = 0; i < MLP_H; i++) s[OFF_V2 + MLP_H * i + k] = 1.0 / bound;
+    }
+}
+
+/* Full-batch training on the mean squared error over (t_i, y_i), fp64.
+ * Step k = 1..steps: the loss L_k and gradient g at the current p (from
+ * orc_mlp_loss_grad), then one Adam step (orc_adam_step, betas 0.9 / 0.999,
+ * eps 1e-8) on q = p / s with gradient s * g, and p = q * s, with
+ * s = orc_mlp_step_scale(p0).  losses[k-1] = L_k (nullable).  p_out gets the
+ * parameters at which the lowest L_k was taken (the earliest on ties; p0
+ * when steps == 0), or with final != 0 the parameters after the last step. */
+void orc_mlp_train(const double *t, const double *y, uint64_t S, const double *p0, uint32_t steps, double lr,
+                   int final, double *p_out, double *losses)
+{
+    double p[MLP_NP], q[MLP_NP], sc[MLP_NP], g[MLP_NP], m[MLP_NP], v[MLP_NP], best[MLP_NP];
+    double best_loss = INFINITY;
+    memcpy(p, p0, sizeof p);
+    memcpy(best, p0, sizeof best);
+    orc_mlp_step_scale(p0, sc);
+    memset(m, 0, sizeof m);
+    memset(v, 0, sizeof v);
+    for (uint32_t k = 1; k <= steps; k++) {
+        double loss = orc_mlp_loss_grad(p, t, y, S, g);
+        if (losses) losses[k - 1] = loss;
+        if (loss < best_loss) {
+            best_loss = loss;
+            memcpy(best, p, sizeof best);
+        }
+        for (int i = 0; i < MLP_NP; i++) {
+            q[i] = p[i] / sc[i];
+            g[i] *= sc[i];
+        }
+        orc_adam_step(q, m, v, g, MLP_NP, k, lr, 0.9, 0.999, 1e-8);
+        for (int i = 0; i < MLP_NP; i++) p[i] = q[i] * sc[i];
+    }
+    memcpy(p_out, final ? p : best, sizeof p);
+}
+
 /* Model input of the MLP: t = clamp((x - lo) * inv, 0, 1) in fp64, rounded to
  * fp32 (a non-decreasing map of x).  lo is the smallest sample key, inv is
  * 1 / (largest - smallest). */
@@ -636,6 +691,28 @@ void orc_mlp_init(const double *t, uint64_t S, double eps, double *p)
         p[OFF_V3 + i] = i < MLP_HALF ? eps : 1.0 / 8.0;
     }
     p[OFF_B3] = 1.0;
+}
+
+/* Effective fp32 weights of a parameter vector: |V| for the weights, the
+ * biases as they are, rounded to fp32 (the form the inference evaluates). */
+void orc_mlp_effective(const double *p, float *w)
+{
+    for (int i = 0; i < MLP_NP; i++) {
+        int weight = (i >= OFF_V1 && i < OFF_B1) || (i >= OFF_V2 && i < OFF_B2) || (i >= OFF_V3 && i < OFF_B3);
+        w[i] = (float)(weight ? fabs(p[i]) : p[i]);
+    }
+}
+
+/* Input range of the MLP from a sorted sample of finite keys: lo = the
+ * smallest model input, inv = 1 / (largest - smallest), 0 when they are
+ * equal. */
+void orc_mlp_lo_inv(const uint64_t *sorted_raw, uint64_t S, int dtype, double *lo_inv)
+{
+    double x0, x1;
+    orc_model_x(sorted_raw[0], dtype, &x0);
+    orc_model_x(sorted_raw[S - 1], dtype, &x1);
+    lo_inv[0] = x0;
+    lo_inv[1] = x1 > x0 ? 1.0 / (x1 - x0) : 0.0;
 }
 
 void orc_mlp_inputs(const uint64_t *raw, uint64_t n, int dtype, double lo, double inv, float *t)
@@ -739,6 +816,13 @@ double orc_pivot_quality(const uint64_t *sorted_ord, uint64_t n, const uint64_t 
 /* ------------------------------------------------------------------------ */
 /* Array forms of the element-wise functions above (same arithmetic).        */
 /* ------------------------------------------------------------------------ */
+
+/* Model inputs of n keys (orc_model_x); a non-finite key gives NaN. */
+void orc_model_x_array(const uint64_t *raw, uint64_t n, int dtype, double *out)
+{
+    for (uint64_t i = 0; i < n; i++)
+        if (orc_model_x(raw[i], dtype, &out[i])) out[i] = NAN;
+}
 
 void orc_ord_array(const uint64_t *raw, uint64_t n, int dtype, uint64_t *out)
 {

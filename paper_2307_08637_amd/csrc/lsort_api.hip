@@ -345,9 +345,9 @@ static ls_status prepare_status(DevPool* pool, uint8_t* base, const Layout& L, h
     return LS_OK;
 }
 
-static ls_status acquire(uint64_t bytes, const Layout& L, DevPool*& pool, uint8_t*& base) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
+// Per-device set-up: compute-unit count, the ordering event, pinned read-back
+// slots.  Runs outside stream capture (ls_set_workspace or the first call).
+static ls_status pool_init(int dev, DevPool*& pool) {
     if (dev < 0 || dev >= 64) return fail(LS_EINVAL, "device index out of range");
     pool = &g_pool[dev];
     if (!pool->cus) {
@@ -355,6 +355,30 @@ static ls_status acquire(uint64_t bytes, const Layout& L, DevPool*& pool, uint8_
         HIP_TRY(hipEventCreateWithFlags(&pool->last, hipEventDisableTiming));
         HIP_TRY(hipHostMalloc((void**)&pool->pinned, std::max<size_t>(4096, sizeof(Ctl)), hipHostMallocDefault));
     }
+    return LS_OK;
+}
+
+static ls_status capturing(hipStream_t st, bool& cap) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    cap = cs != hipStreamCaptureStatusNone;
+    return LS_OK;
+}
+
+// The workspace of a call.  Under stream capture only a caller-owned
+// workspace (ls_set_workspace) is used: the library's own pool is freed and
+// reallocated when a later call needs more, which would leave a captured
+// graph's kernel arguments pointing at freed memory.
+static ls_status acquire(uint64_t bytes, const Layout& L, DevPool*& pool, uint8_t*& base, hipStream_t st) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    bool cap = false;
+    ls_status s0 = capturing(st, cap);
+    if (s0) return s0;
+    if (cap && (dev < 0 || dev >= 64 || !g_pool[dev].user))
+        return fail(LS_EINVAL, "a call under stream capture needs a caller-owned workspace: call ls_set_workspace "
+                               "first (outside capture)");
+    if ((s0 = pool_init(dev, pool))) return s0;
     if (pool->user) {
         if (bytes > pool->user_bytes)
             return fail(LS_ENOMEM, "workspace set by ls_set_workspace is too small: need " + std::to_string(bytes) +
@@ -638,8 +662,8 @@ static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, ui
     Layout L = plan(n, m, payload != nullptr, o);
     DevPool* pool;
     uint8_t* base;
-    if ((s = acquire(L.bytes, L, pool, base))) return s;
     hipStream_t st = (hipStream_t)stream;
+    if ((s = acquire(L.bytes, L, pool, base, st))) return s;
     if ((s = order_after_last(pool, st))) return s;
     if ((s = prepare_status(pool, base, L, st))) return s;
     Call c{};
@@ -651,7 +675,7 @@ static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, ui
 }
 
 // Small scratch for the single-step entry points (model, fit partials).
-static ls_status step_scratch(uint8_t*& base, DevPool*& pool, Layout& L, uint64_t mlp_S = 0) {
+static ls_status step_scratch(uint8_t*& base, DevPool*& pool, Layout& L, hipStream_t st, uint64_t mlp_S = 0) {
     Opts o;
     normalize(nullptr, o);
     L = plan(16, 1, 0, o);
@@ -661,7 +685,7 @@ static ls_status step_scratch(uint8_t*& base, DevPool*& pool, Layout& L, uint64_
         L.o_mlp_y = L.o_mlp_t + align256(mlp_S * 4);
         L.bytes = L.o_mlp_y + align256(mlp_S * 4);
     }
-    ls_status s = acquire(L.bytes, L, pool, base);
+    ls_status s = acquire(L.bytes, L, pool, base, st);
     if (!s) pool->sig = 0;  // this scratch may overlap another layout's look-back words
     return s;
 }
@@ -702,19 +726,27 @@ ls_status ls_workspace_bytes(uint64_t n_total, uint64_t m, ls_dtype dtype, int h
     return LS_OK;
 }
 
-ls_status ls_set_workspace(void* dev_ptr, size_t bytes) {
+ls_status ls_set_workspace(void* dev_ptr, size_t bytes, void* stream) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(LS_EHIP, "hipGetDevice failed");
     if (((uintptr_t)dev_ptr) & 255) return fail(LS_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    bool cap = false;
+    ls_status s = capturing(st, cap);
+    if (s) return s;
+    if (cap) return fail(LS_EINVAL, "ls_set_workspace must be called outside stream capture");
     std::lock_guard<std::mutex> lk(g_mu);
-    DevPool& p = g_pool[dev];
-    if (dev_ptr) {
-        if (hipMemset(dev_ptr, 0, bytes) != hipSuccess) return fail(LS_EHIP, "hipMemset of the workspace failed");
-        if (hipDeviceSynchronize() != hipSuccess) return fail(LS_EHIP, "hipDeviceSynchronize failed");
-    }
-    p.user = dev_ptr;
-    p.user_bytes = dev_ptr ? bytes : 0;
-    p.sig = 0;
+    DevPool* p = nullptr;
+    if ((s = pool_init(dev, p))) return s;
+    // earlier calls that used the previous workspace finish first; the
+    // clearing is ordered before every later call by the pool's event
+    if ((s = order_after_last(p, st))) return s;
+    if (dev_ptr) HIP_TRY(hipMemsetAsync(dev_ptr, 0, bytes, st));
+    HIP_TRY(hipEventRecord(p->last, st));
+    p->last_stream = st;
+    p->user = dev_ptr;
+    p->user_bytes = dev_ptr ? bytes : 0;
+    p->sig = 0;
     return LS_OK;
 }
 
@@ -742,6 +774,7 @@ ls_status ls_get_stats(ls_stats* out) {
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
     out->mlp_loss_last = c.mlp_loss[1];
+    out->overflow = c.overflow;
     return LS_OK;
 }
 
@@ -823,7 +856,7 @@ ls_status ls_rmi_fit(const void* sorted_sample, uint64_t S, ls_dtype dtype, uint
     uint8_t* base;
     DevPool* pool;
     Layout Lo;
-    if ((s = step_scratch(base, pool, Lo))) return s;
+    if ((s = step_scratch(base, pool, Lo, (hipStream_t)stream))) return s;
     hipStream_t st = (hipStream_t)stream;
     if ((s = order_after_last(pool, st))) return s;
     FitArgs A{};
@@ -843,6 +876,26 @@ ls_status ls_rmi_fit(const void* sorted_sample, uint64_t S, ls_dtype dtype, uint
     return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
 }
 
+ls_status ls_rmi_fit_block(const void* sorted_sample, uint64_t S, ls_dtype dtype, uint32_t L, double R,
+                           double* params, void* stream) {
+    ls_status s = check_keys(sorted_sample, S, dtype, nullptr);
+    if (s) return s;
+    if (S < 2 || S > (uint64_t)S_LDS || L < 2 || L > L_MAX || !params || !(R >= 1.0) || R > 4294967295.0 ||
+        R != std::floor(R))
+        return fail(LS_EINVAL, "ls_rmi_fit_block needs 2 <= S <= 16384, 2 <= L <= 1024, integer 1 <= R < 2^32, params");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    if ((s = step_scratch(base, pool, Lo, (hipStream_t)stream))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    double* mdl = (double*)(base + Lo.o_bigmodel);
+    HIP_TRY(launch_fit_block((const uint64_t*)sorted_sample, (uint32_t)S, dtype == LS_U64, L, (uint32_t)R, mdl, st));
+    HIP_TRY(launch_copy_words((const uint64_t*)(mdl + 4), (uint64_t*)params, 2 + 4ull * L, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
 ls_status ls_rmi_buckets(const void* keys, uint64_t n, ls_dtype dtype, const double* params, uint32_t L, double R,
                          uint32_t* out, void* stream) {
     ls_status s = check_keys(keys, n, dtype, nullptr);
@@ -854,7 +907,7 @@ ls_status ls_rmi_buckets(const void* keys, uint64_t n, ls_dtype dtype, const dou
     uint8_t* base;
     DevPool* pool;
     Layout Lo;
-    if ((s = step_scratch(base, pool, Lo))) return s;
+    if ((s = step_scratch(base, pool, Lo, (hipStream_t)stream))) return s;
     hipStream_t st = (hipStream_t)stream;
     if ((s = order_after_last(pool, st))) return s;
     uint64_t* mdl = (uint64_t*)(base + Lo.o_bigmodel);
@@ -873,7 +926,7 @@ ls_status ls_splitters(const void* sorted_sample, uint64_t S, ls_dtype dtype, ui
     uint8_t* base;
     DevPool* pool;
     Layout Lo;
-    if ((s = step_scratch(base, pool, Lo))) return s;
+    if ((s = step_scratch(base, pool, Lo, (hipStream_t)stream))) return s;
     hipStream_t st = (hipStream_t)stream;
     if ((s = order_after_last(pool, st))) return s;
     HIP_TRY(launch_splitters((const uint64_t*)sorted_sample, S, dtype == LS_U64, B, (uint64_t*)(base + Lo.o_bigmodel),
@@ -892,7 +945,7 @@ ls_status ls_splitter_buckets(const void* keys, uint64_t n, ls_dtype dtype, cons
     uint8_t* base;
     DevPool* pool;
     Layout Lo;
-    if ((s = step_scratch(base, pool, Lo))) return s;
+    if ((s = step_scratch(base, pool, Lo, (hipStream_t)stream))) return s;
     hipStream_t st = (hipStream_t)stream;
     if ((s = order_after_last(pool, st))) return s;
     uint64_t* mdl = (uint64_t*)(base + Lo.o_bigmodel);
@@ -928,8 +981,8 @@ static ls_status partition_one(const void* keys, const uint32_t* payload, uint64
     Lo.S_big = 0;
     DevPool* pool;
     uint8_t* base;
-    if ((s = acquire(Lo.bytes, Lo, pool, base))) return s;
     hipStream_t st = (hipStream_t)stream;
+    if ((s = acquire(Lo.bytes, Lo, pool, base, st))) return s;
     if ((s = order_after_last(pool, st))) return s;
     if ((s = prepare_status(pool, base, Lo, st))) return s;
     uint64_t* mdl = (uint64_t*)(base + Lo.o_bigmodel);
@@ -985,7 +1038,7 @@ ls_status ls_mlp_loss_grad(const float* params, const float* t, const float* y, 
     uint8_t* base;
     DevPool* pool;
     Layout Lo;
-    ls_status s = step_scratch(base, pool, Lo);
+    ls_status s = step_scratch(base, pool, Lo, (hipStream_t)stream);
     if (s) return s;
     hipStream_t st = (hipStream_t)stream;
     if ((s = order_after_last(pool, st))) return s;
@@ -1009,7 +1062,7 @@ ls_status ls_mlp_train(const void* sorted_sample, uint64_t S, ls_dtype dtype, co
     uint8_t* base;
     DevPool* pool;
     Layout Lo;
-    if ((s = step_scratch(base, pool, Lo, S))) return s;
+    if ((s = step_scratch(base, pool, Lo, (hipStream_t)stream, S))) return s;
     hipStream_t st = (hipStream_t)stream;
     if ((s = order_after_last(pool, st))) return s;
     const MlpState ms = mlp_state(base, Lo);
@@ -1052,7 +1105,7 @@ ls_status ls_mlp_rmi_fit(const void* sorted_sample, uint64_t S, ls_dtype dtype, 
     uint8_t* base;
     DevPool* pool;
     Layout Lo;
-    if ((s = step_scratch(base, pool, Lo))) return s;
+    if ((s = step_scratch(base, pool, Lo, (hipStream_t)stream))) return s;
     hipStream_t st = (hipStream_t)stream;
     if ((s = order_after_last(pool, st))) return s;
     FitArgs A{};
@@ -1080,7 +1133,7 @@ ls_status ls_mlp_rmi_buckets(const void* keys, uint64_t n, ls_dtype dtype, const
     uint8_t* base;
     DevPool* pool;
     Layout Lo;
-    if ((s = step_scratch(base, pool, Lo))) return s;
+    if ((s = step_scratch(base, pool, Lo, (hipStream_t)stream))) return s;
     hipStream_t st = (hipStream_t)stream;
     if ((s = order_after_last(pool, st))) return s;
     uint64_t* mdl = (uint64_t*)(base + Lo.o_bigmodel);

@@ -137,8 +137,9 @@ __device__ __forceinline__ void base_group_task(const Params& P, const uint64_t*
 #pragma unroll
         for (int r = 0; r < GE; r++) {
             if ((uint32_t)(r * G + gp) >= size) raw[r] = 0x7ff0000000000000ull;  // +inf pads
-            // NaN (signalling, quiet) or -0.0
-            special |= __builtin_amdgcn_class(__builtin_bit_cast(double, raw[r]), 0x001 | 0x002 | 0x020);
+            // NaN (any payload, either sign) or -0.0, tested on the bits: no
+            // floating-point assumption of this file's build can remove it
+            special |= (raw[r] & 0x7fffffffffffffffull) > 0x7ff0000000000000ull || raw[r] == 0x8000000000000000ull;
         }
     }
     if (!U64 && __ballot(special) != 0) {

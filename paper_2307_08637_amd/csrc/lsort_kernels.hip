@@ -281,6 +281,19 @@ __device__ void sample_sort(uint64_t* smp, const uint64_t* src, uint64_t off, ui
     __syncthreads();
 }
 
+// The one-workgroup fit on its own (the fit every small segment's model
+// gets): a sorted sample of S <= S_LDS raw keys into LDS as ordered keys,
+// then fit_rmi_block at total resolution B1 (log2B2 = 0) into dst.
+__global__ __launch_bounds__(M_THREADS) void k_fit_block(const uint64_t* s, uint32_t S, int u64, uint32_t L,
+                                                         uint32_t B1, double* dst) {
+    __shared__ uint64_t smp[S_LDS];
+    __shared__ uint32_t lstart[L_MAX + 1];
+    __shared__ double red[M_THREADS / 64];
+    for (uint32_t i = threadIdx.x; i < S; i += M_THREADS) smp[i] = key_ord(s[i], u64);
+    __syncthreads();
+    fit_rmi_block(smp, S, u64, L, B1, 0, dst, lstart, red);
+}
+
 // The first-level sample's keys in parent bucket b (the run
 // [bstart[b], bstart[b+1]) that k_fit_bstart found), as ordered keys in smp[]
 // (evenly thinned to S_LDS when more); returns their number.
@@ -1362,6 +1375,10 @@ hipError_t launch_seed(const Params& P, const uint64_t* offsets, uint64_t m, uin
     LAUNCH(k_seed, grid, 256, st, P, offsets, m, n_single, prebuilt, persist);
 }
 hipError_t launch_model(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_model, grid, M_THREADS, st, P); }
+hipError_t launch_fit_block(const uint64_t* s, uint32_t S, int u64, uint32_t L, uint32_t B1, double* dst,
+                            hipStream_t st) {
+    LAUNCH(k_fit_block, 1, M_THREADS, st, s, S, u64, L, B1, dst);
+}
 hipError_t launch_hist(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_hist, grid, P_THREADS, st, P); }
 hipError_t launch_scan(const Params& P, uint32_t grid, hipStream_t st) { LAUNCH(k_scan, grid, S_THREADS, st, P); }
 constexpr int SC_THREADS = 1024;  // threads of a scatter workgroup (16 waves, 8 keys each per tile)

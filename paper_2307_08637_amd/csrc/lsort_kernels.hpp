@@ -60,6 +60,8 @@ hipError_t launch_reset(const Params& P, uint64_t* persist, hipStream_t st);
 hipError_t launch_seed(const Params& P, const uint64_t* offsets, uint64_t m, uint64_t n_single, uint32_t prebuilt,
                        const uint64_t* persist, uint32_t grid, hipStream_t st);
 hipError_t launch_model(const Params& P, uint32_t grid, hipStream_t st);
+hipError_t launch_fit_block(const uint64_t* s, uint32_t S, int u64, uint32_t L, uint32_t B1, double* dst,
+                            hipStream_t st);
 hipError_t launch_hist(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_scan(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st);

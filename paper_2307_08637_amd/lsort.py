@@ -39,7 +39,7 @@ class LevelStats(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("levels", C.c_uint32), ("first_model", C.c_uint32), ("base_items", C.c_uint64),
                 ("copy_items", C.c_uint64), ("mlp_loss_first", C.c_double), ("mlp_loss_last", C.c_double),
-                ("level", LevelStats * MAX_STAT_LEVELS)]
+                ("overflow", C.c_uint32), ("reserved", C.c_uint32), ("level", LevelStats * MAX_STAT_LEVELS)]
 
 
 class KernelTiming(C.Structure):
@@ -64,10 +64,11 @@ def lib():
             "ls_sort": [vp, u64, i32, vp, vp, vp],
             "ls_sort_segmented": [vp, vp, u64, u64, i32, vp, vp, vp],
             "ls_workspace_bytes": [u64, u64, i32, i32, vp, vp],
-            "ls_set_workspace": [vp, C.c_size_t],
+            "ls_set_workspace": [vp, C.c_size_t, vp],
             "ls_get_stats": [vp],
             "ls_sample": [vp, u64, i32, u64, u64, vp, vp],
             "ls_rmi_fit": [vp, u64, i32, u32, dbl, vp, vp],
+            "ls_rmi_fit_block": [vp, u64, i32, u32, dbl, vp, vp],
             "ls_rmi_buckets": [vp, u64, i32, vp, u32, dbl, vp, vp],
             "ls_splitters": [vp, u64, i32, u32, vp, vp, vp, vp],
             "ls_splitter_buckets": [vp, u64, i32, vp, vp, u32, vp, vp],
@@ -181,7 +182,8 @@ def stats() -> dict:
         lv = s.level[i]
         levels.append({f: getattr(lv, f) for f, _ in LevelStats._fields_})
     return {"levels": levels, "first_model": s.first_model, "base_items": s.base_items,
-            "copy_items": s.copy_items, "mlp_loss_first": s.mlp_loss_first, "mlp_loss_last": s.mlp_loss_last}
+            "copy_items": s.copy_items, "mlp_loss_first": s.mlp_loss_first, "mlp_loss_last": s.mlp_loss_last,
+            "overflow": s.overflow}
 
 
 def workspace_bytes(n: int, m: int = 1, dtype=torch.float64, payload: bool = False, **opts) -> int:
@@ -194,10 +196,10 @@ def workspace_bytes(n: int, m: int = 1, dtype=torch.float64, payload: bool = Fal
 
 def set_workspace(buf: torch.Tensor | None) -> None:
     if buf is None:
-        _check(lib().ls_set_workspace(None, 0))
+        _check(lib().ls_set_workspace(None, 0, _stream()))
     else:
         _dev(buf, "workspace")
-        _check(lib().ls_set_workspace(_ptr(buf), buf.numel() * buf.element_size()))
+        _check(lib().ls_set_workspace(_ptr(buf), buf.numel() * buf.element_size(), _stream()))
 
 
 # -- single steps -------------------------------------------------------------------
@@ -214,6 +216,14 @@ def rmi_fit(sorted_sample: torch.Tensor, L: int, R: float) -> torch.Tensor:
     out = torch.empty(2 + 4 * L, dtype=torch.float64, device=sorted_sample.device)
     _check(lib().ls_rmi_fit(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), L, float(R), _ptr(out),
                             _stream()))
+    return out
+
+
+def rmi_fit_block(sorted_sample: torch.Tensor, L: int, R: int) -> torch.Tensor:
+    _dev(sorted_sample, "sorted_sample")
+    out = torch.empty(2 + 4 * L, dtype=torch.float64, device=sorted_sample.device)
+    _check(lib().ls_rmi_fit_block(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), L, float(R),
+                                  _ptr(out), _stream()))
     return out
 
 

@@ -38,39 +38,68 @@ def test_batched_mix_vs_oracle(dev):
 
 @pytest.mark.parametrize("m,lo,hi", [(300, 10, 2e5), (40, 1e4, 1e6)])
 def test_graph_capture_replay(dev, m, lo, hi):
-    """A fixed-level call captured into a graph replays correctly several
-    times, with other GPU work and host synchronisation between replays."""
+    """A fixed-level call captured into a graph (with a caller-owned
+    workspace) replays correctly several times, with other GPU work, host
+    synchronisation and a larger eager call on the library's own pool
+    between replays; the overflow word read after each replay is zero."""
     keys, off, pay, _ = inputs.segmented(m, seed=43, lo=lo, hi=hi)
     want, wp = oracle.sort_segmented(keys, off, pay)
     t, o, p = upload(keys, off, pay, dev)
     k0, p0 = t.clone(), p.clone()
     opts = dict(fixed_levels=True, stats=False)
-    lsort.sort_segmented(t, o, p, **opts)  # set-up outside capture: workspace and look-back words
-    torch.cuda.synchronize()
-    check(t, p, want, wp)
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        t.copy_(k0)
-        p.copy_(p0)
-        lsort.sort_segmented(t, o, p, **opts)
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
-    check(t, p, want, wp)
-    g = torch.cuda.CUDAGraph()
-    print(f"[case] capture m={m} n={keys.size}", flush=True)
-    with torch.cuda.graph(g):
-        lsort.sort_segmented(t, o, p, **opts)
+    nbytes = lsort.workspace_bytes(keys.size, m, payload=True, fixed_levels=True)
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=dev)
+    lsort.set_workspace(ws)
+    try:
+        lsort.sort_segmented(t, o, p, **opts)  # set-up outside capture: look-back words of this layout
+        torch.cuda.synchronize()
+        check(t, p, want, wp)
+        assert lsort.stats()["overflow"] == 0
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            t.copy_(k0)
+            p.copy_(p0)
+            lsort.sort_segmented(t, o, p, **opts)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        check(t, p, want, wp)
+        g = torch.cuda.CUDAGraph()
+        print(f"[case] capture m={m} n={keys.size}", flush=True)
+        with torch.cuda.graph(g):
+            lsort.sort_segmented(t, o, p, **opts)
+    finally:
+        torch.cuda.synchronize()
+        lsort.set_workspace(None)
+    big = inputs.generate("normal", 3 * keys.size + 1000, seed=5)
     for r in range(3):
         t.copy_(k0)
         p.copy_(p0)
         junk = torch.arange(1 << 20, device=dev, dtype=torch.float64).sqrt().sum()  # unrelated eager work
+        if r == 1:  # a larger eager call grows the library's own pool; the graph does not use it
+            tb = to_dev(big, dev)
+            lsort.sort(tb)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
         print(f"[case] replay {r}", flush=True)
         check(t, p, want, wp)
         del junk
+    del g, ws
+
+
+def test_capture_needs_caller_workspace(dev):
+    """Under stream capture the library's own (reallocatable) pool is refused."""
+    keys, off, pay, _ = inputs.segmented(20, seed=44, lo=100, hi=1e4)
+    t, o, p = upload(keys, off, pay, dev)
+    lsort.sort_segmented(t, o, p, fixed_levels=True, stats=False)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(lsort.LsortError, match="ls_set_workspace"):
+        with torch.cuda.graph(g):
+            lsort.sort_segmented(t, o, p, fixed_levels=True, stats=False)
+    torch.cuda.synchronize()
+    del g
 
 
 def test_c4_prefix_properties(dev):

@@ -150,3 +150,17 @@ def test_partition_splitters(dev, law):
     assert np.array_equal(to_host(counts).astype(np.uint64), wc)
     assert np.array_equal(to_host(ok).view(np.uint64), wk.view(np.uint64))
     assert np.array_equal(op.view(torch.int32).cpu().numpy().view(np.uint32), wp)
+
+
+@pytest.mark.parametrize("law,L,S", [("uniform", 1000, 1000), ("normal", 1000, 10_000), ("lognormal", 1000, 16384),
+                                     ("u64", 512, 16384), ("mixgauss", 64, 4097), ("exponential", 2, 2)])
+def test_rmi_fit_block(dev, law, L, S):
+    """The one-workgroup fit (the model of every segment whose sample fits in
+    LDS, and of every batched array) against the oracle's long-double fit,
+    within the same relative 1e-9 as the multi-workgroup fit."""
+    keys = inputs.generate(law, max(S * 10, 100_000), seed=6)
+    s = sorted_sample(keys, 17, S)
+    R = 1000 * 8
+    print(f"[case] fit_block {law} L={L} S={S}", flush=True)
+    gp = lsort.rmi_fit_block(to_dev(s, dev), L, R).cpu().numpy()
+    check_fit(gp, s, L, float(R))

@@ -530,3 +530,147 @@ def test_pivot_quality_learned_beats_random_uniform():
     random_q = oracle.pivot_quality(srt_ord, rnd, B)
     assert learned < random_q
     assert math.isfinite(learned) and learned < 1.0
+
+
+# -- MLP bucket, exact cases -------------------------------------------------------------------
+
+def dyadic_mlp(b3=0.25):
+    """Hand-set parameters whose every fp32 product and sum on inputs
+    t = k / 1024 is exact (dyadic values with few bits): units 0..7 are
+    max(t - i/16, 0), units 8..15 min(t - 1/2 - (i-8)/16, 0); layer-2 weights
+    2^-(4 + (i + k) mod 3); output weights 1/8."""
+    p = np.zeros(oracle.MLP_NP)
+    for i in range(16):
+        p[i] = 1.0
+        p[16 + i] = -i / 16 if i < 8 else -0.5 - (i - 8) / 16
+        p[288 + i] = -1 / 32 if i < 8 else 1 / 32
+        p[304 + i] = 1 / 8
+        for k in range(16):
+            p[32 + 16 * i + k] = 2.0 ** -(4 + (i + k) % 3)
+    p[320] = b3
+    return p
+
+
+def exact_forward(p, t):
+    """The network's output with exact rational arithmetic (no rounding)."""
+    from fractions import Fraction as Fr
+    t = Fr(t)
+    h1 = []
+    for i in range(16):
+        z = abs(Fr(p[i])) * t + Fr(p[16 + i])
+        h1.append(max(z, Fr(0)) if i < 8 else min(z, Fr(0)))
+    out = Fr(p[320])
+    for i in range(16):
+        z = Fr(p[288 + i]) + sum(abs(Fr(p[32 + 16 * i + k])) * h1[k] for k in range(16))
+        h = max(z, Fr(0)) if i < 8 else min(z, Fr(0))
+        out += abs(Fr(p[304 + i])) * h
+    return out
+
+
+@pytest.mark.parametrize("R", [1, 2, 1000, 1 << 20])
+def test_mlp_bucket_exact_dyadic(R):
+    """orc_mlp_bucket against an independent evaluation: the network output F
+    in exact rational arithmetic (every fp32 step is exact for these weights
+    and inputs, which the test checks), clamped to [0, 1], then
+    min(floor(fp32(F) * fp32(R)), R - 1) with numpy's IEEE fp32 product."""
+    p = dyadic_mlp()
+    w = oracle.effective(p)
+    keys = np.arange(0, 1025, dtype=np.float64) / 1024.0
+    got = oracle.mlp_buckets(w, 0.0, 1.0, R, keys)
+    for x, g in zip(keys, got):
+        F = exact_forward(p, x)
+        assert F == float(np.float32(float(F)))  # exactly representable in fp32
+        Fc = min(max(float(F), 0.0), 1.0)
+        want = min(int(np.floor(np.float32(Fc) * np.float32(R))), R - 1)
+        assert g == want, (x, float(F), g, want)
+    assert np.all(np.diff(got.astype(np.int64)) >= 0) and got.max() < R
+
+
+@pytest.mark.parametrize("R", [1, 7, 1000])
+def test_mlp_bucket_clamps_at_the_ends(R):
+    """An output clamped to F = 1 maps to the last bucket R - 1 (not R), F = 0
+    to bucket 0; non-finite keys go to 0 / R - 1 by sign."""
+    keys = np.array([0.0, 0.25, 0.5, 1.0, 3.0], dtype=np.float64)
+    hi = oracle.mlp_buckets(oracle.effective(dyadic_mlp(b3=2.0)), 0.0, 1.0, R, keys)
+    assert np.all(hi == R - 1)
+    lo = oracle.mlp_buckets(oracle.effective(dyadic_mlp(b3=-4.0)), 0.0, 1.0, R, keys)
+    assert np.all(lo == 0)
+    nf = np.array([-np.inf, np.nan, -np.nan, np.inf], dtype=np.float64)
+    nf[2] = -abs(nf[2])
+    g = oracle.mlp_buckets(oracle.effective(dyadic_mlp()), 0.0, 1.0, R, nf)
+    assert list(g) == [0, R - 1, 0, R - 1]
+
+
+def test_mlp_bucket_monotone_random_weights():
+    """Random weights: ids are below R and non-decreasing along sorted keys."""
+    w = oracle.effective(rand_params(5))
+    keys = np.sort(np.random.default_rng(3).normal(0, 2, 20_000))
+    for R in (3, 1000, 65536):
+        g = oracle.mlp_buckets(w, -6.0, 1 / 12, R, keys).astype(np.int64)
+        assert np.all(np.diff(g) >= 0) and g.max() < R and g.min() >= 0
+
+
+# -- pivot quality, exact values -----------------------------------------------------------------
+
+@pytest.mark.parametrize("data,pivots,B,want", [
+    ([1, 2, 2, 3, 5, 8, 8, 8], [2, 5, 8], 4, 0.5),      # 3/8-1/4 + 5/8-2/4 + 8/8-3/4
+    ([1, 2, 3, 4, 5, 6, 7, 8], [2, 4, 6], 4, 0.0),      # perfect splitters
+    ([1, 2, 3, 4, 5, 6, 7, 8], [0, 0, 0], 4, 1.5),      # nothing below: 1/4 + 2/4 + 3/4
+    ([5, 5, 5, 5], [5], 2, 0.5),                         # all keys <= the pivot: |1 - 1/2|
+    ([1, 3], [2], 2, 0.0),
+])
+def test_pivot_quality_hand_counted(data, pivots, B, want):
+    """Sec. 3.4 metric sum_i |P(A <= p_i) - (i+1)/B|, counted by hand."""
+    s = oracle.ord_keys(np.array(data, dtype=np.uint64))
+    p = oracle.ord_keys(np.array(pivots, dtype=np.uint64))
+    assert oracle.pivot_quality(s, p, B) == pytest.approx(want, abs=1e-15)
+
+
+# -- MLP training rule ---------------------------------------------------------------------------
+
+def test_mlp_step_scale_closed_form():
+    """s = 1 / max(1, |V1_k| + |b1_k|) on every layer-2 weight of input unit
+    k (row-major V2: entry 32 + 16 i + k), 1 elsewhere."""
+    p = np.zeros(oracle.MLP_NP)
+    p[0:16] = np.arange(16) - 5.0
+    p[16:32] = 0.25
+    s = oracle.mlp_step_scale(p)
+    bound = np.maximum(1.0, np.abs(np.arange(16) - 5.0) + 0.25)
+    for i in range(16):
+        for k in range(16):
+            assert s[32 + 16 * i + k] == 1.0 / bound[k]
+    assert np.all(s[:32] == 1.0) and np.all(s[288:] == 1.0)
+
+
+def test_mlp_train_zero_steps_is_start_point():
+    t = np.linspace(0, 1, 100)
+    p0 = dyadic_mlp()
+    p, losses = oracle.mlp_train(t, t, p0, 0, 1e-2)
+    assert np.array_equal(p, p0) and losses.size == 0
+
+
+def test_mlp_train_unit_scale_is_plain_adam():
+    """With every first-layer bound at most 1 the scale is 1 and training is
+    the pinned Adam step (orc_adam_step, closed form) applied to the pinned
+    gradient (finite differences) step after step; the returned parameters
+    are those of the lowest loss, the final ones on request."""
+    rng = np.random.default_rng(4)
+    t = np.sort(rng.random(300))
+    y = np.arange(300) / 300
+    p0 = rng.normal(0, 0.3, oracle.MLP_NP)
+    p0[0:16] = rng.uniform(-0.5, 0.5, 16)
+    p0[16:32] = rng.uniform(-0.4, 0.4, 16)
+    assert np.all(oracle.mlp_step_scale(p0) == 1.0)
+    steps, lr = 25, 5e-2
+    p, m, v = p0.copy(), np.zeros(oracle.MLP_NP), np.zeros(oracle.MLP_NP)
+    hist, losses = [], []
+    for k in range(1, steps + 1):
+        loss, g = oracle.mlp_loss_grad(p, t, y)
+        hist.append(p.copy())
+        losses.append(loss)
+        p, m, v = oracle.adam_step(p, m, v, g, k, lr=lr)
+    final, fl = oracle.mlp_train(t, y, p0, steps, lr, final=True)
+    best, bl = oracle.mlp_train(t, y, p0, steps, lr)
+    assert np.array_equal(fl, np.array(losses)) and np.array_equal(bl, fl)
+    assert np.array_equal(final, p)
+    assert np.array_equal(best, hist[int(np.argmin(losses))])
