@@ -8,14 +8,24 @@ timed step are already in HBM: K unsorted copies are made before the timed
 region and step k sorts copy k in place.
 
 Besides the headline line it reports, in extra fields of the same JSON
-object: the same sort per input law, the batched form (sort_segmented over
-the 10,000-array workload's first 2e8 keys, with payload), and the learned
-parts on the 70/20/10 piecewise law (RMI root vs MLP root vs splitter
-tree: first-level max/mean bucket ratio and Gkeys/s).
+object:
+  * the output check: sorted, the same multiset as the input (two 64-bit
+    hashes), and -- with the CPU baseline -- equal word for word to the
+    oracle's sort of the same keys;
+  * the pivot quality of Table 1 (Sec. 3.4) at 1e8: the RMI's implicit
+    pivots (Alg. 4) vs the splitter tree's sample quantiles vs random keys;
+  * the same sort per input law, the duplicate-heavy laws included;
+  * the batched form: sort_segmented over the whole 10,000-array workload
+    (sizes log-uniform in [1e3, 1e6], five float64 laws, uint32 payload) and
+    over its first 2e8 keys, learned vs splitter, plus the fixed-level form
+    eager and replayed from a captured HIP graph;
+  * the learned parts on the 70/20/10 piecewise law at 1e8 and at 1e9 keys:
+    RMI root vs MLP root vs splitter tree (first-level max/mean bucket ratio,
+    fallbacks, Gkeys/s).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--law normal]
                        [--n 100000000] [--no-cpu-baseline] [--no-laws]
-                       [--no-batched] [--no-mlp] [--no-splitter]
+                       [--no-batched] [--no-mlp] [--no-c5] [--no-splitter]
 """
 from __future__ import annotations
 
@@ -38,6 +48,7 @@ STREAM_OF = {"k_hist": "read", "k_scatter": "copy", "k_base_small": "copy", "k_b
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2307_08637_amd", "csrc", f)
                   for f in ("lsort_kernels.hip", "lsort_dev.hpp", "lsort_internal.hpp")]
+SIGN = -(1 << 63)
 
 
 def kernel_source_sha() -> str:
@@ -58,13 +69,71 @@ def parse():
     p.add_argument("--seed", type=int, default=21)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-laws", action="store_true", help="skip the per-law table")
-    p.add_argument("--cpu-keys", type=int, default=50_000_000, help="keys in the oracle's timed sample")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    p.add_argument("--batched-arrays", type=int, default=10_000, help="arrays of the batched workload")
     p.add_argument("--no-mlp", action="store_true", help="skip the learned-parts comparison")
+    p.add_argument("--no-c5", action="store_true", help="skip the learned-parts comparison at 1e9 keys")
     p.add_argument("--no-splitter", action="store_true", help="time the learned sort only (for profiling)")
+    p.add_argument("--no-pivots", action="store_true", help="skip the pivot-quality metric")
     p.add_argument("--mlp-n", type=int, default=100_000_000, help="keys of the piecewise-law comparison")
+    p.add_argument("--c5-n", type=int, default=1_000_000_000, help="keys of the large piecewise-law comparison")
     return p.parse_args()
 
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def log(*x):
+    print("[bench]", *x, file=sys.stderr, flush=True)
+
+
+# -- properties of an output (GPU, any size) ----------------------------------------------
+
+def order_key(t, torch):
+    """int64 whose signed order is the keys' order (totalOrder for float64)."""
+    b = t.view(torch.int64)
+    if t.dtype == torch.uint64:
+        return b ^ SIGN
+    return torch.where(b < 0, b ^ 0x7FFFFFFFFFFFFFFF, b)
+
+
+def mix_hash(x, torch, salt=0):
+    """Wrapping sum of a 64-bit mix of every element (equal for any
+    permutation of the same multiset); x: int64 tensor."""
+    def lsr(z, s):
+        return (z >> s) & ((1 << (64 - s)) - 1)
+    z = x ^ salt
+    z = (z ^ lsr(z, 30)) * -4658895280553007687   # 0xBF58476D1CE4E5B9
+    z = (z ^ lsr(z, 27)) * -7723592293110705685   # 0x94D049BB133111EB
+    z = z ^ lsr(z, 31)
+    return int(z.sum().item())
+
+
+def multiset(t, torch):
+    x = t.view(torch.int64)
+    return (t.numel(), mix_hash(x, torch), mix_hash(x, torch, 0x5A5A5A5A5A5A5A5))
+
+
+def is_sorted(t, torch):
+    k = order_key(t, torch)
+    return t.numel() < 2 or bool((k[:-1] <= k[1:]).all().item())
+
+
+# -- the headline sort -------------------------------------------------------------------------
 
 def main():
     a = parse()
@@ -80,13 +149,11 @@ def main():
     dev = torch.device("cuda:0")
     lsort.lib()  # fail loudly if the HIP library is missing
 
-    def log(*x):
-        print("[bench]", *x, file=sys.stderr, flush=True)
-
     log("generating", a.n, a.law)
     host = inputs.generate(a.law, a.n, seed=a.seed)
     dtype = torch.uint64 if host.dtype == np.uint64 else torch.float64
     base = torch.from_numpy(host.view(np.int64) if host.dtype == np.uint64 else host).to(dev).view(dtype)
+    base_ms = multiset(base, torch)
     bufs = [torch.empty_like(base) for _ in range(a.steps)]
     warm = torch.empty_like(base)
 
@@ -117,17 +184,18 @@ def main():
             lsort.sort(b, model=model, stats=False)
         torch.cuda.synchronize()
         kern = lsort.timing_read()
+        recs = lsort.timing_records()
         lsort.timing(False)
         warm.copy_(base)  # one more (untimed) sort for the per-level statistics
         lsort.sort(warm, model=model)
         st = lsort.stats()
-        # the result must be a sorted permutation (cheap properties on the GPU)
-        k = timed_bufs[0].view(torch.int64)
-        key = k ^ (-(1 << 63)) if dtype == torch.uint64 else torch.where(k < 0, k ^ 0x7FFFFFFFFFFFFFFF, k)
-        if not bool((key[:-1] <= key[1:]).all().item()):
-            raise SystemExit(f"bench: output of model={model} is not sorted")
+        # every timed output is a sorted permutation of the input
+        for b in timed_bufs[:steps]:
+            if not is_sorted(b, torch) or multiset(b, torch) != base_ms:
+                raise SystemExit(f"bench: output of model={model} is not a sorted permutation of the input")
         ms = e0.elapsed_time(e1) / steps
-        return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "kernels": kern, "stats": st}
+        return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "kernels": kern, "records": recs,
+                "stats": st}
 
     log("learned", a.steps, "steps")
     L = run("auto", a.steps, bufs)
@@ -137,6 +205,11 @@ def main():
     if not a.no_splitter:
         log("splitter", a.steps, "steps")
         S = run("splitter", a.steps, bufs)
+    gpu_out = bufs[0].clone() if not a.no_splitter else None  # a sorted copy (the splitter's, same bytes)
+    if gpu_out is None:
+        bufs[0].copy_(base)
+        lsort.sort(bufs[0], stats=False)
+        gpu_out = bufs[0].clone()
 
     gk = lambda r: a.n / (r["ms_per_step"] * 1e-3) / 1e9  # noqa: E731
     kern = L["kernels"]
@@ -158,9 +231,15 @@ def main():
                  "radix": lv["radix"], "max_over_mean": lv["max_bucket_x1000_over_mean"] / 1000.0,
                  "fallback": lv["fallback"]} for lv in st["levels"]]
 
+    pivots = None
+    if not a.no_pivots:
+        log("pivot quality")
+        pivots = pivot_quality(base, gpu_out, lsort, torch, seed=a.seed)
+
     laws = {}
     if not a.no_laws and S is not None:
-        for law in ("uniform", "normal", "lognormal", "exponential", "chisquared", "mixgauss", "u64"):
+        for law in ("uniform", "normal", "lognormal", "exponential", "chisquared", "mixgauss", "u64",
+                    "rootdups", "twodups", "zipf"):
             if law == a.law:
                 laws[law] = {"learned": round(gk(L), 3), "splitter": round(gk(S), 3)}
                 continue
@@ -169,33 +248,47 @@ def main():
             dt = torch.uint64 if h.dtype == np.uint64 else torch.float64
             src = torch.from_numpy(h.view(np.int64) if h.dtype == np.uint64 else h).to(dev).view(dt)
             bb = [b.view(dt) for b in bufs[:3]]
-            rl = run_on(src, bb, "auto", lsort, torch)
-            rs = run_on(src, bb, "splitter", lsort, torch)
-            laws[law] = {"learned": round(a.n / (rl * 1e-3) / 1e9, 3), "splitter": round(a.n / (rs * 1e-3) / 1e9, 3)}
+            rl, stl = run_on(src, bb, "auto", lsort, torch)
+            rs, _ = run_on(src, bb, "splitter", lsort, torch)
+            laws[law] = {"learned": round(a.n / (rl * 1e-3) / 1e9, 3), "splitter": round(a.n / (rs * 1e-3) / 1e9, 3),
+                         "first_level": "learned" if stl["levels"][0]["learned"] else "tree"}
             del src, h
 
+    # the CPU oracle on the same keys (rank 0, one GPU): its rate, and the GPU
+    # output compared with its output word for word
+    cpu = None
+    oracle_equal = None
+    if not a.no_cpu_baseline:
+        import oracle
+        model, avail = host_cpu()
+        log("oracle on", a.n, "keys")
+        t0 = time.perf_counter()
+        want, _ = oracle.sort(host)
+        dt = time.perf_counter() - t0
+        got = gpu_out.view(torch.int64).cpu().numpy()
+        oracle_equal = bool(np.array_equal(got, want.view(np.int64)))
+        if not oracle_equal:
+            raise SystemExit("bench: GPU output differs from the oracle's")
+        cpu = {"value": round(a.n / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+               "sample": f"the same {a.n} {a.law} keys, one single-threaded oracle sort (stable bottom-up merge "
+                         f"sort) in {dt:.1f} s; 1 core used of nproc = {avail}, {model}"}
+        del want, got
+    del gpu_out
+
+    bufs = warm = None
     batched = None
     if not a.no_batched:
-        bufs = warm = None
         torch.cuda.empty_cache()
-        batched = run_batched(inputs, lsort, torch, np, dev, log)
+        batched = run_batched(inputs, lsort, torch, np, dev, a.batched_arrays)
     mlp = None
     if not a.no_mlp:
         torch.cuda.empty_cache()
-        mlp = run_learned_parts(inputs, lsort, torch, np, dev, log, a.mlp_n, a.seed)
+        mlp = {"n_1e8": run_learned_parts(inputs, lsort, torch, np, dev, a.mlp_n, a.seed, reps=3)}
+        if not a.no_c5:
+            torch.cuda.empty_cache()
+            mlp["n_1e9"] = run_learned_parts(inputs, lsort, torch, np, dev, a.c5_n, a.seed, reps=2)
 
-    cpu = None
-    if not a.no_cpu_baseline:
-        import oracle
-        m = min(a.cpu_keys, a.n)
-        log("oracle on", m, "keys")
-        t0 = time.perf_counter()
-        oracle.sort(host[:m])
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(m / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {m} of the same {a.n} {a.law} keys, one single-threaded oracle sort "
-                         f"({dt:.1f} s) on {os.cpu_count()} host CPUs"}
-
+    per_level = per_level_rates(L["records"], a.n, a.steps)
     out = {
         "metric": "Gkeys/s sorting 1e8 f64 keys, learned vs splitter buckets; % HBM peak",
         "value": round(gk(L), 4),
@@ -218,8 +311,11 @@ def main():
                      "launches": dk["launches"],
                      # against the reference stream of the same access pattern
                      "frac_of_stream": round(achieved / cal[STREAM_OF[dom]]["GB/s"], 4)},
+        "partition_passes": per_level,
         "streams": cal,
         "cpu_baseline": cpu,
+        "output_check": {"sorted": True, "multiset_equal": True, "oracle_equal": oracle_equal},
+        "pivot_quality": pivots,
         "splitter": None if S is None else {"value": round(gk(S), 4), "ms_per_step": round(S["ms_per_step"], 4),
                                             "levels": level_summary(S["stats"])},
         "learned_over_splitter": None if S is None else round(gk(L) / gk(S), 4),
@@ -232,6 +328,68 @@ def main():
         "learned_parts": mlp,
     }
     print(json.dumps(out), flush=True)
+
+
+def per_level_rates(recs, n, steps):
+    """Achieved HBM rate of each partition pass of the array (launches that
+    processed all n keys, in launch order: level 0, then level 1), apart from
+    the launches that sort the first level's sample."""
+    res = {}
+    for name in ("k_hist", "k_scatter"):
+        rs = [(ms, keys) for nm, ms, keys in recs if nm == name]
+        full = [ms for ms, keys in rs if keys == n]
+        per = len(full) // max(steps, 1)
+        for lv in range(per):
+            sel = full[lv::per]
+            ms = sum(sel) / len(sel)
+            gbs = n * BYTES_PER_KEY[name] / (ms * 1e-3) / 1e9
+            res[f"{name}_level{lv}"] = {"avg_ms": round(ms, 4), "GB/s": round(gbs, 1),
+                                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        other = [ms for ms, keys in rs if keys != n]
+        if other:
+            res[f"{name}_sample_sort"] = {"launches_per_step": len(other) // max(steps, 1),
+                                          "avg_ms": round(sum(other) / len(other), 4)}
+    return res
+
+
+def pivot_quality(src, out, lsort, torch, seed, B=256, L=1000):
+    """Table 1 metric (Sec. 3.4): sum over B-1 pivots p_i of
+    |P(A <= p_i) - (i + 1) / B|, P taken over the sorted keys `out`.
+      learned:  the RMI's implicit pivots (Alg. 4: the largest key of each of
+                B buckets), the RMI fitted on a 1% sample with L leaves; as
+                the buckets do not decrease along sorted keys, P(A <= p_b) is
+                the fraction of keys in buckets 0..b (an empty bucket repeats
+                the previous pivot);
+      splitter: the sample quantiles sample[floor((i + 1) S / B)] a splitter
+                tree takes from the same 1% sample (Sec. 2.4);
+      random:   B - 1 keys drawn at random from the input (the pivots of the
+                paper's random-sample column)."""
+    n = src.numel()
+    dev = src.device
+    S = max(n // 100, B)
+    smp = lsort.sample(src, seed, S)
+    lsort.sort(smp, stats=False)
+    tgt = torch.arange(1, B, dtype=torch.float64, device=dev) / B
+    par = lsort.rmi_fit(smp, L, float(B))
+    ids = lsort.rmi_buckets(out, par, L, float(B)).view(torch.int32).to(torch.int64)
+    cum = torch.cumsum(torch.bincount(ids, minlength=B), 0)[:B - 1].to(torch.float64) / n
+    learned = float((cum - tgt).abs().sum().item())
+    okey = order_key(out, torch)
+
+    def quality(piv):
+        pos = torch.searchsorted(okey, order_key(piv, torch).contiguous(), right=True).to(torch.float64) / n
+        return float((pos - tgt).abs().sum().item())
+    q = (torch.arange(1, B, device=dev, dtype=torch.int64) * S) // B
+    splitter = quality(smp[q])
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    ridx = torch.randint(0, n, (B - 1,), generator=g).to(dev)
+    rnd = src[ridx].clone()
+    rk = order_key(rnd, torch)
+    rnd = rnd[torch.argsort(rk)]
+    random_q = quality(rnd)
+    return {"buckets": B, "sample": S, "leaves": L, "learned_rmi": round(learned, 4),
+            "splitter_quantiles": round(splitter, 4), "random": round(random_q, 4),
+            "paper_table1_uniform": {"random": 1.1016, "rmi": 0.4388}}
 
 
 def calibrate(src, dst, lsort, torch, reps):
@@ -261,79 +419,143 @@ def calibrate(src, dst, lsort, torch, reps):
             "read": {"ms": round(read_ms, 4), "GB/s": round(read_gbs, 1), "frac": round(read_gbs / HBM_PEAK_GBS, 4)}}
 
 
-def run_batched(inputs, lsort, torch, np, dev, log):
-    """sort_segmented over the 10,000-array workload (sizes log-uniform in
-    [1e3, 1e6], five float64 laws, uint32 payload) up to its first 2e8
-    keys; restore copies are outside the timed region."""
-    log("batched: generating")
-    keys, off, pay, _ = inputs.segmented(10_000, seed=41, max_total=200_000_000)
+def time_call(fn, reps, before, torch):
+    """Mean ms of fn() over reps calls after one untimed call; before() runs
+    (untimed) ahead of each call."""
+    tot = 0.0
+    for r in range(reps + 1):
+        before()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        if r:
+            tot += e0.elapsed_time(e1)
+    return tot / reps
+
+
+def run_batched(inputs, lsort, torch, np, dev, arrays):
+    """sort_segmented over the batched workload (sizes log-uniform in
+    [1e3, 1e6], five float64 laws, uint32 payload = index in its array):
+    all `arrays` arrays, and its leading arrays up to 2e8 keys; learned vs
+    splitter with a host read-back per level; the fixed-level form eager and
+    replayed from a captured graph (caller-owned workspace).  Restore copies
+    are outside the timed region."""
+    log("batched: generating", arrays, "arrays")
+    keys, off, pay, _ = inputs.segmented(arrays, seed=41)
+    n, m = keys.size, off.size - 1
+    cut = int(np.searchsorted(off[1:], 200_000_000)) + 1  # arrays of the 2e8 prefix
     k0 = torch.from_numpy(keys).to(dev)
-    p0 = torch.from_numpy(pay.view(np.int32)).to(dev).view(torch.uint32)
+    p0 = torch.from_numpy(pay.view(np.int32)).to(dev)
     o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
-    k, p = torch.empty_like(k0), torch.empty_like(p0)
     del keys, pay
-    res = {}
+    k = torch.empty_like(k0)
+    p = torch.empty_like(p0)
+    pu = p.view(torch.uint32)
+
+    def restore(nk=n):
+        k[:nk].copy_(k0[:nk])
+        p[:nk].copy_(p0[:nk])
+
+    res = {"workload": f"{m} arrays (sizes log-uniform in [1e3, 1e6], five float64 laws) = {n} keys + uint32 "
+                       f"payload, stable", "arrays": m, "keys": n}
     for name, opts in (("learned", {}), ("splitter", {"model": "splitter"})):
         log("batched:", name)
-        tot = 0.0
-        reps = 3
-        for r in range(reps + 1):
-            k.copy_(k0)
-            p.view(torch.int32).copy_(p0.view(torch.int32))
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            lsort.sort_segmented(k, o, p, stats=False, **opts)
-            e1.record()
-            torch.cuda.synchronize()
-            if r:
-                tot += e0.elapsed_time(e1)
-        ms = tot / reps
-        res[name] = {"ms": round(ms, 3), "Gkeys/s": round(k0.numel() / (ms * 1e-3) / 1e9, 3)}
-    return {"workload": f"{off.size - 1} arrays (sizes log-uniform in [1e3, 1e6], five float64 laws) = "
-                        f"{int(off[-1])} keys + uint32 payload, stable", **res}
+        ms = time_call(lambda: lsort.sort_segmented(k, o, pu, stats=False, **opts), 3, restore, torch)
+        res[name] = {"ms": round(ms, 3), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3)}
+    # the output: every array sorted, payload stable, (key, payload, array) pairs the same multiset
+    restore()
+    seg = torch.repeat_interleave(torch.arange(m, device=dev), torch.from_numpy(np.diff(off).astype(np.int64)).to(dev))
+
+    def pair_hash(kk, pp):
+        return mix_hash(kk.view(torch.int64) ^ ((pp.to(torch.int64) & 0xFFFFFFFF) << 17) ^ (seg << 45), torch)
+    h0 = pair_hash(k, p)
+    lsort.sort_segmented(k, o, pu, stats=False)
+    kk = order_key(k, torch)
+    same = seg[:-1] == seg[1:]
+    ok = bool(((kk[:-1] <= kk[1:]) | ~same).all().item())
+    tie = same & (kk[:-1] == kk[1:])
+    pi = p.to(torch.int64) & 0xFFFFFFFF
+    ok = ok and bool(((pi[:-1] < pi[1:]) | ~tie).all().item()) and pair_hash(k, p) == h0
+    del kk, same, tie, pi
+    if not ok:
+        raise SystemExit("bench: batched output is not a stable per-array sort of the input")
+    ref_k, ref_p = k.clone(), p.clone()
+    res["output_check"] = {"sorted_per_array": True, "stable": True, "pair_multiset_equal": True}
+    # the 2e8-key prefix
+    npre = int(off[cut])
+    opre = o[:cut + 1]
+    for name, opts in (("learned", {}), ("splitter", {"model": "splitter"})):
+        ms = time_call(lambda: lsort.sort_segmented(k[:npre], opre, pu[:npre], stats=False, **opts), 3,
+                       lambda: restore(npre), torch)
+        res.setdefault("prefix_2e8", {"arrays": cut, "keys": npre})[name] = {
+            "ms": round(ms, 3), "Gkeys/s": round(npre / (ms * 1e-3) / 1e9, 3)}
+    # fixed levels (no host read-back): eager, then a captured graph replayed
+    log("batched: fixed levels and graph replay")
+    nbytes = lsort.workspace_bytes(n, m, payload=True, fixed_levels=True)
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=dev)
+    lsort.set_workspace(ws)
+    try:
+        fixed = dict(fixed_levels=True, stats=False)
+        ms = time_call(lambda: lsort.sort_segmented(k, o, pu, **fixed), 3, restore, torch)
+        res["fixed_levels_eager"] = {"ms": round(ms, 3), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3)}
+        restore()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            lsort.sort_segmented(k, o, pu, **fixed)
+        ms = time_call(g.replay, 3, restore, torch)
+        equal = bool(torch.equal(k, ref_k) and torch.equal(p, ref_p))
+        ovf = lsort.stats()["overflow"]
+        res["graph_replay"] = {"ms": round(ms, 3), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3),
+                               "output_equal_to_readback_path": equal, "overflow": ovf}
+        if not equal or ovf:
+            raise SystemExit("bench: graph replay output differs from the read-back path")
+        del g
+    finally:
+        torch.cuda.synchronize()
+        lsort.set_workspace(None)
+    del ws, k0, p0, k, p, ref_k, ref_p, seg
+    return res
 
 
-def run_learned_parts(inputs, lsort, torch, np, dev, log, n, seed):
+def run_learned_parts(inputs, lsort, torch, np, dev, n, seed, reps):
     """The piecewise law (70% LogNormal(0, 2), 20% 1e6 + U[0, 1), 10% N(-5e3, 1)):
-    the RMI, the MLP-rooted model (200 Adam steps) and the splitter tree as
-    the first level; first-level max/mean bucket ratio and Gkeys/s."""
+    the RMI, the MLP-rooted model (200 Adam steps on a 1e6-key training set)
+    and the splitter tree as the first level; first-level max/mean bucket
+    ratio, fallbacks and Gkeys/s; every output checked sorted and the same
+    multiset as the input."""
     log("learned parts: generating", n)
     h = inputs.generate("piecewise", n, seed=seed + 30)
     src = torch.from_numpy(h).to(dev)
     del h
+    ms0 = multiset(src, torch)
     buf = torch.empty_like(src)
-    res = {"workload": f"sort {n} float64 keys, piecewise law 70/20/10"}
+    res = {"workload": f"sort {n} float64 keys, piecewise law 70/20/10, out-of-place copy restored per run"}
     for name, model in (("rmi", "auto"), ("mlp", "mlp"), ("splitter", "splitter")):
-        log("learned parts:", name)
-        tot = 0.0
-        reps = 3
-        for r in range(reps + 1):
-            buf.copy_(src)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            lsort.sort(buf, model=model, stats=False)
-            e1.record()
-            torch.cuda.synchronize()
-            if r:
-                tot += e0.elapsed_time(e1)
-        buf.copy_(src)  # one more (untimed) sort for the statistics
+        log("learned parts:", name, n)
+        ms = time_call(lambda: lsort.sort(buf, model=model, stats=False), reps, lambda: buf.copy_(src), torch)
+        buf.copy_(src)  # one more (untimed) sort for the statistics and the check
         lsort.sort(buf, model=model)
         st = lsort.stats()
+        if not is_sorted(buf, torch) or multiset(buf, torch) != ms0:
+            raise SystemExit(f"bench: learned-parts output of {name} is not a sorted permutation")
         lv0 = st["levels"][0]
-        ms = tot / reps
         res[name] = {"ms": round(ms, 3), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3),
                      "first_level_max_over_mean": lv0["max_bucket_x1000_over_mean"] / 1000.0,
                      "first_level_fallbacks": lv0["fallback"], "levels": len(st["levels"])}
         if name == "mlp":
             res[name]["loss_first"] = st["mlp_loss_first"]
             res[name]["loss_best"] = st["mlp_loss_last"]
+    del src, buf
     return res
 
 
 def run_on(src, bufs, model, lsort, torch):
-    """ms per sort of `src` (K = len(bufs) copies, after one warm-up)."""
+    """ms per sort of `src` (K = len(bufs) copies, after one warm-up), and
+    the statistics of one more sort."""
     tmp = bufs[0]
     tmp.copy_(src)
     lsort.sort(tmp, model=model, stats=False)
@@ -346,7 +568,10 @@ def run_on(src, bufs, model, lsort, torch):
         lsort.sort(b, model=model, stats=False)
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / len(bufs)
+    ms = e0.elapsed_time(e1) / len(bufs)
+    tmp.copy_(src)
+    lsort.sort(tmp, model=model)
+    return ms, lsort.stats()
 
 
 if __name__ == "__main__":

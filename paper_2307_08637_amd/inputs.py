@@ -26,6 +26,8 @@ reproducible and memory stays bounded.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -39,11 +41,29 @@ def _rng(seed: int, chunk: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, chunk])))
 
 
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def _chunked(n: int, seed: int, draw, dtype) -> np.ndarray:
+    """Chunk c of the output is drawn from its own stream (seed, c), so the
+    chunks are independent: they are filled by a pool of threads (numpy's
+    generators release the interpreter lock) with the same result as a
+    sequential loop."""
     out = np.empty(n, dtype=dtype)
-    for c, lo in enumerate(range(0, n, CHUNK)):
+
+    def fill(c):
+        lo = c * CHUNK
         hi = min(n, lo + CHUNK)
         out[lo:hi] = draw(_rng(seed, c), hi - lo)
+
+    nchunk = (n + CHUNK - 1) // CHUNK
+    if nchunk <= 1:
+        for c in range(nchunk):
+            fill(c)
+    else:
+        with ThreadPoolExecutor(min(_workers(), nchunk)) as ex:
+            list(ex.map(fill, range(nchunk)))
     return out
 
 
@@ -129,10 +149,18 @@ def segmented(m: int, seed: int, lo: float = 1e3, hi: float = 1e6, laws=F64_LAWS
     off[1:] = np.cumsum(sizes, dtype=np.uint64)
     keys = np.empty(int(off[-1]), dtype=np.float64)
     payload = np.empty(int(off[-1]), dtype=np.uint32)
-    for s in range(m):
+
+    def fill(s):  # array s has its own stream: any order of filling gives the same result
         a, b = int(off[s]), int(off[s + 1])
         keys[a:b] = generate(laws[which[s]], b - a, seed * 100_003 + s)
         payload[a:b] = np.arange(b - a, dtype=np.uint32)
+
+    if m > 16:
+        with ThreadPoolExecutor(_workers()) as ex:
+            list(ex.map(fill, range(m), chunksize=64))
+    else:
+        for s in range(m):
+            fill(s)
     return keys, off, payload, which
 
 
