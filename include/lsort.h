@@ -141,6 +141,29 @@ typedef struct {
 ls_status ls_sort(void *keys, uint64_t n, ls_dtype dtype, uint32_t *payload,
                   const ls_options *opt, void *stream);
 
+/* Allocation-free ls_sort, for callers that cannot allocate device or host
+ * memory during the call (tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as ls_sort, except:
+ *   - the scratch memory is a fixed device array inside the library,
+ *     LS_NOALLOC_SCRATCH_BYTES per device, held from the library's first use
+ *     of a device until the process ends; a call whose workspace
+ *     (ls_workspace_bytes with LS_FLAG_FIXED_LEVELS) exceeds it returns
+ *     LS_ENOMEM without enqueuing anything (about 2.2e6 float64 keys without
+ *     a payload, 1.9e6 with one, at the default options);
+ *   - no hipMalloc, hipHostMalloc, hipFree or event creation, ever (the
+ *     first call on a device looks up the array's device address);
+ *   - LS_FLAG_FIXED_LEVELS is always in effect: no host read-back, so the
+ *     call cannot see a workspace overflow; ls_get_stats().overflow after
+ *     it tells (nonzero: output invalid);
+ *   - not ordered against other calls: every call on a device shares its
+ *     array, so calls on one device that overlap in time race (serialise
+ *     them on one stream); no timing records are taken;
+ *   - the array keeps the last call's contents; what must start at zero is
+ *     cleared by the call itself. */
+#define LS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+ls_status ls_sort_noalloc(void *keys, uint64_t n, ls_dtype dtype, uint32_t *payload,
+                          const ls_options *opt, void *stream);
+
 /* Sort each segment [offsets[i], offsets[i+1]) of keys independently, in
  * place, in one batched pass (all segments share every kernel launch).
  * offsets: DEVICE array of m + 1 non-decreasing uint64 values; offsets[m] is

@@ -288,6 +288,7 @@ struct TRec {
     double keys;
 };
 static bool g_timing = false;
+static thread_local bool t_untimed = false;  // this thread's call takes no timing records (ls_sort_noalloc)
 static std::vector<TRec> g_trec;
 static std::vector<hipEvent_t> g_evfree;
 
@@ -305,7 +306,7 @@ static hipEvent_t ev_get() {
 // Launch `expr` (a hipError_t expression); when timing, bracket it with events.
 #define TIMED(kid, st, expr)                                              \
     do {                                                                  \
-        if (g_timing) {                                                   \
+        if (g_timing && !t_untimed) {                                     \
             TRec r_{(kid), ev_get(), ev_get(), 0.0};                      \
             if (r_.a) HIP_TRY(hipEventRecord(r_.a, (st)));                \
             HIP_TRY(expr);                                                \
@@ -608,7 +609,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     if (!c.one_level) {
         TIMED(KI_BASE, c.st, launch_base_small(P, cus * 8, c.st));
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
-        if (g_timing) {  // keys through the base case (both kernels) and the copies
+        if (g_timing && !t_untimed) {  // keys through the base case (both kernels) and the copies
             HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));
             const Ctl* hc = (const Ctl*)pool->pinned;
@@ -674,6 +675,75 @@ static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, ui
     return mark_done(pool, st, (Ctl*)(base + L.o_ctl));
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free sorting (ls_sort_noalloc)
+//
+// The workspace is `scratch`, a fixed-size device array of the library: each
+// device the library runs on holds its own copy until the process ends.  In
+// host code the array's name is only a host-side stand-in, so its device
+// address is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only that address is handed to the kernels and to memsets.
+// The call launches a fixed number of levels (no host read-back: there is no
+// pinned buffer to read into without allocating one), records no timing
+// events, and is not ordered against other calls: calls that use the array
+// of one device must not overlap in time.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[LS_NOALLOC_SCRATCH_BYTES];
+static DevPool g_npool[64];  // per device: the array's device address (ptr), CU count, layout signature
+
+static ls_status noalloc_pool(DevPool*& pool) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(LS_EINVAL, "device index out of range");
+    pool = &g_npool[dev];
+    if (!pool->ptr) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255)) return fail(LS_EHIP, "scratch array has no usable device address");
+        int cus = 0;
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        pool->cus = cus;
+        pool->bytes = LS_NOALLOC_SCRATCH_BYTES;
+        pool->sig = 0;
+        pool->ptr = p;
+    }
+    return LS_OK;
+}
+
+static ls_status sort_noalloc(void* keys, uint64_t n, ls_dtype dtype, uint32_t* payload, const ls_options* opt,
+                              void* stream) {
+    ls_status s = check_keys(keys, n, dtype, payload);
+    if (s) return s;
+    Opts o;
+    if ((s = normalize(opt, o, n, 1))) return s;
+    o.flags = (o.flags & ~(uint32_t)LS_FLAG_SYNC_LEVELS) | LS_FLAG_FIXED_LEVELS;
+    if (n <= 1) return LS_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Layout L = plan(n, 1, payload != nullptr, o);
+    if (L.bytes > LS_NOALLOC_SCRATCH_BYTES)
+        return fail(LS_ENOMEM, "ls_sort_noalloc: " + std::to_string(n) + " keys need " + std::to_string(L.bytes) +
+                                   " bytes of scratch; the fixed scratch array holds " +
+                                   std::to_string((unsigned long long)LS_NOALLOC_SCRATCH_BYTES) + " (use ls_sort)");
+    DevPool* pool = nullptr;
+    if ((s = noalloc_pool(pool))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* base = (uint8_t*)pool->ptr;
+    // the look-back words and the call epoch start at zero for every new
+    // layout (the array keeps the previous call's contents)
+    if ((s = prepare_status(pool, base, L, st))) return s;
+    Call c{};
+    c.keys = (uint64_t*)keys; c.pay = payload; c.n = n; c.m = 1; c.offsets = nullptr; c.u64 = dtype == LS_U64;
+    c.o = o; c.st = st;
+    t_untimed = true;
+    s = run(c, L, base, pool);
+    t_untimed = false;
+    if (s) return s;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    g_last.ctl = (Ctl*)(base + L.o_ctl); g_last.st = st; g_last.dev = dev; g_last.valid = true;
+    return LS_OK;
+}
+
 // Small scratch for the single-step entry points (model, fit partials).
 static ls_status step_scratch(uint8_t*& base, DevPool*& pool, Layout& L, hipStream_t st, uint64_t mlp_S = 0) {
     Opts o;
@@ -705,6 +775,11 @@ const char* ls_version(void) { return "lsort 0.1 gfx950"; }
 
 ls_status ls_sort(void* keys, uint64_t n, ls_dtype dtype, uint32_t* payload, const ls_options* opt, void* stream) {
     return sort_common(keys, nullptr, 1, n, dtype, payload, opt, stream);
+}
+
+ls_status ls_sort_noalloc(void* keys, uint64_t n, ls_dtype dtype, uint32_t* payload, const ls_options* opt,
+                          void* stream) {
+    return sort_noalloc(keys, n, dtype, payload, opt, stream);
 }
 
 ls_status ls_sort_segmented(void* keys, const uint64_t* offsets, uint64_t m, uint64_t host_total, ls_dtype dtype,

@@ -62,6 +62,7 @@ def lib():
         vp, u64, u32, i32, dbl = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int, C.c_double
         sig = {
             "ls_sort": [vp, u64, i32, vp, vp, vp],
+            "ls_sort_noalloc": [vp, u64, i32, vp, vp, vp],
             "ls_sort_segmented": [vp, vp, u64, u64, i32, vp, vp, vp],
             "ls_workspace_bytes": [u64, u64, i32, i32, vp, vp],
             "ls_set_workspace": [vp, C.c_size_t, vp],
@@ -154,6 +155,18 @@ def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, **opts) -> Non
             raise ValueError("payload must be uint32 with one entry per key")
     o = make_options(**opts)
     _check(lib().ls_sort(_ptr(keys), keys.numel(), _dtype(keys), _ptr(payload), C.byref(o), _stream()))
+
+
+def sort_noalloc(keys: torch.Tensor, payload: torch.Tensor | None = None, **opts) -> None:
+    """sort() through the allocation-free entry point (fixed scratch array in
+    the library; fixed level count; calls on one device must not overlap)."""
+    _dev(keys, "keys")
+    if payload is not None:
+        _dev(payload, "payload")
+        if payload.dtype != torch.uint32 or payload.numel() != keys.numel():
+            raise ValueError("payload must be uint32 with one entry per key")
+    o = make_options(**opts)
+    _check(lib().ls_sort_noalloc(_ptr(keys), keys.numel(), _dtype(keys), _ptr(payload), C.byref(o), _stream()))
 
 
 def sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, payload: torch.Tensor | None = None,
