@@ -95,7 +95,10 @@ typedef struct {
     uint32_t mlp_sample;     /* MLP training-set size: every k-th point of the sorted sample so that at
                                 most this many remain; default 1e6 */
     float mlp_lr;            /* MLP Adam learning rate; default 3e-3 */
-    uint32_t reserved[5];
+    uint32_t tile;           /* keys per work unit of the first level's histogram and scatter passes:
+                                32768 << k, k in [0, 4]; the scatter writes each bucket's share of a unit
+                                in whole 64-byte segments except its first and last; default 32768 */
+    uint32_t reserved[4];
 } ls_options;
 
 /* Per-call statistics (LS_FLAG_COLLECT_STATS). */
@@ -203,8 +206,9 @@ const char *ls_last_error(void);
 /* ---- Tuning (batched and single-array form) -------------------------------- */
 /* Autotuner: on the current device, for each size class -- the decimal order
  * of magnitude of the average array size n / m, 1e3 .. 1e8 -- time every
- * candidate (buckets in {256, 512, 1000, 1024}, cutoff in {256, 512},
- * tree_buckets in {128, 256}) on synthetic arrays it generates on the device
+ * candidate (buckets in {256, 512, 1000, 1024}, cutoff in {256, 512, 1024},
+ * tree_buckets in {128, 256}; from 1e6 keys per array also the first-level
+ * work unit, tile in {32768, 65536, 131072}) on synthetic arrays it generates on the device
  * (uniform, normal and lognormal laws; ~2e7 keys in arrays log-uniform over
  * [avg / 4, 4 avg) for the batched classes, one array of 1e7 or 1e8 keys for
  * the others), keep the fastest, write a JSON table to table_path (host
@@ -214,8 +218,8 @@ const char *ls_last_error(void);
 ls_status ls_autotune(const char *table_path);
 
 /* Load a table written by ls_autotune (NULL: unload).  Afterwards a call
- * with opt == NULL, or with LS_FLAG_TUNED set, takes buckets, cutoff and
- * tree_buckets that it leaves 0 from the entry of its size class (the
+ * with opt == NULL, or with LS_FLAG_TUNED set, takes buckets, cutoff,
+ * tree_buckets and tile that it leaves 0 from the entry of its size class (the
  * nearest class present; ties go to the smaller class).  Errors: LS_EINVAL
  * (unreadable, malformed, out of range, or made on a different device
  * architecture / CU count). */

@@ -48,6 +48,7 @@ struct Opts {
     uint64_t seed;
     uint32_t mlp_steps, mlp_sample;
     float mlp_lr;
+    uint32_t tile;   // keys per work unit of the first level's partition passes
 };
 
 // ---------------------------------------------------------------------------
@@ -84,6 +85,7 @@ static void apply_tuning(const ls_options* o, Opts& r, uint64_t n, uint64_t m) {
     if (!o || !o->buckets) r.buckets = best->buckets;
     if (!o || !o->cutoff) r.cutoff = best->cutoff;
     if (!o || !o->tree_buckets) r.tree_buckets = best->tree_buckets;
+    if (!o || !o->tile) r.tile = best->tile;
 }
 
 static ls_status normalize(const ls_options* o, Opts& r, uint64_t n = 0, uint64_t m = 0) {
@@ -93,6 +95,7 @@ static ls_status normalize(const ls_options* o, Opts& r, uint64_t n = 0, uint64_
     r.model = LS_MODEL_AUTO; r.buckets = 1000; r.leaves = 1000; r.tree_buckets = 256; r.cutoff = m > 1 ? 512 : 1024;
     r.max_levels = 16; r.flags = LS_FLAG_SYNC_LEVELS; r.sample_frac = 0.01; r.fallback_ratio = 2.0; r.seed = 0x5EED;
     r.mlp_steps = 200; r.mlp_sample = 1000000; r.mlp_lr = 3e-3f;
+    r.tile = UNIT;
     if (!o) {
         apply_tuning(o, r, n, m);
         return LS_OK;
@@ -112,7 +115,13 @@ static ls_status normalize(const ls_options* o, Opts& r, uint64_t n = 0, uint64_
     if (o->mlp_steps) r.mlp_steps = o->mlp_steps;
     if (o->mlp_sample) r.mlp_sample = o->mlp_sample;
     if (o->mlp_lr > 0) r.mlp_lr = o->mlp_lr;
+    if (o->tile) r.tile = o->tile;
     apply_tuning(o, r, n, m);
+    {
+        bool ok = false;
+        for (uint32_t s = 0; s <= USHIFT_MAX; s++) ok |= r.tile == ((uint32_t)UNIT << s);
+        if (!ok) return fail(LS_EINVAL, "tile must be 32768 << k keys, k in [0, 4]");
+    }
     if (r.buckets < 2 || r.buckets > B_MAX) return fail(LS_EINVAL, "buckets must be in [2, 1024]");
     if (r.leaves < 2 || r.leaves > L_MAX) return fail(LS_EINVAL, "leaves must be in [2, 1024]");
     if (r.tree_buckets < 2 || r.tree_buckets > 512 || (r.tree_buckets & (r.tree_buckets - 1)))
@@ -187,6 +196,7 @@ static Opts nested_opts(const Opts& o) {
     r.flags = (o.flags & LS_FLAG_FIXED_LEVELS) ? o.flags : ((o.flags & ~(uint32_t)LS_FLAG_FIXED_LEVELS) | LS_FLAG_SYNC_LEVELS);
     r.model = o.model == LS_MODEL_SPLITTER ? LS_MODEL_SPLITTER : LS_MODEL_AUTO;
     r.sample_frac = 0.002;
+    r.tile = UNIT;
     return r;
 }
 
@@ -436,6 +446,8 @@ static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
     P.buckets = c.o.buckets; P.leaves = c.o.leaves; P.tree_buckets = c.o.tree_buckets; P.cutoff = c.o.cutoff;
     P.max_levels = c.o.max_levels; P.flags = c.o.flags; P.model = c.o.model;
     P.sample_frac = c.o.sample_frac; P.fallback_ratio = c.o.fallback_ratio; P.seed = c.o.seed;
+    P.unit0_shift = 0;
+    while (((uint32_t)UNIT << P.unit0_shift) < c.o.tile && P.unit0_shift < USHIFT_MAX) P.unit0_shift++;
     P.ctl = (Ctl*)(base + L.o_ctl);
     for (int i = 0; i < 2; i++) {
         P.segs[i] = (Seg*)(base + L.o_segs[i]);
@@ -1256,7 +1268,7 @@ ls_status ls_tuned_options(uint64_t n_total, uint64_t m, ls_options* out) {
     out->model = o.model; out->buckets = o.buckets; out->leaves = o.leaves; out->tree_buckets = o.tree_buckets;
     out->cutoff = o.cutoff; out->max_levels = o.max_levels; out->flags = o.flags; out->sample_frac = o.sample_frac;
     out->fallback_ratio = o.fallback_ratio; out->seed = o.seed; out->mlp_steps = o.mlp_steps;
-    out->mlp_sample = o.mlp_sample; out->mlp_lr = o.mlp_lr;
+    out->mlp_sample = o.mlp_sample; out->mlp_lr = o.mlp_lr; out->tile = o.tile;
     return LS_OK;
 }
 

@@ -100,6 +100,12 @@ constexpr uint32_t SEG_RESIDENT = 4u;  // sorted by one workgroup (k_resident): 
 constexpr uint32_t SEG_FROM_SAMPLE = 8u;  // fallback child of the first level: its tree's sample is the
                                           // first-level sample's run in its bucket (model = parent's, win = bucket)
 constexpr uint64_t RES_MAX = 8192;     // largest segment a single workgroup takes (one work unit)
+// Work units of a segment: UNIT << s keys, s in bits 8..10 of the flags (0
+// for every segment below the first level).  k_scatter carries a bucket's
+// last partial 64-byte segment from tile to tile within a unit, so larger
+// units leave fewer partial segments in the output.
+constexpr uint32_t SEG_USHIFT_POS = 8, USHIFT_MAX = 4;
+__host__ __device__ inline uint32_t seg_unit(uint32_t flags) { return (uint32_t)UNIT << ((flags >> SEG_USHIFT_POS) & 7u); }
 
 struct Tile {          // one work unit of UNIT keys
     uint32_t seg;     // index in the level's segment list
@@ -163,6 +169,7 @@ struct Params {
     int has_pay;
     // options
     uint32_t buckets, leaves, tree_buckets, cutoff, max_levels, flags, model;
+    uint32_t unit0_shift;           // first-level segments: work units of UNIT << unit0_shift keys
     double sample_frac, fallback_ratio;
     uint64_t seed;
     // workspace

@@ -61,7 +61,8 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
         const bool seg = s < m && (prebuilt ? n >= 1 : n > P.cutoff);
         // an array small enough for one workgroup is sorted whole by k_resident
         const bool resident = seg && !prebuilt && n <= RES_MAX;
-        const uint32_t nt = seg && !resident ? (uint32_t)((n + UNIT - 1) / UNIT) : 0;
+        const uint64_t unit0 = (uint64_t)UNIT << P.unit0_shift;
+        const uint32_t nt = seg && !resident ? (uint32_t)((n + unit0 - 1) / unit0) : 0;
         {
             const uint32_t nr = (uint32_t)__popcll(__ballot(resident));
             if ((threadIdx.x & 63) == 0 && nr) atomicAdd(&P.ctl->nres[0], nr);
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
             } else {
                 Seg sg{};
                 sg.off = lo; sg.n = n; sg.kind = K_FRESH; sg.tile0 = (uint32_t)t0; sg.ntiles = nt;
-                sg.flags = prebuilt ? SEG_PREBUILT : (resident ? SEG_RESIDENT : 0);
+                sg.flags = (prebuilt ? SEG_PREBUILT : (resident ? SEG_RESIDENT : 0)) | (P.unit0_shift << SEG_USHIFT_POS);
                 if (t0 + nt > P.tile_cap) { atomicOr(&P.ctl->overflow, OVF_TILE); sg.flags |= SEG_FAILED; }
                 if (prebuilt) {  // the first level's model and kind were written into segs[1][0]
                     Seg pb = P.segs[1][0];
@@ -492,8 +493,9 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
         for (uint32_t b = tid; b < B_MAX; b += P_THREADS) h[b] = 0;
         __syncthreads();
         const View v = make_view(mdl, sg.kind, sg.nb, sg.win);
-        const uint64_t base = sg.off + (uint64_t)td.idx * UNIT;
-        const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
+        const uint32_t U = seg_unit(sg.flags);
+        const uint64_t base = sg.off + (uint64_t)td.idx * U;
+        const uint32_t un = (uint32_t)min<uint64_t>(U, sg.n - (uint64_t)td.idx * U);
         const int bits = ceil_log2(sg.nb);
         with_kind(v.kind, u64, [&](auto kc) {
             constexpr int KIND = decltype(kc)::value;
@@ -517,15 +519,15 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
                 }
             };
             constexpr uint32_t RND = P_THREADS * HK;  // keys per round
-            if (un == UNIT) {
+            if (un == U) {
                 // full unit: no bounds checks; the next round's HK keys are
                 // loaded (unconditionally: the last round reloads itself)
                 // while this round's are bucketed
                 uint64_t kk[HK], kn[HK];
 #pragma unroll
                 for (int r = 0; r < HK; r++) kk[r] = src[base + r * P_THREADS + tid];
-                for (uint32_t i0 = 0; i0 < UNIT; i0 += RND) {
-                    const uint32_t nx = i0 + RND < UNIT ? i0 + RND : i0;
+                for (uint32_t i0 = 0; i0 < U; i0 += RND) {
+                    const uint32_t nx = i0 + RND < U ? i0 + RND : i0;
 #pragma unroll
                     for (int r = 0; r < HK; r++) kn[r] = src[base + nx + r * P_THREADS + tid];
 #pragma unroll
@@ -939,8 +941,9 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
         }
         const View v = make_view(mdl, sg.kind, sg.nb, sg.win);
         const int bits = ceil_log2(nb);
-        const uint64_t ubase = sg.off + (uint64_t)td.idx * UNIT;
-        const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
+        const uint32_t U = seg_unit(sg.flags);
+        const uint64_t ubase = sg.off + (uint64_t)td.idx * U;
+        const uint32_t un = (uint32_t)min<uint64_t>(U, sg.n - (uint64_t)td.idx * U);
         const uint32_t ntl = (un + TILE - 1) / TILE;
         // the payload variant keeps one copy of the tile loop (registers)
         with_kind<!PAY>(v.kind, u64, [&](auto kc) {

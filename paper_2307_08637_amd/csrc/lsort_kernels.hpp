@@ -108,6 +108,7 @@ struct TuneEntry {
     int cls;                                // floor(log10(n / m))
     uint32_t buckets, cutoff, tree_buckets; // fastest options measured for the class
     double ms, default_ms;                  // their time and the defaults' time (informational)
+    uint32_t tile;                          // first-level work-unit keys (ls_options.tile)
 };
 void tuning_install(const std::vector<TuneEntry>& t);
 int report_error(int status, const char* msg);  // sets ls_last_error(), returns status

@@ -439,8 +439,9 @@ __global__ __launch_bounds__(IDS_T) void k_mlp_ids(Params P) {
         const float Lf = (float)h->L;
         const uint32_t shift = sg.kind == K_MLP ? h->log2B2 : 0u;
         const uint32_t win = sg.kind == K_MLP ? 0u : sg.win;
-        const uint64_t base = sg.off + (uint64_t)td.idx * UNIT;
-        const uint32_t un = (uint32_t)min<uint64_t>(UNIT, sg.n - (uint64_t)td.idx * UNIT);
+        const uint32_t U = seg_unit(sg.flags);
+        const uint64_t base = sg.off + (uint64_t)td.idx * U;
+        const uint32_t un = (uint32_t)min<uint64_t>(U, sg.n - (uint64_t)td.idx * U);
         for (uint32_t i0 = 0; i0 < un; i0 += IDS_T * IDS_K) {
             lds_reload_fence();
             uint64_t raw[IDS_K];

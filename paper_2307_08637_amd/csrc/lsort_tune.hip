@@ -61,7 +61,7 @@ struct DevBuf {
     } while (0)
 
 struct Candidate {
-    uint32_t buckets, cutoff, tree_buckets;
+    uint32_t buckets, cutoff, tree_buckets, tile;
 };
 
 // Device identity the table is keyed by.
@@ -134,10 +134,14 @@ ls_status ls_autotune(const char* table_path) {
     int cus = 0;
     ls_status s = device_id(arch, cus);
     if (s) return s;
-    const Candidate cands[] = {{256, 256, 128}, {256, 512, 256}, {512, 256, 128}, {512, 512, 256},
-                               {1000, 256, 128}, {1000, 512, 256}, {1000, 512, 128}, {1000, 256, 256},
-                               {512, 512, 128}, {256, 512, 128}, {1024, 512, 256}, {1024, 256, 256}};
-    const Candidate defaults = {1000, 512, 256};
+    // (buckets, cutoff, tree fan-out) for every class; the first-level work
+    // unit (tile) only matters for arrays of many units: searched from 1e6 keys
+    const Candidate cands[] = {{256, 256, 128, 0}, {256, 512, 256, 0}, {512, 256, 128, 0}, {512, 512, 256, 0},
+                               {1000, 256, 128, 0}, {1000, 512, 256, 0}, {1000, 512, 128, 0}, {1000, 256, 256, 0},
+                               {512, 512, 128, 0}, {256, 512, 128, 0}, {1024, 512, 256, 0}, {1024, 256, 256, 0},
+                               {1000, 1024, 256, 0}, {1000, 512, 256, 65536}, {1000, 512, 256, 131072},
+                               {1000, 1024, 256, 131072}};
+    const Candidate defaults = {1000, 512, 256, 0};
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     TUNE_HIP(hipStreamCreate(&st));
@@ -163,12 +167,13 @@ ls_status ls_autotune(const char* table_path) {
         TUNE_HIP(hipMalloc(&doff.p, (m + 1) * 8));
         TUNE_HIP(hipMemcpy(doff.p, off.data(), (m + 1) * 8, hipMemcpyHostToDevice));
         TUNE_HIP(launch_tune_fill((double*)pristine.p, (const uint64_t*)doff.p, m, 0x5EED0000ull + cls, st));
-        TuneEntry best{cls, 0, 0, 0, 1e30, 0};
+        TuneEntry best{cls, 0, 0, 0, 1e30, 0, 32768};
         for (const Candidate& c : cands) {
+            if (c.tile && cls < 6) continue;
             ls_options o;
             std::memset(&o, 0, sizeof(o));
             o.struct_size = sizeof(o);
-            o.buckets = c.buckets; o.cutoff = c.cutoff; o.tree_buckets = c.tree_buckets;
+            o.buckets = c.buckets; o.cutoff = c.cutoff; o.tree_buckets = c.tree_buckets; o.tile = c.tile;
             o.flags = LS_FLAG_SYNC_LEVELS;
             double ms = 0;
             s = time_sort((double*)keys.p, (const double*)pristine.p, n, (const uint64_t*)doff.p, m, o, st, e0, e1, 3,
@@ -176,7 +181,10 @@ ls_status ls_autotune(const char* table_path) {
             if (s) return s;
             if (c.buckets == defaults.buckets && c.cutoff == defaults.cutoff && c.tree_buckets == defaults.tree_buckets)
                 best.default_ms = ms;
-            if (ms < best.ms) { best.ms = ms; best.buckets = c.buckets; best.cutoff = c.cutoff; best.tree_buckets = c.tree_buckets; }
+            if (ms < best.ms) {
+                best.ms = ms; best.buckets = c.buckets; best.cutoff = c.cutoff; best.tree_buckets = c.tree_buckets;
+                best.tile = c.tile ? c.tile : 32768;
+            }
         }
         table.push_back(best);
     }
@@ -191,8 +199,9 @@ ls_status ls_autotune(const char* table_path) {
         const TuneEntry& e = table[i];
         std::fprintf(f,
                      "    {\"log10_avg_size\": %d, \"buckets\": %u, \"cutoff\": %u, \"tree_buckets\": %u, "
-                     "\"ms\": %.4f, \"default_ms\": %.4f}%s\n",
-                     e.cls, e.buckets, e.cutoff, e.tree_buckets, e.ms, e.default_ms, i + 1 < table.size() ? "," : "");
+                     "\"tile\": %u, \"ms\": %.4f, \"default_ms\": %.4f}%s\n",
+                     e.cls, e.buckets, e.cutoff, e.tree_buckets, e.tile, e.ms, e.default_ms,
+                     i + 1 < table.size() ? "," : "");
     }
     std::fprintf(f, "  ]\n}\n");
     std::fclose(f);
@@ -234,16 +243,19 @@ ls_status ls_load_tuning(const char* table_path) {
     while ((p = txt.find('{', p + 1)) != std::string::npos) {
         const size_t e = txt.find('}', p);
         if (e == std::string::npos) break;
-        double cls, b, c, t, ms = 0, dms = 0;
+        double cls, b, c, t, ms = 0, dms = 0, tile = 32768;
         if (!json_number(txt, p, e, "log10_avg_size", cls) || !json_number(txt, p, e, "buckets", b) ||
             !json_number(txt, p, e, "cutoff", c) || !json_number(txt, p, e, "tree_buckets", t))
             return (ls_status)report_error(LS_EINVAL, "tuning table entry lacks a field");
         json_number(txt, p, e, "ms", ms);
         json_number(txt, p, e, "default_ms", dms);
+        json_number(txt, p, e, "tile", tile);  // optional: default work unit
         const uint32_t tb = (uint32_t)t;
-        if (b < 2 || b > B_MAX || c < 1 || c > C_MAX || tb < 2 || tb > 512 || (tb & (tb - 1)))
+        bool tile_ok = false;
+        for (uint32_t s = 0; s <= USHIFT_MAX; s++) tile_ok |= tile == (double)((uint32_t)UNIT << s);
+        if (b < 2 || b > B_MAX || c < 1 || c > C_MAX || tb < 2 || tb > 512 || (tb & (tb - 1)) || !tile_ok)
             return (ls_status)report_error(LS_EINVAL, "tuning table entry out of range");
-        table.push_back(TuneEntry{(int)cls, (uint32_t)b, (uint32_t)c, tb, ms, dms});
+        table.push_back(TuneEntry{(int)cls, (uint32_t)b, (uint32_t)c, tb, ms, dms, (uint32_t)tile});
         p = e;
     }
     if (table.empty()) return (ls_status)report_error(LS_EINVAL, "tuning table has no classes");

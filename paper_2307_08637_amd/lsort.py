@@ -26,7 +26,8 @@ class Options(C.Structure):
         ("struct_size", C.c_uint32), ("model", C.c_uint32), ("buckets", C.c_uint32), ("leaves", C.c_uint32),
         ("tree_buckets", C.c_uint32), ("cutoff", C.c_uint32), ("max_levels", C.c_uint32), ("flags", C.c_uint32),
         ("sample_frac", C.c_double), ("fallback_ratio", C.c_double), ("seed", C.c_uint64),
-        ("mlp_steps", C.c_uint32), ("mlp_sample", C.c_uint32), ("mlp_lr", C.c_float), ("reserved", C.c_uint32 * 5),
+        ("mlp_steps", C.c_uint32), ("mlp_sample", C.c_uint32), ("mlp_lr", C.c_float), ("tile", C.c_uint32),
+        ("reserved", C.c_uint32 * 4),
     ]
 
 
@@ -130,7 +131,7 @@ def _dev(t: torch.Tensor, name: str):
 
 
 def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, max_levels=0, flags=0,
-                 sample_frac=0.0, fallback_ratio=0.0, seed=0, mlp_steps=0, mlp_sample=0, mlp_lr=0.0,
+                 sample_frac=0.0, fallback_ratio=0.0, seed=0, mlp_steps=0, mlp_sample=0, mlp_lr=0.0, tile=0,
                  stats=True, fixed_levels=False, no_fallback=False, tuned=False) -> Options:
     o = Options()
     o.struct_size = C.sizeof(Options)
@@ -143,6 +144,7 @@ def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, ma
     o.flags = f
     o.sample_frac, o.fallback_ratio, o.seed = sample_frac, fallback_ratio, seed
     o.mlp_steps, o.mlp_sample, o.mlp_lr = mlp_steps, mlp_sample, mlp_lr
+    o.tile = tile
     return o
 
 
@@ -364,7 +366,8 @@ def load_tuning(table_path: str | None) -> None:
 def tuned_options(n: int, m: int = 1) -> dict:
     o = Options()
     _check(lib().ls_tuned_options(n, m, C.byref(o)))
-    return {"buckets": o.buckets, "cutoff": o.cutoff, "tree_buckets": o.tree_buckets, "leaves": o.leaves}
+    return {"buckets": o.buckets, "cutoff": o.cutoff, "tree_buckets": o.tree_buckets, "leaves": o.leaves,
+            "tile": o.tile}
 
 def timing(enable: bool) -> None:
     """Start (clearing earlier records) or stop per-kernel event timing."""

@@ -99,7 +99,8 @@ TABLE = """{
   "classes": [
     {"log10_avg_size": 3, "buckets": 256, "cutoff": 256, "tree_buckets": 128, "ms": 1.0, "default_ms": 1.2},
     {"log10_avg_size": 6, "buckets": 512, "cutoff": 512, "tree_buckets": 256, "ms": 2.0, "default_ms": 2.1},
-    {"log10_avg_size": 8, "buckets": 1000, "cutoff": 256, "tree_buckets": 256, "ms": 4.0, "default_ms": 4.5}
+    {"log10_avg_size": 8, "buckets": 1000, "cutoff": 256, "tree_buckets": 256, "tile": 131072, "ms": 4.0,
+     "default_ms": 4.5}
   ]
 }
 """
@@ -120,7 +121,9 @@ def test_tuning_table_lookup(tmp_path):
     assert lsort.tuned_options(10**6, 100)["cutoff"] == 512  # the segmented form's default
     lsort.load_tuning(str(path))
     try:
-        assert lsort.tuned_options(10**6, 1) == {"buckets": 512, "cutoff": 512, "tree_buckets": 256, "leaves": 1000}
+        assert lsort.tuned_options(10**6, 1) == {"buckets": 512, "cutoff": 512, "tree_buckets": 256, "leaves": 1000,
+                                                 "tile": 32768}  # no tile in the entry: the default
+        assert lsort.tuned_options(10**8, 1)["tile"] == 131072
         assert lsort.tuned_options(2 * 10**7, 20_000)["buckets"] == 256          # class 3
         assert lsort.tuned_options(10**8, 1)["cutoff"] == 256                    # class 8
         assert lsort.tuned_options(10**4, 1)["buckets"] == 256                   # class 4 -> nearest 3
@@ -132,7 +135,8 @@ def test_tuning_table_lookup(tmp_path):
 
 @pytest.mark.parametrize("text", ["{}", '{"format": "other"}',
                                   TABLE.replace('"buckets": 512', '"buckets": 5000') % ("gfx950", 256),
-                                  TABLE.replace('"tree_buckets": 128', '"tree_buckets": 100') % ("gfx950", 256)])
+                                  TABLE.replace('"tree_buckets": 128', '"tree_buckets": 100') % ("gfx950", 256),
+                                  TABLE.replace('"tile": 131072', '"tile": 100000') % ("gfx950", 256)])
 def test_tuning_table_rejects_bad_files(tmp_path, text):
     import torch
     from paper_2307_08637_amd import lsort

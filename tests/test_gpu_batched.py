@@ -138,6 +138,7 @@ def test_autotune_table_and_tuned_sort(dev, tmp_path):
         assert tab["format"] == "lsort-tuning-1" and len(tab["classes"]) == 6
         for e in tab["classes"]:
             assert e["ms"] <= e["default_ms"] * 1.0001
+            assert e["tile"] in (32768, 65536, 131072)
         lsort.load_tuning(path)
         keys, off, pay, _ = inputs.segmented(500, seed=47, lo=1e3, hi=1e5)
         t, o, p = upload(keys, off, pay, dev)

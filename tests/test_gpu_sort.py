@@ -169,6 +169,21 @@ def test_large_1e7_oracle(dev, law):
     assert_same_bits(got, oracle.sort(keys)[0])
 
 
+@pytest.mark.parametrize("tile", [65536, 131072, 524288])
+@pytest.mark.parametrize("law,n,pay", [("normal", 2_500_000, False), ("u64", 700_003, True),
+                                       ("lognormal", 3_000_017, True)])
+def test_tile_option(dev, tile, law, n, pay):
+    """Larger first-level work units (the carry spans more tiles, several
+    units and a ragged last one): every output word equal to the oracle's."""
+    keys = inputs.generate(law, n, seed=n % 97)
+    payload = np.arange(n, dtype=np.uint32) if pay else None
+    got, gp = gpu_sort(keys, dev, payload, tile=tile)
+    want, wp = oracle.sort(keys, payload)
+    assert_same_bits(got, want)
+    if pay:
+        assert np.array_equal(gp, wp)
+
+
 @pytest.mark.parametrize("law", ["normal", "lognormal", "exponential"])
 def test_first_level_fallback_trees(dev, law):
     """A large array's oversized first-level buckets (above 2x the expected
