@@ -22,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lsort_oracle.c")
 LIB = os.path.join(HERE, "liblsort_oracle.so")
 
-F64, U64 = 0, 1
+F64, U64, I64, F32 = 0, 1, 2, 3
 MLP_NP = 321
 
 
@@ -49,8 +49,8 @@ def lib():
         sig = {
             "orc_ord": (u64, [u64, i32]),
             "orc_unord": (u64, [u64, i32]),
-            "orc_sort": (i32, [vp, vp, vp, u64, i32]),
-            "orc_sort_segmented": (i32, [vp, vp, vp, u64, i32]),
+            "orc_sort": (i32, [vp, vp, i32, vp, u64, i32]),
+            "orc_sort_segmented": (i32, [vp, vp, i32, vp, u64, i32]),
             "orc_splitmix64_at": (u64, [u64, u64]),
             "orc_sample_index": (u64, [u64, u64, u64]),
             "orc_sample": (None, [vp, u64, u64, u64, vp]),
@@ -106,11 +106,18 @@ def dtype_code(a: np.ndarray) -> int:
         return F64
     if a.dtype == np.uint64:
         return U64
-    raise TypeError(f"keys must be float64 or uint64, got {a.dtype}")
+    if a.dtype == np.int64:
+        return I64
+    if a.dtype == np.float32:
+        return F32
+    raise TypeError(f"keys must be float64, uint64, int64 or float32, got {a.dtype}")
 
 
 def raw_bits(a: np.ndarray) -> np.ndarray:
-    return np.ascontiguousarray(a).view(np.uint64)
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.float32:
+        return a.view(np.uint32).astype(np.uint64)
+    return a.view(np.uint64)
 
 
 # -- 1. key order ------------------------------------------------------------
@@ -125,14 +132,25 @@ def ord_keys(a: np.ndarray) -> np.ndarray:
 
 # -- 2. the sort ---------------------------------------------------------------
 
+def _payload(payload):
+    """(copy, width): uint32 payloads stay 4-byte, 64-bit ones are 8-byte."""
+    if payload is None:
+        return None, 4
+    p = np.ascontiguousarray(payload)
+    if p.dtype.itemsize == 8:
+        return p.copy(), 8
+    return np.ascontiguousarray(payload, dtype=np.uint32).copy(), 4
+
+
 def sort(keys: np.ndarray, payload: np.ndarray | None = None, want_perm: bool = False):
-    """Stable sort of keys (float64 by totalOrder, uint64 numerically).
+    """Stable sort of keys (float64 / float32 by totalOrder, uint64 / int64
+    numerically); payload uint32 or 64-bit.
     Returns (sorted keys, permuted payload or None[, perm])."""
     dt = dtype_code(keys)
     k = np.ascontiguousarray(keys).copy()
-    p = None if payload is None else np.ascontiguousarray(payload, dtype=np.uint32).copy()
+    p, pw = _payload(payload)
     perm = np.empty(k.size, dtype=np.uint64) if want_perm else None
-    rc = lib().orc_sort(_p(k), _p(p), _p(perm), k.size, dt)
+    rc = lib().orc_sort(_p(k), _p(p), pw, _p(perm), k.size, dt)
     if rc:
         raise MemoryError("oracle sort: out of memory")
     return (k, p, perm) if want_perm else (k, p)
@@ -141,9 +159,9 @@ def sort(keys: np.ndarray, payload: np.ndarray | None = None, want_perm: bool = 
 def sort_segmented(keys: np.ndarray, offsets: np.ndarray, payload: np.ndarray | None = None):
     dt = dtype_code(keys)
     k = np.ascontiguousarray(keys).copy()
-    p = None if payload is None else np.ascontiguousarray(payload, dtype=np.uint32).copy()
+    p, pw = _payload(payload)
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
-    rc = lib().orc_sort_segmented(_p(k), _p(p), _p(off), off.size - 1, dt)
+    rc = lib().orc_sort_segmented(_p(k), _p(p), pw, _p(off), off.size - 1, dt)
     if rc:
         raise MemoryError("oracle sort: out of memory")
     return k, p

@@ -14,7 +14,8 @@
  * neither fuses nor reorders what is written here.
  *
  * Contents (each function cites the passage it follows):
- *   1. key order and model input          (Sec. 5 key extractor; Sec. 3.1 monotonicity)
+ *   1. key order and model input          (Sec. 5 key extractor; Sec. 3.1 monotonicity);
+ *      float64, uint64, int64 and float32 keys
  *   2. the sort itself: stable merge sort  (Sec. 2.1 sorted position; Sec. 2.2 sortedness)
  *   3. sampling                            (Sec. 2.2 "1% sample"; Alg. 5 Sample)
  *   4. duplicate fraction and policy       (Alg. 5; Sec. 4 constants)
@@ -43,6 +44,8 @@
 
 #define ORC_F64 0
 #define ORC_U64 1
+#define ORC_I64 2   /* two's-complement int64, numeric order */
+#define ORC_F32 3   /* binary32, IEEE-754 totalOrder; 4-byte keys */
 
 /* ------------------------------------------------------------------------ */
 /* 1. Key order and model input                                             */
@@ -53,10 +56,18 @@
  * the result orders keys by IEEE-754 totalOrder:
  * -NaN < -inf < ... < -0.0 < +0.0 < ... < +inf < +NaN.
  * Negative values have every bit flipped, non-negative ones the sign bit set.
- * For uint64 keys the map is the identity. */
+ * For uint64 keys the map is the identity.  For int64 keys it moves the
+ * range [-2^63, 2^63) onto [0, 2^64) by adding 2^63 (mod 2^64), which is the
+ * same as flipping the sign bit.  binary32 keys (the low 32 bits of `raw`)
+ * take the binary64 rule on their own 32 bits; the result fits in 32 bits. */
 uint64_t orc_ord(uint64_t raw, int dtype)
 {
     if (dtype == ORC_U64) return raw;
+    if (dtype == ORC_I64) return raw + 0x8000000000000000ull;
+    if (dtype == ORC_F32) {
+        uint32_t b = (uint32_t)raw;
+        return (b >> 31) ? (uint32_t)~b : (b | 0x80000000u);
+    }
     if (raw >> 63) return ~raw;
     return raw | 0x8000000000000000ull;
 }
@@ -64,6 +75,11 @@ uint64_t orc_ord(uint64_t raw, int dtype)
 uint64_t orc_unord(uint64_t ord, int dtype)
 {
     if (dtype == ORC_U64) return ord;
+    if (dtype == ORC_I64) return ord - 0x8000000000000000ull;
+    if (dtype == ORC_F32) {
+        uint32_t o = (uint32_t)ord;
+        return (o >> 31) ? (o & 0x7fffffffu) : (uint32_t)~o;
+    }
     if (ord >> 63) return ord & 0x7fffffffffffffffull;
     return ~ord;
 }
@@ -105,29 +121,39 @@ static void merge_pass(const orc_pair *src, orc_pair *dst, uint64_t n, uint64_t 
 /* The definition the method must reach (Sec. 2.1: a key's place in the sorted
  * array is given by how many keys precede it; Sec. 2.2: the output must be
  * sorted whatever the model does).  Ties keep input order, so with a payload
- * the result is the unique stable sort.  On return keys[] is sorted, payload[]
- * (nullable) is permuted with it, and perm[] (nullable) holds, for each output
- * slot, the input index it came from.  Returns 0, or -1 when out of memory. */
-int orc_sort(uint64_t *keys, uint32_t *payload, uint64_t *perm, uint64_t n, int dtype)
+ * the result is the unique stable sort.  keys[] holds n keys of `dtype` (8
+ * bytes each, 4 for ORC_F32); payload[] (nullable) n values of pwidth bytes
+ * (4 or 8).  On return keys[] is sorted, payload[] is permuted with it, and
+ * perm[] (nullable) holds, for each output slot, the input index it came
+ * from.  Returns 0, or -1 when out of memory or on a bad width. */
+int orc_sort(void *keys, void *payload, int pwidth, uint64_t *perm, uint64_t n, int dtype)
 {
     if (n == 0) return 0;
+    if (payload && pwidth != 4 && pwidth != 8) return -1;
+    const int kw = dtype == ORC_F32 ? 4 : 8;
     orc_pair *a = (orc_pair *)malloc(n * sizeof(orc_pair));
     orc_pair *b = (orc_pair *)malloc(n * sizeof(orc_pair));
     if (!a || !b) { free(a); free(b); return -1; }
-    for (uint64_t i = 0; i < n; i++) { a[i].k = orc_ord(keys[i], dtype); a[i].i = i; }
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t raw = 0;
+        memcpy(&raw, (const char *)keys + i * kw, kw);
+        a[i].k = orc_ord(raw, dtype);
+        a[i].i = i;
+    }
     for (uint64_t w = 1; w < n; w *= 2) {
         merge_pass(a, b, n, w);
         orc_pair *t = a; a = b; b = t;
     }
-    uint32_t *pl = NULL;
+    char *pl = NULL;
     if (payload) {
-        pl = (uint32_t *)malloc(n * sizeof(uint32_t));
+        pl = (char *)malloc(n * pwidth);
         if (!pl) { free(a); free(b); return -1; }
-        memcpy(pl, payload, n * sizeof(uint32_t));
+        memcpy(pl, payload, n * pwidth);
     }
     for (uint64_t i = 0; i < n; i++) {
-        keys[i] = orc_unord(a[i].k, dtype);
-        if (payload) payload[i] = pl[a[i].i];
+        uint64_t raw = orc_unord(a[i].k, dtype);
+        memcpy((char *)keys + i * kw, &raw, kw);
+        if (payload) memcpy((char *)payload + i * pwidth, pl + a[i].i * pwidth, pwidth);
         if (perm) perm[i] = a[i].i;
     }
     free(pl); free(a); free(b);
@@ -135,12 +161,15 @@ int orc_sort(uint64_t *keys, uint32_t *payload, uint64_t *perm, uint64_t n, int 
 }
 
 /* Segment i is [off[i], off[i+1]); each is sorted on its own. */
-int orc_sort_segmented(uint64_t *keys, uint32_t *payload, const uint64_t *off, uint64_t m, int dtype)
+int orc_sort_segmented(void *keys, void *payload, int pwidth, const uint64_t *off, uint64_t m, int dtype)
 {
+    const int kw = dtype == ORC_F32 ? 4 : 8;
     for (uint64_t s = 0; s < m; s++) {
         uint64_t lo = off[s], hi = off[s + 1];
         if (hi <= lo) continue;
-        if (orc_sort(keys + lo, payload ? payload + lo : NULL, NULL, hi - lo, dtype)) return -1;
+        if (orc_sort((char *)keys + lo * kw, payload ? (char *)payload + lo * pwidth : NULL, pwidth, NULL,
+                     hi - lo, dtype))
+            return -1;
     }
     return 0;
 }
