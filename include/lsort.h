@@ -41,7 +41,14 @@
 extern "C" {
 #endif
 
-typedef enum { LS_F64 = 0, LS_U64 = 1 } ls_dtype;
+/* Key types.  The partition engine works on 8-byte words in the order of
+ * float64 totalOrder or uint64; the other two are mapped onto those around
+ * the engine by order-preserving bijections: int64 by flipping the sign bit
+ * (in place, undone afterwards), float32 by widening to the float64 of the
+ * same value (NaNs keep sign and payload) in the workspace, 8 bytes per key,
+ * and narrowing back bit for bit.  The single-step entry points take
+ * LS_F64 / LS_U64 only. */
+typedef enum { LS_F64 = 0, LS_U64 = 1, LS_I64 = 2, LS_F32 = 3 } ls_dtype;
 
 typedef enum {
     LS_OK = 0,
@@ -136,13 +143,24 @@ typedef struct {
 
 /* ---- Sorting -------------------------------------------------------------- */
 
-/* Sort keys[0..n) in place (stable), permuting payload (nullable) with them.
- * keys: device, 8-byte aligned, n keys of `dtype`.  payload: device, 4-byte
- * aligned, n entries, or NULL.  opt: NULL for defaults.  n = 0 or 1 is a
- * no-op.  Errors: LS_EINVAL (null keys with n > 0, bad dtype, misalignment,
- * option out of range), LS_ENOMEM, LS_EHIP. */
+/* Sort keys[0..n) in place (stable), permuting payload (nullable) with them
+ * (Sec. 2.2 partitioning into buckets, Sec. 2.4 recursion and equality
+ * buckets, Alg. 5 model choice; the result is the unique stable sort).
+ * keys: device, n keys of `dtype`, 8-byte aligned (4-byte for LS_F32).
+ * payload: device, 4-byte aligned, n entries, or NULL.  opt: NULL for
+ * defaults.  n = 0 or 1 is a no-op.  Errors: LS_EINVAL (null keys with n > 0,
+ * bad dtype, misalignment, option out of range), LS_ENOMEM, LS_EHIP. */
 ls_status ls_sort(void *keys, uint64_t n, ls_dtype dtype, uint32_t *payload,
                   const ls_options *opt, void *stream);
+
+/* ls_sort with a 64-bit payload (device, 8-byte aligned, n entries, not
+ * NULL; any 8-byte values, e.g. row ids or pointers).  The engine sorts the
+ * keys with their original 32-bit indices (stable) and the payload is then
+ * gathered through them, which needs n < 2^32 and 12 more workspace bytes
+ * per key (the indices and a saved copy of the payload).  Errors as ls_sort;
+ * LS_EINVAL also for n >= 2^32. */
+ls_status ls_sort_payload64(void *keys, uint64_t n, ls_dtype dtype, uint64_t *payload,
+                            const ls_options *opt, void *stream);
 
 /* Allocation-free ls_sort, for callers that cannot allocate device or host
  * memory during the call (tight serving loops, harnesses that forbid
@@ -168,7 +186,8 @@ ls_status ls_sort_noalloc(void *keys, uint64_t n, ls_dtype dtype, uint32_t *payl
                           const ls_options *opt, void *stream);
 
 /* Sort each segment [offsets[i], offsets[i+1]) of keys independently, in
- * place, in one batched pass (all segments share every kernel launch).
+ * place, in one batched pass (all segments share every kernel launch; the
+ * counterpart of the paper's task scheduler, Sec. 2.4).
  * offsets: DEVICE array of m + 1 non-decreasing uint64 values; offsets[m] is
  * the total length.  host_total: offsets[m] as known by the host (sizes the
  * workspace; must be >= offsets[m]).  Malformed offsets are undefined
@@ -176,7 +195,8 @@ ls_status ls_sort_noalloc(void *keys, uint64_t n, ls_dtype dtype, uint32_t *payl
 ls_status ls_sort_segmented(void *keys, const uint64_t *offsets, uint64_t m, uint64_t host_total,
                             ls_dtype dtype, uint32_t *payload, const ls_options *opt, void *stream);
 
-/* Bytes of workspace a call with these sizes needs (written to *out, host). */
+/* Bytes of workspace a call with these sizes needs (written to *out, host).
+ * has_payload: 0 none, 1 uint32 payload, 2 64-bit payload. */
 ls_status ls_workspace_bytes(uint64_t n_total, uint64_t m, ls_dtype dtype, int has_payload,
                              const ls_options *opt, size_t *out);
 

@@ -149,6 +149,9 @@ struct Layout {
     uint64_t mlp_stride;  // training set = every mlp_stride-th point of the sorted sample
     uint64_t bytes;
     std::vector<Layout> nested;  // sorting the large-path sample
+    // key types / payload width mapped onto the engine's (lsort_types.hip):
+    // widened float32 keys, original indices, saved 64-bit payload
+    uint64_t o_wide = 0, o_idx = 0, o_save = 0;
 };
 
 // The MLP-rooted model is built only on the large-array path, and there for
@@ -186,6 +189,16 @@ static MlpState mlp_state(uint8_t* base, const Layout& L) {
     s.best_loss = (float*)(b + tail + 4);
     s.lo_inv = (double*)(b + tail + 16);
     return s;
+}
+
+// Extra regions at the end of a sort's workspace for the key types and the
+// payload width the engine does not handle natively.
+static void plan_types(Layout& L, uint64_t n, ls_dtype dtype, int pay64) {
+    if (dtype == LS_F32) { L.o_wide = L.bytes; L.bytes += align256(n * 8); }
+    if (pay64) {
+        L.o_idx = L.bytes; L.bytes += align256(n * 4);
+        L.o_save = L.bytes; L.bytes += align256(n * 8);
+    }
 }
 
 // Options of the engine run that sorts a large first level's sample.  The
@@ -288,10 +301,11 @@ static thread_local LastCall g_last;
 // ---------------------------------------------------------------------------
 enum KernelId {
     KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_BASE_BIG, KI_GATHER, KI_FIT, KI_MLP_TRAIN,
-    KI_MLP_IDS, KI_RESIDENT, KI_N
+    KI_MLP_IDS, KI_RESIDENT, KI_CONVERT, KI_N
 };
 static const char* KNAME[KI_N] = {"k_reset", "k_seed", "k_model", "k_hist", "k_scan", "k_scatter", "k_base_small",
-                                  "k_base_big", "k_gather", "k_fit", "k_mlp_step", "k_mlp_ids", "k_resident"};
+                                  "k_base_big", "k_gather", "k_fit", "k_mlp_step", "k_mlp_ids", "k_resident",
+                                  "k_convert"};
 struct TRec {
     int kid;
     hipEvent_t a, b;
@@ -641,6 +655,50 @@ static ls_status check_keys(const void* keys, uint64_t n, ls_dtype dtype, const 
     return LS_OK;
 }
 
+// Arguments of the sort entry points: every key type, uint32 or 64-bit payload.
+static ls_status check_sort_args(const void* keys, uint64_t n, ls_dtype dtype, const void* payload, int pay64) {
+    if (dtype != LS_F64 && dtype != LS_U64 && dtype != LS_I64 && dtype != LS_F32)
+        return fail(LS_EINVAL, "dtype must be LS_F64, LS_U64, LS_I64 or LS_F32");
+    if (n > 0 && !keys) return fail(LS_EINVAL, "keys is NULL");
+    if (((uintptr_t)keys) & (dtype == LS_F32 ? 3 : 7))
+        return fail(LS_EINVAL, dtype == LS_F32 ? "keys must be 4-byte aligned" : "keys must be 8-byte aligned");
+    if (((uintptr_t)payload) & (pay64 ? 7 : 3))
+        return fail(LS_EINVAL, pay64 ? "payload must be 8-byte aligned" : "payload must be 4-byte aligned");
+    if (pay64 && n > 0 && !payload) return fail(LS_EINVAL, "payload is NULL");
+    if (pay64 && n >= (1ull << 32)) return fail(LS_EINVAL, "64-bit payloads need fewer than 2^32 keys");
+    if (n >= (1ull << 45)) return fail(LS_EINVAL, "n too large");
+    return LS_OK;
+}
+
+// Before the engine runs: int64 keys flipped to uint64 order in place,
+// float32 keys widened into the workspace (the engine then sorts those),
+// 64-bit payloads saved and replaced by the original indices.
+static ls_status types_before(Call& c, void* keys, void* payload, ls_dtype dtype, int pay64, const Layout& L,
+                              uint8_t* base, uint32_t cus) {
+    if (dtype == LS_I64) TIMED(KI_CONVERT, c.st, launch_flip_sign((uint64_t*)keys, c.n, cus, c.st));
+    if (dtype == LS_F32) {
+        c.keys = (uint64_t*)(base + L.o_wide);
+        TIMED(KI_CONVERT, c.st, launch_widen((const uint32_t*)keys, c.keys, c.n, cus, c.st));
+    }
+    if (pay64) {
+        c.pay = (uint32_t*)(base + L.o_idx);
+        TIMED(KI_CONVERT, c.st, launch_index_save((const uint64_t*)payload, (uint64_t*)(base + L.o_save), c.pay,
+                                                  c.n, cus, c.st));
+    }
+    return LS_OK;
+}
+
+// After it: the inverse maps, and the payload gathered through the indices.
+static ls_status types_after(const Call& c, void* keys, void* payload, ls_dtype dtype, int pay64, const Layout& L,
+                             uint8_t* base, uint32_t cus) {
+    if (pay64)
+        TIMED(KI_CONVERT, c.st, launch_gather64((const uint64_t*)(base + L.o_save), c.pay, (uint64_t*)payload, c.n,
+                                                cus, c.st));
+    if (dtype == LS_I64) TIMED(KI_CONVERT, c.st, launch_flip_sign((uint64_t*)keys, c.n, cus, c.st));
+    if (dtype == LS_F32) TIMED(KI_CONVERT, c.st, launch_narrow(c.keys, (uint32_t*)keys, c.n, cus, c.st));
+    return LS_OK;
+}
+
 static ls_status order_after_last(DevPool* pool, hipStream_t st) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(st, &cs));
@@ -663,8 +721,8 @@ static ls_status mark_done(DevPool* pool, hipStream_t st, Ctl* ctl) {
 }
 
 static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, uint64_t n, ls_dtype dtype,
-                             uint32_t* payload, const ls_options* opt, void* stream) {
-    ls_status s = check_keys(keys, n, dtype, payload);
+                             void* payload, int pay64, const ls_options* opt, void* stream) {
+    ls_status s = check_sort_args(keys, n, dtype, payload, pay64);
     if (s) return s;
     Opts o;
     if ((s = normalize(opt, o, n, m))) return s;
@@ -673,6 +731,7 @@ static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, ui
     if (n <= 1 || m == 0) return LS_OK;
     std::lock_guard<std::mutex> lk(g_mu);
     Layout L = plan(n, m, payload != nullptr, o);
+    plan_types(L, n, dtype, pay64);
     DevPool* pool;
     uint8_t* base;
     hipStream_t st = (hipStream_t)stream;
@@ -680,10 +739,12 @@ static ls_status sort_common(void* keys, const uint64_t* offsets, uint64_t m, ui
     if ((s = order_after_last(pool, st))) return s;
     if ((s = prepare_status(pool, base, L, st))) return s;
     Call c{};
-    c.keys = (uint64_t*)keys; c.pay = payload; c.n = n; c.m = m; c.offsets = offsets; c.u64 = dtype == LS_U64;
+    c.keys = (uint64_t*)keys; c.pay = (uint32_t*)payload; c.n = n; c.m = m; c.offsets = offsets;
+    c.u64 = dtype == LS_U64 || dtype == LS_I64;
     c.o = o; c.st = st;
-    s = run(c, L, base, pool);
-    if (s) return s;
+    if ((s = types_before(c, keys, payload, dtype, pay64, L, base, (uint32_t)pool->cus))) return s;
+    if ((s = run(c, L, base, pool))) return s;
+    if ((s = types_after(c, keys, payload, dtype, pay64, L, base, (uint32_t)pool->cus))) return s;
     return mark_done(pool, st, (Ctl*)(base + L.o_ctl));
 }
 
@@ -724,14 +785,15 @@ static ls_status noalloc_pool(DevPool*& pool) {
 
 static ls_status sort_noalloc(void* keys, uint64_t n, ls_dtype dtype, uint32_t* payload, const ls_options* opt,
                               void* stream) {
-    ls_status s = check_keys(keys, n, dtype, payload);
+    ls_status s = check_sort_args(keys, n, dtype, payload, 0);
     if (s) return s;
     Opts o;
     if ((s = normalize(opt, o, n, 1))) return s;
     o.flags = (o.flags & ~(uint32_t)LS_FLAG_SYNC_LEVELS) | LS_FLAG_FIXED_LEVELS;
     if (n <= 1) return LS_OK;
     std::lock_guard<std::mutex> lk(g_mu);
-    const Layout L = plan(n, 1, payload != nullptr, o);
+    Layout L = plan(n, 1, payload != nullptr, o);
+    plan_types(L, n, dtype, 0);
     if (L.bytes > LS_NOALLOC_SCRATCH_BYTES)
         return fail(LS_ENOMEM, "ls_sort_noalloc: " + std::to_string(n) + " keys need " + std::to_string(L.bytes) +
                                    " bytes of scratch; the fixed scratch array holds " +
@@ -744,10 +806,13 @@ static ls_status sort_noalloc(void* keys, uint64_t n, ls_dtype dtype, uint32_t* 
     // layout (the array keeps the previous call's contents)
     if ((s = prepare_status(pool, base, L, st))) return s;
     Call c{};
-    c.keys = (uint64_t*)keys; c.pay = payload; c.n = n; c.m = 1; c.offsets = nullptr; c.u64 = dtype == LS_U64;
+    c.keys = (uint64_t*)keys; c.pay = payload; c.n = n; c.m = 1; c.offsets = nullptr;
+    c.u64 = dtype == LS_U64 || dtype == LS_I64;
     c.o = o; c.st = st;
     t_untimed = true;
-    s = run(c, L, base, pool);
+    s = types_before(c, keys, payload, dtype, 0, L, base, (uint32_t)pool->cus);
+    if (!s) s = run(c, L, base, pool);
+    if (!s) s = types_after(c, keys, payload, dtype, 0, L, base, (uint32_t)pool->cus);
     t_untimed = false;
     if (s) return s;
     int dev = 0;
@@ -786,7 +851,12 @@ const char* ls_last_error(void) { return g_err.c_str(); }
 const char* ls_version(void) { return "lsort 0.1 gfx950"; }
 
 ls_status ls_sort(void* keys, uint64_t n, ls_dtype dtype, uint32_t* payload, const ls_options* opt, void* stream) {
-    return sort_common(keys, nullptr, 1, n, dtype, payload, opt, stream);
+    return sort_common(keys, nullptr, 1, n, dtype, payload, 0, opt, stream);
+}
+
+ls_status ls_sort_payload64(void* keys, uint64_t n, ls_dtype dtype, uint64_t* payload, const ls_options* opt,
+                            void* stream) {
+    return sort_common(keys, nullptr, 1, n, dtype, payload, 1, opt, stream);
 }
 
 ls_status ls_sort_noalloc(void* keys, uint64_t n, ls_dtype dtype, uint32_t* payload, const ls_options* opt,
@@ -799,17 +869,21 @@ ls_status ls_sort_segmented(void* keys, const uint64_t* offsets, uint64_t m, uin
     if (m > 0 && !offsets) return fail(LS_EINVAL, "offsets is NULL");
     if (((uintptr_t)offsets) & 7) return fail(LS_EINVAL, "offsets must be 8-byte aligned");
     if (m >= (1ull << 32)) return fail(LS_EINVAL, "too many segments");
-    return sort_common(keys, offsets, m, host_total, dtype, payload, opt, stream);
+    return sort_common(keys, offsets, m, host_total, dtype, payload, 0, opt, stream);
 }
 
 ls_status ls_workspace_bytes(uint64_t n_total, uint64_t m, ls_dtype dtype, int has_payload, const ls_options* opt,
                              size_t* out) {
     if (!out) return fail(LS_EINVAL, "out is NULL");
-    if (dtype != LS_F64 && dtype != LS_U64) return fail(LS_EINVAL, "bad dtype");
+    if (dtype != LS_F64 && dtype != LS_U64 && dtype != LS_I64 && dtype != LS_F32) return fail(LS_EINVAL, "bad dtype");
+    if (has_payload < 0 || has_payload > 2) return fail(LS_EINVAL, "has_payload must be 0, 1 or 2");
     Opts o;
     ls_status s = normalize(opt, o, std::max<uint64_t>(n_total, 16), std::max<uint64_t>(m, 1));
     if (s) return s;
-    *out = (size_t)plan(std::max<uint64_t>(n_total, 16), std::max<uint64_t>(m, 1), has_payload, o).bytes;
+    const uint64_t nn = std::max<uint64_t>(n_total, 16);
+    Layout L = plan(nn, std::max<uint64_t>(m, 1), has_payload != 0, o);
+    plan_types(L, nn, dtype, has_payload == 2);
+    *out = (size_t)L.bytes;
     return LS_OK;
 }
 

@@ -114,6 +114,15 @@ void tuning_install(const std::vector<TuneEntry>& t);
 int report_error(int status, const char* msg);  // sets ls_last_error(), returns status
 hipError_t launch_tune_fill(double* keys, const uint64_t* offsets, uint64_t m, uint64_t seed, hipStream_t st);
 
+// key types and payload widths mapped onto the engine's (lsort_types.hip)
+hipError_t launch_flip_sign(uint64_t* k, uint64_t n, uint32_t cus, hipStream_t st);
+hipError_t launch_widen(const uint32_t* src, uint64_t* dst, uint64_t n, uint32_t cus, hipStream_t st);
+hipError_t launch_narrow(const uint64_t* src, uint32_t* dst, uint64_t n, uint32_t cus, hipStream_t st);
+hipError_t launch_index_save(const uint64_t* pay, uint64_t* save, uint32_t* idx, uint64_t n, uint32_t cus,
+                             hipStream_t st);
+hipError_t launch_gather64(const uint64_t* save, const uint32_t* idx, uint64_t* pay, uint64_t n, uint32_t cus,
+                           hipStream_t st);
+
 // reference streams (lsort_stream.hip): copy of n words; wrapping sum of n words into *sum
 hipError_t launch_stream_copy(const uint64_t* src, uint64_t* dst, uint64_t n, uint32_t cus, hipStream_t st);
 hipError_t launch_stream_read(const uint64_t* src, uint64_t n, uint64_t* sum, uint32_t cus, hipStream_t st);

@@ -217,6 +217,25 @@ def adversarial(kind: str, n: int, seed: int = 0) -> np.ndarray:
         a = np.where((u >= 1e-4) & (u < 2e-4), neg_nan, a)
         a = np.where((u >= 2e-4) & (u < 3e-4), -0.0, a)
         return np.where((u >= 3e-4) & (u < 4e-4), 0.0, a)
+    if kind == "f32_specials":
+        # float32 normal keys with every class of special value: NaNs of both
+        # signs with payload bits (quiet and signalling), infinities, signed
+        # zeros, subnormals and the extreme normals
+        a = g.normal(0, 10, n).astype(np.float32)
+        pool = np.array([0xFFC00001, 0xFFC00000, 0xFF800001, 0xFF800000, 0xFF7FFFFF, 0x80800000, 0x807FFFFF,
+                         0x80000001, 0x80000000, 0x00000000, 0x00000001, 0x007FFFFF, 0x00800000, 0x7F7FFFFF,
+                         0x7F800000, 0x7F800001, 0x7FC00000, 0x7FC00001], dtype=np.uint32).view(np.float32)
+        sel = g.random(n) < 0.1
+        a[sel] = pool[g.integers(0, pool.size, int(sel.sum()))]
+        return a
+    if kind == "i64_extremes":
+        # int64 keys: the full range, the extremes and a heavy run of one small value
+        a = g.integers(-2**63, 2**63 - 1, n, dtype=np.int64, endpoint=True)
+        ext = np.array([-2**63, -2**63 + 1, -1, 0, 1, 2**63 - 2, 2**63 - 1], dtype=np.int64)
+        sel = g.random(n) < 0.1
+        a[sel] = ext[g.integers(0, ext.size, int(sel.sum()))]
+        a[g.random(n) < 0.2] = -3
+        return a
     raise ValueError(kind)
 
 

@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblsort.so")
 
-LS_F64, LS_U64 = 0, 1
+LS_F64, LS_U64, LS_I64, LS_F32 = 0, 1, 2, 3
 MODEL = {"auto": 0, "rmi": 1, "mlp": 2, "splitter": 3}
 FLAG_NO_FALLBACK, FLAG_SYNC_LEVELS, FLAG_FIXED_LEVELS, FLAG_COLLECT_STATS, FLAG_TUNED = 1, 2, 4, 8, 16
 MAX_STAT_LEVELS = 32
@@ -64,6 +64,7 @@ def lib():
         sig = {
             "ls_sort": [vp, u64, i32, vp, vp, vp],
             "ls_sort_noalloc": [vp, u64, i32, vp, vp, vp],
+            "ls_sort_payload64": [vp, u64, i32, vp, vp, vp],
             "ls_sort_segmented": [vp, vp, u64, u64, i32, vp, vp, vp],
             "ls_workspace_bytes": [u64, u64, i32, i32, vp, vp],
             "ls_set_workspace": [vp, C.c_size_t, vp],
@@ -115,12 +116,21 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
-def _dtype(t: torch.Tensor) -> int:
-    if t.dtype == torch.float64:
-        return LS_F64
-    if t.dtype == torch.uint64:
-        return LS_U64
-    raise TypeError(f"keys must be float64 or uint64, got {t.dtype}")
+def _dtype(t) -> int:
+    """Key-type code of a tensor (or of a torch dtype)."""
+    d = t if isinstance(t, torch.dtype) else t.dtype
+    codes = {torch.float64: LS_F64, torch.uint64: LS_U64, torch.int64: LS_I64, torch.float32: LS_F32}
+    if d not in codes:
+        raise TypeError(f"keys must be float64, uint64, int64 or float32, got {d}")
+    return codes[d]
+
+
+def _dtype_engine(t: torch.Tensor) -> int:
+    """Code for the single-step entry points (float64 / uint64 only)."""
+    c = _dtype(t)
+    if c not in (LS_F64, LS_U64):
+        raise TypeError(f"this step takes float64 or uint64 keys, got {t.dtype}")
+    return c
 
 
 def _dev(t: torch.Tensor, name: str):
@@ -148,14 +158,24 @@ def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, ma
     return o
 
 
+PAYLOAD64 = (torch.uint64, torch.int64, torch.float64)
+
+
 def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, **opts) -> None:
-    """Sort keys (float64 totalOrder / uint64) in place; payload (uint32) follows stably."""
+    """Sort keys (float64 / float32 by totalOrder, uint64 / int64 numerically)
+    in place; payload (uint32, or any 8-byte type) follows stably."""
     _dev(keys, "keys")
+    o = make_options(**opts)
     if payload is not None:
         _dev(payload, "payload")
-        if payload.dtype != torch.uint32 or payload.numel() != keys.numel():
-            raise ValueError("payload must be uint32 with one entry per key")
-    o = make_options(**opts)
+        if payload.numel() != keys.numel():
+            raise ValueError("payload must have one entry per key")
+        if payload.dtype in PAYLOAD64:
+            _check(lib().ls_sort_payload64(_ptr(keys), keys.numel(), _dtype(keys), _ptr(payload), C.byref(o),
+                                           _stream()))
+            return
+        if payload.dtype != torch.uint32:
+            raise ValueError("payload must be uint32 or an 8-byte type")
     _check(lib().ls_sort(_ptr(keys), keys.numel(), _dtype(keys), _ptr(payload), C.byref(o), _stream()))
 
 
@@ -201,11 +221,12 @@ def stats() -> dict:
             "overflow": s.overflow}
 
 
-def workspace_bytes(n: int, m: int = 1, dtype=torch.float64, payload: bool = False, **opts) -> int:
+def workspace_bytes(n: int, m: int = 1, dtype=torch.float64, payload=False, **opts) -> int:
+    """payload: False / True (uint32) / 64 (64-bit payload)."""
     out = C.c_size_t()
     o = make_options(**opts)
-    _check(lib().ls_workspace_bytes(n, m, LS_F64 if dtype == torch.float64 else LS_U64, int(payload), C.byref(o),
-                                    C.byref(out)))
+    has = 2 if payload == 64 else int(bool(payload))
+    _check(lib().ls_workspace_bytes(n, m, _dtype(dtype), has, C.byref(o), C.byref(out)))
     return out.value
 
 
@@ -222,14 +243,14 @@ def set_workspace(buf: torch.Tensor | None) -> None:
 def sample(keys: torch.Tensor, seed: int, S: int) -> torch.Tensor:
     _dev(keys, "keys")
     out = torch.empty(S, dtype=keys.dtype, device=keys.device)
-    _check(lib().ls_sample(_ptr(keys), keys.numel(), _dtype(keys), seed, S, _ptr(out), _stream()))
+    _check(lib().ls_sample(_ptr(keys), keys.numel(), _dtype_engine(keys), seed, S, _ptr(out), _stream()))
     return out
 
 
 def rmi_fit(sorted_sample: torch.Tensor, L: int, R: float) -> torch.Tensor:
     _dev(sorted_sample, "sorted_sample")
     out = torch.empty(2 + 4 * L, dtype=torch.float64, device=sorted_sample.device)
-    _check(lib().ls_rmi_fit(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), L, float(R), _ptr(out),
+    _check(lib().ls_rmi_fit(_ptr(sorted_sample), sorted_sample.numel(), _dtype_engine(sorted_sample), L, float(R), _ptr(out),
                             _stream()))
     return out
 
@@ -237,7 +258,7 @@ def rmi_fit(sorted_sample: torch.Tensor, L: int, R: float) -> torch.Tensor:
 def rmi_fit_block(sorted_sample: torch.Tensor, L: int, R: int) -> torch.Tensor:
     _dev(sorted_sample, "sorted_sample")
     out = torch.empty(2 + 4 * L, dtype=torch.float64, device=sorted_sample.device)
-    _check(lib().ls_rmi_fit_block(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), L, float(R),
+    _check(lib().ls_rmi_fit_block(_ptr(sorted_sample), sorted_sample.numel(), _dtype_engine(sorted_sample), L, float(R),
                                   _ptr(out), _stream()))
     return out
 
@@ -246,7 +267,7 @@ def rmi_buckets(keys: torch.Tensor, params: torch.Tensor, L: int, R: float) -> t
     _dev(keys, "keys")
     _dev(params, "params")
     out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
-    _check(lib().ls_rmi_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(params), L, float(R), _ptr(out),
+    _check(lib().ls_rmi_buckets(_ptr(keys), keys.numel(), _dtype_engine(keys), _ptr(params), L, float(R), _ptr(out),
                                 _stream()))
     return out
 
@@ -256,7 +277,7 @@ def splitters(sorted_sample: torch.Tensor, B: int):
     u = torch.empty(max(B - 1, 1), dtype=torch.uint64, device=sorted_sample.device)
     eq = torch.zeros(max(B - 1, 1), dtype=torch.uint8, device=sorted_sample.device)
     m = torch.zeros(1, dtype=torch.uint32, device=sorted_sample.device)
-    _check(lib().ls_splitters(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), B, _ptr(u), _ptr(eq),
+    _check(lib().ls_splitters(_ptr(sorted_sample), sorted_sample.numel(), _dtype_engine(sorted_sample), B, _ptr(u), _ptr(eq),
                               _ptr(m), _stream()))
     k = int(m.cpu().item())
     return u[:k], eq[:k]
@@ -267,7 +288,7 @@ def splitter_buckets(keys: torch.Tensor, u: torch.Tensor, eq: torch.Tensor) -> t
     u = u.contiguous()
     eq = eq.contiguous()
     out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
-    _check(lib().ls_splitter_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(u), _ptr(eq), u.numel(), _ptr(out),
+    _check(lib().ls_splitter_buckets(_ptr(keys), keys.numel(), _dtype_engine(keys), _ptr(u), _ptr(eq), u.numel(), _ptr(out),
                                      _stream()))
     return out
 
@@ -277,7 +298,7 @@ def partition_rmi(keys, params, L, R, nb, payload=None):
     ok = torch.empty_like(keys)
     op = None if payload is None else torch.empty_like(payload)
     counts = torch.zeros(nb, dtype=torch.uint64, device=keys.device)
-    _check(lib().ls_partition_rmi(_ptr(keys), _ptr(payload), keys.numel(), _dtype(keys), _ptr(params), L, float(R), nb,
+    _check(lib().ls_partition_rmi(_ptr(keys), _ptr(payload), keys.numel(), _dtype_engine(keys), _ptr(params), L, float(R), nb,
                                   _ptr(ok), _ptr(op), _ptr(counts), _stream()))
     return ok, op, counts
 
@@ -288,7 +309,7 @@ def partition_splitters(keys, u, eq, payload=None):
     op = None if payload is None else torch.empty_like(payload)
     nb = u.numel() + 1 + int(eq.to(torch.int64).sum().item())
     counts = torch.zeros(nb, dtype=torch.uint64, device=keys.device)
-    _check(lib().ls_partition_splitters(_ptr(keys), _ptr(payload), keys.numel(), _dtype(keys), _ptr(u), _ptr(eq),
+    _check(lib().ls_partition_splitters(_ptr(keys), _ptr(payload), keys.numel(), _dtype_engine(keys), _ptr(u), _ptr(eq),
                                         u.numel(), _ptr(ok), _ptr(op), _ptr(counts), _stream()))
     return ok, op, counts
 
@@ -319,7 +340,7 @@ def mlp_train(sorted_sample: torch.Tensor, steps: int, lr: float, params_init: t
     params = torch.empty(MLP_NP, dtype=torch.float32, device=dev)
     lo_inv = torch.empty(2, dtype=torch.float64, device=dev)
     losses = torch.empty(max(steps, 1), dtype=torch.float32, device=dev)
-    _check(lib().ls_mlp_train(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), _ptr(params_init),
+    _check(lib().ls_mlp_train(_ptr(sorted_sample), sorted_sample.numel(), _dtype_engine(sorted_sample), _ptr(params_init),
                               steps, float(lr), _ptr(params), _ptr(lo_inv), _ptr(losses), _stream()))
     return params, lo_inv, losses[:steps]
 
@@ -327,7 +348,7 @@ def mlp_train(sorted_sample: torch.Tensor, steps: int, lr: float, params_init: t
 def mlp_buckets(keys: torch.Tensor, params: torch.Tensor, lo_inv: torch.Tensor, R: int) -> torch.Tensor:
     _dev(keys, "keys")
     out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
-    _check(lib().ls_mlp_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(params), _ptr(lo_inv), R, _ptr(out),
+    _check(lib().ls_mlp_buckets(_ptr(keys), keys.numel(), _dtype_engine(keys), _ptr(params), _ptr(lo_inv), R, _ptr(out),
                                 _stream()))
     return out
 
@@ -336,7 +357,7 @@ def mlp_rmi_fit(sorted_sample: torch.Tensor, params: torch.Tensor, lo_inv: torch
                 R: float) -> torch.Tensor:
     _dev(sorted_sample, "sorted_sample")
     leaves = torch.empty(4 * L, dtype=torch.float64, device=sorted_sample.device)
-    _check(lib().ls_mlp_rmi_fit(_ptr(sorted_sample), sorted_sample.numel(), _dtype(sorted_sample), _ptr(params),
+    _check(lib().ls_mlp_rmi_fit(_ptr(sorted_sample), sorted_sample.numel(), _dtype_engine(sorted_sample), _ptr(params),
                                 _ptr(lo_inv), L, float(R), _ptr(leaves), _stream()))
     return leaves
 
@@ -345,7 +366,7 @@ def mlp_rmi_buckets(keys: torch.Tensor, params: torch.Tensor, lo_inv: torch.Tens
                     R: float) -> torch.Tensor:
     _dev(keys, "keys")
     out = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
-    _check(lib().ls_mlp_rmi_buckets(_ptr(keys), keys.numel(), _dtype(keys), _ptr(params), _ptr(lo_inv), _ptr(leaves),
+    _check(lib().ls_mlp_rmi_buckets(_ptr(keys), keys.numel(), _dtype_engine(keys), _ptr(params), _ptr(lo_inv), _ptr(leaves),
                                     L, float(R), _ptr(out), _stream()))
     return out
 

@@ -259,7 +259,7 @@ def test_segmented_laws(dev, m):
 
 
 def test_errors(dev):
-    t = torch.zeros(10, dtype=torch.float32, device=dev)
+    t = torch.zeros(10, dtype=torch.int32, device=dev)
     with pytest.raises(TypeError):
         lsort.sort(t)
     k = torch.zeros(10, dtype=torch.float64, device=dev)
