@@ -23,9 +23,15 @@ object:
     RMI root vs MLP root vs splitter tree (first-level max/mean bucket ratio,
     fallbacks, Gkeys/s).
 
+  * the sample-once / model-reuse question and the sample size (refit per
+    bucket vs reuse; samples of 0.1% .. 4%), with the pivot quality;
+  * the other key types and payload widths at 1e8: float32 and int64 keys,
+    float64 keys with a 64-bit payload.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--law normal]
                        [--n 100000000] [--no-cpu-baseline] [--no-laws]
                        [--no-batched] [--no-mlp] [--no-c5] [--no-splitter]
+                       [--no-study] [--no-types]
 """
 from __future__ import annotations
 
@@ -49,6 +55,8 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2307_08637_amd", "csrc", f)
                   for f in ("lsort_kernels.hip", "lsort_dev.hpp", "lsort_internal.hpp")]
 SIGN = -(1 << 63)
+PAY_MUL = 0x2545F4914F6CDD1D                    # odd: index * PAY_MUL (mod 2^64) is a bijection
+PAY_MUL_INV = pow(PAY_MUL, -1, 1 << 64) - (1 << 64) if pow(PAY_MUL, -1, 1 << 64) >= 1 << 63 else pow(PAY_MUL, -1, 1 << 64)
 
 
 def kernel_source_sha() -> str:
@@ -75,6 +83,8 @@ def parse():
     p.add_argument("--no-c5", action="store_true", help="skip the learned-parts comparison at 1e9 keys")
     p.add_argument("--no-splitter", action="store_true", help="time the learned sort only (for profiling)")
     p.add_argument("--no-pivots", action="store_true", help="skip the pivot-quality metric")
+    p.add_argument("--no-study", action="store_true", help="skip the sampling / refit study")
+    p.add_argument("--no-types", action="store_true", help="skip the other key types and payload widths")
     p.add_argument("--mlp-n", type=int, default=100_000_000, help="keys of the piecewise-law comparison")
     p.add_argument("--c5-n", type=int, default=1_000_000_000, help="keys of the large piecewise-law comparison")
     return p.parse_args()
@@ -288,6 +298,16 @@ def main():
             torch.cuda.empty_cache()
             mlp["n_1e9"] = run_learned_parts(inputs, lsort, torch, np, dev, a.c5_n, a.seed, reps=2)
 
+    study = None
+    if not a.no_study:
+        torch.cuda.empty_cache()
+        study = run_sampling_study(inputs, lsort, torch, np, dev, a.n, a.seed)
+
+    types = None
+    if not a.no_types:
+        torch.cuda.empty_cache()
+        types = run_types(inputs, lsort, torch, np, dev, a.n, a.seed)
+
     per_level = per_level_rates(L["records"], a.n, a.steps)
     out = {
         "metric": "Gkeys/s sorting 1e8 f64 keys, learned vs splitter buckets; % HBM peak",
@@ -326,6 +346,8 @@ def main():
         "laws": laws,
         "batched": batched,
         "learned_parts": mlp,
+        "sampling_study": study,
+        "key_types": types,
     }
     print(json.dumps(out), flush=True)
 
@@ -352,7 +374,7 @@ def per_level_rates(recs, n, steps):
     return res
 
 
-def pivot_quality(src, out, lsort, torch, seed, B=256, L=1000):
+def pivot_quality(src, out, lsort, torch, seed, B=256, L=1000, sample_frac=0.01):
     """Table 1 metric (Sec. 3.4): sum over B-1 pivots p_i of
     |P(A <= p_i) - (i + 1) / B|, P taken over the sorted keys `out`.
       learned:  the RMI's implicit pivots (Alg. 4: the largest key of each of
@@ -366,7 +388,7 @@ def pivot_quality(src, out, lsort, torch, seed, B=256, L=1000):
                 paper's random-sample column)."""
     n = src.numel()
     dev = src.device
-    S = max(n // 100, B)
+    S = max(int(n * sample_frac), B)
     smp = lsort.sample(src, seed, S)
     lsort.sort(smp, stats=False)
     tgt = torch.arange(1, B, dtype=torch.float64, device=dev) / B
@@ -553,25 +575,115 @@ def run_learned_parts(inputs, lsort, torch, np, dev, n, seed, reps):
     return res
 
 
-def run_on(src, bufs, model, lsort, torch):
+def run_on(src, bufs, model, lsort, torch, **opts):
     """ms per sort of `src` (K = len(bufs) copies, after one warm-up), and
     the statistics of one more sort."""
     tmp = bufs[0]
     tmp.copy_(src)
-    lsort.sort(tmp, model=model, stats=False)
+    lsort.sort(tmp, model=model, stats=False, **opts)
     for b in bufs:
         b.copy_(src)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for b in bufs:
-        lsort.sort(b, model=model, stats=False)
+        lsort.sort(b, model=model, stats=False, **opts)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / len(bufs)
     tmp.copy_(src)
-    lsort.sort(tmp, model=model)
+    lsort.sort(tmp, model=model, **opts)
     return ms, lsort.stats()
+
+
+def run_types(inputs, lsort, torch, np, dev, n, seed, reps=3):
+    """float32 keys (the normal law rounded to float32), int64 keys (the
+    uniform 64-bit law read as signed) and float64 keys with a 64-bit
+    payload: Gkeys/s of the whole call (the maps around the engine
+    included), each output checked sorted and the same multiset."""
+    res = {"n": n}
+    h = inputs.generate("normal", n, seed=seed)
+    cases = [("float32", torch.from_numpy(h.astype(np.float32)).to(dev), None),
+             ("int64", torch.from_numpy(inputs.generate("u64", n, seed=seed).view(np.int64)).to(dev), None),
+             ("float64_payload64", torch.from_numpy(h).to(dev),
+              torch.arange(n, dtype=torch.int64, device=dev).mul_(PAY_MUL))]
+    del h
+    for name, src, pay in cases:
+        log("key types:", name)
+        buf = torch.empty_like(src)
+        pbuf = None if pay is None else torch.empty_like(pay)
+
+        def before():
+            buf.copy_(src)
+            if pay is not None:
+                pbuf.copy_(pay)
+        ms = time_call(lambda: lsort.sort(buf, pbuf, stats=False), reps, before, torch)
+        before()
+        lsort.sort(buf, pbuf, stats=False)
+        k = buf.view(torch.int32).to(torch.int64) if src.dtype == torch.float32 else buf.view(torch.int64)
+        if src.dtype == torch.float32:
+            kk = torch.where(k < 0, k ^ 0x7FFFFFFF, k)
+        else:
+            kk = k if src.dtype == torch.int64 else torch.where(k < 0, k ^ 0x7FFFFFFF_FFFFFFFF, k)
+        ok = bool((kk[:-1] <= kk[1:]).all().item())
+        s0 = src.view(torch.int32).to(torch.int64) if src.dtype == torch.float32 else src.view(torch.int64)
+        ok = ok and mix_hash(k, torch) == mix_hash(s0, torch)
+        if pay is not None:  # payload: the key's original index times an odd constant, so it names the key
+            idx = pbuf * PAY_MUL_INV  # (wrapping) the original index back
+            ok = ok and bool(((idx >= 0) & (idx < n)).all().item()) and torch.equal(src[idx], buf)
+            del idx
+        if not ok:
+            raise SystemExit(f"bench: output for key type {name} is not a sorted permutation")
+        res[name] = {"ms": round(ms, 3), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3)}
+        del buf, pbuf, k, kk, s0
+    return res
+
+
+def run_sampling_study(inputs, lsort, torch, np, dev, n, seed, laws=("normal", "lognormal")):
+    """The sample-once vs sample-per-call question (Sec. 3.3: LearnedSort
+    samples once and reuses its model; Sec. 5.1: AIPS2o trains a model per
+    recursive call) and the sample size (Sec. 6 future work on sampling):
+    per law at n keys, the reused model (default) against a fresh model per
+    bucket (refit), and the 1% sample against smaller and larger ones --
+    Gkeys/s, max/mean bucket ratio per level, fallbacks, and the Table 1
+    pivot quality of the RMI fitted on that sample.  Every output is checked
+    sorted and the same multiset as the input."""
+    res = {"n": n, "workload": f"sort {n} float64 keys per law, 3 timed sorts per configuration"}
+    bufs = None
+    for law in laws:
+        log("sampling study:", law)
+        h = inputs.generate(law, n, seed=seed)
+        src = torch.from_numpy(h).to(dev)
+        del h
+        ms0 = multiset(src, torch)
+        if bufs is None:
+            bufs = [torch.empty_like(src) for _ in range(3)]
+        ref = bufs[0]
+        ref.copy_(src)
+        lsort.sort(ref, stats=False)
+        out = ref.clone()
+        row = {}
+        configs = [("reuse", {}), ("refit", {"refit": True})] + [
+            (f"sample_{f:g}", {"sample_frac": f}) for f in (0.001, 0.0025, 0.04)]
+        for name, opts in configs:
+            ms, st = run_on(src, bufs, "auto", lsort, torch, **opts)
+            for b in bufs:
+                if not is_sorted(b, torch) or multiset(b, torch) != ms0:
+                    raise SystemExit(f"bench: sampling-study output ({law}, {name}) is not a sorted permutation")
+            lv = st["levels"]
+            row[name] = {"Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 4),
+                         "max_over_mean": [x["max_bucket_x1000_over_mean"] / 1000.0 for x in lv],
+                         "fallback": [x["fallback"] for x in lv],
+                         "learned_segments": [x["learned"] for x in lv], "tree_segments": [x["tree"] for x in lv]}
+        for f in (0.001, 0.0025, 0.01, 0.04):
+            q = pivot_quality(src, out, lsort, torch, seed, sample_frac=f)
+            key = "reuse" if f == 0.01 else f"sample_{f:g}"
+            row[key]["pivot_quality_rmi"] = q["learned_rmi"]
+            row[key]["pivot_quality_splitter"] = q["splitter_quantiles"]
+        res[law] = row
+        del src, out
+    del bufs
+    return res
 
 
 if __name__ == "__main__":

@@ -80,6 +80,10 @@ typedef enum {
                                        invalid */
 #define LS_FLAG_COLLECT_STATS 0x8u  /* record per-level statistics (read with ls_get_stats) */
 #define LS_FLAG_TUNED         0x10u /* take buckets / cutoff / tree_buckets left 0 from the loaded tuning table */
+#define LS_FLAG_REFIT         0x20u /* a learned bucket that needs another level gets a model of its own (a
+                                       fresh sample and fit under the Alg. 5 policy, as AIPS2o trains per
+                                       call, Sec. 5.1) instead of the parent's model evaluated at a finer
+                                       resolution (LearnedSort's reuse, Sec. 3.3); default off */
 
 /* Options.  Zero-initialise and set struct_size = sizeof(ls_options); every
  * zero field takes its default. */

@@ -94,6 +94,7 @@ struct Seg {
 };
 static_assert(sizeof(Seg) == 64, "segment descriptor is 64 bytes");
 constexpr uint32_t FLAG_STATS = 0x8u;   // LS_FLAG_COLLECT_STATS: per-level statistics wanted
+constexpr uint32_t FLAG_REFIT = 0x20u;  // LS_FLAG_REFIT: children of learned buckets get fresh models
 constexpr uint32_t SEG_PREBUILT = 1u;  // model already built (large first level)
 constexpr uint32_t SEG_FAILED = 2u;    // capacity exceeded; not partitioned
 constexpr uint32_t SEG_RESIDENT = 4u;  // sorted by one workgroup (k_resident): no work units

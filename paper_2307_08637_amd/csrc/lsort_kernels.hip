@@ -599,7 +599,8 @@ __device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q,
         return d;
     }
     const bool oversized = (double)c > P.fallback_ratio * expected;
-    const bool fine = fine_ok && !oversized && (4ull << log2B2) <= c && (uint32_t)lvl + 1 < P.max_levels;
+    const bool fine = fine_ok && !(P.flags & FLAG_REFIT) && !oversized && (4ull << log2B2) <= c &&
+                      (uint32_t)lvl + 1 < P.max_levels;
     // The base case takes a bucket at or below the cutoff, and any bucket it
     // can hold (BIG_MAX): sorting it directly is one pass, another level is at
     // least a partition pass plus the fixed work of a segment.  At the depth

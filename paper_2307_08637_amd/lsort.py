@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "liblsort.so")
 
 LS_F64, LS_U64, LS_I64, LS_F32 = 0, 1, 2, 3
 MODEL = {"auto": 0, "rmi": 1, "mlp": 2, "splitter": 3}
-FLAG_NO_FALLBACK, FLAG_SYNC_LEVELS, FLAG_FIXED_LEVELS, FLAG_COLLECT_STATS, FLAG_TUNED = 1, 2, 4, 8, 16
+FLAG_NO_FALLBACK, FLAG_SYNC_LEVELS, FLAG_FIXED_LEVELS, FLAG_COLLECT_STATS, FLAG_TUNED, FLAG_REFIT = 1, 2, 4, 8, 16, 32
 MAX_STAT_LEVELS = 32
 
 
@@ -142,7 +142,7 @@ def _dev(t: torch.Tensor, name: str):
 
 def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, max_levels=0, flags=0,
                  sample_frac=0.0, fallback_ratio=0.0, seed=0, mlp_steps=0, mlp_sample=0, mlp_lr=0.0, tile=0,
-                 stats=True, fixed_levels=False, no_fallback=False, tuned=False) -> Options:
+                 stats=True, fixed_levels=False, no_fallback=False, tuned=False, refit=False) -> Options:
     o = Options()
     o.struct_size = C.sizeof(Options)
     o.model = MODEL[model] if isinstance(model, str) else int(model)
@@ -151,6 +151,7 @@ def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, ma
     f |= FLAG_FIXED_LEVELS if fixed_levels else FLAG_SYNC_LEVELS
     f |= FLAG_NO_FALLBACK if no_fallback else 0
     f |= FLAG_TUNED if tuned else 0
+    f |= FLAG_REFIT if refit else 0
     o.flags = f
     o.sample_frac, o.fallback_ratio, o.seed = sample_frac, fallback_ratio, seed
     o.mlp_steps, o.mlp_sample, o.mlp_lr = mlp_steps, mlp_sample, mlp_lr

@@ -169,6 +169,24 @@ def test_large_1e7_oracle(dev, law):
     assert_same_bits(got, oracle.sort(keys)[0])
 
 
+@pytest.mark.parametrize("law,n,buckets,pay", [("normal", 20_000_000, 100, True), ("exponential", 3_000_000, 0, False),
+                                                ("u64", 12_000_000, 60, False)])
+def test_refit_per_bucket(dev, law, n, buckets, pay):
+    """Every bucket that needs another level gets a model of its own (fresh
+    sample and fit, the policy deciding): every output word equal to the
+    oracle's, and the children of the large cases are learned models."""
+    keys = inputs.generate(law, n, seed=n % 89)
+    payload = np.arange(n, dtype=np.uint32) if pay else None
+    got, gp = gpu_sort(keys, dev, payload, refit=True, buckets=buckets)
+    st = lsort.stats()["levels"]
+    if buckets:
+        assert len(st) >= 2 and st[1]["learned"] > 0, st[:2]
+    want, wp = oracle.sort(keys, payload)
+    assert_same_bits(got, want)
+    if pay:
+        assert np.array_equal(gp, wp)
+
+
 @pytest.mark.parametrize("tile", [65536, 131072, 524288])
 @pytest.mark.parametrize("law,n,pay", [("normal", 2_500_000, False), ("u64", 700_003, True),
                                        ("lognormal", 3_000_017, True)])
