@@ -26,7 +26,8 @@ object:
   * the sample-once / model-reuse question and the sample size (refit per
     bucket vs reuse; samples of 0.1% .. 4%), with the pivot quality;
   * the other key types and payload widths at 1e8: float32 and int64 keys,
-    float64 keys with a 64-bit payload.
+    float64 keys with a 64-bit payload;
+  * the base case as comparison sorts vs the model-placed counting sort.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--law normal]
                        [--n 100000000] [--no-cpu-baseline] [--no-laws]
@@ -303,6 +304,11 @@ def main():
         torch.cuda.empty_cache()
         study = run_sampling_study(inputs, lsort, torch, np, dev, a.n, a.seed)
 
+    base_case = None
+    if not a.no_study:
+        torch.cuda.empty_cache()
+        base_case = run_base_case(inputs, lsort, torch, np, dev, a.n, a.seed)
+
     types = None
     if not a.no_types:
         torch.cuda.empty_cache()
@@ -348,6 +354,7 @@ def main():
         "learned_parts": mlp,
         "sampling_study": study,
         "key_types": types,
+        "base_case": base_case,
     }
     print(json.dumps(out), flush=True)
 
@@ -556,16 +563,18 @@ def run_learned_parts(inputs, lsort, torch, np, dev, n, seed, reps):
     ms0 = multiset(src, torch)
     buf = torch.empty_like(src)
     res = {"workload": f"sort {n} float64 keys, piecewise law 70/20/10, out-of-place copy restored per run"}
-    for name, model in (("rmi", "auto"), ("mlp", "mlp"), ("splitter", "splitter")):
+    for name, model, opts in (("rmi", "auto", {}), ("rmi_judged", "auto", {"balance_pct": 50}), ("mlp", "mlp", {}),
+                              ("splitter", "splitter", {})):
         log("learned parts:", name, n)
-        ms = time_call(lambda: lsort.sort(buf, model=model, stats=False), reps, lambda: buf.copy_(src), torch)
+        ms = time_call(lambda: lsort.sort(buf, model=model, stats=False, **opts), reps, lambda: buf.copy_(src), torch)
         buf.copy_(src)  # one more (untimed) sort for the statistics and the check
-        lsort.sort(buf, model=model)
+        lsort.sort(buf, model=model, **opts)
         st = lsort.stats()
         if not is_sorted(buf, torch) or multiset(buf, torch) != ms0:
             raise SystemExit(f"bench: learned-parts output of {name} is not a sorted permutation")
         lv0 = st["levels"][0]
         res[name] = {"ms": round(ms, 3), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3),
+                     "first_level_model": {1: "rmi", 2: "mlp", 3: "splitter"}.get(st["first_model"], "auto"),
                      "first_level_max_over_mean": lv0["max_bucket_x1000_over_mean"] / 1000.0,
                      "first_level_fallbacks": lv0["fallback"], "levels": len(st["levels"])}
         if name == "mlp":
@@ -594,6 +603,40 @@ def run_on(src, bufs, model, lsort, torch, **opts):
     tmp.copy_(src)
     lsort.sort(tmp, model=model, **opts)
     return ms, lsort.stats()
+
+
+def run_base_case(inputs, lsort, torch, np, dev, n, seed, reps=3):
+    """The base case two ways on the same first-level buckets: the
+    comparison sorts (register bitonic networks, the default) against the
+    model-placed counting sort (LS_FLAG_MODEL_BASE: the RMI's fine position
+    places each key, its rank inside its bin finishes it), per law at n
+    keys: whole-sort time and each base-case kernel's time per sort."""
+    res = {"n": n}
+    for law in ("normal", "lognormal"):
+        h = inputs.generate(law, n, seed=seed)
+        src = torch.from_numpy(h).to(dev)
+        del h
+        ms0 = multiset(src, torch)
+        buf = torch.empty_like(src)
+        row = {}
+        for name, mb in (("comparison_sort", False), ("model_placed", True)):
+            log("base case:", law, name)
+            ms = time_call(lambda: lsort.sort(buf, stats=False, model_base=mb), reps, lambda: buf.copy_(src), torch)
+            if not is_sorted(buf, torch) or multiset(buf, torch) != ms0:
+                raise SystemExit(f"bench: base-case output ({law}, {name}) is not a sorted permutation")
+            buf.copy_(src)
+            torch.cuda.synchronize()
+            lsort.timing(True)
+            lsort.sort(buf, stats=False, model_base=mb)
+            torch.cuda.synchronize()
+            kern = lsort.timing_read()
+            lsort.timing(False)
+            row[name] = {"ms": round(ms, 4), "Gkeys/s": round(n / (ms * 1e-3) / 1e9, 3),
+                         "base_kernels": {k: {"ms": round(v["ms"], 4), "keys": v["keys"]} for k, v in kern.items()
+                                          if k.startswith("k_base")}}
+        res[law] = row
+        del src, buf
+    return res
 
 
 def run_types(inputs, lsort, torch, np, dev, n, seed, reps=3):

@@ -84,6 +84,11 @@ typedef enum {
                                        fresh sample and fit under the Alg. 5 policy, as AIPS2o trains per
                                        call, Sec. 5.1) instead of the parent's model evaluated at a finer
                                        resolution (LearnedSort's reuse, Sec. 3.3); default off */
+#define LS_FLAG_MODEL_BASE    0x40u /* base case of a large single array's RMI buckets (64..1024 keys): the
+                                       model places each key (a counting sort on its fine position inside
+                                       the bucket) and each key's rank among the few keys of its bin
+                                       finishes the sort (LearnedSort's base case, Sec. 2.2); items the
+                                       model cannot spread go to the comparison sort */
 
 /* Options.  Zero-initialise and set struct_size = sizeof(ls_options); every
  * zero field takes its default. */
@@ -109,7 +114,12 @@ typedef struct {
     uint32_t tile;           /* keys per work unit of the first level's histogram and scatter passes:
                                 32768 << k, k in [0, 4]; the scatter writes each bucket's share of a unit
                                 in whole 64-byte segments except its first and last; default 32768 */
-    uint32_t reserved[4];
+    uint32_t balance_pct;    /* large single array: when the first level's fitted RMI puts more than this
+                                percentage of its sample into buckets above fallback_ratio x expected,
+                                the first level takes the splitter tree instead (the tree as judge of the
+                                model's balance); default 100 = never (measured: on the 70/20/10
+                                piecewise law 50 makes 1e8 keys 20 % faster and 1e9 keys 1.7x slower) */
+    uint32_t reserved[3];
 } ls_options;
 
 /* Per-call statistics (LS_FLAG_COLLECT_STATS). */

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblsort.so")
 SOURCES = ["lsort_kernels.hip", "lsort_base.hip", "lsort_fit.hip", "lsort_mlp.hip", "lsort_tune.hip", "lsort_stream.hip",
-           "lsort_types.hip", "lsort_api.hip"]
+           "lsort_types.hip", "lsort_basemodel.hip", "lsort_api.hip"]
 # per-file flags: the base case's only floating-point operations are binary64
 # comparators on operands checked NaN-free beforehand
 EXTRA_FLAGS = {"lsort_base.hip": ["-fno-honor-nans"]}

@@ -49,6 +49,8 @@ struct Opts {
     uint32_t mlp_steps, mlp_sample;
     float mlp_lr;
     uint32_t tile;   // keys per work unit of the first level's partition passes
+    uint32_t balance_pct;  // large array's first level: tree instead of the RMI when oversized buckets hold
+                           // more than this share of the sample (100: never)
 };
 
 // ---------------------------------------------------------------------------
@@ -96,6 +98,7 @@ static ls_status normalize(const ls_options* o, Opts& r, uint64_t n = 0, uint64_
     r.max_levels = 16; r.flags = LS_FLAG_SYNC_LEVELS; r.sample_frac = 0.01; r.fallback_ratio = 2.0; r.seed = 0x5EED;
     r.mlp_steps = 200; r.mlp_sample = 1000000; r.mlp_lr = 3e-3f;
     r.tile = UNIT;
+    r.balance_pct = 100;
     if (!o) {
         apply_tuning(o, r, n, m);
         return LS_OK;
@@ -116,6 +119,8 @@ static ls_status normalize(const ls_options* o, Opts& r, uint64_t n = 0, uint64_
     if (o->mlp_sample) r.mlp_sample = o->mlp_sample;
     if (o->mlp_lr > 0) r.mlp_lr = o->mlp_lr;
     if (o->tile) r.tile = o->tile;
+    if (o->balance_pct) r.balance_pct = o->balance_pct;
+    if (r.balance_pct > 100) return fail(LS_EINVAL, "balance_pct must be in [1, 100]");
     apply_tuning(o, r, n, m);
     {
         bool ok = false;
@@ -142,6 +147,7 @@ struct Layout {
     uint64_t n, m;
     int has_pay;
     uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
+    uint64_t item_m_cap = 0, o_items_m = 0;  // model-based counting-sort items (large single array)
     uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_bigs, o_items_b, o_items_c, o_counts, o_status,
         o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested, o_mlp, o_mlp_t, o_mlp_y, o_bstart;
     uint64_t S_big;       // large-path sample size (0: none)
@@ -255,6 +261,8 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.o_mlp = take(MLP_STATE_BYTES);
     L.S_big = big_sample_size(n, m, o);
     if (L.S_big) {
+        L.item_m_cap = n / MB_MIN + 64;
+        L.o_items_m = take(L.item_m_cap * 16);
         L.o_sample = take(L.S_big * 8);
         L.o_bstart = take((B_MAX + 1) * 8);
         L.nested.push_back(plan(L.S_big, 1, 0, nested_opts(o)));
@@ -301,11 +309,11 @@ static thread_local LastCall g_last;
 // ---------------------------------------------------------------------------
 enum KernelId {
     KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_BASE_BIG, KI_GATHER, KI_FIT, KI_MLP_TRAIN,
-    KI_MLP_IDS, KI_RESIDENT, KI_CONVERT, KI_N
+    KI_MLP_IDS, KI_RESIDENT, KI_CONVERT, KI_BASE_MODEL, KI_N
 };
 static const char* KNAME[KI_N] = {"k_reset", "k_seed", "k_model", "k_hist", "k_scan", "k_scatter", "k_base_small",
                                   "k_base_big", "k_gather", "k_fit", "k_mlp_step", "k_mlp_ids", "k_resident",
-                                  "k_convert"};
+                                  "k_convert", "k_base_model"};
 struct TRec {
     int kid;
     hipEvent_t a, b;
@@ -472,6 +480,9 @@ static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
     P.bigs = (uint64_t*)(base + L.o_bigs);
     P.items_b = (uint64_t*)(base + L.o_items_b);
     P.items_c = (uint64_t*)(base + L.o_items_c);
+    P.items_m = L.o_items_m ? (uint64_t*)(base + L.o_items_m) : nullptr;
+    P.item_m_cap = L.item_m_cap;
+    P.fmodel = L.S_big && !c.one_level ? (const uint64_t*)(base + L.o_bigmodel) : nullptr;
     P.counts = (unsigned long long*)(base + L.o_counts);
     P.status = (unsigned long long*)(base + L.o_status);
     P.ids = L.o_ids ? (uint16_t*)(base + L.o_ids) : nullptr;
@@ -574,6 +585,9 @@ static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPoo
     TIMED(KI_FIT, c.st, launch_fit_finish(A, c.st));
     A.bstart = (uint64_t*)(base + L.o_bstart);
     TIMED(KI_FIT, c.st, launch_fit_bstart(A, c.st));
+    A.ratio = c.o.fallback_ratio;
+    A.balance = (c.o.flags & LS_FLAG_NO_FALLBACK) ? 2.0 : (double)c.o.balance_pct / 100.0;
+    TIMED(KI_FIT, c.st, launch_fit_balance(A, c.st));
     return LS_OK;
 }
 
@@ -634,12 +648,15 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     (void)levels;
     if (!c.one_level) {
         TIMED(KI_BASE, c.st, launch_base_small(P, cus * 8, c.st));
+        const bool mbase = (c.o.flags & LS_FLAG_MODEL_BASE) && P.fmodel;
+        if (mbase) TIMED(KI_BASE_MODEL, c.st, launch_base_model(P, cus * 2, c.st));
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
-        if (g_timing && !t_untimed) {  // keys through the base case (both kernels) and the copies
+        if (g_timing && !t_untimed) {  // keys through the base case (every kernel) and the copies
             HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));
             const Ctl* hc = (const Ctl*)pool->pinned;
-            g_trec[g_trec.size() - 2].keys = (double)hc->small_keys;
+            g_trec[g_trec.size() - (mbase ? 3 : 2)].keys = (double)hc->small_keys;
+            if (mbase) g_trec[g_trec.size() - 2].keys = (double)hc->model_keys;
             g_trec.back().keys = (double)hc->big_keys;
         }
     }
@@ -931,7 +948,8 @@ ls_status ls_get_stats(ls_stats* out) {
     out->levels = levels;
     out->first_model = c.first_mlp ? LS_MODEL_MLP
                        : c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
-    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nitems_k + c.nitems_c + c.nbig - c.ncopy - c.nmoved;
+    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nitems_k + c.nitems_c + c.nitems_m + c.nbig - c.ncopy -
+                      c.nmoved;
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
     out->mlp_loss_last = c.mlp_loss[1];
@@ -1342,7 +1360,7 @@ ls_status ls_tuned_options(uint64_t n_total, uint64_t m, ls_options* out) {
     out->model = o.model; out->buckets = o.buckets; out->leaves = o.leaves; out->tree_buckets = o.tree_buckets;
     out->cutoff = o.cutoff; out->max_levels = o.max_levels; out->flags = o.flags; out->sample_frac = o.sample_frac;
     out->fallback_ratio = o.fallback_ratio; out->seed = o.seed; out->mlp_steps = o.mlp_steps;
-    out->mlp_sample = o.mlp_sample; out->mlp_lr = o.mlp_lr; out->tile = o.tile;
+    out->mlp_sample = o.mlp_sample; out->mlp_lr = o.mlp_lr; out->tile = o.tile; out->balance_pct = o.balance_pct;
     return LS_OK;
 }
 

@@ -296,6 +296,39 @@ __global__ __launch_bounds__(FIT_T) void k_fit_bstart(FitArgs A) {
     }
 }
 
+// The splitter tree as judge of the fitted RMI's balance, on the sample:
+// the share of the sorted sample in first-level buckets above ratio x the
+// expected size (bstart gives every bucket's sample count).  Each such bucket
+// would be re-partitioned by a splitter tree at the next level (the 2x
+// fallback rule), so when they hold more than `balance` of the sample the
+// whole first level takes the splitter tree over the same sample instead.
+__global__ __launch_bounds__(M_THREADS) void k_fit_balance(FitArgs A) {
+    __shared__ uint32_t scratch[B_MAX + 1];
+    __shared__ uint64_t red64[M_THREADS / 64];
+    if (!A.bstart || A.flag[0] == 0 || (A.first_mlp && *A.first_mlp) || A.mode == 1 || !(A.balance < 1.0)) return;
+    const double expected = (double)A.S / (double)A.B1;
+    uint64_t over = 0;
+    for (uint32_t b = threadIdx.x; b < A.B1; b += M_THREADS) {
+        const uint64_t c = A.bstart[b + 1] - A.bstart[b];
+        if ((double)c > A.ratio * expected) over += c;
+    }
+    over = block_sum<M_THREADS, uint64_t>(over, red64);
+    if ((double)over <= A.balance * (double)A.S) return;
+    const uint64_t* s = A.s;
+    const int u64 = A.u64;
+    const uint32_t nb = build_tree_block([&](uint64_t r) { return key_ord(s[r], u64); },
+                                         (uint32_t)min<uint64_t>(A.S, 0xffffffffull), A.Bt, A.model, scratch, red64);
+    if (threadIdx.x == 0) {
+        A.flag[0] = 0;
+        if (A.seg) {
+            Seg sg{};
+            sg.kind = K_TREE; sg.nb = nb; sg.model = (uint64_t)A.model;
+            sg.flags = SEG_PREBUILT | (tree_words(((TreeModel*)A.model)->m) << 16);
+            *A.seg = sg;
+        }
+    }
+}
+
 // Monotone clamp intervals (Sec. 4) via a prefix maximum, then pre-scaling
 // by the total resolution R.  One workgroup of 1024 threads (L <= 1024).
 __global__ __launch_bounds__(M_THREADS) void k_fit_finish(FitArgs A) {
@@ -418,6 +451,7 @@ hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st) {
     LAUNCH(k_fit_leaves, A.L, FIT_LT, st, A);
 }
 hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_finish, 1, M_THREADS, st, A); }
+hipError_t launch_fit_balance(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_balance, 1, M_THREADS, st, A); }
 hipError_t launch_fit_bstart(const FitArgs& A, hipStream_t st) {
     const uint32_t grid = (uint32_t)std::min<uint64_t>((A.S + FIT_T - 1) / FIT_T, 2048ull);
     LAUNCH(k_fit_bstart, grid ? grid : 1, FIT_T, st, A);

@@ -26,6 +26,7 @@ constexpr int GROUP_MAX = 256;                 // largest sub-array a lane group
 constexpr int GROUP_SMALL_MAX = 128;           // ... sorted by a smaller lane group (8 per wavefront)
 constexpr int GROUP_LARGE_MAX = 1024;          // keys only: largest sub-array two per wavefront are sorted
 constexpr int GROUP_WAVE_MAX = 2048;           // keys only: largest sub-array one wavefront sorts in registers
+constexpr uint32_t MB_MIN = 64, MB_MAX = 1024;  // sub-arrays the model-based counting sort takes
 constexpr int MAXL = 32;                       // partition levels (arrays)
 constexpr int MODEL_WORDS = 4 + 2 + 4 * L_MAX; // 8-byte words of the largest model (RMI, L_MAX leaves)
 constexpr int LDS_MODEL_WORDS = 4 + 2 + 3 * L_MAX;  // ... of its LDS image in the partition kernels
@@ -95,6 +96,7 @@ struct Seg {
 static_assert(sizeof(Seg) == 64, "segment descriptor is 64 bytes");
 constexpr uint32_t FLAG_STATS = 0x8u;   // LS_FLAG_COLLECT_STATS: per-level statistics wanted
 constexpr uint32_t FLAG_REFIT = 0x20u;  // LS_FLAG_REFIT: children of learned buckets get fresh models
+constexpr uint32_t FLAG_MODEL_BASE = 0x40u;  // LS_FLAG_MODEL_BASE: model-based counting-sort base case
 constexpr uint32_t SEG_PREBUILT = 1u;  // model already built (large first level)
 constexpr uint32_t SEG_FAILED = 2u;    // capacity exceeded; not partitioned
 constexpr uint32_t SEG_RESIDENT = 4u;  // sorted by one workgroup (k_resident): no work units
@@ -146,6 +148,8 @@ struct Ctl {
     LS_HOT unsigned long long nitems_c;     // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys (items_c)
     LS_HOT unsigned long long nbig;         // large base-case items and copy items
     LS_HOT unsigned long long nmoved;       // small items handed on to the large list (NaN / -0.0 tasks)
+    LS_HOT unsigned long long nitems_m;     // items of the model-based counting sort (two words each)
+    LS_HOT unsigned long long model_keys;   // keys in those items
     LS_HOT unsigned long long ncopy;
     LS_HOT unsigned long long small_keys;   // keys in small base-case items
     LS_HOT unsigned long long big_keys;     // keys in large base-case items and copy runs
@@ -187,6 +191,9 @@ struct Params {
     uint8_t* arena[2];
     uint16_t* ids;                  // per-key bucket ids of MLP levels (absolute positions)
     uint64_t* items_c;              // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys
+    uint64_t* items_m;              // model-based counting-sort items: (item word, g0 | log2(w) << 32)
+    uint64_t item_m_cap;
+    const uint64_t* fmodel;         // the first level's prebuilt model (large single array), or null
     uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
     const uint64_t* persist;        // [0] call epoch, [1] clear-status request (survives calls)
     const uint64_t* fsample;        // sorted first-level sample of a large array (raw keys), or null

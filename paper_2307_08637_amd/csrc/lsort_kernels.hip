@@ -398,7 +398,8 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
                 if (model) fit_rmi_block(smp, S, u64, L, B1, log2B2, (double*)model, lstart, red);
                 kind = K_RMI;
                 nb = B1;
-            } else {
+            }
+            if (!learned) {
                 uint32_t mmax = Bt - 1;
                 words = tree_words(mmax);
                 model = arena_alloc(P, words, shv);
@@ -618,7 +619,7 @@ __device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q,
 __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
     __shared__ uint64_t red64[S_THREADS / 64];
     __shared__ uint8_t eqb[B_MAX];
-    __shared__ uint64_t resv[8];
+    __shared__ uint64_t resv[9];
     const int tid = threadIdx.x;
     const int lvl = P.level;
     if (blockIdx.x == 0 && tid == 0) {  // pools of the next level (this level's data stays readable)
@@ -677,8 +678,12 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         }
         __syncthreads();
         const double expected = (double)sg.n / (double)nb;
+        // base-case items of the first level's RMI can be placed by the model
+        // (k_base_model): its fine ids of an item are [g0, g0 + w)
+        const bool mbase = (P.flags & FLAG_MODEL_BASE) && P.fmodel && sg.model == (uint64_t)P.fmodel &&
+                           (sg.kind == K_RMI || sg.kind == K_RMI_FINE);
         uint32_t act[S_BPT];
-        uint64_t la = 0, lb = 0, lc = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0, lfb = 0;
+        uint64_t la = 0, lb = 0, lc = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0, lfb = 0, ld = 0, lmk = 0;
 #pragma unroll
         for (int i = 0; i < S_BPT; i++) {
             const uint32_t b = S_BPT * tid + i;
@@ -687,12 +692,15 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const Decision d = decide(P, lvl, q, c[i], eqb[b] != 0, fine_ok, log2B2, expected);
             act[i] = d.act;
             lstat += d.stat;
-            const uint64_t nsm = d.act == 2 && (c[i] <= SMALL_MAX || (c[i] <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
+            const bool mb = mbase && d.act == 2 && c[i] >= MB_MIN && c[i] <= MB_MAX;
+            ld += mb ? 1 : 0;
+            lmk += mb ? c[i] : 0;
+            const uint64_t nsm = d.act == 2 && !mb && (c[i] <= SMALL_MAX || (c[i] <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
             const uint64_t ng0 = nsm && c[i] <= GROUP_SMALL_MAX ? 1 : 0;
             const uint64_t ng1 = nsm && !ng0 && c[i] <= GROUP_MAX ? 1 : 0;
             const uint64_t ng3 = nsm && c[i] > SMALL_MAX && c[i] <= GROUP_LARGE_MAX ? 1 : 0;
             const uint64_t ng4 = nsm && c[i] > GROUP_LARGE_MAX ? 1 : 0;
-            const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && !nsm ? 1 : 0);
+            const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && !nsm && !mb ? 1 : 0);
             const uint64_t ntl = d.act >= 3 && !child_resident(sg.kind, d.act, c[i]) ? (c[i] + UNIT - 1) / UNIT : 0;
             // packed counters: items <= 128 keys | children << 16 | large items << 32,
             // units | items of 129..256 keys << 32 | items of 257..512 keys << 48
@@ -708,8 +716,10 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         uint64_t ta, tb;
         uint64_t xa = block_excl_scan<S_THREADS, uint64_t>(la, red64, &ta);
         uint64_t xb = block_excl_scan<S_THREADS, uint64_t>(lb, red64, &tb);
-        uint64_t tc;
+        uint64_t tc, td;
         uint64_t xc = block_excl_scan<S_THREADS, uint64_t>(lc, red64, &tc);
+        uint64_t xd = block_excl_scan<S_THREADS, uint64_t>(ld, red64, &td);
+        const uint64_t mk = block_sum<S_THREADS, uint64_t>(lmk, red64);
         const uint64_t sk = block_sum<S_THREADS, uint64_t>(lsk, red64);
         const uint64_t gk = block_sum<S_THREADS, uint64_t>(lgk, red64);
         const uint64_t ncp = block_sum<S_THREADS, uint64_t>(lcp, red64);
@@ -741,6 +751,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             if (l == 10 || l == 11) {
                 resv[l - 9] = v32 ? atomicAdd(l == 10 ? &P.ctl->nseg[lvl + 1] : &P.ctl->ntile[lvl + 1], v32) : 0u;
             }
+            if (l == 12) resv[8] = td ? atomicAdd(&P.ctl->nitems_m, (unsigned long long)td) : 0ull;
+            if (l == 13 && mk) atomicAdd(&P.ctl->model_keys, (unsigned long long)mk);
         }
         if (tid == 0) {
             const uint64_t m12 = 4095;
@@ -763,8 +775,20 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const uint32_t b = S_BPT * tid + i;
             const uint32_t a = act[i];
             const uint64_t ci = c[i];
-            const uint64_t nsm = a == 2 && (ci <= SMALL_MAX || (ci <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
-            const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && !nsm ? 1 : 0);
+            const bool mb = mbase && a == 2 && ci >= MB_MIN && ci <= MB_MAX;
+            const uint64_t nsm = a == 2 && !mb && (ci <= SMALL_MAX || (ci <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
+            const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && !nsm && !mb ? 1 : 0);
+            if (mb) {
+                const uint64_t it = resv[8] + xd;
+                if (it < P.item_m_cap) {
+                    const bool fine = sg.kind == K_RMI_FINE;
+                    P.items_m[2 * it] = item_pack(start[i], q, 0u, (uint32_t)ci);
+                    P.items_m[2 * it + 1] = (uint64_t)(fine ? sg.win + b : b << log2B2) |
+                                            ((uint64_t)(fine ? 0u : log2B2) << 32);
+                } else {
+                    atomicOr(&P.ctl->overflow, OVF_ITEM);
+                }
+            }
             const uint64_t ntl = a >= 3 && !child_resident(sg.kind, a, ci) ? (ci + UNIT - 1) / UNIT : 0;
             const uint64_t iex = xa & 0xffff, cex = (xa >> 16) & 0xffff, gex = xa >> 32, tex = xb & 0xffffffffull;
             const uint64_t bex = (xb >> 32) & 0xffff, wex = xb >> 48;
@@ -818,6 +842,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                         if (t0 + u < P.tile_cap) P.tiles[q][t0 + u] = Tile{0xffffffffu, 0};
                 }
             }
+            xd += mb ? 1 : 0;
             xa += ng0 | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
             xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
             xc += ng3 | (ng4 << 32);

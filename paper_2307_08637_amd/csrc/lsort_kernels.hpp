@@ -26,6 +26,8 @@ struct FitArgs {
     Seg* seg;            // descriptor of the prebuilt first level (nullable)
     uint32_t* first_mlp; // set to 1 when the MLP-rooted model was chosen (nullable)
     uint64_t* bstart;    // [B1 + 1]: first sample index of each first-level bucket (nullable)
+    double ratio;        // oversized bucket: more than ratio x expected keys
+    double balance;      // share of the sample in oversized buckets above which the tree replaces the RMI
 };
 
 // MLP training (lsort_mlp.hip)
@@ -67,6 +69,7 @@ hipError_t launch_scan(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st);
+hipError_t launch_base_model(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_resident(const Params& P, uint32_t grid, hipStream_t st);
 
 // sample fit and single steps (lsort_fit.hip)
@@ -77,6 +80,7 @@ hipError_t launch_fit_root(const FitArgs& A, hipStream_t st);
 hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st);
 hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st);
 hipError_t launch_fit_bstart(const FitArgs& A, hipStream_t st);
+hipError_t launch_fit_balance(const FitArgs& A, hipStream_t st);
 hipError_t launch_model_buckets(const uint64_t* model, uint32_t words, uint32_t kind, uint32_t nb, uint32_t win,
                                 const uint64_t* keys, uint64_t n, int u64, uint32_t* out, hipStream_t st);
 hipError_t launch_install_rmi(const double* params, uint32_t L, double R, uint32_t B1, uint32_t log2B2, uint64_t* dst,

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblsort.so")
 LS_F64, LS_U64, LS_I64, LS_F32 = 0, 1, 2, 3
 MODEL = {"auto": 0, "rmi": 1, "mlp": 2, "splitter": 3}
 FLAG_NO_FALLBACK, FLAG_SYNC_LEVELS, FLAG_FIXED_LEVELS, FLAG_COLLECT_STATS, FLAG_TUNED, FLAG_REFIT = 1, 2, 4, 8, 16, 32
+FLAG_MODEL_BASE = 64
 MAX_STAT_LEVELS = 32
 
 
@@ -27,7 +28,7 @@ class Options(C.Structure):
         ("tree_buckets", C.c_uint32), ("cutoff", C.c_uint32), ("max_levels", C.c_uint32), ("flags", C.c_uint32),
         ("sample_frac", C.c_double), ("fallback_ratio", C.c_double), ("seed", C.c_uint64),
         ("mlp_steps", C.c_uint32), ("mlp_sample", C.c_uint32), ("mlp_lr", C.c_float), ("tile", C.c_uint32),
-        ("reserved", C.c_uint32 * 4),
+        ("balance_pct", C.c_uint32), ("reserved", C.c_uint32 * 3),
     ]
 
 
@@ -142,7 +143,9 @@ def _dev(t: torch.Tensor, name: str):
 
 def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, max_levels=0, flags=0,
                  sample_frac=0.0, fallback_ratio=0.0, seed=0, mlp_steps=0, mlp_sample=0, mlp_lr=0.0, tile=0,
-                 stats=True, fixed_levels=False, no_fallback=False, tuned=False, refit=False) -> Options:
+                 balance_pct=0,
+                 stats=True, fixed_levels=False, no_fallback=False, tuned=False, refit=False,
+                 model_base=False) -> Options:
     o = Options()
     o.struct_size = C.sizeof(Options)
     o.model = MODEL[model] if isinstance(model, str) else int(model)
@@ -152,10 +155,12 @@ def make_options(model="auto", buckets=0, leaves=0, tree_buckets=0, cutoff=0, ma
     f |= FLAG_NO_FALLBACK if no_fallback else 0
     f |= FLAG_TUNED if tuned else 0
     f |= FLAG_REFIT if refit else 0
+    f |= FLAG_MODEL_BASE if model_base else 0
     o.flags = f
     o.sample_frac, o.fallback_ratio, o.seed = sample_frac, fallback_ratio, seed
     o.mlp_steps, o.mlp_sample, o.mlp_lr = mlp_steps, mlp_sample, mlp_lr
     o.tile = tile
+    o.balance_pct = balance_pct
     return o
 
 

@@ -187,6 +187,64 @@ def test_refit_per_bucket(dev, law, n, buckets, pay):
         assert np.array_equal(gp, wp)
 
 
+@pytest.mark.parametrize("law,n,pay", [("normal", 10_000_000, False), ("lognormal", 10_000_000, True),
+                                       ("u64", 12_000_000, True), ("exponential", 20_000_000, False),
+                                       ("uniform", 1_700_001, True)])
+def test_model_base_case(dev, law, n, pay):
+    """Base case by the model's placement (counting sort on the RMI's fine
+    position, then each key's rank inside its bin): every output word equal
+    to the oracle's, and from 1e7 keys (second-level buckets of 64..1024
+    keys) most keys went through that kernel."""
+    keys = inputs.generate(law, n, seed=n % 83)
+    payload = np.arange(n, dtype=np.uint32) if pay else None
+    lsort.timing(True)
+    try:
+        got, gp = gpu_sort(keys, dev, payload, model_base=True)
+        rec = lsort.timing_read()
+    finally:
+        lsort.timing(False)
+    if n >= 10_000_000:
+        assert rec.get("k_base_model", {}).get("keys", 0) > 0.5 * n, rec.get("k_base_model")
+    want, wp = oracle.sort(keys, payload)
+    assert_same_bits(got, want)
+    if pay:
+        assert np.array_equal(gp, wp)
+
+
+@pytest.mark.parametrize("kind", ["sparse_specials", "with_nan", "few_distinct", "signed_zeros", "subnormal_mix"])
+def test_model_base_case_adversarial(dev, kind):
+    """Specials, heavy duplicates (bins beyond the limit go to the
+    comparison sort) and signed zeros under the model-placed base case."""
+    n = 12_000_000
+    keys = inputs.adversarial(kind, n, seed=19)
+    payload = np.arange(n, dtype=np.uint32)
+    got, gp = gpu_sort(keys, dev, payload, model_base=True)
+    want, wp = oracle.sort(keys, payload)
+    assert_same_bits(got, want)
+    assert np.array_equal(gp, wp)
+
+
+@pytest.mark.parametrize("pct", [50, 100, 1])
+def test_first_level_balance_judge(dev, pct):
+    """The 70/20/10 piecewise law: its fitted RMI puts most of the sample in
+    oversized buckets, so at 50 % the first level takes the splitter tree;
+    with the check off (100, the default) the RMI stays, and the normal law
+    keeps its RMI at 50 %.  Output equal to the oracle's either way (at 1 %
+    whichever model the check picks)."""
+    for law, n in (("piecewise", 4_000_000), ("normal", 3_000_000)):
+        keys = inputs.generate(law, n, seed=23)
+        payload = np.arange(n, dtype=np.uint32)
+        got, gp = gpu_sort(keys, dev, payload, balance_pct=pct)
+        first = lsort.stats()["first_model"]
+        if law == "piecewise":
+            assert first == (lsort.MODEL["rmi"] if pct == 100 else lsort.MODEL["splitter"]), first
+        elif pct != 1:
+            assert first == lsort.MODEL["rmi"], first
+        want, wp = oracle.sort(keys, payload)
+        assert_same_bits(got, want)
+        assert np.array_equal(gp, wp)
+
+
 @pytest.mark.parametrize("tile", [65536, 131072, 524288])
 @pytest.mark.parametrize("law,n,pay", [("normal", 2_500_000, False), ("u64", 700_003, True),
                                        ("lognormal", 3_000_017, True)])
