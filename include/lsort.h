@@ -377,6 +377,18 @@ ls_status ls_partition_splitters(const void *keys, const uint32_t *payload, uint
 ls_status ls_mlp_loss_grad(const float *params, const float *t, const float *y, uint64_t S,
                            float *grad, float *loss, void *stream);
 
+/* The same loss and gradient computed by activation regions, the way the
+ * training runs: t must be non-decreasing (a sorted training set).  Every
+ * hidden pre-activation is non-decreasing in t, so each hidden unit switches
+ * on or off once along the training set; the 32 switch indices (found by
+ * binary search of the pre-activations, in FP64) cut it into at most 33 regions on which
+ * the network is affine in t, and each gradient entry is a combination of
+ * the regions' moments (count, sums of t, t^2, y, t y, y^2) from FP64 prefix
+ * sums -- the per-sample gradient summed over every sample in another order,
+ * in FP64 from the FP32 parameters, returned in FP32.  Errors: LS_EINVAL. */
+ls_status ls_mlp_loss_grad_regions(const float *params, const float *t, const float *y, uint64_t S,
+                                   float *grad, float *loss, void *stream);
+
 /* Train on a SORTED sample of S keys: t from the sample's own lo_inv
  * (written to lo_inv), targets y_i = i / S, full-batch Adam (Kingma & Ba
  * 2015; betas 0.9 / 0.999, eps 1e-8, learning rate lr) for `steps` steps
@@ -384,7 +396,9 @@ ls_status ls_mlp_loss_grad(const float *params, const float *t, const float *y, 
  * network the piecewise-linear interpolant of the sample CDF through its
  * octiles.  Adam runs on q = p / s: s = 1 / max(1, |V1_k| + |b1_k|) (at the
  * start point) for the layer-2 weights of input unit k, 1 otherwise, so that
- * no step moves a pre-activation by much more than lr.  The loss is evaluated at the start of every step; params_out
+ * no step moves a pre-activation by much more than lr.  Every step's gradient
+ * and loss are computed by activation regions (as ls_mlp_loss_grad_regions),
+ * all steps in one launch.  The loss is evaluated at the start of every step; params_out
  * (float[321]) receives the parameters with the lowest of those losses (the
  * start point when steps == 0) and losses (float[steps], nullable) the
  * losses.

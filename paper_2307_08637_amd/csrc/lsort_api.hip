@@ -158,7 +158,17 @@ struct Layout {
     // key types / payload width mapped onto the engine's (lsort_types.hip):
     // widened float32 keys, original indices, saved 64-bit payload
     uint64_t o_wide = 0, o_idx = 0, o_save = 0;
+    // MLP training by regions: prefix moments of the training set, block totals
+    uint64_t o_mlp_mom = 0, o_mlp_bsum = 0;
 };
+
+// Prefix moments of an MLP training set of S points at the end of a layout.
+static void plan_mlp_moments(Layout& L, uint64_t S, uint64_t& o_) {
+    L.o_mlp_mom = o_;
+    o_ += align256((S + 1) * MOM_W * 16);
+    L.o_mlp_bsum = o_;
+    o_ += align256(((S + MOM_BLOCK - 1) / MOM_BLOCK) * MOM_W * 16);
+}
 
 // The MLP-rooted model is built only on the large-array path, and there for
 // any array the policy could give a learned model (n >= 1e5).
@@ -273,6 +283,7 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
         L.mlp_S = (L.S_big + L.mlp_stride - 1) / L.mlp_stride;
         L.o_mlp_t = take(L.mlp_S * 4);
         L.o_mlp_y = take(L.mlp_S * 4);
+        plan_mlp_moments(L, L.mlp_S, o_);
         L.o_ids = take(n * 2);
     }
     L.bytes = o_;
@@ -568,16 +579,15 @@ static ls_status big_model(const Call& c, const Layout& L, uint8_t* base, DevPoo
         TIMED(KI_FIT, c.st, launch_mlp_prep(smp, L.S_big, L.mlp_stride, c.u64, t, y, ms.lo_inv, A.flag, c.st));
         TIMED(KI_FIT, c.st, launch_mlp_setup(t, L.mlp_S, nullptr, 1e-3, ms.p, ms.m, ms.v, ms.best, ms.scale,
                                              ms.best_loss, ms.done, A.flag, c.st));
-        for (uint32_t k = 1; k <= c.o.mlp_steps; k++) {
-            MlpStep S{};
-            S.t = t; S.y = y; S.S = L.mlp_S; S.p = ms.p; S.m = ms.m; S.v = ms.v; S.partial = ms.partial;
-            S.done = ms.done; S.loss_pair = P.ctl->mlp_loss; S.gate = A.flag; S.step = k; S.update = 1;
-            S.best = ms.best; S.best_loss = ms.best_loss; S.scale = ms.scale;
-            S.lr = c.o.mlp_lr; S.b1 = 0.9f; S.b2 = 0.999f; S.eps = 1e-8f;
-            S.c1 = (float)(1.0 - std::pow(0.9, (double)k));
-            S.c2 = (float)(1.0 - std::pow(0.999, (double)k));
-            TIMED(KI_MLP_TRAIN, c.st, launch_mlp_step(S, c.st));
-        }
+        // every Adam step of the training in one launch (gradients by activation regions)
+        double* mom = (double*)(base + L.o_mlp_mom);
+        TIMED(KI_MLP_TRAIN, c.st, launch_mlp_moments(t, y, L.mlp_S, (double*)(base + L.o_mlp_bsum), mom, A.flag,
+                                                     c.st));
+        MlpRegion R{};
+        R.t = t; R.mom = mom; R.S = L.mlp_S; R.p = ms.p; R.m = ms.m; R.v = ms.v; R.scale = ms.scale;
+        R.best = ms.best; R.best_loss = ms.best_loss; R.loss_pair = P.ctl->mlp_loss; R.gate = A.flag;
+        R.steps = c.o.mlp_steps; R.lr = c.o.mlp_lr; R.b1 = 0.9f; R.b2 = 0.999f; R.eps = 1e-8f;
+        TIMED(KI_MLP_TRAIN, c.st, launch_mlp_regions(R, c.st));
         TIMED(KI_FIT, c.st, launch_mlp_install(ms.best, ms.lo_inv, A.L, A.B1, A.log2B2, A.R, nullptr, A.flag, nullptr,
                                                A.model, c.st));
     }
@@ -847,7 +857,9 @@ static ls_status step_scratch(uint8_t*& base, DevPool*& pool, Layout& L, hipStre
         L.mlp_S = mlp_S;
         L.o_mlp_t = L.bytes;
         L.o_mlp_y = L.o_mlp_t + align256(mlp_S * 4);
-        L.bytes = L.o_mlp_y + align256(mlp_S * 4);
+        uint64_t o_ = L.o_mlp_y + align256(mlp_S * 4);
+        plan_mlp_moments(L, mlp_S, o_);
+        L.bytes = o_;
     }
     ls_status s = acquire(L.bytes, L, pool, base, st);
     if (!s) pool->sig = 0;  // this scratch may overlap another layout's look-back words
@@ -1231,6 +1243,30 @@ ls_status ls_mlp_loss_grad(const float* params, const float* t, const float* y, 
     return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
 }
 
+ls_status ls_mlp_loss_grad_regions(const float* params, const float* t, const float* y, uint64_t S, float* grad,
+                                   float* loss, void* stream) {
+    if (!params || !t || !y || S == 0 || (!grad && !loss))
+        return fail(LS_EINVAL, "ls_mlp_loss_grad_regions needs params, t, y, S >= 1 and an output");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* base;
+    DevPool* pool;
+    Layout Lo;
+    ls_status s = step_scratch(base, pool, Lo, (hipStream_t)stream, S);
+    if (s) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(pool, st))) return s;
+    const MlpState ms = mlp_state(base, Lo);
+    HIP_TRY(launch_mlp_setup(t, S, params, 0.0, ms.p, ms.m, ms.v, ms.best, ms.scale, ms.best_loss, ms.done, nullptr,
+                             st));
+    double* mom = (double*)(base + Lo.o_mlp_mom);
+    HIP_TRY(launch_mlp_moments(t, y, S, (double*)(base + Lo.o_mlp_bsum), mom, nullptr, st));
+    MlpRegion R{};
+    R.t = t; R.mom = mom; R.S = S; R.p = ms.p; R.m = ms.m; R.v = ms.v; R.grad_out = grad; R.loss_out = loss;
+    R.steps = 0;
+    HIP_TRY(launch_mlp_regions(R, st));
+    return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));
+}
+
 ls_status ls_mlp_train(const void* sorted_sample, uint64_t S, ls_dtype dtype, const float* params_init, uint32_t steps,
                        float lr, float* params_out, double* lo_inv, float* losses, void* stream) {
     ls_status s = check_keys(sorted_sample, S, dtype, nullptr);
@@ -1250,14 +1286,14 @@ ls_status ls_mlp_train(const void* sorted_sample, uint64_t S, ls_dtype dtype, co
     HIP_TRY(launch_mlp_prep((const uint64_t*)sorted_sample, S, 1, dtype == LS_U64, t, y, lo_inv, nullptr, st));
     HIP_TRY(launch_mlp_setup(t, S, params_init, 1e-3, ms.p, ms.m, ms.v, ms.best, ms.scale, ms.best_loss, ms.done,
                              nullptr, st));
-    for (uint32_t k = 1; k <= steps; k++) {
-        MlpStep A{};
-        A.t = t; A.y = y; A.S = S; A.p = ms.p; A.m = ms.m; A.v = ms.v; A.partial = ms.partial; A.done = ms.done;
-        A.losses = losses; A.step = k; A.update = 1; A.lr = lr; A.b1 = 0.9f; A.b2 = 0.999f; A.eps = 1e-8f;
-        A.best = ms.best; A.best_loss = ms.best_loss; A.scale = ms.scale;
-        A.c1 = (float)(1.0 - std::pow(0.9, (double)k));
-        A.c2 = (float)(1.0 - std::pow(0.999, (double)k));
-        HIP_TRY(launch_mlp_step(A, st));
+    if (steps) {
+        double* mom = (double*)(base + Lo.o_mlp_mom);
+        HIP_TRY(launch_mlp_moments(t, y, S, (double*)(base + Lo.o_mlp_bsum), mom, nullptr, st));
+        MlpRegion R{};
+        R.t = t; R.mom = mom; R.S = S; R.p = ms.p; R.m = ms.m; R.v = ms.v; R.scale = ms.scale;
+        R.best = ms.best; R.best_loss = ms.best_loss; R.losses = losses;
+        R.steps = steps; R.lr = lr; R.b1 = 0.9f; R.b2 = 0.999f; R.eps = 1e-8f;
+        HIP_TRY(launch_mlp_regions(R, st));
     }
     HIP_TRY(hipMemcpyAsync(params_out, ms.best, 4 * MLP_NP, hipMemcpyDeviceToDevice, st));
     return mark_done(pool, st, (Ctl*)(base + Lo.o_ctl));

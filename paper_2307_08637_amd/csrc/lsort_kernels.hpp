@@ -57,6 +57,32 @@ struct MlpStep {
     float c1, c2;         // bias corrections 1 - b1^step, 1 - b2^step
 };
 
+// Full-batch training by activation regions (lsort_mlp.hip): the training
+// set's prefix moments, then every Adam step in one workgroup.
+constexpr int MOM_BLOCK = 4096;      // samples per block of the moment scan
+constexpr int MOM_W = 5;             // moments per sample: t, t^2, y, t y, y^2
+struct MlpRegion {
+    const float* t;       // model inputs of the training set (non-decreasing)
+    const double* mom;    // (S + 1) x MOM_W prefix moments, double-double (hi, lo): sums over samples < i
+    uint64_t S;
+    float* p;             // parameters V / biases
+    float* m;             // Adam first moment
+    float* v;             // Adam second moment
+    const float* scale;   // nullable: per-parameter optimiser step scale
+    float* best;          // nullable: parameters with the lowest loss seen
+    float* best_loss;     // that loss (with best)
+    float* grad_out;      // nullable: gradient of the first evaluation w.r.t. p
+    float* loss_out;      // nullable: loss of the first evaluation
+    float* losses;        // nullable: loss of step k at losses[k - 1]
+    double* loss_pair;    // nullable: [0] loss at step 1, [1] lowest loss
+    const uint32_t* gate; // nullable: do nothing when gate[0] == 0
+    uint32_t steps;       // Adam steps; 0: one gradient evaluation, no update
+    float lr, b1, b2, eps;
+};
+hipError_t launch_mlp_moments(const float* t, const float* y, uint64_t S, double* block_sums, double* mom,
+                              const uint32_t* gate, hipStream_t st);
+hipError_t launch_mlp_regions(const MlpRegion& A, hipStream_t st);
+
 // level kernels (lsort_kernels.hip)
 hipError_t launch_reset(const Params& P, uint64_t* persist, hipStream_t st);
 hipError_t launch_seed(const Params& P, const uint64_t* offsets, uint64_t m, uint64_t n_single, uint32_t prebuilt,

@@ -379,6 +379,392 @@ __global__ __launch_bounds__(MLP_T) void k_mlp_step(MlpStep A) {
 }
 
 // ---------------------------------------------------------------------------
+// Full-batch training by activation regions.
+//
+// Every hidden pre-activation is a non-decreasing function of the input t
+// (effective weights |V| >= 0, and each operation of the forward pass --
+// fma with a non-negative weight, max, min -- is monotone, in fp32 too), and
+// the training set is sorted by t.  So each hidden unit switches once along
+// the training set: a max unit is active from the first index where its
+// pre-activation is > 0, a min unit up to the first index where it is >= 0.
+// The 32 switch indices, found by binary search of the pre-activations,
+// cut the training set into at most 33 contiguous regions, each with one
+// activation pattern (the switches are decided in fp64, like the algebra
+// below).  On a region the network is affine in t:
+//   h1 = a1 t + c1,  z2 = a2 t + c2,  out = alpha t + gamma,
+// so every term of the full-batch gradient of the mean squared error is a
+// combination of the region's sums n, sum t, sum t^2, sum y, sum t y, sum y^2.
+// Around the region's first input t_r (D = t - t_r, o_r = alpha t_r + gamma,
+// the output there) with dout = 2 e / S, e = alpha D + o_r - y:
+//   E0 = sum e = alpha SD + n o_r - Sy,   E1 = sum e t = t_r E0 + alpha SDD + o_r SD - SDy
+//   dV1_k = m1_k s_k E1,  db1_k = m1_k s_k E0   (s_k = sum_i V2_ik u_i, u_i = m2_i V3_i)
+//   dV2_ik = u_i (a1_k E1 + c1_k E0),  db2_i = u_i E0
+//   dV3_i = m2_i (a2_i E1 + c2_i E0),  db3 = E0      (all times 2 / S)
+//   loss = (alpha^2 SDD + 2 alpha (o_r SD - SDy) + n o_r^2 - 2 o_r Sy + Syy) / S
+// Steep ramps give alpha up to ~1e6, so the region sums must be accurate far
+// beyond fp64 rounding of a prefix sum of 1e6 terms: the prefix sums are
+// double-double (Knuth's two-sum / Dekker's two-product; every sum in a fixed
+// order), and the centred sums SD, SDD, SDy are formed in double-double too.
+// The region algebra then runs in fp64 on the fp32 parameters: the result is
+// the per-sample gradient summed over every sample, in another order.
+// ---------------------------------------------------------------------------
+constexpr int MOM_T = 256, MOM_E = MOM_BLOCK / MOM_T;
+
+struct dd2 {  // double-double: hi + lo, |lo| <= ulp(hi) / 2
+    double hi, lo;
+};
+__device__ __forceinline__ dd2 dd_add(dd2 a, dd2 b) {
+    const double s = a.hi + b.hi, bb = s - a.hi;
+    double e = (a.hi - (s - bb)) + (b.hi - bb);
+    e += a.lo + b.lo;
+    const double h = s + e;
+    return {h, e - (h - s)};
+}
+__device__ __forceinline__ dd2 dd_neg(dd2 a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dd2 dd_mul(dd2 a, double b) {
+    const double p = a.hi * b;
+    double e = __builtin_fma(a.hi, b, -p);
+    e += a.lo * b;
+    const double h = p + e;
+    return {h, e - (h - p)};
+}
+__device__ __forceinline__ dd2 dd_of(double a) { return {a, 0.0}; }
+
+__device__ __forceinline__ void mom_of(float tf, float yf, double q[MOM_W]) {
+    const double t = tf, y = yf;  // the products of fp32 values are exact in fp64
+    q[0] = t; q[1] = t * t; q[2] = y; q[3] = t * y; q[4] = y * y;
+}
+
+// Per-block moment totals (fixed order: each thread's samples in order, lanes
+// by a fixed butterfly, waves in order).  bsum: blocks x MOM_W x 2 doubles.
+__global__ __launch_bounds__(MOM_T) void k_mlp_mom_blocks(const float* t, const float* y, uint64_t S, double* bsum,
+                                                          const uint32_t* gate) {
+    if (gate && gate[0] == 0) return;
+    __shared__ dd2 red[MOM_T / 64][MOM_W];
+    const uint64_t b0 = (uint64_t)blockIdx.x * MOM_BLOCK + (uint64_t)threadIdx.x * MOM_E;
+    dd2 acc[MOM_W];
+#pragma unroll
+    for (int c = 0; c < MOM_W; c++) acc[c] = dd_of(0.0);
+    for (int e = 0; e < MOM_E; e++) {
+        const uint64_t i = b0 + e;
+        if (i < S) {
+            double q[MOM_W];
+            mom_of(t[i], y[i], q);
+#pragma unroll
+            for (int c = 0; c < MOM_W; c++) acc[c] = dd_add(acc[c], dd_of(q[c]));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < MOM_W; c++) {
+        dd2 v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) v = dd_add(v, dd2{__shfl_xor(v.hi, o), __shfl_xor(v.lo, o)});
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < MOM_W) {
+        dd2 v = dd_of(0.0);
+        for (int w = 0; w < MOM_T / 64; w++) v = dd_add(v, red[w][threadIdx.x]);
+        bsum[((uint64_t)blockIdx.x * MOM_W + threadIdx.x) * 2] = v.hi;
+        bsum[((uint64_t)blockIdx.x * MOM_W + threadIdx.x) * 2 + 1] = v.lo;
+    }
+}
+
+// mom[i] = sums over samples < i (double-double, MOM_W x 2 doubles per i):
+// the totals of earlier blocks (in block order), of earlier threads of this
+// block (lane-ordered scan, then waves in order) and of the thread's earlier
+// samples; no subtraction anywhere.
+__global__ __launch_bounds__(MOM_T) void k_mlp_mom_scan(const float* t, const float* y, uint64_t S, const double* bsum,
+                                                        double* mom, const uint32_t* gate) {
+    if (gate && gate[0] == 0) return;
+    __shared__ dd2 base[MOM_W];
+    __shared__ dd2 wsum[MOM_T / 64][MOM_W];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid < MOM_W) {
+        dd2 v = dd_of(0.0);
+        for (uint32_t b = 0; b < blockIdx.x; b++)
+            v = dd_add(v, dd2{bsum[((uint64_t)b * MOM_W + tid) * 2], bsum[((uint64_t)b * MOM_W + tid) * 2 + 1]});
+        base[tid] = v;
+    }
+    const uint64_t b0 = (uint64_t)blockIdx.x * MOM_BLOCK + (uint64_t)tid * MOM_E;
+    dd2 own[MOM_W];
+#pragma unroll
+    for (int c = 0; c < MOM_W; c++) own[c] = dd_of(0.0);
+    for (int e = 0; e < MOM_E; e++) {
+        const uint64_t i = b0 + e;
+        if (i < S) {
+            double q[MOM_W];
+            mom_of(t[i], y[i], q);
+#pragma unroll
+            for (int c = 0; c < MOM_W; c++) own[c] = dd_add(own[c], dd_of(q[c]));
+        }
+    }
+    dd2 excl[MOM_W];
+#pragma unroll
+    for (int c = 0; c < MOM_W; c++) {
+        dd2 x = own[c];
+        for (int o = 1; o < 64; o <<= 1) {
+            const dd2 u{__shfl_up(x.hi, o), __shfl_up(x.lo, o)};
+            if (lane >= o) x = dd_add(u, x);
+        }
+        const dd2 ex{__shfl_up(x.hi, 1), __shfl_up(x.lo, 1)};
+        excl[c] = lane ? ex : dd_of(0.0);
+        if (lane == 63) wsum[w][c] = x;
+    }
+    __syncthreads();
+    dd2 run[MOM_W];
+#pragma unroll
+    for (int c = 0; c < MOM_W; c++) {
+        dd2 before = base[c];
+        for (int q = 0; q < w; q++) before = dd_add(before, wsum[q][c]);
+        run[c] = dd_add(before, excl[c]);
+    }
+    for (int e = 0; e < MOM_E; e++) {
+        const uint64_t i = b0 + e;
+        if (i > S) break;
+#pragma unroll
+        for (int c = 0; c < MOM_W; c++) {
+            mom[(i * MOM_W + c) * 2] = run[c].hi;
+            mom[(i * MOM_W + c) * 2 + 1] = run[c].lo;
+        }
+        if (i == S) break;
+        double q[MOM_W];
+        mom_of(t[i], y[i], q);
+#pragma unroll
+        for (int c = 0; c < MOM_W; c++) run[c] = dd_add(run[c], dd_of(q[c]));
+        if (i + 1 == S) {
+#pragma unroll
+            for (int c = 0; c < MOM_W; c++) {
+                mom[(S * MOM_W + c) * 2] = run[c].hi;
+                mom[(S * MOM_W + c) * 2 + 1] = run[c].lo;
+            }
+        }
+    }
+}
+
+constexpr int RG_T = 1024;            // one workgroup: 16 waves
+constexpr int RG_UNITS = 2 * MLP_H;   // hidden units (switch indices)
+constexpr int RG_MAXR = RG_UNITS + 1; // regions
+constexpr int RG_CN = 24576;          // coarse copy of t in LDS (every sp-th sample)
+enum : int { RG_A1 = 0, RG_C1 = 16, RG_A2 = 32, RG_C2 = 48, RG_U = 64, RG_Q = 80, RG_E0 = 96, RG_E1 = 97, RG_L = 98,
+             RG_REC = 100 };
+
+// Pre-activation of hidden unit u (0..15 layer 1, 16..31 layer 2) at input tt,
+// in fp64 from the fp32 parameters -- the arithmetic of the region algebra
+// below, so a unit's switch and the affine piece it selects agree -- and
+// whether it is past its switch: > 0 for a max unit, >= 0 for a min unit
+// (non-decreasing along t: every operation is monotone).
+__device__ __forceinline__ bool rg_past(const float* w, int u, float tt) {
+    const double t = tt;
+    if (u < MLP_H) {
+        const double z = (double)w[OFF_V1 + u] * t + (double)w[OFF_B1 + u];
+        return u < MLP_HALF ? z > 0.0 : z >= 0.0;
+    }
+    const int i = u - MLP_H;
+    double z = (double)w[OFF_B2 + i];
+#pragma unroll
+    for (int k = 0; k < MLP_H; k++) {
+        const double z1 = (double)w[OFF_V1 + k] * t + (double)w[OFF_B1 + k];
+        const double h1 = k < MLP_HALF ? fmax(z1, 0.0) : fmin(z1, 0.0);
+        z += (double)w[OFF_V2 + MLP_H * i + k] * h1;
+    }
+    return i < MLP_HALF ? z > 0.0 : z >= 0.0;
+}
+
+// First index in [lo, hi) at which unit u is past its switch (hi if none),
+// by 64-ary search of one wavefront; at(i) gives the input of index i.
+template <typename At>
+__device__ __forceinline__ uint64_t rg_search(const float* w, int u, uint64_t lo, uint64_t hi, At at) {
+    const int lane = threadIdx.x & 63;
+    while (lo < hi) {
+        // probes lo + l * step, l = 0..63: the last one is at or past hi
+        // (taken as true), so some lane's predicate holds
+        const uint64_t step = (hi - lo + 62) / 63;
+        const uint64_t idx = lo + (uint64_t)lane * step;
+        const bool pred = idx >= hi || rg_past(w, u, at(idx));
+        const uint64_t mask = __ballot(pred);
+        const int f = __ffsll((unsigned long long)mask) - 1;
+        if (f == 0) return lo;
+        lo = lo + (uint64_t)(f - 1) * step + 1;
+        hi = min<uint64_t>(lo - 1 + step, hi);
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(RG_T) void k_mlp_regions(MlpRegion A) {
+    if (A.gate && A.gate[0] == 0) return;
+    __shared__ float ct[RG_CN];
+    __shared__ float w[MLP_NP + 3];
+    __shared__ uint64_t thr[RG_UNITS];
+    __shared__ uint64_t bnd[RG_MAXR + 1];
+    __shared__ double rec[RG_MAXR][RG_REC];
+    __shared__ double sh_loss;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint64_t S = A.S;
+    const uint64_t sp = (S + RG_CN - 1) / RG_CN > 0 ? (S + RG_CN - 1) / RG_CN : 1;
+    const uint64_t nc = (S + sp - 1) / sp;
+    for (uint64_t j = tid; j < nc; j += RG_T) ct[j] = A.t[j * sp];
+    const double inv_s = 1.0 / (double)S;
+    double pb1 = 1.0, pb2 = 1.0;
+    const uint32_t nstep = A.steps ? A.steps : 1;
+    for (uint32_t k = 1; k <= nstep; k++) {
+        for (int i = tid; i < MLP_NP; i += RG_T) w[i] = mlp_is_weight(i) ? fabsf(A.p[i]) : A.p[i];
+        __syncthreads();
+        // switch indices: wave wv searches units wv and wv + 16
+        for (int u = wv; u < RG_UNITS; u += RG_T / 64) {
+            const uint64_t jc = rg_search(w, u, 0, nc, [&](uint64_t j) { return ct[j]; });
+            uint64_t T;
+            if (jc == 0) {
+                T = 0;
+            } else {
+                const uint64_t lo = (jc - 1) * sp + 1, hi = min<uint64_t>(jc * sp, S);
+                T = rg_search(w, u, lo, hi, [&](uint64_t i) { return A.t[i]; });
+            }
+            if (lane == 0) thr[u] = T;
+        }
+        __syncthreads();
+        if (tid < RG_UNITS) {  // region boundaries: the switch indices in order
+            const uint64_t mine = thr[tid];
+            uint32_t r = 0;
+            for (int q = 0; q < RG_UNITS; q++) r += (thr[q] < mine || (thr[q] == mine && q < tid)) ? 1u : 0u;
+            bnd[r + 1] = mine;
+        }
+        if (tid == 0) { bnd[0] = 0; bnd[RG_MAXR] = S; }
+        __syncthreads();
+        // one wavefront per region: its affine pieces, moments and the
+        // per-region factors of the gradient
+        for (int r = wv; r < RG_MAXR; r += RG_T / 64) {
+            const uint64_t b = bnd[r], e = bnd[r + 1];
+            double* R = rec[r];
+            if (b >= e) {
+                for (int x = lane; x < RG_REC; x += 64) R[x] = 0.0;
+                continue;
+            }
+            const int kk = lane & 15;
+            // unit masks at the region's first index
+            const bool on1 = kk < MLP_HALF ? b >= thr[kk] : b < thr[kk];
+            const bool on2 = kk < MLP_HALF ? b >= thr[MLP_H + kk] : b < thr[MLP_H + kk];
+            const double a1 = on1 ? (double)w[OFF_V1 + kk] : 0.0, c1 = on1 ? (double)w[OFF_B1 + kk] : 0.0;
+            double a2 = 0.0, c2 = (double)w[OFF_B2 + kk];
+            for (int q = 0; q < MLP_H; q++) {
+                const double wq = (double)w[OFF_V2 + MLP_H * kk + q];
+                a2 += wq * __shfl(a1, q);
+                c2 += wq * __shfl(c1, q);
+            }
+            const double u = on2 ? (double)w[OFF_V3 + kk] : 0.0;
+            double s = 0.0;
+            for (int q = 0; q < MLP_H; q++) s += (double)w[OFF_V2 + MLP_H * q + kk] * __shfl(u, q);
+            double al = lane < MLP_H ? u * a2 : 0.0, ga = lane < MLP_H ? u * c2 : 0.0;
+            for (int o = 8; o > 0; o >>= 1) { al += __shfl_xor(al, o); ga += __shfl_xor(ga, o); }
+            al = __shfl(al, 0);
+            ga = __shfl(ga, 0) + (double)w[OFF_B3];
+            // region sums (double-double differences of the prefix sums),
+            // centred at the region's first input t_r
+            const double tr = (double)A.t[b];
+            auto rsum = [&](int c) {
+                const double* p0 = A.mom + (b * MOM_W + c) * 2;
+                const double* p1 = A.mom + (e * MOM_W + c) * 2;
+                return dd_add(dd2{p1[0], p1[1]}, dd_neg(dd2{p0[0], p0[1]}));
+            };
+            const double n = (double)(e - b);
+            const dd2 St = rsum(0), Stt = rsum(1), Sy = rsum(2), Sty = rsum(3), Syy = rsum(4);
+            const dd2 ntr = dd_mul(dd_of(n), tr);
+            const double SD = dd_add(St, dd_neg(ntr)).hi;                                   // sum (t - t_r)
+            const double SDD = dd_add(dd_add(Stt, dd_neg(dd_mul(St, 2.0 * tr))), dd_mul(ntr, tr)).hi;
+            const double SDy = dd_add(Sty, dd_neg(dd_mul(Sy, tr))).hi;
+            const double sy = Sy.hi;
+            const double orr = al * tr + ga;  // output at t_r
+            const double E0 = al * SD + n * orr - sy;
+            const double E1 = tr * E0 + al * SDD + orr * SD - SDy;
+            if (lane < MLP_H) {
+                R[RG_A1 + kk] = a1; R[RG_C1 + kk] = c1;
+                R[RG_A2 + kk] = on2 ? a2 : 0.0; R[RG_C2 + kk] = on2 ? c2 : 0.0;
+                R[RG_U + kk] = u; R[RG_Q + kk] = on1 ? s : 0.0;
+            }
+            if (lane == 0) {
+                R[RG_E0] = E0; R[RG_E1] = E1;
+                const double Soo = dd_add(dd_add(dd_mul(dd_of(n * orr), orr), dd_neg(dd_mul(Sy, 2.0 * orr))), Syy).hi;
+                R[RG_L] = al * al * SDD + 2.0 * al * (orr * SD - SDy) + Soo;
+            }
+        }
+        __syncthreads();
+        // gradient entries, each summed over the regions in order
+        double g = 0.0;
+        if (tid < MLP_NP) {
+            for (int r = 0; r < RG_MAXR; r++) {
+                const double* R = rec[r];
+                const double E0 = R[RG_E0], E1 = R[RG_E1];
+                double c;
+                if (tid < OFF_B1) c = R[RG_Q + tid] * E1;
+                else if (tid < OFF_V2) c = R[RG_Q + tid - OFF_B1] * E0;
+                else if (tid < OFF_B2) {
+                    const int i = (tid - OFF_V2) / MLP_H, q = (tid - OFF_V2) % MLP_H;
+                    c = R[RG_U + i] * (R[RG_A1 + q] * E1 + R[RG_C1 + q] * E0);
+                } else if (tid < OFF_V3) c = R[RG_U + tid - OFF_B2] * E0;
+                else if (tid < OFF_B3) c = R[RG_A2 + tid - OFF_V3] * E1 + R[RG_C2 + tid - OFF_V3] * E0;
+                else c = E0;
+                g += c;
+            }
+            g *= 2.0 * inv_s;
+        } else if (tid == MLP_NP) {
+            double l = 0.0;
+            for (int r = 0; r < RG_MAXR; r++) l += rec[r][RG_L];
+            sh_loss = l * inv_s;
+        }
+        __syncthreads();
+        const float loss = (float)sh_loss;
+        const bool better = A.best && loss < *A.best_loss;
+        __syncthreads();
+        pb1 *= (double)A.b1;
+        pb2 *= (double)A.b2;
+        if (tid < MLP_NP) {
+            const float pv = A.p[tid];
+            if (better) A.best[tid] = pv;
+            float gf = (float)g;
+            if (mlp_is_weight(tid)) gf *= pv > 0.0f ? 1.0f : (pv < 0.0f ? -1.0f : 0.0f);  // d|V|/dV
+            if (k == 1 && A.grad_out) A.grad_out[tid] = gf;
+            if (A.steps) {
+                const float sc = A.scale ? A.scale[tid] : 1.0f;
+                const float gs = sc * gf;
+                const float mm = A.b1 * A.m[tid] + (1.0f - A.b1) * gs;
+                const float vv = A.b2 * A.v[tid] + (1.0f - A.b2) * gs * gs;
+                A.m[tid] = mm;
+                A.v[tid] = vv;
+                const float c1 = (float)(1.0 - pb1), c2 = (float)(1.0 - pb2);
+                A.p[tid] = pv - sc * (A.lr * (mm / c1) / (sqrtf(vv / c2) + A.eps));
+            }
+        }
+        if (tid == 0) {
+            if (better) *A.best_loss = loss;
+            if (k == 1 && A.loss_out) *A.loss_out = loss;
+            if (A.losses && A.steps) A.losses[k - 1] = loss;
+            if (A.loss_pair) {
+                if (k == 1) A.loss_pair[0] = loss;
+                A.loss_pair[1] = A.best ? fminf(*A.best_loss, loss) : loss;
+            }
+        }
+        // the next step reads p and best_loss written above
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+hipError_t launch_mlp_moments(const float* t, const float* y, uint64_t S, double* block_sums, double* mom,
+                              const uint32_t* gate, hipStream_t st) {
+    const uint32_t nb = (uint32_t)((S + MOM_BLOCK - 1) / MOM_BLOCK);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_mom_blocks, dim3(nb), dim3(MOM_T), 0, st, t, y, S, block_sums, gate);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_mom_scan, dim3(nb), dim3(MOM_T), 0, st, t, y, S, block_sums, mom, gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_regions(const MlpRegion& A, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_regions, dim3(1), dim3(RG_T), 0, st, A);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Model record of the MLP-rooted model: header, effective weights and
 // (optionally) the caller's pre-scaled leaves.
 // ---------------------------------------------------------------------------

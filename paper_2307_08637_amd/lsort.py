@@ -79,6 +79,7 @@ def lib():
             "ls_partition_rmi": [vp, vp, u64, i32, vp, u32, dbl, u32, vp, vp, vp, vp],
             "ls_partition_splitters": [vp, vp, u64, i32, vp, vp, u32, vp, vp, vp, vp],
             "ls_mlp_loss_grad": [vp, vp, vp, u64, vp, vp, vp],
+            "ls_mlp_loss_grad_regions": [vp, vp, vp, u64, vp, vp, vp],
             "ls_mlp_train": [vp, u64, i32, vp, u32, C.c_float, vp, vp, vp, vp],
             "ls_mlp_buckets": [vp, u64, i32, vp, vp, u32, vp, vp],
             "ls_mlp_rmi_fit": [vp, u64, i32, vp, vp, u32, dbl, vp, vp],
@@ -325,16 +326,18 @@ def partition_splitters(keys, u, eq, payload=None):
 MLP_NP = 321
 
 
-def mlp_loss_grad(params: torch.Tensor, t: torch.Tensor, y: torch.Tensor):
+def mlp_loss_grad(params: torch.Tensor, t: torch.Tensor, y: torch.Tensor, regions: bool = False):
     """(loss, grad) of the mean squared error at params (float32[321]) over
-    inputs t and targets y (float32, device)."""
+    inputs t and targets y (float32, device); regions: by activation regions
+    (t non-decreasing), as the training computes it."""
     for a, nm in ((params, "params"), (t, "t"), (y, "y")):
         _dev(a, nm)
         if a.dtype != torch.float32:
             raise ValueError(f"{nm} must be float32")
     grad = torch.empty(MLP_NP, dtype=torch.float32, device=t.device)
     loss = torch.empty(1, dtype=torch.float32, device=t.device)
-    _check(lib().ls_mlp_loss_grad(_ptr(params), _ptr(t), _ptr(y), t.numel(), _ptr(grad), _ptr(loss), _stream()))
+    fn = lib().ls_mlp_loss_grad_regions if regions else lib().ls_mlp_loss_grad
+    _check(fn(_ptr(params), _ptr(t), _ptr(y), t.numel(), _ptr(grad), _ptr(loss), _stream()))
     return loss, grad
 
 
