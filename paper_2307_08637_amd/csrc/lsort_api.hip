@@ -146,9 +146,9 @@ static inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 struct Layout {
     uint64_t n, m;
     int has_pay;
-    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
+    uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap, merge_cap;
     uint64_t item_m_cap = 0, o_items_m = 0;  // model-based counting-sort items (large single array)
-    uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_bigs, o_items_b, o_items_c, o_counts, o_status,
+    uint64_t o_persist, o_ctl, o_tmp, o_tmppay, o_ids, o_segs[2], o_tiles[2], o_items, o_bigs, o_items_b, o_items_c, o_merges, o_counts, o_status,
         o_arena[2], o_bigmodel, o_part, o_leaf, o_flag, o_sample, o_nested, o_mlp, o_mlp_t, o_mlp_y, o_bstart;
     uint64_t S_big;       // large-path sample size (0: none)
     uint64_t mlp_S;       // MLP training-set size (0: no MLP training)
@@ -238,7 +238,10 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.item_cap = n + m + 64;        // small items hold >= 1 key
     L.big_cap = n / 2 + m + 64;     // large items > 512 keys, copy runs >= 2 keys
     L.item_b_cap = n / (GROUP_SMALL_MAX + 1) + m + 64;  // items of 129..256 keys and of 513..1024
-    L.item_c_cap = n / (GROUP_LARGE_MAX + 1) + m + 64;  // items of 1025..2048 keys
+    // items of 1025..2048 keys, and the chunks of at most 2048 keys of the
+    // keys-only items of 2049..8192 (at most 2 per 2049 keys: <= n / 1024)
+    L.item_c_cap = n / GROUP_LARGE_MAX + m + 64;
+    L.merge_cap = n / (GROUP_WAVE_MAX + 1) + m + 64;  // those 2049..8192-key items
     // Bucket counts per level: a segment gets at most n_seg / 4 buckets (at
     // least 2), except one first-level segment whose model the caller gives
     // (up to B_MAX).  Look-back words: tiles x buckets of each segment.
@@ -260,6 +263,7 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.o_bigs = take(L.big_cap * 8);
     L.o_items_b = take(L.item_b_cap * 8);
     L.o_items_c = take(L.item_c_cap * 8);
+    L.o_merges = take(L.merge_cap * 8);
     L.o_counts = take(L.counts_cap * 8);
     L.o_status = take(L.status_cap * 8);
     L.o_arena[0] = take(L.arena_cap);
@@ -320,11 +324,11 @@ static thread_local LastCall g_last;
 // ---------------------------------------------------------------------------
 enum KernelId {
     KI_RESET, KI_SEED, KI_MODEL, KI_HIST, KI_SCAN, KI_SCATTER, KI_BASE, KI_BASE_BIG, KI_GATHER, KI_FIT, KI_MLP_TRAIN,
-    KI_MLP_IDS, KI_RESIDENT, KI_CONVERT, KI_BASE_MODEL, KI_N
+    KI_MLP_IDS, KI_RESIDENT, KI_CONVERT, KI_BASE_MODEL, KI_BASE_MERGE, KI_N
 };
 static const char* KNAME[KI_N] = {"k_reset", "k_seed", "k_model", "k_hist", "k_scan", "k_scatter", "k_base_small",
                                   "k_base_big", "k_gather", "k_fit", "k_mlp_step", "k_mlp_ids", "k_resident",
-                                  "k_convert", "k_base_model"};
+                                  "k_convert", "k_base_model", "k_base_merge"};
 struct TRec {
     int kid;
     hipEvent_t a, b;
@@ -491,6 +495,8 @@ static Params make_params(const Call& c, const Layout& L, uint8_t* base) {
     P.bigs = (uint64_t*)(base + L.o_bigs);
     P.items_b = (uint64_t*)(base + L.o_items_b);
     P.items_c = (uint64_t*)(base + L.o_items_c);
+    P.merges = (uint64_t*)(base + L.o_merges);
+    P.merge_cap = L.merge_cap;
     P.items_m = L.o_items_m ? (uint64_t*)(base + L.o_items_m) : nullptr;
     P.item_m_cap = L.item_m_cap;
     P.fmodel = L.S_big && !c.one_level ? (const uint64_t*)(base + L.o_bigmodel) : nullptr;
@@ -657,17 +663,22 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     }
     (void)levels;
     if (!c.one_level) {
+        const size_t r0 = g_trec.size();
         TIMED(KI_BASE, c.st, launch_base_small(P, cus * 8, c.st));
         const bool mbase = (c.o.flags & LS_FLAG_MODEL_BASE) && P.fmodel;
         if (mbase) TIMED(KI_BASE_MODEL, c.st, launch_base_model(P, cus * 2, c.st));
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
-        if (g_timing && !t_untimed) {  // keys through the base case (every kernel) and the copies
+        // keys only: the items of 2049..8192 keys, sorted above as chunks, merged
+        if (!P.has_pay) TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus * 2, c.st));
+        if (g_timing && !t_untimed && g_trec.size() > r0) {  // keys through each base-case kernel
             HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));
             const Ctl* hc = (const Ctl*)pool->pinned;
-            g_trec[g_trec.size() - (mbase ? 3 : 2)].keys = (double)hc->small_keys;
-            if (mbase) g_trec[g_trec.size() - 2].keys = (double)hc->model_keys;
-            g_trec.back().keys = (double)hc->big_keys;
+            size_t r = r0;
+            g_trec[r++].keys = (double)hc->small_keys;
+            if (mbase) g_trec[r++].keys = (double)hc->model_keys;
+            g_trec[r++].keys = (double)hc->big_keys;
+            if (!P.has_pay) g_trec[r++].keys = (double)hc->merge_keys;
         }
     }
     return LS_OK;
@@ -960,12 +971,13 @@ ls_status ls_get_stats(ls_stats* out) {
     out->levels = levels;
     out->first_model = c.first_mlp ? LS_MODEL_MLP
                        : c.lv[0].learned ? LS_MODEL_RMI : (c.lv[0].segments ? LS_MODEL_SPLITTER : LS_MODEL_AUTO);
-    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nitems_k + c.nitems_c + c.nitems_m + c.nbig - c.ncopy -
-                      c.nmoved;
+    out->base_items = c.nitems + c.nitems_b + c.nitems_w + c.nitems_k + c.nitems_c - c.nchunk + c.nmerge + c.nitems_m +
+                      c.nbig - c.ncopy - c.nmoved;
     out->copy_items = c.ncopy;
     out->mlp_loss_first = c.mlp_loss[0];
     out->mlp_loss_last = c.mlp_loss[1];
     out->overflow = c.overflow;
+    out->merged_items = (uint32_t)std::min<uint64_t>(c.nmerge, 0xffffffffull);
     return LS_OK;
 }
 

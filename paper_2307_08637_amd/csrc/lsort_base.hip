@@ -349,6 +349,94 @@ __global__ __launch_bounds__(NT) void k_base_mid(Params P) {
     }
 }
 
+// Keys-only items of GROUP_WAVE_MAX+1 .. BIG_MAX keys: k_base_small has sorted
+// each chunk of GROUP_WAVE_MAX keys into the caller's buffer (k_base_mid the
+// chunks holding a NaN or a -0.0); one workgroup per item merges the sorted
+// runs pairwise in LDS, runs of 2048 into 4096 into 8192 keys.  Keys are
+// compared as ordered 64-bit images (the totalOrder map), which order every
+// chunk the same way whichever kernel sorted it.  Each thread produces 16
+// consecutive outputs of a round: its start in the pair of runs comes from a
+// merge-path search (the number of keys the first run contributes to the
+// outputs before it, ties taken from the first run), then it merges
+// sequentially.  The item sits in LDS with one pad word after every 16 keys,
+// so that the 16-key output runs of a wavefront's lanes fall on distinct
+// banks (17 l mod 32 is a bijection).  Two workgroups per CU.
+constexpr int MG_THREADS = 512, MG_OUT = BIG_MAX / MG_THREADS;
+static_assert(MG_OUT == 16 && GROUP_WAVE_MAX % MG_OUT == 0, "a thread's outputs lie inside one pair of runs");
+
+__device__ __forceinline__ uint32_t mslot(uint32_t i) { return i + (i >> 4); }
+
+__global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
+    __shared__ uint64_t L[BIG_MAX + BIG_MAX / 16];
+    const int tid = threadIdx.x;
+    const uint64_t nm = min<unsigned long long>(P.ctl->nmerge, P.merge_cap);
+    uint64_t* keys = P.keys[0];
+    const int u64 = P.u64;
+    for (uint64_t it = blockIdx.x; it < nm; it += gridDim.x) {
+        const uint64_t wd = P.merges[it];
+        const uint64_t off = wd >> 18;
+        const uint32_t n = (uint32_t)(wd & 0xffffu) + 1;
+        {
+            uint64_t v[MG_OUT];
+#pragma unroll
+            for (int r = 0; r < MG_OUT; r++) {
+                const uint32_t i = r * MG_THREADS + tid;
+                v[r] = i < n ? keys[off + i] : 0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < MG_OUT; r++) {
+                const uint32_t i = r * MG_THREADS + tid;
+                if (i < n) L[mslot(i)] = key_ord(v[r], u64);
+            }
+        }
+        __syncthreads();
+        const uint32_t p0 = (uint32_t)tid * MG_OUT;
+        for (uint32_t w = GROUP_WAVE_MAX; w < n; w <<= 1) {
+            uint64_t o[MG_OUT];
+            if (p0 < n) {
+                const uint32_t a0 = p0 / (2 * w) * (2 * w);     // the pair of runs [a0, a0 + la), [b0, b0 + lb)
+                const uint32_t la = min(w, n - a0);
+                const uint32_t b0 = a0 + la;
+                const uint32_t lb = b0 < n ? min(w, n - b0) : 0u;
+                const uint32_t d = p0 - a0;
+                // smallest i in [d - lb, min(d, la)] whose A[i] does not precede B[d - i - 1]
+                uint32_t lo = d > lb ? d - lb : 0u, hi = min(d, la);
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (L[mslot(a0 + mid)] <= L[mslot(b0 + d - mid - 1)]) lo = mid + 1;
+                    else hi = mid;
+                }
+                uint32_t ia = lo, ib = d - lo;
+                uint64_t va = ia < la ? L[mslot(a0 + ia)] : 0ull;
+                uint64_t vb = ib < lb ? L[mslot(b0 + ib)] : 0ull;
+#pragma unroll
+                for (int r = 0; r < MG_OUT; r++) {
+                    const bool ta = ib >= lb || (ia < la && va <= vb);
+                    o[r] = ta ? va : vb;
+                    if (ta) {
+                        ia++;
+                        va = ia < la ? L[mslot(a0 + ia)] : 0ull;
+                    } else {
+                        ib++;
+                        vb = ib < lb ? L[mslot(b0 + ib)] : 0ull;
+                    }
+                }
+            }
+            __syncthreads();  // every read of this round is done
+#pragma unroll
+            for (int r = 0; r < MG_OUT; r++)
+                if (p0 + r < n) L[mslot(p0 + r)] = o[r];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < MG_OUT; r++) {
+            const uint32_t i = r * MG_THREADS + tid;
+            if (i < n) keys[off + i] = key_unord(L[mslot(i)], u64);
+        }
+        __syncthreads();  // the next item rewrites L
+    }
+}
+
 #define LAUNCH(kernel, grid, block, stream, ...)                                     \
     do {                                                                             \
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, stream, __VA_ARGS__); \
@@ -362,8 +450,12 @@ hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st) {
 }
 hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) {
     hipLaunchKernelGGL(k_base_mid<MID_THREADS>, dim3(grid / 2 * 5), dim3(MID_THREADS), 0, st, P);  // 5 per CU
+    if (!P.has_pay) LAUNCH(k_base_big<C_MAX>, grid, BIG_THREADS, st, P);  // keys only: copies (large items merge)
     hipLaunchKernelGGL(k_base_big<C_MAX>, dim3(grid), dim3(BIG_THREADS), 0, st, P);
     LAUNCH(k_base_big<BIG_MAX>, grid / 2 ? grid / 2 : 1, BIG_THREADS, st, P);
+}
+hipError_t launch_base_merge(const Params& P, uint32_t grid, hipStream_t st) {
+    LAUNCH(k_base_merge, grid, MG_THREADS, st, P);
 }
 
 }  // namespace ls

@@ -117,6 +117,13 @@ struct Tile {          // one work unit of UNIT keys
 
 // Base-case / copy work item packed in 64 bits:
 // [63:18] offset, [17] source buffer (0 caller, 1 temp), [16] copy-only, [15:0] size - 1.
+// Keys-only base-case items of GROUP_WAVE_MAX+1 .. BIG_MAX keys: the number
+// of chunks of GROUP_WAVE_MAX keys (the last one shorter) that are sorted as
+// items of their own and then merged; 0 for any other size.
+__host__ __device__ inline uint64_t split_chunks(uint64_t c) {
+    return c > (uint64_t)GROUP_WAVE_MAX && c <= (uint64_t)BIG_MAX ? (c + GROUP_WAVE_MAX - 1) / GROUP_WAVE_MAX : 0;
+}
+
 __host__ __device__ inline uint64_t item_pack(uint64_t off, uint32_t src, uint32_t copy, uint32_t size) {
     return (off << 18) | ((uint64_t)src << 17) | ((uint64_t)copy << 16) | (uint64_t)(size - 1);
 }
@@ -149,6 +156,10 @@ struct Ctl {
     LS_HOT unsigned long long nbig;         // large base-case items and copy items
     LS_HOT unsigned long long nmoved;       // small items handed on to the large list (NaN / -0.0 tasks)
     LS_HOT unsigned long long nitems_m;     // items of the model-based counting sort (two words each)
+    LS_HOT unsigned long long nmerge;       // keys only: items of GROUP_WAVE_MAX+1 .. BIG_MAX keys, sorted as
+                                            // chunks of GROUP_WAVE_MAX keys, then merged (k_base_merge)
+    LS_HOT unsigned long long merge_keys;   // keys in those items
+    LS_HOT unsigned long long nchunk;       // their chunks (in nitems_c)
     LS_HOT unsigned long long model_keys;   // keys in those items
     LS_HOT unsigned long long ncopy;
     LS_HOT unsigned long long small_keys;   // keys in small base-case items
@@ -193,6 +204,8 @@ struct Params {
     uint64_t* items_c;              // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys
     uint64_t* items_m;              // model-based counting-sort items: (item word, g0 | log2(w) << 32)
     uint64_t item_m_cap;
+    uint64_t* merges;               // keys only: items whose chunks are merged (k_base_merge)
+    uint64_t merge_cap;
     const uint64_t* fmodel;         // the first level's prebuilt model (large single array), or null
     uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;
     const uint64_t* persist;        // [0] call epoch, [1] clear-status request (survives calls)

@@ -619,7 +619,7 @@ __device__ __forceinline__ Decision decide(const Params& P, int lvl, uint32_t q,
 __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
     __shared__ uint64_t red64[S_THREADS / 64];
     __shared__ uint8_t eqb[B_MAX];
-    __shared__ uint64_t resv[9];
+    __shared__ uint64_t resv[10];
     const int tid = threadIdx.x;
     const int lvl = P.level;
     if (blockIdx.x == 0 && tid == 0) {  // pools of the next level (this level's data stays readable)
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         const bool mbase = (P.flags & FLAG_MODEL_BASE) && P.fmodel && sg.model == (uint64_t)P.fmodel &&
                            (sg.kind == K_RMI || sg.kind == K_RMI_FINE);
         uint32_t act[S_BPT];
-        uint64_t la = 0, lb = 0, lc = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0, lfb = 0, ld = 0, lmk = 0;
+        uint64_t la = 0, lb = 0, lc = 0, lstat = 0, lsk = 0, lgk = 0, lcp = 0, lfb = 0, ld = 0, lmk = 0, lm = 0;
 #pragma unroll
         for (int i = 0; i < S_BPT; i++) {
             const uint32_t b = S_BPT * tid + i;
@@ -696,19 +696,21 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             ld += mb ? 1 : 0;
             lmk += mb ? c[i] : 0;
             const uint64_t nsm = d.act == 2 && !mb && (c[i] <= SMALL_MAX || (c[i] <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
+            const uint64_t nsp = d.act == 2 && !mb && !nsm && !P.has_pay ? split_chunks(c[i]) : 0;
             const uint64_t ng0 = nsm && c[i] <= GROUP_SMALL_MAX ? 1 : 0;
             const uint64_t ng1 = nsm && !ng0 && c[i] <= GROUP_MAX ? 1 : 0;
             const uint64_t ng3 = nsm && c[i] > SMALL_MAX && c[i] <= GROUP_LARGE_MAX ? 1 : 0;
             const uint64_t ng4 = nsm && c[i] > GROUP_LARGE_MAX ? 1 : 0;
-            const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && !nsm && !mb ? 1 : 0);
+            const uint64_t nbg = d.act == 1 ? (c[i] + COPY_CHUNK - 1) / COPY_CHUNK : (d.act == 2 && !nsm && !mb && !nsp ? 1 : 0);
             const uint64_t ntl = d.act >= 3 && !child_resident(sg.kind, d.act, c[i]) ? (c[i] + UNIT - 1) / UNIT : 0;
             // packed counters: items <= 128 keys | children << 16 | large items << 32,
             // units | items of 129..256 keys << 32 | items of 257..512 keys << 48
             la += ng0 | ((uint64_t)(d.act >= 3) << 16) | (nbg << 32);
             lb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
-            lc += ng3 | (ng4 << 32);
+            lc += ng3 | ((ng4 + nsp) << 32);
+            lm += nsp ? 1 | (nsp << 16) | (c[i] << 32) : 0;
             lfb += d.act == 5 ? 1 : 0;
-            lsk += nsm ? c[i] : 0;
+            lsk += nsm || nsp ? c[i] : 0;
             lgk += nbg ? c[i] : 0;
             lcp += d.act == 1 ? nbg : 0;
         }
@@ -719,6 +721,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         uint64_t tc, td;
         uint64_t xc = block_excl_scan<S_THREADS, uint64_t>(lc, red64, &tc);
         uint64_t xd = block_excl_scan<S_THREADS, uint64_t>(ld, red64, &td);
+        uint64_t tm;  // merged items | their chunks << 16 | their keys << 32
+        uint64_t xm = block_excl_scan<S_THREADS, uint64_t>(lm, red64, &tm);
         const uint64_t mk = block_sum<S_THREADS, uint64_t>(lmk, red64);
         const uint64_t sk = block_sum<S_THREADS, uint64_t>(lsk, red64);
         const uint64_t gk = block_sum<S_THREADS, uint64_t>(lgk, red64);
@@ -753,6 +757,9 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             }
             if (l == 12) resv[8] = td ? atomicAdd(&P.ctl->nitems_m, (unsigned long long)td) : 0ull;
             if (l == 13 && mk) atomicAdd(&P.ctl->model_keys, (unsigned long long)mk);
+            if (l == 14) resv[9] = (tm & 0xffff) ? atomicAdd(&P.ctl->nmerge, (unsigned long long)(tm & 0xffff)) : 0ull;
+            if (l == 15 && (tm >> 32)) atomicAdd(&P.ctl->merge_keys, (unsigned long long)(tm >> 32));
+            if (l == 16 && (tm & 0xffff)) atomicAdd(&P.ctl->nchunk, (unsigned long long)((tm >> 16) & 0xffff));
         }
         if (tid == 0) {
             const uint64_t m12 = 4095;
@@ -777,7 +784,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const uint64_t ci = c[i];
             const bool mb = mbase && a == 2 && ci >= MB_MIN && ci <= MB_MAX;
             const uint64_t nsm = a == 2 && !mb && (ci <= SMALL_MAX || (ci <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
-            const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && !nsm && !mb ? 1 : 0);
+            const uint64_t nsp = a == 2 && !mb && !nsm && !P.has_pay ? split_chunks(ci) : 0;
+            const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && !nsm && !mb && !nsp ? 1 : 0);
             if (mb) {
                 const uint64_t it = resv[8] + xd;
                 if (it < P.item_m_cap) {
@@ -806,6 +814,19 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                 const uint64_t cap = inb ? P.item_b_cap : ng4 ? P.item_c_cap : P.item_cap;
                 uint64_t* list = inb ? P.items_b : ng4 ? P.items_c : P.items;
                 if (it < cap) list[ng0 || ng1 || ng4 ? it : cap - 1 - it] = item_pack(start[i], q, 0u, (uint32_t)ci);
+                else atomicOr(&P.ctl->overflow, OVF_ITEM);
+            }
+            if (nsp) {
+                // chunks of GROUP_WAVE_MAX keys (the last one shorter) sorted as
+                // items of their own, then one merge of the whole bucket
+                for (uint64_t k = 0; k < nsp; k++) {
+                    const uint64_t it = resv[7] + (xc >> 32) + k;
+                    if (it >= P.item_c_cap) { atomicOr(&P.ctl->overflow, OVF_ITEM); break; }
+                    const uint64_t sz = min<uint64_t>(GROUP_WAVE_MAX, ci - k * GROUP_WAVE_MAX);
+                    P.items_c[it] = item_pack(start[i] + k * GROUP_WAVE_MAX, q, 0u, (uint32_t)sz);
+                }
+                const uint64_t it = resv[9] + (xm & 0xffff);
+                if (it < P.merge_cap) P.merges[it] = item_pack(start[i], 0u, 0u, (uint32_t)ci);
                 else atomicOr(&P.ctl->overflow, OVF_ITEM);
             }
             for (uint64_t k = 0; k < nbg; k++) {
@@ -845,7 +866,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             xd += mb ? 1 : 0;
             xa += ng0 | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
             xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
-            xc += ng3 | (ng4 << 32);
+            xc += ng3 | ((ng4 + nsp) << 32);
+            xm += nsp ? 1 | (nsp << 16) | (ci << 32) : 0;
         }
         {  // resident children, one atomic per wavefront that has any
             const uint32_t wt = wave_incl_sum(nresc);

@@ -41,7 +41,7 @@ class LevelStats(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("levels", C.c_uint32), ("first_model", C.c_uint32), ("base_items", C.c_uint64),
                 ("copy_items", C.c_uint64), ("mlp_loss_first", C.c_double), ("mlp_loss_last", C.c_double),
-                ("overflow", C.c_uint32), ("reserved", C.c_uint32), ("level", LevelStats * MAX_STAT_LEVELS)]
+                ("overflow", C.c_uint32), ("merged_items", C.c_uint32), ("level", LevelStats * MAX_STAT_LEVELS)]
 
 
 class KernelTiming(C.Structure):
@@ -225,7 +225,7 @@ def stats() -> dict:
         levels.append({f: getattr(lv, f) for f, _ in LevelStats._fields_})
     return {"levels": levels, "first_model": s.first_model, "base_items": s.base_items,
             "copy_items": s.copy_items, "mlp_loss_first": s.mlp_loss_first, "mlp_loss_last": s.mlp_loss_last,
-            "overflow": s.overflow}
+            "overflow": s.overflow, "merged_items": s.merged_items}
 
 
 def workspace_bytes(n: int, m: int = 1, dtype=torch.float64, payload=False, **opts) -> int:

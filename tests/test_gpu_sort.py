@@ -130,6 +130,57 @@ def test_group_items_every_size(dev):
     assert_same_bits(to_host(t), oracle.sort_segmented(keys, off)[0])
 
 
+@pytest.mark.parametrize("kind,n,buckets", [("uniform", 200_000, 40), ("normal", 300_000, 64), ("u64", 250_000, 40),
+                                             ("lognormal", 400_000, 100), ("sparse_specials", 200_000, 40),
+                                             ("subnormal_mix", 150_000, 32), ("few_distinct", 200_000, 40)])
+def test_split_merge_items(dev, kind, n, buckets):
+    """Keys-only base-case items of 2049..8192 keys (first-level buckets of a
+    few thousand keys): sorted as chunks of 2048 keys (the register group
+    sort; chunks holding NaN / -0.0 by the workgroup sort), then merged in
+    LDS.  Bit-exact against the oracle; the statistics say merges ran."""
+    if kind in inputs.ALL_LAWS:
+        keys = inputs.generate(kind, n, seed=61)
+    else:
+        keys = inputs.adversarial(kind, n, seed=61)
+    got, _ = gpu_sort(keys, dev, buckets=buckets, stats=True)
+    st = lsort.stats()
+    assert_same_bits(got, oracle.sort(keys)[0])
+    if kind not in ("few_distinct", "subnormal_mix"):  # those laws leave no bucket of that size
+        assert st["merged_items"] > 0, st
+
+
+def test_split_merge_with_payload_unchanged(dev):
+    """The same bucket sizes with a payload keep the stable workgroup sort
+    (no merges), bit-exact with the payload."""
+    keys = inputs.generate("normal", 300_000, seed=62)
+    pay = np.arange(keys.size, dtype=np.uint32)
+    got, gp = gpu_sort(keys, dev, pay, buckets=64, stats=True)
+    st = lsort.stats()
+    want, wp = oracle.sort(keys, pay)
+    assert_same_bits(got, want)
+    assert np.array_equal(gp, wp)
+    assert st["merged_items"] == 0
+
+
+def test_split_merge_segmented_sizes(dev):
+    """Segmented arrays whose first-level buckets cover 2049..8192 keys, next
+    to arrays small enough for the register sort, in one call."""
+    rng = np.random.default_rng(63)
+    sizes = np.concatenate([rng.integers(20_000, 120_000, 12), rng.integers(1, 2100, 40)]).astype(np.int64)
+    rng.shuffle(sizes)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    keys = inputs.generate("normal", int(off[-1]), seed=64)
+    t = to_dev(keys, dev)
+    o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+    print(f"[case] split/merge segmented n={keys.size} m={sizes.size}", flush=True)
+    lsort.sort_segmented(t, o, buckets=16, stats=True)
+    torch.cuda.synchronize()
+    st = lsort.stats()
+    assert_same_bits(to_host(t), oracle.sort_segmented(keys, off)[0])
+    assert st["merged_items"] > 0, st
+
+
 @pytest.mark.parametrize("law", ["uniform", "normal", "rootdups", "u64"])
 def test_splitter_model(dev, law):
     keys = inputs.generate(law, 400_000, seed=41)
