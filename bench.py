@@ -563,7 +563,7 @@ def run_learned_parts(inputs, lsort, torch, np, dev, n, seed, reps):
     ms0 = multiset(src, torch)
     buf = torch.empty_like(src)
     res = {"workload": f"sort {n} float64 keys, piecewise law 70/20/10, out-of-place copy restored per run"}
-    for name, model, opts in (("rmi", "auto", {}), ("rmi_judged", "auto", {"balance_pct": 50}), ("mlp", "mlp", {}),
+    for name, model, opts in (("rmi", "auto", {}), ("rmi_no_judge", "auto", {"balance_pct": 100}), ("mlp", "mlp", {}),
                               ("splitter", "splitter", {})):
         log("learned parts:", name, n)
         ms = time_call(lambda: lsort.sort(buf, model=model, stats=False, **opts), reps, lambda: buf.copy_(src), torch)

@@ -218,23 +218,113 @@ __global__ __launch_bounds__(FIT_T) void k_fit_bounds_mlp(FitArgs A) {
     }
 }
 
-// One workgroup of FIT_LT threads per leaf: the leaves the root clamps the
-// distribution's tails into hold a few per cent of the sample each, and
-// their two passes set the kernel's time.  The rank term i / S is taken as
-// i * (1 / S) (a rounding apart from the quotient).
+// Leaf least squares, two passes per leaf (the mean, then centred sums).  A
+// leaf is cut into pieces of A.piece sample points, one workgroup of FIT_LT
+// threads each, so that a leaf holding most of the sample (a distribution
+// whose mass sits in a small part of its key range: the linear root sends it
+// to a few leaves) is summed by many workgroups; a leaf of at most one piece
+// is summed exactly as by a single workgroup.  Pass one writes each piece's
+// sum of x (leaves of several pieces only: a one-piece leaf's workgroup in
+// pass two sums its own x first); pass two adds a leaf's piece sums in piece
+// order (the mean) and writes each piece's centred sums; k_fit_finish adds
+// those in piece order.
+// Workgroup w takes the piece numbered w (numbering below).
+// The rank term i / S is taken as i * (1 / S) (a rounding apart from the
+// quotient).
 constexpr int FIT_LT = 1024;
+static_assert(FIT_LT >= L_MAX && M_THREADS >= L_MAX, "one thread per leaf in the piece numbering");
+
+__device__ __forceinline__ uint64_t leaf_pieces(uint64_t c, uint64_t piece) { return c > piece ? (c + piece - 1) / piece : 1; }
+
+// Piece numbering: piece 0 of leaf j is number j; pieces 1.. of the leaves of
+// several pieces follow from L on, leaf by leaf: piece q >= 1 of leaf j is
+// L + ex_j + q - 1, ex_j = sum over i < j of (pieces of i - 1).
+__device__ __forceinline__ uint64_t piece_slot(uint32_t L, uint32_t j, uint64_t ex, uint64_t q) {
+    return q == 0 ? j : L + ex + q - 1;
+}
+
+// Thread j (< L): its leaf's piece count, and ex_j (returned).
+template <int NT>
+__device__ __forceinline__ uint64_t extra_table(const FitArgs& A, uint64_t& np, uint64_t* red64) {
+    const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
+    const uint32_t j = threadIdx.x;
+    np = j < A.L ? leaf_pieces(bounds[j + 1] - bounds[j], A.piece) : 1;
+    uint64_t tot;
+    return block_excl_scan<NT, uint64_t>(np - 1, red64, &tot);
+}
+
+// This workgroup's piece: leaf j, index q within it, the leaf's piece count
+// and ex_j (the extra-piece table is built only where it is needed: a leaf
+// of several pieces, or a workgroup past the first L); false past the last.
+__device__ bool my_piece(const FitArgs& A, uint32_t& j, uint64_t& q, uint64_t& ex, uint64_t& np, uint64_t* red64,
+                         uint64_t* sh) {
+    const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
+    const uint64_t w = blockIdx.x;
+    if (w < A.L) {
+        j = (uint32_t)w;
+        q = 0;
+        np = leaf_pieces(bounds[j + 1] - bounds[j], A.piece);
+        ex = 0;
+        if (np > 1) {  // uniform: the workgroup's leaf
+            uint64_t npt;
+            const uint64_t ext = extra_table<FIT_LT>(A, npt, red64);
+            if (threadIdx.x == j) sh[0] = ext;
+            __syncthreads();
+            ex = sh[0];
+        }
+        return true;
+    }
+    uint64_t npt;
+    const uint64_t ext = extra_table<FIT_LT>(A, npt, red64);
+    if (threadIdx.x == 0) sh[0] = ~0ull;
+    __syncthreads();
+    const uint64_t e = w - A.L;
+    if (threadIdx.x < A.L && npt > 1 && e >= ext && e < ext + npt - 1) {
+        sh[0] = threadIdx.x; sh[1] = e - ext + 1; sh[2] = ext; sh[3] = npt;
+    }
+    __syncthreads();
+    if (sh[0] == ~0ull) return false;
+    j = (uint32_t)sh[0]; q = sh[1]; ex = sh[2]; np = sh[3];
+    return true;
+}
+
+__global__ __launch_bounds__(FIT_LT) void k_fit_lsum(FitArgs A) {
+    __shared__ double red[FIT_LT / 64];
+    __shared__ uint64_t red64[FIT_LT / 64];
+    __shared__ uint64_t sh[4];
+    if (A.flag[0] == 0) return;
+    uint32_t j;
+    uint64_t q, ex, np;
+    if (!my_piece(A, j, q, ex, np, red64, sh) || np == 1) return;
+    const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
+    const uint64_t lo = bounds[j] + q * A.piece, hi = min(bounds[j + 1], lo + A.piece);
+    double s = 0;
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)FIT_LT * FIT_LU) {
+        uint64_t r[FIT_LU];
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++) r[u] = i0 + (uint64_t)u * FIT_LT < hi ? A.s[i0 + (uint64_t)u * FIT_LT] : 0;
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++)
+            if (i0 + (uint64_t)u * FIT_LT < hi) { double x; key_x(r[u], A.u64, x); s += x; }
+    }
+    s = block_sum<FIT_LT, double>(s, red);
+    if (threadIdx.x == 0) A.lpart[blockIdx.x * 4 + 0] = s;
+}
 
 __global__ __launch_bounds__(FIT_LT) void k_fit_leaves(FitArgs A) {
     __shared__ double red[FIT_LT / 64];
+    __shared__ uint64_t red64[FIT_LT / 64];
+    __shared__ uint64_t sh[4];
+    __shared__ double sh_mx;
     if (A.flag[0] == 0) return;
-    const uint32_t j = blockIdx.x;
+    uint32_t j;
+    uint64_t q, ex, np;
+    if (!my_piece(A, j, q, ex, np, red64, sh)) return;
     const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
-    const uint64_t range[2] = {bounds[j], bounds[j + 1]};
-    const uint64_t lo = range[0], hi = range[1];
+    const uint64_t llo = bounds[j], lhi = bounds[j + 1];
+    const uint64_t lo = llo + q * A.piece, hi = min(lhi, lo + A.piece);
     const double Sd = (double)A.S, invS = 1.0 / Sd;
-    double a = 0, b = 0, pmin = 0, pmax = 0;
-    if (hi > lo) {
-        const double cnt = (double)(hi - lo);
+    if (np == 1) {  // the whole leaf: its own sum of x
         double s = 0;
         for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)FIT_LT * FIT_LU) {
             uint64_t r[FIT_LU];
@@ -245,36 +335,37 @@ __global__ __launch_bounds__(FIT_LT) void k_fit_leaves(FitArgs A) {
                 if (i0 + (uint64_t)u * FIT_LT < hi) { double x; key_x(r[u], A.u64, x); s += x; }
         }
         s = block_sum<FIT_LT, double>(s, red);
-        const double mx = s / cnt, my = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
-        double sxx = 0, sxy = 0;
-        for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)FIT_LT * FIT_LU) {
-            uint64_t r[FIT_LU];
+        if (threadIdx.x == 0) {
+            A.lpart[blockIdx.x * 4 + 0] = s;
+            sh_mx = hi > lo ? s / (double)(hi - lo) : 0.0;
+        }
+    } else if (threadIdx.x == 0) {
+        double s = 0;
+        for (uint64_t r = 0; r < np; r++) s += A.lpart[piece_slot(A.L, j, ex, r) * 4 + 0];
+        sh_mx = lhi > llo ? s / (double)(lhi - llo) : 0.0;
+    }
+    __syncthreads();
+    const double mx = sh_mx, my = ((double)llo + (double)lhi - 1.0) / (2.0 * Sd);
+    double sxx = 0, sxy = 0;
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)FIT_LT * FIT_LU) {
+        uint64_t r[FIT_LU];
 #pragma unroll
-            for (int u = 0; u < FIT_LU; u++) r[u] = i0 + (uint64_t)u * FIT_LT < hi ? A.s[i0 + (uint64_t)u * FIT_LT] : 0;
+        for (int u = 0; u < FIT_LU; u++) r[u] = i0 + (uint64_t)u * FIT_LT < hi ? A.s[i0 + (uint64_t)u * FIT_LT] : 0;
 #pragma unroll
-            for (int u = 0; u < FIT_LU; u++) {
-                const uint64_t i = i0 + (uint64_t)u * FIT_LT;
-                if (i < hi) {
-                    double x; key_x(r[u], A.u64, x);
-                    double dx = x - mx, dy = (double)i * invS - my;
-                    sxx += dx * dx; sxy += dx * dy;
-                }
+        for (int u = 0; u < FIT_LU; u++) {
+            const uint64_t i = i0 + (uint64_t)u * FIT_LT;
+            if (i < hi) {
+                double x; key_x(r[u], A.u64, x);
+                double dx = x - mx, dy = (double)i * invS - my;
+                sxx += dx * dx; sxy += dx * dy;
             }
         }
-        sxx = block_sum<FIT_LT, double>(sxx, red);
-        sxy = block_sum<FIT_LT, double>(sxy, red);
-        a = sxx > 0 ? sxy / sxx : 0.0;
-        if (a < 0) a = 0;
-        b = my - a * mx;
-        double x0, x1;
-        key_x(A.s[lo], A.u64, x0);
-        key_x(A.s[hi - 1], A.u64, x1);
-        pmin = a * x0 + b;
-        pmax = a * x1 + b;
     }
+    sxx = block_sum<FIT_LT, double>(sxx, red);
+    sxy = block_sum<FIT_LT, double>(sxy, red);
     if (threadIdx.x == 0) {
-        double* q = A.leaf + (uint64_t)j * 8;
-        q[0] = a; q[1] = b; q[2] = pmin; q[3] = pmax; q[4] = hi > lo ? 1.0 : 0.0;
+        A.lpart[blockIdx.x * 4 + 1] = sxx;
+        A.lpart[blockIdx.x * 4 + 2] = sxy;
     }
 }
 
@@ -334,12 +425,39 @@ __global__ __launch_bounds__(M_THREADS) void k_fit_balance(FitArgs A) {
 __global__ __launch_bounds__(M_THREADS) void k_fit_finish(FitArgs A) {
     __shared__ double red[M_THREADS / 64];
     __shared__ double wave_last[M_THREADS / 64];
+    __shared__ uint64_t red64[M_THREADS / 64];
     if (A.flag[0] == 0) return;
     const int tid = threadIdx.x;
     const bool in = (uint32_t)tid < A.L;
-    const double* q = A.leaf + (uint64_t)tid * 8;
-    double a = in ? q[0] : 0, b = in ? q[1] : 0, pmin = in ? q[2] : 0, pmax = in ? q[3] : 0;
-    const bool ne = in && q[4] != 0.0;
+    // leaf line from its pieces' sums, added in piece order (as the mean in
+    // k_fit_leaves)
+    uint64_t np;
+    const uint64_t ex = extra_table<M_THREADS>(A, np, red64);
+    double a = 0, b = 0, pmin = 0, pmax = 0;
+    bool ne = false;
+    if (in) {
+        const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
+        const uint64_t lo = bounds[tid], hi = bounds[tid + 1];
+        if (hi > lo) {
+            double s = 0, sxx = 0, sxy = 0;
+            for (uint64_t r = 0; r < np; r++) s += A.lpart[piece_slot(A.L, tid, ex, r) * 4 + 0];
+            for (uint64_t r = 0; r < np; r++) {
+                sxx += A.lpart[piece_slot(A.L, tid, ex, r) * 4 + 1];
+                sxy += A.lpart[piece_slot(A.L, tid, ex, r) * 4 + 2];
+            }
+            const double Sd = (double)A.S;
+            const double mx = s / (double)(hi - lo), my = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
+            a = sxx > 0 ? sxy / sxx : 0.0;
+            if (a < 0) a = 0;
+            b = my - a * mx;
+            double x0, x1;
+            key_x(A.s[lo], A.u64, x0);
+            key_x(A.s[hi - 1], A.u64, x1);
+            pmin = a * x0 + b;
+            pmax = a * x1 + b;
+            ne = true;
+        }
+    }
     double v = ne ? pmax : -INFINITY;
     double incl = block_incl_max<M_THREADS>(v, red);
     double excl = __shfl_up(incl, 1);
@@ -442,15 +560,29 @@ hipError_t launch_gather(const uint64_t* keys, uint64_t n, uint64_t seed, uint64
 hipError_t launch_fit1(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit1, A.G, FIT_T, st, A); }
 hipError_t launch_fit2(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit2, A.G, FIT_T, st, A); }
 hipError_t launch_fit_root(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_root, 1, M_THREADS, st, A); }
-hipError_t launch_fit_leaves(const FitArgs& A, hipStream_t st) {
+// The piece size (at least FIT_PIECE points, larger for samples of more than
+// FIT_PIECES * FIT_PIECE, so that the pieces never exceed L + FIT_PIECES) and
+// the piece sums' place after the leaf boundaries.
+static FitArgs with_pieces(const FitArgs& A) {
+    FitArgs B = A;
+    B.piece = std::max<uint64_t>(FIT_PIECE, (A.S + FIT_PIECES - 1) / FIT_PIECES);
+    B.lpart = A.leaf + (uint64_t)L_MAX * 8 + (L_MAX + 1);
+    return B;
+}
+hipError_t launch_fit_leaves(const FitArgs& A0, hipStream_t st) {
+    const FitArgs A = with_pieces(A0);
     const uint32_t grid = (uint32_t)std::min<uint64_t>((A.S + FIT_T - 1) / FIT_T, 2048ull);
     if (A.mlp) hipLaunchKernelGGL(k_fit_bounds_mlp, dim3(grid ? grid : 1), dim3(FIT_T), 0, st, A);
     else hipLaunchKernelGGL(k_fit_bounds, dim3(grid ? grid : 1), dim3(FIT_T), 0, st, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    LAUNCH(k_fit_leaves, A.L, FIT_LT, st, A);
+    const uint32_t pieces = A.L + (uint32_t)((A.S + A.piece - 1) / A.piece);  // bounds every leaf's piece count
+    hipLaunchKernelGGL(k_fit_lsum, dim3(pieces), dim3(FIT_LT), 0, st, A);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    LAUNCH(k_fit_leaves, pieces, FIT_LT, st, A);
 }
-hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_finish, 1, M_THREADS, st, A); }
+hipError_t launch_fit_finish(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_finish, 1, M_THREADS, st, with_pieces(A)); }
 hipError_t launch_fit_balance(const FitArgs& A, hipStream_t st) { LAUNCH(k_fit_balance, 1, M_THREADS, st, A); }
 hipError_t launch_fit_bstart(const FitArgs& A, hipStream_t st) {
     const uint32_t grid = (uint32_t)std::min<uint64_t>((A.S + FIT_T - 1) / FIT_T, 2048ull);

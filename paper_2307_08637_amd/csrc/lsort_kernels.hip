@@ -190,13 +190,17 @@ __device__ void fit_rmi_block(const uint64_t* smp, uint32_t S, int u64, uint32_t
     __syncthreads();
     // per-leaf least squares: two threads per leaf (even and odd points, the
     // partial sums combined through a lane swap), so that a leaf the root
-    // clamps a tail into is walked in half the time; the raw line and its
-    // ends go to the leaf's model slots and are read back below
+    // clamps a tail into is walked in half the time; a leaf of more than
+    // FB_HEAVY points (a distribution whose mass the linear root sends to a
+    // few leaves) is summed by a whole wavefront instead, below.  The raw
+    // line and its ends go to the leaf's model slots and are read back below.
+    constexpr uint32_t FB_HEAVY = 128;
     const double invS = 1.0 / Sd;  // i / S as i * (1 / S): no division per point
     for (uint32_t j0 = 0; j0 < L; j0 += M_THREADS / 2) {
         const uint32_t j = j0 + ((uint32_t)tid >> 1), half = (uint32_t)tid & 1u;
         const uint32_t jl = j < L ? j : L - 1;
-        const uint32_t lo = lstart[jl], hi = j < L ? lstart[jl + 1] : lo;
+        const uint32_t lo = lstart[jl];
+        const uint32_t hi = j < L && lstart[jl + 1] - lo <= FB_HEAVY ? lstart[jl + 1] : lo;
         const double cnt = (double)(hi - lo);
         double s = 0;
         for (uint32_t i = lo + half; i < hi; i += 2) { double x; key_x(key_unord(smp[i], u64), u64, x); s += x; }
@@ -220,6 +224,46 @@ __device__ void fit_rmi_block(const uint64_t* smp, uint32_t S, int u64, uint32_t
             key_x(key_unord(smp[hi - 1], u64), u64, x1);
             double* q = dst + 4 + 2 + 4 * j;
             q[0] = a; q[1] = b; q[2] = a * x0 + b; q[3] = a * x1 + b;
+        }
+    }
+    {  // leaves of more than FB_HEAVY points: one wavefront each, dealt to the
+       // wavefronts in leaf order; lanes stride the points, sums in a fixed order
+        constexpr uint32_t NW = M_THREADS / 64;
+        const uint32_t wv = (uint32_t)tid >> 6, lane = (uint32_t)tid & 63u;
+        uint32_t seen = 0;
+        for (uint32_t c0 = 0; c0 < L; c0 += 64) {
+            const uint32_t jj = c0 + lane;
+            uint64_t m = __ballot(jj < L && lstart[jj + 1] - lstart[jj] > FB_HEAVY);
+            while (m) {
+                const uint32_t j = c0 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
+                m &= m - 1;
+                if (seen++ % NW != wv) continue;
+                const uint32_t lo = lstart[j], hi = lstart[j + 1];
+                const double cnt = (double)(hi - lo);
+                double s = 0;
+                for (uint32_t i = lo + lane; i < hi; i += 64) { double x; key_x(key_unord(smp[i], u64), u64, x); s += x; }
+                s = wave_sum(s);
+                const double lmx = s / cnt;
+                const double lmy = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
+                double lxx = 0, lxy = 0;
+                for (uint32_t i = lo + lane; i < hi; i += 64) {
+                    double x; key_x(key_unord(smp[i], u64), u64, x);
+                    const double dx = x - lmx, dy = (double)i * invS - lmy;
+                    lxx += dx * dx; lxy += dx * dy;
+                }
+                lxx = wave_sum(lxx);
+                lxy = wave_sum(lxy);
+                if (lane == 0) {
+                    double a = lxx > 0 ? lxy / lxx : 0.0;
+                    if (a < 0) a = 0;
+                    const double b = lmy - a * lmx;
+                    double x0, x1;
+                    key_x(key_unord(smp[lo], u64), u64, x0);
+                    key_x(key_unord(smp[hi - 1], u64), u64, x1);
+                    double* q = dst + 4 + 2 + 4 * j;
+                    q[0] = a; q[1] = b; q[2] = a * x0 + b; q[3] = a * x1 + b;
+                }
+            }
         }
     }
     __syncthreads();

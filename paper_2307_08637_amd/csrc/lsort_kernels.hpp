@@ -28,7 +28,11 @@ struct FitArgs {
     uint64_t* bstart;    // [B1 + 1]: first sample index of each first-level bucket (nullable)
     double ratio;        // oversized bucket: more than ratio x expected keys
     double balance;      // share of the sample in oversized buckets above which the tree replaces the RMI
+    double* lpart;       // leaf least squares: 4 sums per piece of a leaf (set by the launchers)
+    uint64_t piece;      // sample points per piece
 };
+constexpr uint64_t FIT_PIECE = 65536;   // sample points per workgroup of a leaf's least-squares passes
+constexpr uint64_t FIT_PIECES = 1024;   // pieces beyond one per leaf (the piece grows for larger samples)
 
 // MLP training (lsort_mlp.hip)
 constexpr int MLP_G = 512;           // workgroups of a training step (gradient partials; two per CU)

@@ -275,13 +275,13 @@ def test_model_base_case_adversarial(dev, kind):
     assert np.array_equal(gp, wp)
 
 
-@pytest.mark.parametrize("pct", [50, 100, 1])
+@pytest.mark.parametrize("pct", [0, 50, 100, 1])
 def test_first_level_balance_judge(dev, pct):
     """The 70/20/10 piecewise law: its fitted RMI puts most of the sample in
-    oversized buckets, so at 50 % the first level takes the splitter tree;
-    with the check off (100, the default) the RMI stays, and the normal law
-    keeps its RMI at 50 %.  Output equal to the oracle's either way (at 1 %
-    whichever model the check picks)."""
+    oversized buckets, so at 50 % (the default, pct 0) the first level takes
+    the splitter tree; with the check off (100) the RMI stays, and the normal
+    law keeps its RMI at 50 %.  Output equal to the oracle's either way (at
+    1 % whichever model the check picks)."""
     for law, n in (("piecewise", 4_000_000), ("normal", 3_000_000)):
         keys = inputs.generate(law, n, seed=23)
         payload = np.arange(n, dtype=np.uint32)

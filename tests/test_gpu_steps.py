@@ -64,7 +64,9 @@ def check_fit(gp, s, L, R):
 
 
 @pytest.mark.parametrize("law,L,S", [("uniform", 1000, 10_000), ("lognormal", 1000, 1_000_000), ("normal", 64, 5000),
-                                     ("u64", 1000, 200_000), ("mixgauss", 513, 77_777), ("exponential", 2, 1000)])
+                                     ("u64", 1000, 200_000), ("mixgauss", 513, 77_777), ("exponential", 2, 1000),
+                                     # leaves of more than one 65536-point piece (summed by several workgroups)
+                                     ("piecewise", 1000, 1_000_000), ("normal", 3, 400_000)])
 def test_rmi_fit(dev, law, L, S):
     keys = inputs.generate(law, max(S * 10, 100_000), seed=5)
     s = sorted_sample(keys, 99, S)
@@ -153,7 +155,9 @@ def test_partition_splitters(dev, law):
 
 
 @pytest.mark.parametrize("law,L,S", [("uniform", 1000, 1000), ("normal", 1000, 10_000), ("lognormal", 1000, 16384),
-                                     ("u64", 512, 16384), ("mixgauss", 64, 4097), ("exponential", 2, 2)])
+                                     ("u64", 512, 16384), ("mixgauss", 64, 4097), ("exponential", 2, 2),
+                                     # leaves of more than 128 points (summed by a whole wavefront)
+                                     ("piecewise", 1000, 2048), ("piecewise", 1000, 16384), ("normal", 4, 16384)])
 def test_rmi_fit_block(dev, law, L, S):
     """The one-workgroup fit (the model of every segment whose sample fits in
     LDS, and of every batched array) against the oracle's long-double fit,
