@@ -606,8 +606,21 @@ __global__ __launch_bounds__(RG_T) void k_mlp_regions(MlpRegion A) {
     const double inv_s = 1.0 / (double)S;
     double pb1 = 1.0, pb2 = 1.0;
     const uint32_t nstep = A.steps ? A.steps : 1;
+    // parameter tid's value, Adam moments and step scale live in thread
+    // tid's registers for the whole training (written back at the end)
+    static_assert(MLP_NP <= RG_T, "one thread per parameter");
+    float pv = 0.0f, mv = 0.0f, vv = 0.0f, sc = 1.0f;
+    if (tid < MLP_NP) {
+        pv = A.p[tid];
+        if (A.steps) {
+            mv = A.m[tid];
+            vv = A.v[tid];
+            sc = A.scale ? A.scale[tid] : 1.0f;
+        }
+    }
+    float best_loss = A.best ? *A.best_loss : 0.0f;
     for (uint32_t k = 1; k <= nstep; k++) {
-        for (int i = tid; i < MLP_NP; i += RG_T) w[i] = mlp_is_weight(i) ? fabsf(A.p[i]) : A.p[i];
+        if (tid < MLP_NP) w[tid] = mlp_is_weight(tid) ? fabsf(pv) : pv;
         __syncthreads();
         // switch indices: wave wv searches units wv and wv + 16
         for (int u = wv; u < RG_UNITS; u += RG_T / 64) {
@@ -630,16 +643,18 @@ __global__ __launch_bounds__(RG_T) void k_mlp_regions(MlpRegion A) {
         }
         if (tid == 0) { bnd[0] = 0; bnd[RG_MAXR] = S; }
         __syncthreads();
-        // one wavefront per region: its affine pieces, moments and the
-        // per-region factors of the gradient
-        for (int r = wv; r < RG_MAXR; r += RG_T / 64) {
+        // one group of 16 lanes per region (four per wavefront, every region
+        // in one round): its affine pieces, moments and the per-region
+        // factors of the gradient
+        static_assert(RG_MAXR <= RG_T / 16, "a lane group for every region");
+        for (int r = tid >> 4; r < RG_MAXR; r += RG_T / 16) {
             const uint64_t b = bnd[r], e = bnd[r + 1];
             double* R = rec[r];
+            const int kk = lane & 15, g0 = lane & 48;  // unit, the group's first lane
             if (b >= e) {
-                for (int x = lane; x < RG_REC; x += 64) R[x] = 0.0;
+                for (int x = kk; x < RG_REC; x += 16) R[x] = 0.0;
                 continue;
             }
-            const int kk = lane & 15;
             // unit masks at the region's first index
             const bool on1 = kk < MLP_HALF ? b >= thr[kk] : b < thr[kk];
             const bool on2 = kk < MLP_HALF ? b >= thr[MLP_H + kk] : b < thr[MLP_H + kk];
@@ -647,16 +662,16 @@ __global__ __launch_bounds__(RG_T) void k_mlp_regions(MlpRegion A) {
             double a2 = 0.0, c2 = (double)w[OFF_B2 + kk];
             for (int q = 0; q < MLP_H; q++) {
                 const double wq = (double)w[OFF_V2 + MLP_H * kk + q];
-                a2 += wq * __shfl(a1, q);
-                c2 += wq * __shfl(c1, q);
+                a2 += wq * __shfl(a1, g0 + q);
+                c2 += wq * __shfl(c1, g0 + q);
             }
             const double u = on2 ? (double)w[OFF_V3 + kk] : 0.0;
             double s = 0.0;
-            for (int q = 0; q < MLP_H; q++) s += (double)w[OFF_V2 + MLP_H * q + kk] * __shfl(u, q);
-            double al = lane < MLP_H ? u * a2 : 0.0, ga = lane < MLP_H ? u * c2 : 0.0;
+            for (int q = 0; q < MLP_H; q++) s += (double)w[OFF_V2 + MLP_H * q + kk] * __shfl(u, g0 + q);
+            double al = u * a2, ga = u * c2;
             for (int o = 8; o > 0; o >>= 1) { al += __shfl_xor(al, o); ga += __shfl_xor(ga, o); }
-            al = __shfl(al, 0);
-            ga = __shfl(ga, 0) + (double)w[OFF_B3];
+            al = __shfl(al, g0);
+            ga = __shfl(ga, g0) + (double)w[OFF_B3];
             // region sums (double-double differences of the prefix sums),
             // centred at the region's first input t_r
             const double tr = (double)A.t[b];
@@ -675,12 +690,10 @@ __global__ __launch_bounds__(RG_T) void k_mlp_regions(MlpRegion A) {
             const double orr = al * tr + ga;  // output at t_r
             const double E0 = al * SD + n * orr - sy;
             const double E1 = tr * E0 + al * SDD + orr * SD - SDy;
-            if (lane < MLP_H) {
-                R[RG_A1 + kk] = a1; R[RG_C1 + kk] = c1;
-                R[RG_A2 + kk] = on2 ? a2 : 0.0; R[RG_C2 + kk] = on2 ? c2 : 0.0;
-                R[RG_U + kk] = u; R[RG_Q + kk] = on1 ? s : 0.0;
-            }
-            if (lane == 0) {
+            R[RG_A1 + kk] = a1; R[RG_C1 + kk] = c1;
+            R[RG_A2 + kk] = on2 ? a2 : 0.0; R[RG_C2 + kk] = on2 ? c2 : 0.0;
+            R[RG_U + kk] = u; R[RG_Q + kk] = on1 ? s : 0.0;
+            if (kk == 0) {
                 R[RG_E0] = E0; R[RG_E1] = E1;
                 const double Soo = dd_add(dd_add(dd_mul(dd_of(n * orr), orr), dd_neg(dd_mul(Sy, 2.0 * orr))), Syy).hi;
                 R[RG_L] = al * al * SDD + 2.0 * al * (orr * SD - SDy) + Soo;
@@ -712,39 +725,38 @@ __global__ __launch_bounds__(RG_T) void k_mlp_regions(MlpRegion A) {
         }
         __syncthreads();
         const float loss = (float)sh_loss;
-        const bool better = A.best && loss < *A.best_loss;
-        __syncthreads();
+        const bool better = A.best && loss < best_loss;
         pb1 *= (double)A.b1;
         pb2 *= (double)A.b2;
         if (tid < MLP_NP) {
-            const float pv = A.p[tid];
             if (better) A.best[tid] = pv;
             float gf = (float)g;
             if (mlp_is_weight(tid)) gf *= pv > 0.0f ? 1.0f : (pv < 0.0f ? -1.0f : 0.0f);  // d|V|/dV
             if (k == 1 && A.grad_out) A.grad_out[tid] = gf;
             if (A.steps) {
-                const float sc = A.scale ? A.scale[tid] : 1.0f;
                 const float gs = sc * gf;
-                const float mm = A.b1 * A.m[tid] + (1.0f - A.b1) * gs;
-                const float vv = A.b2 * A.v[tid] + (1.0f - A.b2) * gs * gs;
-                A.m[tid] = mm;
-                A.v[tid] = vv;
+                mv = A.b1 * mv + (1.0f - A.b1) * gs;
+                vv = A.b2 * vv + (1.0f - A.b2) * gs * gs;
                 const float c1 = (float)(1.0 - pb1), c2 = (float)(1.0 - pb2);
-                A.p[tid] = pv - sc * (A.lr * (mm / c1) / (sqrtf(vv / c2) + A.eps));
+                pv = pv - sc * (A.lr * (mv / c1) / (sqrtf(vv / c2) + A.eps));
             }
         }
+        if (better) best_loss = loss;
         if (tid == 0) {
             if (better) *A.best_loss = loss;
             if (k == 1 && A.loss_out) *A.loss_out = loss;
             if (A.losses && A.steps) A.losses[k - 1] = loss;
             if (A.loss_pair) {
                 if (k == 1) A.loss_pair[0] = loss;
-                A.loss_pair[1] = A.best ? fminf(*A.best_loss, loss) : loss;
+                A.loss_pair[1] = A.best ? fminf(best_loss, loss) : loss;
             }
         }
-        // the next step reads p and best_loss written above
-        __threadfence_block();
-        __syncthreads();
+        __syncthreads();  // the next step rewrites w and rec
+    }
+    if (tid < MLP_NP && A.steps) {
+        A.p[tid] = pv;
+        A.m[tid] = mv;
+        A.v[tid] = vv;
     }
 }
 
