@@ -152,8 +152,8 @@ typedef struct {
                                 unsorted (the call returned LS_ENOMEM, or with LS_FLAG_FIXED_LEVELS could
                                 not tell); bits: 1 segments, 2 work units, 4 base-case items, 8 bucket
                                 counts, 16 look-back words, 32 model arena, 64 look-back sequence */
-    uint32_t merged_items;   /* of base_items: keys-only sub-arrays of 2049..8192 keys sorted as chunks of
-                                2048 keys, then merged */
+    uint32_t merged_items;   /* of base_items: sub-arrays sorted as chunks, then merged (keys only: 2049..8192
+                                keys in chunks of 2048; with a payload: 1025..8192 keys in chunks of 1024) */
     ls_level_stats level[LS_MAX_STAT_LEVELS];
 } ls_stats;
 

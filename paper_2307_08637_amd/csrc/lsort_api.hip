@@ -241,10 +241,11 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.item_cap = n + m + 64;        // small items hold >= 1 key
     L.big_cap = n / 2 + m + 64;     // large items > 512 keys, copy runs >= 2 keys
     L.item_b_cap = n / (GROUP_SMALL_MAX + 1) + m + 64;  // items of 129..256 keys and of 513..1024
-    // items of 1025..2048 keys, and the chunks of at most 2048 keys of the
-    // keys-only items of 2049..8192 (at most 2 per 2049 keys: <= n / 1024)
-    L.item_c_cap = n / GROUP_LARGE_MAX + m + 64;
-    L.merge_cap = n / (GROUP_WAVE_MAX + 1) + m + 64;  // those 2049..8192-key items
+    // keys only: items of 1025..2048 keys, and the 2048-key chunks of items of
+    // 2049..8192 (at most 2 per 2049 keys: <= n / 1024); with a payload:
+    // items and 1024-key chunks of 513..8192-key items (<= n / 512)
+    L.item_c_cap = n / SMALL_MAX + m + 64;
+    L.merge_cap = n / (PAIR_CHUNK + 1) + m + 64;  // items of more than one chunk
     // Bucket counts per level: a segment gets at most n_seg / 4 buckets (at
     // least 2), except one first-level segment whose model the caller gives
     // (up to B_MAX).  Look-back words: tiles x buckets of each segment.
@@ -672,8 +673,8 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         const bool mbase = (c.o.flags & LS_FLAG_MODEL_BASE) && P.fmodel;
         if (mbase) TIMED(KI_BASE_MODEL, c.st, launch_base_model(P, cus * 2, c.st));
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
-        // keys only: the items of 2049..8192 keys, sorted above as chunks, merged
-        if (!P.has_pay) TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus * 2, c.st));
+        // the items sorted above as chunks, merged
+        TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus * 2, c.st));
         if (g_timing && !t_untimed && g_trec.size() > r0) {  // keys through each base-case kernel
             HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));
@@ -682,7 +683,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
             g_trec[r++].keys = (double)hc->small_keys;
             if (mbase) g_trec[r++].keys = (double)hc->model_keys;
             g_trec[r++].keys = (double)hc->big_keys;
-            if (!P.has_pay) g_trec[r++].keys = (double)hc->merge_keys;
+            g_trec[r++].keys = (double)hc->merge_keys;
         }
     }
     return LS_OK;

@@ -349,29 +349,38 @@ __global__ __launch_bounds__(NT) void k_base_mid(Params P) {
     }
 }
 
-// Keys-only items of GROUP_WAVE_MAX+1 .. BIG_MAX keys: k_base_small has sorted
-// each chunk of GROUP_WAVE_MAX keys into the caller's buffer (k_base_mid the
-// chunks holding a NaN or a -0.0); one workgroup per item merges the sorted
-// runs pairwise in LDS, runs of 2048 into 4096 into 8192 keys.  Keys are
-// compared as ordered 64-bit images (the totalOrder map), which order every
-// chunk the same way whichever kernel sorted it.  Each thread produces 16
-// consecutive outputs of a round: its start in the pair of runs comes from a
-// merge-path search (the number of keys the first run contributes to the
-// outputs before it, ties taken from the first run), then it merges
-// sequentially.  The item sits in LDS with one pad word after every 16 keys,
-// so that the 16-key output runs of a wavefront's lanes fall on distinct
-// banks (17 l mod 32 is a bijection).  Two workgroups per CU.
+// Chunk-and-merge items (split_chunks).  Keys only: items of 2049..8192
+// keys, whose 2048-key chunks k_base_small has sorted into the caller's
+// buffer (k_base_mid the chunks holding a NaN or a -0.0).  With a payload:
+// items of 1025..8192 keys, whose 1024-key chunks k_base_pairs has sorted
+// stably.  One workgroup per item merges the sorted runs pairwise in LDS,
+// runs of one chunk into two, four, eight.  Keys are compared as ordered
+// 64-bit images (the totalOrder map), which order every chunk the same way
+// whichever kernel sorted it; on equal keys the earlier run's key comes first,
+// so the merge of stable runs is stable and the payload follows.  Each
+// thread produces 16 consecutive outputs of a round: its start in the pair of
+// runs comes from a merge-path search (the number of keys the first run
+// contributes to the outputs before it), then it merges sequentially.  The
+// item sits in LDS with one pad word after every 16 keys, so that the 16-key
+// output runs of a wavefront's lanes fall on distinct banks (17 l mod 32 is a
+// bijection).  Keys only: 68 KB of LDS, two workgroups per CU; with a
+// payload 102 KB, one.
 constexpr int MG_THREADS = 512, MG_OUT = BIG_MAX / MG_THREADS;
-static_assert(MG_OUT == 16 && GROUP_WAVE_MAX % MG_OUT == 0, "a thread's outputs lie inside one pair of runs");
+static_assert(MG_OUT == 16 && PAIR_CHUNK % MG_OUT == 0 && GROUP_WAVE_MAX % MG_OUT == 0,
+              "a thread's outputs lie inside one pair of runs");
 
 __device__ __forceinline__ uint32_t mslot(uint32_t i) { return i + (i >> 4); }
 
+template <bool PAY>
 __global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
     __shared__ uint64_t L[BIG_MAX + BIG_MAX / 16];
+    __shared__ uint32_t Lp[PAY ? BIG_MAX + BIG_MAX / 16 : 1];
     const int tid = threadIdx.x;
     const uint64_t nm = min<unsigned long long>(P.ctl->nmerge, P.merge_cap);
     uint64_t* keys = P.keys[0];
+    uint32_t* pay = P.pay[0];
     const int u64 = P.u64;
+    const uint32_t w0 = chunk_keys(PAY);
     for (uint64_t it = blockIdx.x; it < nm; it += gridDim.x) {
         const uint64_t wd = P.merges[it];
         const uint64_t off = wd >> 18;
@@ -388,11 +397,25 @@ __global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
                 const uint32_t i = r * MG_THREADS + tid;
                 if (i < n) L[mslot(i)] = key_ord(v[r], u64);
             }
+            if (PAY) {
+                uint32_t pv[MG_OUT];
+#pragma unroll
+                for (int r = 0; r < MG_OUT; r++) {
+                    const uint32_t i = r * MG_THREADS + tid;
+                    pv[r] = i < n ? pay[off + i] : 0u;
+                }
+#pragma unroll
+                for (int r = 0; r < MG_OUT; r++) {
+                    const uint32_t i = r * MG_THREADS + tid;
+                    if (i < n) Lp[mslot(i)] = pv[r];
+                }
+            }
         }
         __syncthreads();
         const uint32_t p0 = (uint32_t)tid * MG_OUT;
-        for (uint32_t w = GROUP_WAVE_MAX; w < n; w <<= 1) {
+        for (uint32_t w = w0; w < n; w <<= 1) {
             uint64_t o[MG_OUT];
+            uint32_t op[MG_OUT];
             if (p0 < n) {
                 const uint32_t a0 = p0 / (2 * w) * (2 * w);     // the pair of runs [a0, a0 + la), [b0, b0 + lb)
                 const uint32_t la = min(w, n - a0);
@@ -413,6 +436,7 @@ __global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
                 for (int r = 0; r < MG_OUT; r++) {
                     const bool ta = ib >= lb || (ia < la && va <= vb);
                     o[r] = ta ? va : vb;
+                    if (PAY) op[r] = Lp[mslot(ta ? a0 + ia : b0 + ib)];
                     if (ta) {
                         ia++;
                         va = ia < la ? L[mslot(a0 + ia)] : 0ull;
@@ -425,15 +449,69 @@ __global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
             __syncthreads();  // every read of this round is done
 #pragma unroll
             for (int r = 0; r < MG_OUT; r++)
-                if (p0 + r < n) L[mslot(p0 + r)] = o[r];
+                if (p0 + r < n) {
+                    L[mslot(p0 + r)] = o[r];
+                    if (PAY) Lp[mslot(p0 + r)] = op[r];
+                }
             __syncthreads();
         }
 #pragma unroll
         for (int r = 0; r < MG_OUT; r++) {
             const uint32_t i = r * MG_THREADS + tid;
-            if (i < n) keys[off + i] = key_unord(L[mslot(i)], u64);
+            if (i < n) {
+                keys[off + i] = key_unord(L[mslot(i)], u64);
+                if (PAY) pay[off + i] = Lp[mslot(i)];
+            }
         }
         __syncthreads();  // the next item rewrites L
+    }
+}
+
+// With a payload: items and chunks of SMALL_MAX+1 .. PAIR_CHUNK keys, one
+// wavefront each, sorted stably in registers as (ordered key, index) pairs
+// (pair_bitonic: 16 pairs per lane, 8 for a chunk of at most 512 keys); the
+// payload follows through the sorted indices, read before any write.
+template <int LE>
+__device__ __forceinline__ void base_pair_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, int lane) {
+    constexpr int E = 1 << LE;
+    const uint64_t* in = P.keys[srcb];
+    uint64_t* out = P.keys[0];
+    const int u64 = P.u64;
+    uint64_t k[E];
+    uint32_t ix[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const uint32_t i = lane * E + e;
+        k[e] = i < size ? key_ord(in[off + i], u64) : ~0ull;
+        ix[e] = i;
+    }
+    pair_bitonic<LE, 6>(k, ix, lane);
+    const uint32_t* pin = P.pay[srcb];
+    uint32_t* pout = P.pay[0];
+    uint32_t pv[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) pv[e] = (lane * E + e < (int)size) ? pin[off + ix[e]] : 0u;
+#pragma unroll
+    for (int e = 0; e < E; e++)
+        if (lane * E + e < (int)size) {
+            pout[off + lane * E + e] = pv[e];
+            out[off + lane * E + e] = key_unord(k[e], u64);
+        }
+}
+
+__global__ __launch_bounds__(BASE_THREADS) void k_base_pairs(Params P) {
+    constexpr int W = BASE_THREADS / 64;
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * W, wid = (uint64_t)blockIdx.x * W + (threadIdx.x >> 6);
+    const uint64_t nc = min<unsigned long long>(P.ctl->nitems_c, P.item_c_cap);
+    for (uint64_t t = wid; t < nc; t += waves) {
+        const uint64_t wd = P.items_c[t];
+        const uint64_t off = wd >> 18;
+        const uint32_t srcb = (wd >> 17) & 1u;
+        const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
+        static_assert(SMALL_MAX == 8 * WAVE && PAIR_CHUNK == 16 * WAVE, "8 and 16 pairs per lane");
+        if (size <= SMALL_MAX) base_pair_item<3>(P, off, size, srcb, lane);
+        else base_pair_item<4>(P, off, size, srcb, lane);
     }
 }
 
@@ -444,7 +522,10 @@ __global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
     } while (0)
 
 hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st) {
-    if (P.has_pay) LAUNCH((k_base_small<true, false>), grid, BASE_THREADS, st, P);
+    if (P.has_pay) {
+        hipLaunchKernelGGL((k_base_small<true, false>), dim3(grid), dim3(BASE_THREADS), 0, st, P);
+        LAUNCH(k_base_pairs, grid, BASE_THREADS, st, P);  // items and chunks of 513..1024 keys
+    }
     if (P.u64) LAUNCH((k_base_small<false, true>), grid, BASE_THREADS, st, P);
     LAUNCH((k_base_small<false, false>), grid, BASE_THREADS, st, P);
 }
@@ -455,7 +536,8 @@ hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) {
     LAUNCH(k_base_big<BIG_MAX>, grid / 2 ? grid / 2 : 1, BIG_THREADS, st, P);
 }
 hipError_t launch_base_merge(const Params& P, uint32_t grid, hipStream_t st) {
-    LAUNCH(k_base_merge, grid, MG_THREADS, st, P);
+    if (P.has_pay) LAUNCH(k_base_merge<true>, grid / 2 ? grid / 2 : 1, MG_THREADS, st, P);  // one per CU
+    LAUNCH(k_base_merge<false>, grid, MG_THREADS, st, P);
 }
 
 }  // namespace ls

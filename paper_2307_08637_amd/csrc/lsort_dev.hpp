@@ -654,6 +654,103 @@ __device__ __forceinline__ void group_bitonic(T (&k)[1 << LE], int lane) {
     group_phases<T, LE, LG, 1>(k, lane);
 }
 
+// The same network over (key, index) pairs, ordered by key, then index
+// (indices are distinct: a total order, so the result is the stable order):
+// 2^LE pairs per lane, element i = lane * 2^LE + register, 2^LG lanes.
+template <int OP>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v, uint32_t lane) {
+    auto m = [](uint32_t x, auto ctrl) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, decltype(ctrl)::value, 0xF, 0xF, false);
+    };
+    using C0 = std::integral_constant<int, 0xB1>;
+    using C1 = std::integral_constant<int, 0x4E>;
+    using C3 = std::integral_constant<int, 0x1B>;
+    using C7 = std::integral_constant<int, 0x141>;
+    using C8 = std::integral_constant<int, 0x128>;
+    using C15 = std::integral_constant<int, 0x140>;
+    if constexpr (OP == 0 || OP == 8) return m(v, C0{});
+    else if constexpr (OP == 1) return m(v, C1{});
+    else if constexpr (OP == 2) return m(m(v, C7{}), C3{});
+    else if constexpr (OP == 3) return m(v, C8{});
+    else if constexpr (OP == 4) return xor_lane32(v, 16, lane);
+    else if constexpr (OP == 5) return xor_lane32(v, 32, lane);
+    else if constexpr (OP == 9) return m(v, C3{});
+    else if constexpr (OP == 10) return m(v, C7{});
+    else if constexpr (OP == 11) return m(v, C15{});
+    else if constexpr (OP == 12) return xor_lane32(m(v, C15{}), 16, lane);
+    else return xor_lane32(xor_lane32(m(v, C15{}), 16, lane), 32, lane);
+}
+
+__device__ __forceinline__ bool pair_lt(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+template <int LE, int B, bool FLIP>
+__device__ __forceinline__ void pair_stage(uint64_t (&k)[1 << LE], uint32_t (&x)[1 << LE], int lane) {
+    constexpr int E = 1 << LE;
+    if constexpr (B < LE) {  // inside the lane
+#pragma unroll
+        for (int q = 0; q < E / 2; q++) {
+            const int r = ins0(q, B), s = FLIP ? r ^ ((2 << B) - 1) : r | (1 << B);
+            const bool lt = pair_lt(k[r], x[r], k[s], x[s]);
+            const uint64_t k0 = lt ? k[r] : k[s], k1 = lt ? k[s] : k[r];
+            const uint32_t x0 = lt ? x[r] : x[s], x1 = lt ? x[s] : x[r];
+            k[r] = k0; k[s] = k1; x[r] = x0; x[s] = x1;
+            cx_window(q);
+        }
+    } else {
+        constexpr int S = B - LE;
+        const bool km = (lane >> S) & 1;
+        // the lane holding the higher element keeps the larger pair
+        auto take = [&](int r, uint64_t ky, uint32_t iy) {
+            const bool t = pair_lt(ky, iy, k[r], x[r]) != km;
+            k[r] = t ? ky : k[r];
+            x[r] = t ? iy : x[r];
+        };
+        if constexpr (FLIP) {  // partner lane ^ (2^(S+1) - 1), register E-1-r
+#pragma unroll
+            for (int r = 0; r < E / 2; r++) {
+                const uint64_t y0 = dpp_t<8 + S>(k[E - 1 - r], (uint32_t)lane), y1 = dpp_t<8 + S>(k[r], (uint32_t)lane);
+                const uint32_t j0 = dpp32<8 + S>(x[E - 1 - r], (uint32_t)lane), j1 = dpp32<8 + S>(x[r], (uint32_t)lane);
+                take(r, y0, j0);
+                take(E - 1 - r, y1, j1);
+                cx_window(r);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < E; r++) {
+                const uint64_t y = dpp_t<S>(k[r], (uint32_t)lane);
+                const uint32_t j = dpp32<S>(x[r], (uint32_t)lane);
+                take(r, y, j);
+                cx_window(r);
+            }
+        }
+    }
+}
+
+template <int LE, int C>
+__device__ __forceinline__ void pair_clean(uint64_t (&k)[1 << LE], uint32_t (&x)[1 << LE], int lane) {
+    if constexpr (C >= 0) {
+        pair_stage<LE, C, false>(k, x, lane);
+        pair_clean<LE, C - 1>(k, x, lane);
+    }
+}
+
+template <int LE, int LG, int PH>
+__device__ __forceinline__ void pair_phases(uint64_t (&k)[1 << LE], uint32_t (&x)[1 << LE], int lane) {
+    if constexpr (PH <= LE + LG) {
+        pair_stage<LE, PH - 1, true>(k, x, lane);
+        pair_clean<LE, PH - 2>(k, x, lane);
+        pair_phases<LE, LG, PH + 1>(k, x, lane);
+    }
+}
+
+template <int LE, int LG>
+__device__ __forceinline__ void pair_bitonic(uint64_t (&k)[1 << LE], uint32_t (&x)[1 << LE], int lane) {
+    static_assert(LG <= 6, "lane groups within one wavefront");
+    pair_phases<LE, LG, 1>(k, x, lane);
+}
+
 // Bitonic sort of 64*E (key, index) pairs held by one wavefront, lane l
 // holding elements l*E .. l*E+E-1 in registers.  Compare-exchanges between
 // elements of one lane stay in registers; those between lanes exchange

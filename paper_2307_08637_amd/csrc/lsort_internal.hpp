@@ -117,11 +117,17 @@ struct Tile {          // one work unit of UNIT keys
 
 // Base-case / copy work item packed in 64 bits:
 // [63:18] offset, [17] source buffer (0 caller, 1 temp), [16] copy-only, [15:0] size - 1.
-// Keys-only base-case items of GROUP_WAVE_MAX+1 .. BIG_MAX keys: the number
-// of chunks of GROUP_WAVE_MAX keys (the last one shorter) that are sorted as
-// items of their own and then merged; 0 for any other size.
-__host__ __device__ inline uint64_t split_chunks(uint64_t c) {
-    return c > (uint64_t)GROUP_WAVE_MAX && c <= (uint64_t)BIG_MAX ? (c + GROUP_WAVE_MAX - 1) / GROUP_WAVE_MAX : 0;
+// Base-case items sorted as chunks of their own, then merged: keys only,
+// items of GROUP_WAVE_MAX+1 .. BIG_MAX keys in chunks of GROUP_WAVE_MAX keys
+// (the register group sort); with a payload, items of SMALL_MAX+1 .. BIG_MAX
+// keys in chunks of PAIR_CHUNK keys (the wavefront pair sort; an item of one
+// chunk needs no merge).  The number of chunks (the last one shorter), 0 for
+// any other size.
+constexpr int PAIR_CHUNK = 1024;
+__host__ __device__ inline uint32_t chunk_keys(bool pay) { return pay ? (uint32_t)PAIR_CHUNK : (uint32_t)GROUP_WAVE_MAX; }
+__host__ __device__ inline uint64_t split_chunks(uint64_t c, bool pay) {
+    const uint64_t lo = pay ? (uint64_t)SMALL_MAX : (uint64_t)GROUP_WAVE_MAX, ch = chunk_keys(pay);
+    return c > lo && c <= (uint64_t)BIG_MAX ? (c + ch - 1) / ch : 0;
 }
 
 __host__ __device__ inline uint64_t item_pack(uint64_t off, uint32_t src, uint32_t copy, uint32_t size) {
@@ -156,8 +162,7 @@ struct Ctl {
     LS_HOT unsigned long long nbig;         // large base-case items and copy items
     LS_HOT unsigned long long nmoved;       // small items handed on to the large list (NaN / -0.0 tasks)
     LS_HOT unsigned long long nitems_m;     // items of the model-based counting sort (two words each)
-    LS_HOT unsigned long long nmerge;       // keys only: items of GROUP_WAVE_MAX+1 .. BIG_MAX keys, sorted as
-                                            // chunks of GROUP_WAVE_MAX keys, then merged (k_base_merge)
+    LS_HOT unsigned long long nmerge;       // items sorted as chunks, then merged (k_base_merge; split_chunks)
     LS_HOT unsigned long long merge_keys;   // keys in those items
     LS_HOT unsigned long long nchunk;       // their chunks (in nitems_c)
     LS_HOT unsigned long long model_keys;   // keys in those items
@@ -201,10 +206,12 @@ struct Params {
     unsigned long long* status;
     uint8_t* arena[2];
     uint16_t* ids;                  // per-key bucket ids of MLP levels (absolute positions)
-    uint64_t* items_c;              // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys
+    uint64_t* items_c;              // keys only: items of GROUP_LARGE_MAX+1 .. GROUP_WAVE_MAX keys and the
+                                    // chunks of larger ones; with a payload: items and chunks of
+                                    // SMALL_MAX+1 .. PAIR_CHUNK keys (k_base_pairs)
     uint64_t* items_m;              // model-based counting-sort items: (item word, g0 | log2(w) << 32)
     uint64_t item_m_cap;
-    uint64_t* merges;               // keys only: items whose chunks are merged (k_base_merge)
+    uint64_t* merges;               // items whose chunks are merged (k_base_merge)
     uint64_t merge_cap;
     const uint64_t* fmodel;         // the first level's prebuilt model (large single array), or null
     uint64_t seg_cap, tile_cap, item_cap, big_cap, counts_cap, status_cap, arena_cap, item_b_cap, item_c_cap;

@@ -740,7 +740,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             ld += mb ? 1 : 0;
             lmk += mb ? c[i] : 0;
             const uint64_t nsm = d.act == 2 && !mb && (c[i] <= SMALL_MAX || (c[i] <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
-            const uint64_t nsp = d.act == 2 && !mb && !nsm && !P.has_pay ? split_chunks(c[i]) : 0;
+            const uint64_t nsp = d.act == 2 && !mb && !nsm ? split_chunks(c[i], P.has_pay) : 0;
             const uint64_t ng0 = nsm && c[i] <= GROUP_SMALL_MAX ? 1 : 0;
             const uint64_t ng1 = nsm && !ng0 && c[i] <= GROUP_MAX ? 1 : 0;
             const uint64_t ng3 = nsm && c[i] > SMALL_MAX && c[i] <= GROUP_LARGE_MAX ? 1 : 0;
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             la += ng0 | ((uint64_t)(d.act >= 3) << 16) | (nbg << 32);
             lb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
             lc += ng3 | ((ng4 + nsp) << 32);
-            lm += nsp ? 1 | (nsp << 16) | (c[i] << 32) : 0;
+            lm += nsp > 1 ? 1 | (nsp << 16) | (c[i] << 32) : 0;  // merged items (one chunk: none)
             lfb += d.act == 5 ? 1 : 0;
             lsk += nsm || nsp ? c[i] : 0;
             lgk += nbg ? c[i] : 0;
@@ -828,7 +828,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             const uint64_t ci = c[i];
             const bool mb = mbase && a == 2 && ci >= MB_MIN && ci <= MB_MAX;
             const uint64_t nsm = a == 2 && !mb && (ci <= SMALL_MAX || (ci <= GROUP_WAVE_MAX && !P.has_pay)) ? 1 : 0;
-            const uint64_t nsp = a == 2 && !mb && !nsm && !P.has_pay ? split_chunks(ci) : 0;
+            const uint64_t nsp = a == 2 && !mb && !nsm ? split_chunks(ci, P.has_pay) : 0;
             const uint64_t nbg = a == 1 ? (ci + COPY_CHUNK - 1) / COPY_CHUNK : (a == 2 && !nsm && !mb && !nsp ? 1 : 0);
             if (mb) {
                 const uint64_t it = resv[8] + xd;
@@ -861,17 +861,20 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
                 else atomicOr(&P.ctl->overflow, OVF_ITEM);
             }
             if (nsp) {
-                // chunks of GROUP_WAVE_MAX keys (the last one shorter) sorted as
-                // items of their own, then one merge of the whole bucket
+                // chunks (the last one shorter) sorted as items of their own,
+                // then, for more than one, a merge of the whole bucket
+                const uint64_t ch = chunk_keys(P.has_pay);
                 for (uint64_t k = 0; k < nsp; k++) {
                     const uint64_t it = resv[7] + (xc >> 32) + k;
                     if (it >= P.item_c_cap) { atomicOr(&P.ctl->overflow, OVF_ITEM); break; }
-                    const uint64_t sz = min<uint64_t>(GROUP_WAVE_MAX, ci - k * GROUP_WAVE_MAX);
-                    P.items_c[it] = item_pack(start[i] + k * GROUP_WAVE_MAX, q, 0u, (uint32_t)sz);
+                    const uint64_t sz = min<uint64_t>(ch, ci - k * ch);
+                    P.items_c[it] = item_pack(start[i] + k * ch, q, 0u, (uint32_t)sz);
                 }
-                const uint64_t it = resv[9] + (xm & 0xffff);
-                if (it < P.merge_cap) P.merges[it] = item_pack(start[i], 0u, 0u, (uint32_t)ci);
-                else atomicOr(&P.ctl->overflow, OVF_ITEM);
+                if (nsp > 1) {
+                    const uint64_t it = resv[9] + (xm & 0xffff);
+                    if (it < P.merge_cap) P.merges[it] = item_pack(start[i], 0u, 0u, (uint32_t)ci);
+                    else atomicOr(&P.ctl->overflow, OVF_ITEM);
+                }
             }
             for (uint64_t k = 0; k < nbg; k++) {
                 const uint64_t it = resv[3] + gex + k;
@@ -911,7 +914,7 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             xa += ng0 | ((uint64_t)(a >= 3) << 16) | (nbg << 32);
             xb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
             xc += ng3 | ((ng4 + nsp) << 32);
-            xm += nsp ? 1 | (nsp << 16) | (ci << 32) : 0;
+            xm += nsp > 1 ? 1 | (nsp << 16) | (ci << 32) : 0;
         }
         {  // resident children, one atomic per wavefront that has any
             const uint32_t wt = wave_incl_sum(nresc);
