@@ -35,7 +35,9 @@ __device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, u
         ix[e] = i;
     }
     if (PAY) {
-        wave_bitonic<E, true>(k, ix, lane);
+        constexpr int LE = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : 3;
+        static_assert((1 << LE) == E, "1, 2, 4 or 8 pairs per lane");
+        pair_bitonic<LE, 6>(k, ix, lane);
         const uint32_t* pin = P.pay[srcb];
         uint32_t* pout = P.pay[0];
         uint32_t pv[E];

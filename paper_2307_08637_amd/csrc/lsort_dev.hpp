@@ -707,7 +707,9 @@ __device__ __forceinline__ void pair_stage(uint64_t (&k)[1 << LE], uint32_t (&x)
             k[r] = t ? ky : k[r];
             x[r] = t ? iy : x[r];
         };
-        if constexpr (FLIP) {  // partner lane ^ (2^(S+1) - 1), register E-1-r
+        if constexpr (FLIP && E == 1) {  // one register: the mirror lane's
+            take(0, dpp_t<8 + S>(k[0], (uint32_t)lane), dpp32<8 + S>(x[0], (uint32_t)lane));
+        } else if constexpr (FLIP) {  // partner lane ^ (2^(S+1) - 1), register E-1-r
 #pragma unroll
             for (int r = 0; r < E / 2; r++) {
                 const uint64_t y0 = dpp_t<8 + S>(k[E - 1 - r], (uint32_t)lane), y1 = dpp_t<8 + S>(k[r], (uint32_t)lane);

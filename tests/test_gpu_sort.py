@@ -130,6 +130,29 @@ def test_group_items_every_size(dev):
     assert_same_bits(to_host(t), oracle.sort_segmented(keys, off)[0])
 
 
+def test_pair_items_every_size(dev):
+    """Segments of every size 1..600 with a uint32 payload, sorted directly by
+    the base case: the wavefront pair network with 1, 2, 4 and 8 (key, index)
+    pairs per lane up to 512 keys (every boundary 64/65 .. 512/513), the
+    workgroup sort above; stable on a duplicate-heavy law too."""
+    sizes = np.tile(np.arange(1, 601, dtype=np.int64), 2)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    for law in ("normal", "rootdups"):
+        keys = inputs.generate(law, n, seed=12)
+        pay = np.arange(n, dtype=np.uint32)
+        t = to_dev(keys, dev)
+        p = torch.from_numpy(pay.view(np.int32).copy()).to(dev).view(torch.uint32)
+        o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+        print(f"[case] pair items {law} n={n}", flush=True)
+        lsort.sort_segmented(t, o, p, cutoff=600)
+        torch.cuda.synchronize()
+        want, wp = oracle.sort_segmented(keys, off, pay)
+        assert_same_bits(to_host(t), want)
+        assert np.array_equal(p.view(torch.int32).cpu().numpy().view(np.uint32), wp)
+
+
 @pytest.mark.parametrize("kind,n,buckets", [("uniform", 200_000, 40), ("normal", 300_000, 64), ("u64", 250_000, 40),
                                              ("lognormal", 400_000, 100), ("sparse_specials", 200_000, 40),
                                              ("subnormal_mix", 150_000, 32), ("few_distinct", 200_000, 40)])
