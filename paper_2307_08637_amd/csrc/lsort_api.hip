@@ -631,6 +631,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     const uint32_t max_run = c.one_level ? 1 : std::min<uint32_t>(MAXL - 1, c.o.max_levels + 9);
     uint32_t levels = 0;
     uint32_t next_res = 0;  // resident segments of the next level (read back)
+    uint64_t nmerge = ~0ull;  // chunk-and-merge items (read back after the last level; unknown: fixed levels)
     for (uint32_t lvl = 0; lvl < max_run; lvl++) {
         P.level = (int)lvl;
         const size_t rec0 = g_trec.size();
@@ -662,6 +663,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         uint32_t ovf = hc->overflow;
         double lkeys = (double)hc->lv[lvl].keys;
         next_res = hc->nres[lvl + 1];
+        nmerge = hc->nmerge;
         for (size_t i = rec0; i < g_trec.size(); i++) g_trec[i].keys = lkeys;
         if (ovf) return fail(LS_ENOMEM, "workspace capacity exceeded:" + overflow_text(ovf));
         if (next == 0) break;
@@ -673,8 +675,9 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         const bool mbase = (c.o.flags & LS_FLAG_MODEL_BASE) && P.fmodel;
         if (mbase) TIMED(KI_BASE_MODEL, c.st, launch_base_model(P, cus * 2, c.st));
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
-        // the items sorted above as chunks, merged
-        TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus * 2, c.st));
+        // the items sorted above as chunks, merged (none: no launch)
+        const bool merge = nmerge != 0;
+        if (merge) TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus * 2, c.st));
         if (g_timing && !t_untimed && g_trec.size() > r0) {  // keys through each base-case kernel
             HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));
@@ -683,7 +686,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
             g_trec[r++].keys = (double)hc->small_keys;
             if (mbase) g_trec[r++].keys = (double)hc->model_keys;
             g_trec[r++].keys = (double)hc->big_keys;
-            g_trec[r++].keys = (double)hc->merge_keys;
+            if (merge) g_trec[r++].keys = (double)hc->merge_keys;
         }
     }
     return LS_OK;
