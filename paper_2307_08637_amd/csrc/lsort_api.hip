@@ -237,7 +237,9 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     L.n = n; L.m = m; L.has_pay = has_pay;
     const uint64_t C = o.cutoff;
     L.seg_cap = std::max<uint64_t>(m, n / (C + 1)) + 16;
-    L.tile_cap = n / UNIT + L.seg_cap + 16;
+    // (a single array of at most SMALL_UNIT_N keys: units of one tile)
+    const uint64_t small_units = m == 1 && n <= SMALL_UNIT_N ? n / TILE + 1 : 0;
+    L.tile_cap = n / UNIT + small_units + L.seg_cap + 16;
     L.item_cap = n + m + 64;        // small items hold >= 1 key
     L.big_cap = n / 2 + m + 64;     // large items > 512 keys, copy runs >= 2 keys
     L.item_b_cap = n / (GROUP_SMALL_MAX + 1) + m + 64;  // items of 129..256 keys and of 513..1024
@@ -250,7 +252,7 @@ static Layout plan(uint64_t n, uint64_t m, int has_pay, const Opts& o) {
     // least 2), except one first-level segment whose model the caller gives
     // (up to B_MAX).  Look-back words: tiles x buckets of each segment.
     L.counts_cap = 2 * (n / 4 + 2 * L.seg_cap + B_MAX) + 64;
-    L.status_cap = (n / UNIT) * B_MAX + n / 4 + 2 * L.seg_cap + 2 * B_MAX + 64;
+    L.status_cap = (n / UNIT + small_units) * B_MAX + n / 4 + 2 * L.seg_cap + 2 * B_MAX + 64;
     L.arena_cap = (n / 100000 + m + 2) * (8ull * MODEL_WORDS + 16) + (uint64_t)(0.7 * (double)n) + L.seg_cap * 32 + 65536;
     uint64_t o_ = 0;
     auto take = [&](uint64_t bytes) { uint64_t r = o_; o_ += align256(bytes); return r; };

@@ -107,8 +107,15 @@ constexpr uint64_t RES_MAX = 8192;     // largest segment a single workgroup tak
 // for every segment below the first level).  k_scatter carries a bucket's
 // last partial 64-byte segment from tile to tile within a unit, so larger
 // units leave fewer partial segments in the output.
-constexpr uint32_t SEG_USHIFT_POS = 8, USHIFT_MAX = 4;
-__host__ __device__ inline uint32_t seg_unit(uint32_t flags) { return (uint32_t)UNIT << ((flags >> SEG_USHIFT_POS) & 7u); }
+// Value 7 marks one-tile units (TILE keys): a single array of at most
+// SMALL_UNIT_N keys, whose few units of UNIT keys would leave most CUs idle
+// (the nested sort of a large array's sample is one).
+constexpr uint32_t SEG_USHIFT_POS = 8, USHIFT_MAX = 4, USHIFT_TILE = 7;
+constexpr uint64_t SMALL_UNIT_N = 1ull << 20;
+__host__ __device__ inline uint32_t seg_unit(uint32_t flags) {
+    const uint32_t s = (flags >> SEG_USHIFT_POS) & 7u;
+    return s == USHIFT_TILE ? (uint32_t)TILE : (uint32_t)UNIT << s;
+}
 
 struct Tile {          // one work unit of UNIT keys
     uint32_t seg;     // index in the level's segment list

@@ -61,7 +61,10 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
         const bool seg = s < m && (prebuilt ? n >= 1 : n > P.cutoff);
         // an array small enough for one workgroup is sorted whole by k_resident
         const bool resident = seg && !prebuilt && n <= RES_MAX;
-        const uint64_t unit0 = (uint64_t)UNIT << P.unit0_shift;
+        // a single array of at most SMALL_UNIT_N keys at the default unit:
+        // one-tile units, so that its first level spreads over the CUs
+        const uint32_t us = m == 1 && !prebuilt && n <= SMALL_UNIT_N && P.unit0_shift == 0 ? USHIFT_TILE : P.unit0_shift;
+        const uint64_t unit0 = us == USHIFT_TILE ? (uint64_t)TILE : (uint64_t)UNIT << us;
         const uint32_t nt = seg && !resident ? (uint32_t)((n + unit0 - 1) / unit0) : 0;
         {
             const uint32_t nr = (uint32_t)__popcll(__ballot(resident));
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(256) void k_seed(Params P, const uint64_t* offsets,
             } else {
                 Seg sg{};
                 sg.off = lo; sg.n = n; sg.kind = K_FRESH; sg.tile0 = (uint32_t)t0; sg.ntiles = nt;
-                sg.flags = (prebuilt ? SEG_PREBUILT : (resident ? SEG_RESIDENT : 0)) | (P.unit0_shift << SEG_USHIFT_POS);
+                sg.flags = (prebuilt ? SEG_PREBUILT : (resident ? SEG_RESIDENT : 0)) | (us << SEG_USHIFT_POS);
                 if (t0 + nt > P.tile_cap) { atomicOr(&P.ctl->overflow, OVF_TILE); sg.flags |= SEG_FAILED; }
                 if (prebuilt) {  // the first level's model and kind were written into segs[1][0]
                     Seg pb = P.segs[1][0];
