@@ -156,3 +156,48 @@ def test_c4_full_batched_properties(dev):
         assert_same_bits(host_k[a:b], want)
         assert np.array_equal(host_p[a:b], wp)
     del t, p, o, seg
+
+
+def _chunked_hash(t: torch.Tensor, salt: int, chunk: int = 1 << 28) -> int:
+    h = 0
+    for a in range(0, t.numel(), chunk):
+        h = (h + multiset_hash(t[a:a + chunk], salt=salt)) % (1 << 64)
+    return h
+
+
+def _chunked_sorted(t: torch.Tensor, chunk: int = 1 << 28) -> bool:
+    n = t.numel()
+    for a in range(0, n - 1, chunk):
+        if not is_sorted(t[a:min(n, a + chunk + 1)]):  # each chunk with the first key of the next
+            return False
+    return True
+
+
+def test_beyond_2_32_keys(dev):
+    """4.4e9 float64 keys (more than 2^32; 35 GB, normal law, drawn on the
+    device from a seeded generator) sorted in place with a caller workspace:
+    every count, offset and unit index of the path is 64-bit.  Checked by
+    properties that pin the result at any size: sorted, and the same multiset
+    (two independent 64-bit hashes)."""
+    n = 4_400_000_000
+    g = torch.Generator(device=dev)
+    g.manual_seed(91)
+    t = torch.randn(n, dtype=torch.float64, device=dev, generator=g)
+    h1, h2 = _chunked_hash(t, 0), _chunked_hash(t, 0x5A5A5A5A5A5A5A5)
+    ws = torch.empty(lsort.workspace_bytes(n), dtype=torch.uint8, device=dev)
+    print(f"[case] n={n} workspace {ws.numel() / 1e9:.1f} GB", flush=True)
+    try:
+        lsort.set_workspace(ws)
+        lsort.sort(t)
+        torch.cuda.synchronize()
+        st = lsort.stats()
+    finally:
+        lsort.set_workspace(None)
+        torch.cuda.synchronize()
+    del ws
+    assert st["overflow"] == 0
+    assert st["levels"][0]["keys"] == n
+    assert _chunked_sorted(t)
+    assert _chunked_hash(t, 0) == h1 and _chunked_hash(t, 0x5A5A5A5A5A5A5A5) == h2
+    del t
+    torch.cuda.empty_cache()
