@@ -95,11 +95,12 @@ __device__ __forceinline__ uint64_t gload(const uint64_t* p) {
 __device__ __forceinline__ void gstore(uint64_t* p, uint64_t v) { *(__attribute__((address_space(1))) uint64_t*)p = v; }
 
 // One task: 64 / G items, entries [task * GPW, ...) of a list (read from the
-// back when REV).  U64: ordered-integer network.  binary64: the numeric
-// network, unless the task holds a NaN or a -0.0; then (rarely) its items are
-// handed to k_base_big, which runs after this kernel and orders by the
-// totalOrder image (a one-key item is only moved).  Keeping the integer
-// network out of this kernel keeps its register count down.
+// back when REV).  binary64: the numeric network, unless the task holds a NaN
+// or a -0.0.  U64: the same network over the differences key - min of each
+// item, unless an item spans the +inf bit pattern or more.  Such tasks
+// (rarely) hand their items to k_base_mid, which runs after this kernel and
+// orders by the totalOrder image (a one-key item is only moved).  Keeping
+// the integer network out of this kernel keeps its register count down.
 // The descriptor of this lane's item in a task.  Every load is in bounds
 // without a branch: an idle group (past the last item) reads the last item
 // and gets size 0 from base_group_task.
@@ -134,8 +135,34 @@ __device__ __forceinline__ void base_group_task(const Params& P, const uint64_t*
         __builtin_amdgcn_sched_barrier(0);
     }
     const int gp = opaque(lane) & (G - 1);  // fresh copy: the offsets below are formed again, not kept
-    bool special = U64;
-    if (!U64) {
+    bool special = false;
+    uint64_t lo = 0;
+    if (U64) {
+        // uint64 keys: an item whose keys span less than the +inf bit pattern
+        // (max - min < 0x7ff0...) sorts as the binary64 values of the
+        // differences key - min: non-negative and finite (subnormal or zero
+        // included), their numeric order is the integers' order, so the
+        // floating-point network sorts them; min is added back afterwards.
+        // A wider item is handed on like a NaN item below.
+        uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+        for (int r = 0; r < GE; r++) {
+            const bool in = (uint32_t)(r * G + gp) < size;
+            mn = in && raw[r] < mn ? raw[r] : mn;
+            mx = in && raw[r] > mx ? raw[r] : mx;
+        }
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {  // over the item's lanes (the low LG lane bits)
+            const uint64_t a = __shfl_xor(mn, o), b = __shfl_xor(mx, o);
+            mn = a < mn ? a : mn;
+            mx = b > mx ? b : mx;
+        }
+        lo = size ? mn : 0;
+        special = size && mx - mn >= 0x7ff0000000000000ull;
+#pragma unroll
+        for (int r = 0; r < GE; r++)
+            raw[r] = (uint32_t)(r * G + gp) < size ? raw[r] - lo : 0x7ff0000000000000ull;  // +inf pads
+    } else {
 #pragma unroll
         for (int r = 0; r < GE; r++) {
             if ((uint32_t)(r * G + gp) >= size) raw[r] = 0x7ff0000000000000ull;  // +inf pads
@@ -144,7 +171,7 @@ __device__ __forceinline__ void base_group_task(const Params& P, const uint64_t*
             special |= (raw[r] & 0x7fffffffffffffffull) > 0x7ff0000000000000ull || raw[r] == 0x8000000000000000ull;
         }
     }
-    if (!U64 && __ballot(special) != 0) {
+    if (__ballot(special) != 0) {
         if (gp == 0 && size == 1) {
             if (src != dst) gstore(dst, gload(src));
         } else if (gp == 0 && size > 1) {
@@ -155,18 +182,13 @@ __device__ __forceinline__ void base_group_task(const Params& P, const uint64_t*
         }
         return;
     }
-    if (U64) {
-#pragma unroll
-        for (int r = 0; r < GE; r++)
-            if ((uint32_t)(r * G + gp) >= size) raw[r] = ~0ull;
-        group_bitonic<uint64_t, GLE, LG>(raw, lane);
-    } else {
+    {
         double k[GE];
 #pragma unroll
         for (int r = 0; r < GE; r++) k[r] = __builtin_bit_cast(double, raw[r]);
         group_bitonic<double, GLE, LG>(k, lane);
 #pragma unroll
-        for (int r = 0; r < GE; r++) raw[r] = __builtin_bit_cast(uint64_t, k[r]);
+        for (int r = 0; r < GE; r++) raw[r] = __builtin_bit_cast(uint64_t, k[r]) + (U64 ? lo : 0ull);
     }
     // Element i of the sub-array is lane i / E, register i % E.  Phase h moves
     // registers 16h .. 16h+15 of every lane: lane c's run lands at LDS slots

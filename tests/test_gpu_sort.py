@@ -130,6 +130,33 @@ def test_group_items_every_size(dev):
     assert_same_bits(to_host(t), oracle.sort_segmented(keys, off)[0])
 
 
+def test_u64_items_as_differences(dev):
+    """uint64 base-case items whose keys span less than the +inf bit pattern
+    sort as binary64 differences key - min (the floating-point network):
+    segments of every size 1..2100 with narrow ranges (differences up to
+    2^52, subnormal as binary64), mixed with wide segments (handed to the
+    workgroup sort), and the boundary spans 0x7fef.. (narrow) and 0x7ff0..
+    (wide), against the oracle."""
+    rng = np.random.default_rng(14)
+    sizes = np.tile(np.arange(1, 2101, dtype=np.int64), 2)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    base = rng.integers(0, 2**63, sizes.size, dtype=np.uint64).repeat(sizes)
+    narrow = base + (rng.integers(0, 2**52, n, dtype=np.uint64) >> rng.integers(0, 52, n, dtype=np.uint64))
+    wide = rng.integers(0, 2**64 - 1, n, dtype=np.uint64, endpoint=True)
+    pick = (np.arange(sizes.size) % 3 == 0).repeat(sizes)  # every third segment wide
+    edge = np.array([5, 5 + 0x7FEFFFFFFFFFFFFF, 7, 3, 3 + 0x7FF0000000000000, 9, 2**64 - 1, 0], dtype=np.uint64)
+    eoff = np.array([0, 3, 6, 8], dtype=np.uint64)
+    for keys, o_h in ((narrow, off), (np.where(pick, wide, narrow), off), (edge, eoff)):
+        t = to_dev(keys, dev)
+        o = torch.from_numpy(o_h.view(np.int64)).to(dev).view(torch.uint64)
+        print(f"[case] u64 items n={keys.size}", flush=True)
+        lsort.sort_segmented(t, o, cutoff=2100)
+        torch.cuda.synchronize()
+        assert_same_bits(to_host(t), oracle.sort_segmented(keys, o_h)[0])
+
+
 def test_pair_items_every_size(dev):
     """Segments of every size 1..600 with a uint32 payload, sorted directly by
     the base case: the wavefront pair network with 1, 2, 4 and 8 (key, index)
