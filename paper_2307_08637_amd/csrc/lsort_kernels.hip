@@ -402,6 +402,12 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             // sample (Sec. 2.2: ~1% random sample; Alg. 5 Sample) and sort it
             const uint64_t n = sg.n;
             uint32_t Bt = min(P.tree_buckets, max(2u, floor_pow2((uint32_t)min<uint64_t>(n / 16, 1u << 30))));
+            // children that would be base-case items of more than
+            // GROUP_LARGE_MAX keys: twice the fan-out (up to 512), so that they
+            // fall into the cheaper register classes
+            if (Bt == P.tree_buckets && Bt < 512 && n / Bt > (uint64_t)GROUP_LARGE_MAX && n / Bt <= (uint64_t)BIG_MAX &&
+                2ull * Bt <= n / 16)
+                Bt *= 2;
             uint64_t want = (uint64_t)ceil(P.sample_frac * (double)n);
             uint64_t floor_s = min<uint64_t>(n, 8ull * Bt);  // 8 sample keys per bucket at least
             uint32_t S = (uint32_t)min<uint64_t>(S_LDS, max<uint64_t>(want, max<uint64_t>(floor_s, 2)));
