@@ -634,8 +634,10 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     uint32_t levels = 0;
     uint32_t next_res = 0;  // resident segments of the next level (read back)
     uint64_t nmerge = ~0ull;  // chunk-and-merge items (read back after the last level; unknown: fixed levels)
+    uint32_t split = 0;       // the next level has fewer work units than CUs (read back)
     for (uint32_t lvl = 0; lvl < max_run; lvl++) {
         P.level = (int)lvl;
+        P.split = split;
         const size_t rec0 = g_trec.size();
         const uint32_t g0 = lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024;
         TIMED(KI_MODEL, c.st, launch_model(P, g0, c.st));
@@ -666,6 +668,10 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         double lkeys = (double)hc->lv[lvl].keys;
         next_res = hc->nres[lvl + 1];
         nmerge = hc->nmerge;
+        // a next level of few work units (a few small segments) is re-cut
+        // into one-tile units, when the unit list has room for them
+        const uint64_t nu = hc->ntile[lvl + 1];
+        split = nu > 0 && nu < cus && 4 * nu + hc->nseg[lvl + 1] <= P.tile_cap ? 1u : 0u;
         for (size_t i = rec0; i < g_trec.size(); i++) g_trec[i].keys = lkeys;
         if (ovf) return fail(LS_ENOMEM, "workspace capacity exceeded:" + overflow_text(ovf));
         if (next == 0) break;

@@ -161,6 +161,7 @@ struct Ctl {
     LS_HOT uint32_t rticket[MAXL + 1];      // k_resident segment tickets
     LS_HOT uint32_t hticket[MAXL + 1];      // k_hist unit tickets
     LS_HOT uint32_t nres[MAXL + 1];         // segments at each level that k_resident sorts whole
+    LS_HOT uint32_t nsplit[MAXL + 1];       // work units of a level re-cut into one-tile units (Params::split)
     LS_HOT unsigned long long nitems;       // small base-case items of <= GROUP_SMALL_MAX keys (front of items)
     LS_HOT unsigned long long nitems_w;     // small base-case items of GROUP_MAX+1 .. SMALL_MAX keys (back of items)
     LS_HOT unsigned long long nitems_b;     // small base-case items of GROUP_SMALL_MAX+1 .. GROUP_MAX keys (items_b)
@@ -198,6 +199,8 @@ struct Params {
     // options
     uint32_t buckets, leaves, tree_buckets, cutoff, max_levels, flags, model;
     uint32_t unit0_shift;           // first-level segments: work units of UNIT << unit0_shift keys
+    uint32_t split;                 // this level has fewer units than CUs: k_model re-cuts every segment
+                                    // into one-tile units, counted in ctl->nsplit
     double sample_frac, fallback_ratio;
     uint64_t seed;
     // workspace
@@ -228,6 +231,11 @@ struct Params {
     uint64_t fS;                    // its size
     int level;
 };
+
+// Work units of the level the kernels run on (k_model re-cut them when split).
+__device__ __forceinline__ uint32_t level_units(const Params& P, int lvl) {
+    return min(P.split ? P.ctl->nsplit[lvl] : P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
+}
 
 // Status word of the decoupled look-back:
 // [63:38] tag = call epoch * MAXL + level (never 0), [37:36] flag

@@ -467,6 +467,22 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             }
         }
         __syncthreads();
+        // a level with fewer work units than CUs: this segment's units are
+        // cut again into one-tile units (from a fresh count), so that the
+        // level's histogram and scatter spread over the CUs
+        if (P.split && sg.ntiles && !(sg.flags & (SEG_FAILED | SEG_RESIDENT))) {
+            const uint32_t nt2 = (uint32_t)((sg.n + TILE - 1) / TILE);
+            if (tid == 0) shv[3] = atomicAdd(&P.ctl->nsplit[lvl], nt2);
+            __syncthreads();
+            sg.tile0 = (uint32_t)shv[3];
+            sg.ntiles = nt2;
+            sg.flags = (sg.flags & ~(7u << SEG_USHIFT_POS)) | (USHIFT_TILE << SEG_USHIFT_POS);
+            if ((uint64_t)sg.tile0 + nt2 > P.tile_cap) {
+                if (tid == 0) atomicOr(&P.ctl->overflow, OVF_TILE);
+                sg.flags |= SEG_FAILED;
+            }
+            __syncthreads();  // shv is rewritten below
+        }
         // bucket counts and look-back words
         if (tid == 0) {
             uint32_t fl = (sg.flags & 0xffffu) | (words << 16);
@@ -483,6 +499,7 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
             shv[0] = cb; shv[1] = sb; shv[2] = fl;
             Seg& o = P.segs[lvl & 1][s];
             o.kind = kind; o.nb = nb; o.model = model; o.cbase = cb; o.sbase = sb; o.flags = fl;
+            o.tile0 = sg.tile0; o.ntiles = sg.ntiles;
             LevelStats& st = P.ctl->lv[lvl];
             if (P.flags & FLAG_STATS) {
                 if (kind == K_RMI || kind == K_RMI_FINE || kind == K_MLP || kind == K_MLP_FINE) atomicAdd(&st.learned, 1ull);
@@ -521,7 +538,7 @@ __global__ __launch_bounds__(P_THREADS) void k_hist(Params P) {
     __shared__ uint32_t h[B_MAX];
     const int tid = threadIdx.x;
     const int lvl = P.level;
-    const uint32_t nunit = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
+    const uint32_t nunit = level_units(P, lvl);
     const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
     const uint64_t tag = ((uint64_t)(P.persist[0] * MAXL + lvl)) << ST_TAG_SHIFT;
     const uint64_t* src = P.keys[lvl & 1];
@@ -985,7 +1002,7 @@ __global__ __launch_bounds__(NT) void k_scatter(Params P) {
     __shared__ uint64_t red64[SW];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lvl = P.level;
-    const uint32_t nunit = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
+    const uint32_t nunit = level_units(P, lvl);
     const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
     const uint64_t tag = ((uint64_t)(P.persist[0] * MAXL + lvl)) << ST_TAG_SHIFT;
     const uint64_t* src = P.keys[lvl & 1];

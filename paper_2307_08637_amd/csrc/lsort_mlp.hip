@@ -816,7 +816,7 @@ __global__ __launch_bounds__(IDS_T) void k_mlp_ids(Params P) {
     __shared__ double leaves[4 * L_MAX];
     const int tid = threadIdx.x;
     const int lvl = P.level;
-    const uint32_t nunit = min(P.ctl->ntile[lvl], (uint32_t)P.tile_cap);
+    const uint32_t nunit = level_units(P, lvl);
     const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
     const uint64_t* src = P.keys[lvl & 1];
     uint64_t cur = 0;

@@ -130,6 +130,27 @@ def test_group_items_every_size(dev):
     assert_same_bits(to_host(t), oracle.sort_segmented(keys, off)[0])
 
 
+@pytest.mark.parametrize("pay", [False, True])
+def test_few_units_level_recut(dev, pay):
+    """A level with fewer work units than CUs (here the second level: three
+    first-level buckets of ~1e6 keys each, ~90 units) is re-cut by k_model
+    into one-tile units; bit-exact against the oracle, with a payload too."""
+    n = 3_000_000
+    z = inputs.generate("normal", n, seed=71)
+    c = (np.arange(n) % 3).astype(np.float64) * 1e3
+    keys = np.where(np.arange(n) % 33 == 0, z * 1e4, c + z * 1e-3)  # three tight clusters, 3 % spread wide
+    payload = np.arange(n, dtype=np.uint32) if pay else None
+    got, gp = gpu_sort(keys, dev, payload, buckets=64, stats=True)
+    st = lsort.stats()
+    want, wp = oracle.sort(keys, payload)
+    assert_same_bits(got, want)
+    if pay:
+        assert np.array_equal(gp, wp)
+    # the second level's work units (at most keys / 32768 + segments) are fewer than the CUs
+    lv1 = st["levels"][1]
+    assert lv1["keys"] // 32768 + lv1["segments"] < 256, st["levels"]
+
+
 def test_u64_items_as_differences(dev):
     """uint64 base-case items whose keys span less than the +inf bit pattern
     sort as binary64 differences key - min (the floating-point network):
