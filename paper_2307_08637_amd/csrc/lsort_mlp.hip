@@ -571,19 +571,20 @@ __device__ __forceinline__ bool rg_past(const float* w, int u, float tt) {
 }
 
 // First index in [lo, hi) at which unit u is past its switch (hi if none),
-// by 64-ary search of one wavefront; at(i) gives the input of index i.
+// by 32-ary search of one half-wavefront (lanes 0..31 or 32..63), so that a
+// wavefront searches two units at once; at(i) gives the input of index i.
 template <typename At>
-__device__ __forceinline__ uint64_t rg_search(const float* w, int u, uint64_t lo, uint64_t hi, At at) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ uint64_t rg_search_half(const float* w, int u, uint64_t lo, uint64_t hi, At at) {
+    const int lane = threadIdx.x & 63, hl = lane & 31, hb = lane & 32;
     while (lo < hi) {
-        // probes lo + l * step, l = 0..63: the last one is at or past hi
+        // probes lo + l * step, l = 0..31: the last one is at or past hi
         // (taken as true), so some lane's predicate holds
-        const uint64_t step = (hi - lo + 62) / 63;
-        const uint64_t idx = lo + (uint64_t)lane * step;
+        const uint64_t step = (hi - lo + 30) / 31;
+        const uint64_t idx = lo + (uint64_t)hl * step;
         const bool pred = idx >= hi || rg_past(w, u, at(idx));
-        const uint64_t mask = __ballot(pred);
-        const int f = __ffsll((unsigned long long)mask) - 1;
-        if (f == 0) return lo;
+        const uint32_t mask = (uint32_t)(__ballot(pred) >> hb);
+        const int f = __ffs(mask) - 1;
+        if (f == 0) break;
         lo = lo + (uint64_t)(f - 1) * step + 1;
         hi = min<uint64_t>(lo - 1 + step, hi);
     }
@@ -622,17 +623,19 @@ __global__ __launch_bounds__(RG_T) void k_mlp_regions(MlpRegion A) {
     for (uint32_t k = 1; k <= nstep; k++) {
         if (tid < MLP_NP) w[tid] = mlp_is_weight(tid) ? fabsf(pv) : pv;
         __syncthreads();
-        // switch indices: wave wv searches units wv and wv + 16
-        for (int u = wv; u < RG_UNITS; u += RG_T / 64) {
-            const uint64_t jc = rg_search(w, u, 0, nc, [&](uint64_t j) { return ct[j]; });
+        // switch indices: the two halves of wave wv search units wv and wv + 16
+        static_assert(RG_UNITS == 2 * (RG_T / 64), "two units per wavefront");
+        {
+            const int u = wv + (lane >= 32 ? RG_UNITS / 2 : 0);
+            const uint64_t jc = rg_search_half(w, u, 0, nc, [&](uint64_t j) { return ct[j]; });
             uint64_t T;
             if (jc == 0) {
                 T = 0;
             } else {
                 const uint64_t lo = (jc - 1) * sp + 1, hi = min<uint64_t>(jc * sp, S);
-                T = rg_search(w, u, lo, hi, [&](uint64_t i) { return A.t[i]; });
+                T = rg_search_half(w, u, lo, hi, [&](uint64_t i) { return A.t[i]; });
             }
-            if (lane == 0) thr[u] = T;
+            if ((lane & 31) == 0) thr[u] = T;
         }
         __syncthreads();
         if (tid < RG_UNITS) {  // region boundaries: the switch indices in order
