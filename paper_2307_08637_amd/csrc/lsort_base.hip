@@ -15,43 +15,63 @@ namespace ls {
 // k_base_small: sub-arrays of at most 2048 keys sorted in registers by groups
 // of 4, 8, 16, 32 or 64 lanes (group_bitonic, 16 .. 1 sub-arrays per
 // wavefront); with a payload, sub-arrays of at most 512 keys, one per
-// wavefront (wave_bitonic); k_base_big: one workgroup per larger sub-array
+// wavefront, as (key, index) pairs (packed_pair_sort, else pair_bitonic);
+// k_base_pairs: with a payload, 513..1024 keys the same way; k_base_merge:
+// chunk-and-merge items; k_base_big: one workgroup per larger sub-array
 // (up to 8192) sorted in LDS, and the copies of finished runs.
 // ===========================================================================
 
 constexpr int BASE_THREADS = 256;
 
-template <int E, bool PAY>
-__device__ __forceinline__ void base_small_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, int lane) {
-    const uint64_t* in = P.keys[srcb];
-    uint64_t* out = P.keys[0];
-    const int u64 = P.u64;
-    uint64_t k[E];
-    uint32_t ix[E];
+// Smallest and largest ordered key of a wavefront's item (pads excluded by
+// the caller), in every lane: a butterfly over lane ^ 1 .. lane ^ 32.
+template <int S>
+__device__ __forceinline__ void wave_span(uint64_t& mn, uint64_t& mx, int lane) {
+    if constexpr (S < 6) {
+        const uint64_t a = dpp_t<S>(mn, (uint32_t)lane), b = dpp_t<S>(mx, (uint32_t)lane);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+        wave_span<S + 1>(mn, mx, lane);
+    }
+}
+
+// Stable sort of one wavefront's item of (ordered key, index) pairs, 2^LE per
+// lane (indices distinct, below 2^(LE + 6); those at or above size mark
+// pads), through the binary64 network.  With IB = LE + 6 index bits, an item
+// whose keys span less than 2^(62 - IB) maps each pair to
+// (key - min) * 2^IB + index: below 2^62, so the bit pattern of a finite
+// non-negative binary64 number, and such numbers order as their bit patterns.
+// The numeric network (one v_min_f64 / v_max_f64 per compare-exchange inside
+// a lane) then orders by key, then index: the stable order, the same result
+// as the pair network, whose 64-bit key and index compares and selects cost
+// several times more.  Pads sort last as +inf.  A wider item returns false
+// with k and ix untouched (the caller runs the pair network).
+template <int LE>
+__device__ __forceinline__ bool packed_pair_sort(uint64_t (&k)[1 << LE], uint32_t (&ix)[1 << LE], uint32_t size,
+                                                 int lane) {
+    constexpr int E = 1 << LE, IB = LE + 6;
+    uint64_t mn = ~0ull, mx = 0;
 #pragma unroll
     for (int e = 0; e < E; e++) {
-        const uint32_t i = lane * E + e;
-        k[e] = i < size ? key_ord(in[off + i], u64) : ~0ull;
-        ix[e] = i;
+        const bool in = ix[e] < size;
+        mn = in && k[e] < mn ? k[e] : mn;
+        mx = in && k[e] > mx ? k[e] : mx;
     }
-    if (PAY) {
-        constexpr int LE = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : 3;
-        static_assert((1 << LE) == E, "1, 2, 4 or 8 pairs per lane");
-        pair_bitonic<LE, 6>(k, ix, lane);
-        const uint32_t* pin = P.pay[srcb];
-        uint32_t* pout = P.pay[0];
-        uint32_t pv[E];
-#pragma unroll
-        for (int e = 0; e < E; e++) pv[e] = (lane * E + e < (int)size) ? pin[off + ix[e]] : 0u;
-#pragma unroll
-        for (int e = 0; e < E; e++)
-            if (lane * E + e < (int)size) pout[off + lane * E + e] = pv[e];
-    } else {
-        wave_bitonic<E, false>(k, ix, lane);
-    }
+    wave_span<0>(mn, mx, lane);
+    // the same value in every lane: a uniform branch
+    if (__builtin_amdgcn_readfirstlane((int)((mx - mn) >> (62 - IB) != 0))) return false;
+    double d[E];
 #pragma unroll
     for (int e = 0; e < E; e++)
-        if (lane * E + e < (int)size) out[off + lane * E + e] = key_unord(k[e], u64);
+        d[e] = __builtin_bit_cast(double, ix[e] < size ? ((k[e] - mn) << IB) | ix[e] : 0x7ff0000000000000ull);
+    group_bitonic<double, LE, 6>(d, lane);
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, d[e]);
+        k[e] = mn + (u >> IB);
+        ix[e] = (uint32_t)u & ((1u << IB) - 1);
+    }
+    return true;
 }
 
 // Group items: 64 / G sub-arrays per wavefront, G lanes and E = 32 keys per
@@ -93,6 +113,72 @@ __device__ __forceinline__ uint64_t gload(const uint64_t* p) {
     return *(const __attribute__((address_space(1))) uint64_t*)p;
 }
 __device__ __forceinline__ void gstore(uint64_t* p, uint64_t v) { *(__attribute__((address_space(1))) uint64_t*)p = v; }
+
+// One payload item of up to 64 * 2^LE keys, one wavefront: a stable sort of
+// (ordered key, index) pairs in registers, 2^LE per lane (packed_pair_sort
+// when the keys are narrow enough, else pair_bitonic).  Keys and payload are
+// read coalesced (element i at lane i % 64, register i / 64: any placement of
+// unsorted input is valid), the payload kept in the wave's LDS region by
+// position; after the sort element j sits at lane j / 2^LE, register
+// j % 2^LE, and takes its payload from LDS through its index.  The sorted
+// keys, then the payload, leave through the same region (one pad slot after
+// every 2^LE, so that a lane's run starts on a different bank than its
+// neighbours') and are stored coalesced.  lr: the wave's region,
+// pay_slots(LE) 8-byte slots.
+__device__ __forceinline__ constexpr int pay_slots(int LE) { return (WAVE << LE) + WAVE; }
+
+template <int LE>
+__device__ __forceinline__ void pay_wave_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, int lane,
+                                              uint64_t* lr) {
+    constexpr int E = 1 << LE;
+    const uint64_t* in = P.keys[srcb];
+    const uint32_t* pin = P.pay[srcb];
+    uint64_t* out = P.keys[0];
+    uint32_t* pout = P.pay[0];
+    uint32_t* lp = reinterpret_cast<uint32_t*>(lr);
+    const int u64 = P.u64;
+    auto slot = [](uint32_t j) { return j + (j >> LE); };
+    uint64_t k[E];
+    uint32_t ix[E];
+    // indices clamp to size - 1: every load is in bounds without a branch (the
+    // pads' payload slots are never read)
+    const uint32_t last = size - 1;
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        const uint32_t i = r * WAVE + opaque(lane), c = min(i, last);
+        const uint64_t raw = gload(in + off + c);
+        lp[i] = pin[off + c];
+        k[r] = i < size ? key_ord(raw, u64) : ~0ull;
+        ix[r] = i;
+        // each address formed next to its load
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!packed_pair_sort<LE>(k, ix, size, lane)) pair_bitonic<LE, 6>(k, ix, lane);
+    wave_lds_sync();
+    uint32_t pv[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) pv[e] = (uint32_t)(lane * E + e) < size ? lp[ix[e]] : 0u;
+    wave_lds_sync();  // every gather done before the region is rewritten
+#pragma unroll
+    for (int e = 0; e < E; e++) lr[slot(lane * E + e)] = k[e];
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        const uint32_t j = r * WAVE + opaque(lane);
+        if (j < size) gstore(out + off + j, key_unord(lr[slot(j)], u64));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E; e++) lp[slot(lane * E + e)] = pv[e];
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        const uint32_t j = r * WAVE + opaque(lane);
+        if (j < size) pout[off + j] = lp[slot(j)];
+    }
+    wave_lds_sync();  // the next item rewrites the region
+}
 
 // One task: 64 / G items, entries [task * GPW, ...) of a list (read from the
 // back when REV).  binary64: the numeric network, unless the task holds a NaN
@@ -236,11 +322,12 @@ __device__ __forceinline__ void group_loop(const Params& P, const uint64_t* item
 // 1025..2048 keys and of 2 items of 513..1024 (keys only), of 4 items of
 // 257..512, of 8 of 129..256, of 16 of up to 128.  Separate loops keep each class's loop-invariant registers
 // out of the others'.  With a payload every item is one wave task (the
-// stable pair sort, wave_bitonic).
+// stable sort of (key, index) pairs).
 template <bool PAY, bool U64>
 __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
     constexpr int W = BASE_THREADS / 64;
     __shared__ uint64_t glds[PAY ? 1 : W][PAY ? 1 : G_SLOTS];
+    __shared__ uint64_t plr[PAY ? W : 1][PAY ? pay_slots(3) : 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t waves = (uint64_t)gridDim.x * W, wid = (uint64_t)blockIdx.x * W + wv;
     const uint64_t n0 = min<unsigned long long>(P.ctl->nitems, P.item_cap);
@@ -252,10 +339,10 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
             const uint64_t off = wd >> 18;
             const uint32_t srcb = (wd >> 17) & 1u;
             const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
-            if (size <= 64) base_small_item<1, PAY>(P, off, size, srcb, lane);
-            else if (size <= 128) base_small_item<2, PAY>(P, off, size, srcb, lane);
-            else if (size <= 256) base_small_item<4, PAY>(P, off, size, srcb, lane);
-            else base_small_item<8, PAY>(P, off, size, srcb, lane);
+            if (size <= 64) pay_wave_item<0>(P, off, size, srcb, lane, plr[wv]);
+            else if (size <= 128) pay_wave_item<1>(P, off, size, srcb, lane, plr[wv]);
+            else if (size <= 256) pay_wave_item<2>(P, off, size, srcb, lane, plr[wv]);
+            else pay_wave_item<3>(P, off, size, srcb, lane, plr[wv]);
         }
         return;
     }
@@ -492,41 +579,13 @@ __global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
 }
 
 // With a payload: items and chunks of SMALL_MAX+1 .. PAIR_CHUNK keys, one
-// wavefront each, sorted stably in registers as (ordered key, index) pairs
-// (pair_bitonic: 16 pairs per lane, 8 for a chunk of at most 512 keys); the
-// payload follows through the sorted indices, read before any write.
-template <int LE>
-__device__ __forceinline__ void base_pair_item(const Params& P, uint64_t off, uint32_t size, uint32_t srcb, int lane) {
-    constexpr int E = 1 << LE;
-    const uint64_t* in = P.keys[srcb];
-    uint64_t* out = P.keys[0];
-    const int u64 = P.u64;
-    uint64_t k[E];
-    uint32_t ix[E];
-#pragma unroll
-    for (int e = 0; e < E; e++) {
-        const uint32_t i = lane * E + e;
-        k[e] = i < size ? key_ord(in[off + i], u64) : ~0ull;
-        ix[e] = i;
-    }
-    pair_bitonic<LE, 6>(k, ix, lane);
-    const uint32_t* pin = P.pay[srcb];
-    uint32_t* pout = P.pay[0];
-    uint32_t pv[E];
-#pragma unroll
-    for (int e = 0; e < E; e++) pv[e] = (lane * E + e < (int)size) ? pin[off + ix[e]] : 0u;
-#pragma unroll
-    for (int e = 0; e < E; e++)
-        if (lane * E + e < (int)size) {
-            pout[off + lane * E + e] = pv[e];
-            out[off + lane * E + e] = key_unord(k[e], u64);
-        }
-}
-
+// wavefront each (pay_wave_item: 16 pairs per lane, 8 for a chunk of at most
+// 512 keys).
 __global__ __launch_bounds__(BASE_THREADS) void k_base_pairs(Params P) {
     constexpr int W = BASE_THREADS / 64;
-    const int lane = threadIdx.x & 63;
-    const uint64_t waves = (uint64_t)gridDim.x * W, wid = (uint64_t)blockIdx.x * W + (threadIdx.x >> 6);
+    __shared__ uint64_t plr[W][pay_slots(4)];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t waves = (uint64_t)gridDim.x * W, wid = (uint64_t)blockIdx.x * W + wv;
     const uint64_t nc = min<unsigned long long>(P.ctl->nitems_c, P.item_c_cap);
     for (uint64_t t = wid; t < nc; t += waves) {
         const uint64_t wd = P.items_c[t];
@@ -534,8 +593,8 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_pairs(Params P) {
         const uint32_t srcb = (wd >> 17) & 1u;
         const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
         static_assert(SMALL_MAX == 8 * WAVE && PAIR_CHUNK == 16 * WAVE, "8 and 16 pairs per lane");
-        if (size <= SMALL_MAX) base_pair_item<3>(P, off, size, srcb, lane);
-        else base_pair_item<4>(P, off, size, srcb, lane);
+        if (size <= SMALL_MAX) pay_wave_item<3>(P, off, size, srcb, lane, plr[wv]);
+        else pay_wave_item<4>(P, off, size, srcb, lane, plr[wv]);
     }
 }
 

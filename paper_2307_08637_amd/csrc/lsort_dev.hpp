@@ -610,6 +610,10 @@ __device__ __forceinline__ void group_stage(T (&k)[1 << LE], int lane) {
             cx_reg(k[r], k[FLIP ? r ^ ((2 << B) - 1) : r | (1 << B)]);
             cx_window(q);
         }
+    } else if constexpr (FLIP && E == 1) {  // one register: the mirror lane's
+        constexpr int S = B - LE;
+        const bool km = (lane >> S) & 1;
+        k[0] = cx_lane(k[0], dpp_t<8 + S>(k[0], (uint32_t)lane), km);
     } else if constexpr (FLIP) {  // partner lane ^ (2^(s+1) - 1), register E-1-r
         constexpr int S = B - LE;
         const bool km = (lane >> S) & 1;

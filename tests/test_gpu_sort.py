@@ -201,6 +201,82 @@ def test_pair_items_every_size(dev):
         assert np.array_equal(p.view(torch.int32).cpu().numpy().view(np.uint32), wp)
 
 
+def _seg_sort_pay(keys, off, dev, **opts):
+    """Segmented sort with payload = global index on the device, and the oracle's."""
+    pay = np.arange(keys.size, dtype=np.uint32)
+    t = to_dev(keys, dev)
+    p = torch.from_numpy(pay.view(np.int32).copy()).to(dev).view(torch.uint32)
+    o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+    print(f"[case] packed pairs n={keys.size} dtype={keys.dtype} segments={off.size - 1} opts={opts}", flush=True)
+    lsort.sort_segmented(t, o, p, **opts)
+    torch.cuda.synchronize()
+    want, wp = oracle.sort_segmented(keys, off, pay)
+    assert_same_bits(to_host(t), want)
+    assert np.array_equal(p.view(torch.int32).cpu().numpy().view(np.uint32), wp)
+
+
+def test_pair_items_packed(dev):
+    """Payload items whose keys span less than 2^(56 - log2 pairs per lane)
+    sort as packed binary64 values (key - min) * 2^IB + index in the numeric
+    network, wider ones by the pair network; both must give the stable order.
+    uint64 segments of every size 1..600 with spans 2^0 .. 2^63 (either side
+    of every class's limit 2^56 / 2^55 / 2^54 / 2^53 / 2^52), spans at and
+    just past each limit with both extremes present, and duplicate-heavy
+    segments (ties decided by the index bits)."""
+    rng = np.random.default_rng(15)
+    sizes = np.tile(np.arange(1, 601, dtype=np.int64), 3)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    span_bits = rng.integers(0, 64, sizes.size).repeat(sizes)
+    base = rng.integers(0, 2**63, sizes.size, dtype=np.uint64).repeat(sizes)
+    r = rng.integers(0, 2**64 - 1, n, dtype=np.uint64, endpoint=True)
+    keys = base + (r >> (np.uint64(64) - span_bits.astype(np.uint64)).clip(0, 63))
+    dups = (np.arange(sizes.size) % 5 == 0).repeat(sizes)  # every fifth segment: four distinct values
+    keys = np.where(dups, base + (r & np.uint64(3)), keys)
+    _seg_sort_pay(keys, off, dev, cutoff=600)
+    # each class's limit: span 2^L - 1 (packed) and 2^L, 2^(L+1) (pair network)
+    segs = []
+    for size, lim in ((64, 56), (128, 55), (256, 54), (512, 53), (40, 56), (500, 53)):
+        for span in (2**lim - 1, 2**lim, 2**(lim + 1), 2**63 + 5):
+            lo = int(rng.integers(0, 2**64 - span, dtype=np.uint64, endpoint=True))
+            v = lo + rng.integers(0, span, size, dtype=np.uint64, endpoint=True)
+            v[rng.permutation(size)[:4]] = np.array([lo, lo, lo + span, lo + span], dtype=np.uint64)
+            segs.append(v)
+    keys = np.concatenate(segs)
+    off = np.zeros(len(segs) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([v.size for v in segs])
+    _seg_sort_pay(keys, off, dev, cutoff=600)
+
+
+@pytest.mark.parametrize("law", ["narrow_f64", "narrow_u64", "zero_mix"])
+def test_pair_items_packed_levels(dev, law):
+    """The same after partition levels: segments of 2e3..3e4 keys with a
+    payload, whose buckets reach the base case as items of up to 512 keys,
+    items and 1024-key chunks of 513..1024 (one wavefront each), and chunk
+    merges.  Narrow float64 segments (one binade: packed), narrow uint64 ones,
+    and float64 keys around zero with -0.0, subnormals and NaN (the buckets
+    spanning zero take the pair network)."""
+    rng = np.random.default_rng(16)
+    sizes = rng.integers(2000, 30000, 40)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    if law == "narrow_f64":
+        c = rng.uniform(1.0, 2.0, sizes.size).repeat(sizes)
+        keys = c * (1.0 + rng.uniform(0.0, 1e-3, n))
+        keys[rng.random(n) < 0.2] = 1.5  # ties across the payload
+    elif law == "narrow_u64":
+        keys = rng.integers(0, 2**60, sizes.size, dtype=np.uint64).repeat(sizes) + rng.integers(0, 2**44, n,
+                                                                                              dtype=np.uint64)
+    else:
+        keys = rng.normal(0.0, 1e-300, n) * rng.choice([1.0, 1e-8, 1e300], n)
+        keys[rng.random(n) < 0.05] = -0.0
+        keys[rng.random(n) < 0.05] = 0.0
+        keys[rng.random(n) < 0.01] = np.nan
+    _seg_sort_pay(keys, off, dev)
+
+
 @pytest.mark.parametrize("kind,n,buckets", [("uniform", 200_000, 40), ("normal", 300_000, 64), ("u64", 250_000, 40),
                                              ("lognormal", 400_000, 100), ("sparse_specials", 200_000, 40),
                                              ("subnormal_mix", 150_000, 32), ("few_distinct", 200_000, 40)])
