@@ -685,7 +685,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
         // the items sorted above as chunks, merged (none: no launch)
         const bool merge = nmerge != 0;
-        if (merge) TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus * 2, c.st));
+        if (merge) TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus, c.st));
         if (g_timing && !t_untimed && g_trec.size() > r0) {  // keys through each base-case kernel
             HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));

@@ -474,18 +474,23 @@ __global__ __launch_bounds__(NT) void k_base_mid(Params P) {
 // contributes to the outputs before it), then it merges sequentially.  The
 // item sits in LDS with one pad word after every 16 keys, so that the 16-key
 // output runs of a wavefront's lanes fall on distinct banks (17 l mod 32 is a
-// bijection).  Keys only: 68 KB of LDS, two workgroups per CU; with a
-// payload 102 KB, one.
-constexpr int MG_THREADS = 512, MG_OUT = BIG_MAX / MG_THREADS;
-static_assert(MG_OUT == 16 && PAIR_CHUNK % MG_OUT == 0 && GROUP_WAVE_MAX % MG_OUT == 0,
-              "a thread's outputs lie inside one pair of runs");
+// bijection).
+constexpr int MG_OUT = 16;
+static_assert(PAIR_CHUNK % MG_OUT == 0 && GROUP_WAVE_MAX % MG_OUT == 0, "a thread's outputs lie inside one pair of runs");
 
 __device__ __forceinline__ uint32_t mslot(uint32_t i) { return i + (i >> 4); }
 
-template <bool PAY>
-__global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
-    __shared__ uint64_t L[BIG_MAX + BIG_MAX / 16];
-    __shared__ uint32_t Lp[PAY ? BIG_MAX + BIG_MAX / 16 : 1];
+// CAP: the largest item of the launch (CAP / 16 threads, its LDS); each size
+// class (up to 2048 keys, 2049..4096, 4097..8192) has a launch of its own
+// with as many workgroups per CU as its LDS allows, and skips the others'
+// items.
+template <bool PAY, int CAP>
+__global__ __launch_bounds__(CAP / MG_OUT) void k_base_merge(Params P) {
+    constexpr int MG_THREADS = CAP / MG_OUT;
+    constexpr uint32_t NMIN = CAP <= GROUP_WAVE_MAX ? 0u : CAP / 2;  // items of NMIN+1 .. CAP keys
+    static_assert(CAP <= BIG_MAX && CAP % MG_OUT == 0, "item size classes");
+    __shared__ uint64_t L[CAP + CAP / 16];
+    __shared__ uint32_t Lp[PAY ? CAP + CAP / 16 : 1];
     const int tid = threadIdx.x;
     const uint64_t nm = min<unsigned long long>(P.ctl->nmerge, P.merge_cap);
     uint64_t* keys = P.keys[0];
@@ -496,6 +501,7 @@ __global__ __launch_bounds__(MG_THREADS) void k_base_merge(Params P) {
         const uint64_t wd = P.merges[it];
         const uint64_t off = wd >> 18;
         const uint32_t n = (uint32_t)(wd & 0xffffu) + 1;
+        if (n <= NMIN || n > CAP) continue;  // another launch's item
         {
             uint64_t v[MG_OUT];
 #pragma unroll
@@ -618,9 +624,18 @@ hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) {
     hipLaunchKernelGGL(k_base_big<C_MAX>, dim3(grid), dim3(BIG_THREADS), 0, st, P);
     LAUNCH(k_base_big<BIG_MAX>, grid / 2 ? grid / 2 : 1, BIG_THREADS, st, P);
 }
-hipError_t launch_base_merge(const Params& P, uint32_t grid, hipStream_t st) {
-    if (P.has_pay) LAUNCH(k_base_merge<true>, grid / 2 ? grid / 2 : 1, MG_THREADS, st, P);  // one per CU
-    LAUNCH(k_base_merge<false>, grid, MG_THREADS, st, P);
+hipError_t launch_base_merge(const Params& P, uint32_t cus, hipStream_t st) {
+    // workgroups per CU by LDS: keys only 35 / 70 KB (4096 / 8192 keys), with
+    // a payload 26 / 52 / 104 KB (2048 / 4096 / 8192)
+    if (P.has_pay) {
+        hipLaunchKernelGGL((k_base_merge<true, GROUP_WAVE_MAX>), dim3(cus * 6), dim3(GROUP_WAVE_MAX / MG_OUT), 0, st, P);
+        hipLaunchKernelGGL((k_base_merge<true, 2 * GROUP_WAVE_MAX>), dim3(cus * 3), dim3(2 * GROUP_WAVE_MAX / MG_OUT), 0,
+                           st, P);
+        LAUNCH((k_base_merge<true, BIG_MAX>), cus, BIG_MAX / MG_OUT, st, P);
+    }
+    hipLaunchKernelGGL((k_base_merge<false, 2 * GROUP_WAVE_MAX>), dim3(cus * 4), dim3(2 * GROUP_WAVE_MAX / MG_OUT), 0, st,
+                       P);
+    LAUNCH((k_base_merge<false, BIG_MAX>), cus * 2, BIG_MAX / MG_OUT, st, P);
 }
 
 }  // namespace ls

@@ -99,7 +99,7 @@ hipError_t launch_scan(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st);
-hipError_t launch_base_merge(const Params& P, uint32_t grid, hipStream_t st);
+hipError_t launch_base_merge(const Params& P, uint32_t cus, hipStream_t st);
 hipError_t launch_base_model(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_resident(const Params& P, uint32_t grid, hipStream_t st);
 
