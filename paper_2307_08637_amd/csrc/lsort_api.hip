@@ -634,6 +634,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     uint32_t levels = 0;
     uint32_t next_res = 0;  // resident segments of the next level (read back)
     uint64_t nmerge = ~0ull;  // chunk-and-merge items (read back after the last level; unknown: fixed levels)
+    uint32_t mclasses = 7;    // their size classes present (bits: up to 2048 keys, 2049..4096, 4097..8192)
     uint32_t split = 0;       // the next level has fewer work units than CUs (read back)
     for (uint32_t lvl = 0; lvl < max_run; lvl++) {
         P.level = (int)lvl;
@@ -668,6 +669,11 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         double lkeys = (double)hc->lv[lvl].keys;
         next_res = hc->nres[lvl + 1];
         nmerge = hc->nmerge;
+        // a launch per size class present; with fewer items than CUs x 4,
+        // one launch for all (their merges are latency, not throughput)
+        mclasses = nmerge < 4ull * cus ? 8u
+                 : (nmerge > hc->nmerge_cls[0] ? 1u : 0u) | (hc->nmerge_cls[0] > hc->nmerge_cls[1] ? 2u : 0u) |
+                       (hc->nmerge_cls[1] ? 4u : 0u);
         // a next level of few work units (a few small segments) is re-cut
         // into one-tile units, when the unit list has room for them
         const uint64_t nu = hc->ntile[lvl + 1];
@@ -685,7 +691,7 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         TIMED(KI_BASE_BIG, c.st, launch_base_big(P, cus * 2, c.st));
         // the items sorted above as chunks, merged (none: no launch)
         const bool merge = nmerge != 0;
-        if (merge) TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus, c.st));
+        if (merge) TIMED(KI_BASE_MERGE, c.st, launch_base_merge(P, cus, mclasses, c.st));
         if (g_timing && !t_untimed && g_trec.size() > r0) {  // keys through each base-case kernel
             HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
             HIP_TRY(hipStreamSynchronize(c.st));

@@ -480,14 +480,16 @@ static_assert(PAIR_CHUNK % MG_OUT == 0 && GROUP_WAVE_MAX % MG_OUT == 0, "a threa
 
 __device__ __forceinline__ uint32_t mslot(uint32_t i) { return i + (i >> 4); }
 
-// CAP: the largest item of the launch (CAP / 16 threads, its LDS); each size
-// class (up to 2048 keys, 2049..4096, 4097..8192) has a launch of its own
-// with as many workgroups per CU as its LDS allows, and skips the others'
-// items.
-template <bool PAY, int CAP>
+// CAP: the largest item of the launch (CAP / 16 threads, its LDS).  Many
+// items: each size class (up to 2048 keys, 2049..4096, 4097..8192) has a
+// launch of its own with as many workgroups per CU as its LDS allows, and
+// skips the others' items.  Few items (ALL): one launch takes every size,
+// so that the largest items' merges overlap the others' instead of
+// following them.
+template <bool PAY, int CAP, bool ALL>
 __global__ __launch_bounds__(CAP / MG_OUT) void k_base_merge(Params P) {
     constexpr int MG_THREADS = CAP / MG_OUT;
-    constexpr uint32_t NMIN = CAP <= GROUP_WAVE_MAX ? 0u : CAP / 2;  // items of NMIN+1 .. CAP keys
+    constexpr uint32_t NMIN = ALL || CAP <= GROUP_WAVE_MAX ? 0u : CAP / 2;  // items of NMIN+1 .. CAP keys
     static_assert(CAP <= BIG_MAX && CAP % MG_OUT == 0, "item size classes");
     __shared__ uint64_t L[CAP + CAP / 16];
     __shared__ uint32_t Lp[PAY ? CAP + CAP / 16 : 1];
@@ -624,18 +626,31 @@ hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) {
     hipLaunchKernelGGL(k_base_big<C_MAX>, dim3(grid), dim3(BIG_THREADS), 0, st, P);
     LAUNCH(k_base_big<BIG_MAX>, grid / 2 ? grid / 2 : 1, BIG_THREADS, st, P);
 }
-hipError_t launch_base_merge(const Params& P, uint32_t cus, hipStream_t st) {
+hipError_t launch_base_merge(const Params& P, uint32_t cus, uint32_t classes, hipStream_t st) {
     // workgroups per CU by LDS: keys only 35 / 70 KB (4096 / 8192 keys), with
     // a payload 26 / 52 / 104 KB (2048 / 4096 / 8192)
-    if (P.has_pay) {
-        hipLaunchKernelGGL((k_base_merge<true, GROUP_WAVE_MAX>), dim3(cus * 6), dim3(GROUP_WAVE_MAX / MG_OUT), 0, st, P);
-        hipLaunchKernelGGL((k_base_merge<true, 2 * GROUP_WAVE_MAX>), dim3(cus * 3), dim3(2 * GROUP_WAVE_MAX / MG_OUT), 0,
-                           st, P);
-        LAUNCH((k_base_merge<true, BIG_MAX>), cus, BIG_MAX / MG_OUT, st, P);
+    if (classes & 8) {  // one launch for every size
+        if (P.has_pay) LAUNCH((k_base_merge<true, BIG_MAX, true>), cus, BIG_MAX / MG_OUT, st, P);
+        LAUNCH((k_base_merge<false, BIG_MAX, true>), cus * 2, BIG_MAX / MG_OUT, st, P);
     }
-    hipLaunchKernelGGL((k_base_merge<false, 2 * GROUP_WAVE_MAX>), dim3(cus * 4), dim3(2 * GROUP_WAVE_MAX / MG_OUT), 0, st,
-                       P);
-    LAUNCH((k_base_merge<false, BIG_MAX>), cus * 2, BIG_MAX / MG_OUT, st, P);
+    if (P.has_pay) {
+        if (classes & 1)
+            hipLaunchKernelGGL((k_base_merge<true, GROUP_WAVE_MAX, false>), dim3(cus * 6), dim3(GROUP_WAVE_MAX / MG_OUT), 0,
+                               st, P);
+        if (classes & 2)
+            hipLaunchKernelGGL((k_base_merge<true, 2 * GROUP_WAVE_MAX, false>), dim3(cus * 3),
+                               dim3(2 * GROUP_WAVE_MAX / MG_OUT), 0, st, P);
+        if (classes & 4)
+            hipLaunchKernelGGL((k_base_merge<true, BIG_MAX, false>), dim3(cus), dim3(BIG_MAX / MG_OUT), 0, st, P);
+        return hipGetLastError();
+    }
+    // keys only: merged items hold more than GROUP_WAVE_MAX keys
+    if (classes & 2)
+        hipLaunchKernelGGL((k_base_merge<false, 2 * GROUP_WAVE_MAX, false>), dim3(cus * 4),
+                           dim3(2 * GROUP_WAVE_MAX / MG_OUT), 0, st, P);
+    if (classes & 4)
+        hipLaunchKernelGGL((k_base_merge<false, BIG_MAX, false>), dim3(cus * 2), dim3(BIG_MAX / MG_OUT), 0, st, P);
+    return hipGetLastError();
 }
 
 }  // namespace ls

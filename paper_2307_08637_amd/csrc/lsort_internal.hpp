@@ -172,6 +172,7 @@ struct Ctl {
     LS_HOT unsigned long long nitems_m;     // items of the model-based counting sort (two words each)
     LS_HOT unsigned long long nmerge;       // items sorted as chunks, then merged (k_base_merge; split_chunks)
     LS_HOT unsigned long long merge_keys;   // keys in those items
+    LS_HOT unsigned long long nmerge_cls[2];  // those of more than GROUP_WAVE_MAX keys, of more than 2 GROUP_WAVE_MAX
     LS_HOT unsigned long long nchunk;       // their chunks (in nitems_c)
     LS_HOT unsigned long long model_keys;   // keys in those items
     LS_HOT unsigned long long ncopy;

@@ -779,7 +779,11 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             lb += ntl | (ng1 << 32) | ((nsm - ng0 - ng1 - ng3 - ng4) << 48);
             lc += ng3 | ((ng4 + nsp) << 32);
             lm += nsp > 1 ? 1 | (nsp << 16) | (c[i] << 32) : 0;  // merged items (one chunk: none)
-            lfb += d.act == 5 ? 1 : 0;
+            // fallbacks | merged items of more than GROUP_WAVE_MAX keys << 16 |
+            // of more than twice that << 32 (each at most B_MAX per segment)
+            static_assert(B_MAX < (1 << 16), "16-bit count fields");
+            lfb += (d.act == 5 ? 1 : 0) | (nsp > 1 && c[i] > GROUP_WAVE_MAX ? 1ull << 16 : 0) |
+                   (nsp > 1 && c[i] > 2 * GROUP_WAVE_MAX ? 1ull << 32 : 0);
             lsk += nsm || nsp ? c[i] : 0;
             lgk += nbg ? c[i] : 0;
             lcp += d.act == 1 ? nbg : 0;
@@ -798,7 +802,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
         const uint64_t gk = block_sum<S_THREADS, uint64_t>(lgk, red64);
         const uint64_t ncp = block_sum<S_THREADS, uint64_t>(lcp, red64);
         const uint64_t sc = block_sum<S_THREADS, uint64_t>(lstat, red64);
-        const uint64_t nfb = block_sum<S_THREADS, uint64_t>(lfb, red64);
+        const uint64_t fbm = block_sum<S_THREADS, uint64_t>(lfb, red64);
+        const uint64_t nfb = fbm & 0xffff;
         const uint64_t mx = block_max<S_THREADS, uint64_t>(cmax, red64);
         if (tid < WAVE) {
             // the reservations: one device-scope atomic per lane, issued as one
@@ -830,6 +835,8 @@ __global__ __launch_bounds__(S_THREADS) void k_scan(Params P) {
             if (l == 14) resv[9] = (tm & 0xffff) ? atomicAdd(&P.ctl->nmerge, (unsigned long long)(tm & 0xffff)) : 0ull;
             if (l == 15 && (tm >> 32)) atomicAdd(&P.ctl->merge_keys, (unsigned long long)(tm >> 32));
             if (l == 16 && (tm & 0xffff)) atomicAdd(&P.ctl->nchunk, (unsigned long long)((tm >> 16) & 0xffff));
+            const uint64_t mcl = l == 17 ? (fbm >> 16) & 0xffff : fbm >> 32;
+            if ((l == 17 || l == 18) && mcl) atomicAdd(&P.ctl->nmerge_cls[l - 17], (unsigned long long)mcl);
         }
         if (tid == 0) {
             const uint64_t m12 = 4095;

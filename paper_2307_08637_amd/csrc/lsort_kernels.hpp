@@ -99,7 +99,9 @@ hipError_t launch_scan(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_scatter(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st);
-hipError_t launch_base_merge(const Params& P, uint32_t cus, hipStream_t st);
+// classes: bit 0 items of up to 2048 keys, bit 1 of 2049..4096, bit 2 of
+// 4097..8192 (a launch per class present); bit 3: one launch for all
+hipError_t launch_base_merge(const Params& P, uint32_t cus, uint32_t classes, hipStream_t st);
 hipError_t launch_base_model(const Params& P, uint32_t grid, hipStream_t st);
 hipError_t launch_resident(const Params& P, uint32_t grid, hipStream_t st);
 

@@ -335,6 +335,35 @@ def test_split_merge_segmented_sizes(dev):
     assert st["merged_items"] > 0, st
 
 
+@pytest.mark.parametrize("pay", [False, True])
+def test_merge_size_classes(dev, pay):
+    """Thousands of chunk-and-merge items (600 arrays of 2e4..1.2e5 keys, 16
+    first-level buckets each: buckets of ~1e3..8e3 keys), so that the merges
+    run as one launch per size class (up to 2048 keys, 2049..4096,
+    4097..8192) rather than one launch for all; keys (and payload) against
+    the oracle."""
+    rng = np.random.default_rng(65)
+    sizes = rng.integers(20_000, 120_000, 600).astype(np.int64)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    keys = inputs.generate("lognormal", n, seed=66)
+    t = to_dev(keys, dev)
+    o = torch.from_numpy(off.view(np.int64)).to(dev).view(torch.uint64)
+    pay_h = np.arange(n, dtype=np.uint32) if pay else None
+    p = torch.from_numpy(pay_h.view(np.int32).copy()).to(dev).view(torch.uint32) if pay else None
+    print(f"[case] merge size classes n={n} pay={pay}", flush=True)
+    lsort.sort_segmented(t, o, p, buckets=16, stats=True)
+    torch.cuda.synchronize()
+    st = lsort.stats()
+    want, wp = oracle.sort_segmented(keys, off, pay_h)
+    assert_same_bits(to_host(t), want)
+    if pay:
+        assert np.array_equal(p.view(torch.int32).cpu().numpy().view(np.uint32), wp)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert st["merged_items"] >= 4 * cus, st  # at the class-launch form's threshold or above
+
+
 @pytest.mark.parametrize("law", ["uniform", "normal", "rootdups", "u64"])
 def test_splitter_model(dev, law):
     keys = inputs.generate(law, 400_000, seed=41)
