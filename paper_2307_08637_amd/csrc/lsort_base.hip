@@ -23,6 +23,14 @@ namespace ls {
 
 constexpr int BASE_THREADS = 256;
 
+// A value the same in every lane, moved to scalar registers: addresses formed
+// from it are a scalar base plus a lane offset.
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Smallest and largest ordered key of a wavefront's item (pads excluded by
 // the caller), in every lane: a butterfly over lane ^ 1 .. lane ^ 32.
 template <int S>
@@ -140,18 +148,27 @@ __device__ __forceinline__ void pay_wave_item(const Params& P, uint64_t off, uin
     auto slot = [](uint32_t j) { return j + (j >> LE); };
     uint64_t k[E];
     uint32_t ix[E];
-    // indices clamp to size - 1: every load is in bounds without a branch (the
-    // pads' payload slots are never read)
-    const uint32_t last = size - 1;
+    {
+        // indices clamp to size - 1: every load is in bounds without a branch
+        // (the pads' payload slots are never read).  Every load is issued
+        // before any is used, so that they are all in flight at once.
+        const uint32_t last = size - 1;
+        uint32_t pr[E];
 #pragma unroll
-    for (int r = 0; r < E; r++) {
-        const uint32_t i = r * WAVE + opaque(lane), c = min(i, last);
-        const uint64_t raw = gload(in + off + c);
-        lp[i] = pin[off + c];
-        k[r] = i < size ? key_ord(raw, u64) : ~0ull;
-        ix[r] = i;
-        // each address formed next to its load
-        __builtin_amdgcn_sched_barrier(0);
+        for (int r = 0; r < E; r++) {
+            const uint32_t c = min<uint32_t>(r * WAVE + opaque(lane), last);
+            k[r] = gload(in + off + c);
+            pr[r] = pin[off + c];
+            // each address formed next to its load
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+            const uint32_t i = r * WAVE + lane;
+            lp[i] = pr[r];
+            k[r] = i < size ? key_ord(k[r], u64) : ~0ull;
+            ix[r] = i;
+        }
     }
     if (!packed_pair_sort<LE>(k, ix, size, lane)) pair_bitonic<LE, 6>(k, ix, lane);
     wave_lds_sync();
@@ -162,20 +179,30 @@ __device__ __forceinline__ void pay_wave_item(const Params& P, uint64_t off, uin
 #pragma unroll
     for (int e = 0; e < E; e++) lr[slot(lane * E + e)] = k[e];
     wave_lds_sync();
+    {
+        // every LDS read before any store: one wait for all of them
+        uint64_t o[E];
 #pragma unroll
-    for (int r = 0; r < E; r++) {
-        const uint32_t j = r * WAVE + opaque(lane);
-        if (j < size) gstore(out + off + j, key_unord(lr[slot(j)], u64));
-        __builtin_amdgcn_sched_barrier(0);
+        for (int r = 0; r < E; r++) o[r] = lr[slot(r * WAVE + lane)];
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+            const uint32_t j = r * WAVE + opaque(lane);
+            if (j < size) gstore(out + off + j, key_unord(o[r], u64));
+        }
     }
     wave_lds_sync();
 #pragma unroll
     for (int e = 0; e < E; e++) lp[slot(lane * E + e)] = pv[e];
     wave_lds_sync();
+    {
+        uint32_t o[E];
 #pragma unroll
-    for (int r = 0; r < E; r++) {
-        const uint32_t j = r * WAVE + opaque(lane);
-        if (j < size) pout[off + j] = lp[slot(j)];
+        for (int r = 0; r < E; r++) o[r] = lp[slot(r * WAVE + lane)];
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+            const uint32_t j = r * WAVE + opaque(lane);
+            if (j < size) pout[off + j] = o[r];
+        }
     }
     wave_lds_sync();  // the next item rewrites the region
 }
@@ -321,31 +348,16 @@ __device__ __forceinline__ void group_loop(const Params& P, const uint64_t* item
 // class is spread evenly), largest items first: tasks of 1 item of
 // 1025..2048 keys and of 2 items of 513..1024 (keys only), of 4 items of
 // 257..512, of 8 of 129..256, of 16 of up to 128.  Separate loops keep each class's loop-invariant registers
-// out of the others'.  With a payload every item is one wave task (the
-// stable sort of (key, index) pairs).
-template <bool PAY, bool U64>
+// out of the others'.  Keys only (with a payload: k_base_pay_small).
+template <bool U64>
 __global__ __launch_bounds__(BASE_THREADS) void k_base_small(Params P) {
     constexpr int W = BASE_THREADS / 64;
-    __shared__ uint64_t glds[PAY ? 1 : W][PAY ? 1 : G_SLOTS];
-    __shared__ uint64_t plr[PAY ? W : 1][PAY ? pay_slots(3) : 1];
+    __shared__ uint64_t glds[W][G_SLOTS];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t waves = (uint64_t)gridDim.x * W, wid = (uint64_t)blockIdx.x * W + wv;
     const uint64_t n0 = min<unsigned long long>(P.ctl->nitems, P.item_cap);
     const uint64_t n1 = min<unsigned long long>(P.ctl->nitems_b, P.item_b_cap);
     const uint64_t nw = min<unsigned long long>(P.ctl->nitems_w, P.item_cap);
-    if (PAY) {
-        for (uint64_t t = wid; t < nw + n1 + n0; t += waves) {
-            const uint64_t wd = t < nw ? P.items[P.item_cap - 1 - t] : t < nw + n1 ? P.items_b[t - nw] : P.items[t - nw - n1];
-            const uint64_t off = wd >> 18;
-            const uint32_t srcb = (wd >> 17) & 1u;
-            const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
-            if (size <= 64) pay_wave_item<0>(P, off, size, srcb, lane, plr[wv]);
-            else if (size <= 128) pay_wave_item<1>(P, off, size, srcb, lane, plr[wv]);
-            else if (size <= 256) pay_wave_item<2>(P, off, size, srcb, lane, plr[wv]);
-            else pay_wave_item<3>(P, off, size, srcb, lane, plr[wv]);
-        }
-        return;
-    }
     const uint64_t nk = min<unsigned long long>(P.ctl->nitems_k, P.item_b_cap);
     const uint64_t nc = min<unsigned long long>(P.ctl->nitems_c, P.item_c_cap);
     // the classes' tasks are dealt out as one list: a class starts at the
@@ -586,17 +598,44 @@ __global__ __launch_bounds__(CAP / MG_OUT) void k_base_merge(Params P) {
     }
 }
 
+// With a payload: items of up to SMALL_MAX keys, one wavefront each
+// (pay_wave_item, 1..8 pairs per lane), the three lists dealt out as one.
+// (Held to 80 registers for six wavefronts per SIMD it spilled and measured
+// 12 % slower.)
+__global__ __launch_bounds__(BASE_THREADS) void k_base_pay_small(Params P) {
+    constexpr int W = BASE_THREADS / 64;
+    __shared__ uint64_t plr[W][pay_slots(3)];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t waves = (uint64_t)gridDim.x * W, wid = (uint64_t)blockIdx.x * W + wv;
+    const uint64_t n0 = min<unsigned long long>(P.ctl->nitems, P.item_cap);
+    const uint64_t n1 = min<unsigned long long>(P.ctl->nitems_b, P.item_b_cap);
+    const uint64_t nw = min<unsigned long long>(P.ctl->nitems_w, P.item_cap);
+    for (uint64_t t = wid; t < nw + n1 + n0; t += waves) {
+        const uint64_t wd = wave_uniform(t < nw ? P.items[P.item_cap - 1 - t] : t < nw + n1 ? P.items_b[t - nw]
+                                                                                         : P.items[t - nw - n1]);
+        const uint64_t off = wd >> 18;
+        const uint32_t srcb = (wd >> 17) & 1u;
+        const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
+        if (size <= 64) pay_wave_item<0>(P, off, size, srcb, lane, plr[wv]);
+        else if (size <= 128) pay_wave_item<1>(P, off, size, srcb, lane, plr[wv]);
+        else if (size <= 256) pay_wave_item<2>(P, off, size, srcb, lane, plr[wv]);
+        else pay_wave_item<3>(P, off, size, srcb, lane, plr[wv]);
+    }
+}
+
 // With a payload: items and chunks of SMALL_MAX+1 .. PAIR_CHUNK keys, one
 // wavefront each (pay_wave_item: 16 pairs per lane, 8 for a chunk of at most
-// 512 keys).
-__global__ __launch_bounds__(BASE_THREADS) void k_base_pairs(Params P) {
+// 512 keys).  Held to 128 registers (four wavefronts per SIMD; a few values
+// of the rarely taken pair network go to scratch): measured ~9 % faster than
+// with the 172 it would take.
+__global__ __launch_bounds__(BASE_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_base_pairs(Params P) {
     constexpr int W = BASE_THREADS / 64;
     __shared__ uint64_t plr[W][pay_slots(4)];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t waves = (uint64_t)gridDim.x * W, wid = (uint64_t)blockIdx.x * W + wv;
     const uint64_t nc = min<unsigned long long>(P.ctl->nitems_c, P.item_c_cap);
     for (uint64_t t = wid; t < nc; t += waves) {
-        const uint64_t wd = P.items_c[t];
+        const uint64_t wd = wave_uniform(P.items_c[t]);
         const uint64_t off = wd >> 18;
         const uint32_t srcb = (wd >> 17) & 1u;
         const uint32_t size = (uint32_t)(wd & 0xffffu) + 1;
@@ -614,11 +653,11 @@ __global__ __launch_bounds__(BASE_THREADS) void k_base_pairs(Params P) {
 
 hipError_t launch_base_small(const Params& P, uint32_t grid, hipStream_t st) {
     if (P.has_pay) {
-        hipLaunchKernelGGL((k_base_small<true, false>), dim3(grid), dim3(BASE_THREADS), 0, st, P);
+        hipLaunchKernelGGL(k_base_pay_small, dim3(grid), dim3(BASE_THREADS), 0, st, P);
         LAUNCH(k_base_pairs, grid, BASE_THREADS, st, P);  // items and chunks of 513..1024 keys
     }
-    if (P.u64) LAUNCH((k_base_small<false, true>), grid, BASE_THREADS, st, P);
-    LAUNCH((k_base_small<false, false>), grid, BASE_THREADS, st, P);
+    if (P.u64) LAUNCH(k_base_small<true>, grid, BASE_THREADS, st, P);
+    LAUNCH(k_base_small<false>, grid, BASE_THREADS, st, P);
 }
 hipError_t launch_base_big(const Params& P, uint32_t grid, hipStream_t st) {
     hipLaunchKernelGGL(k_base_mid<MID_THREADS>, dim3(grid / 2 * 5), dim3(MID_THREADS), 0, st, P);  // 5 per CU
