@@ -641,7 +641,9 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         P.split = split;
         const size_t rec0 = g_trec.size();
         const uint32_t g0 = lvl == 0 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c.m, 1), 4096) : 1024;
-        TIMED(KI_MODEL, c.st, launch_model(P, g0, c.st));
+        // k_model holds a CU's LDS per workgroup: after the first level (mostly
+        // fine windows, a wavefront each) one workgroup per CU
+        TIMED(KI_MODEL, c.st, launch_model(P, lvl == 0 ? g0 : cus, c.st));
         // (after the first level the read-back below says whether any segment is resident)
         if (!c.one_level && (lvl == 0 || fixed || next_res))
             TIMED(KI_RESIDENT, c.st, launch_resident(P, cus * (c.pay ? 2 : 3), c.st));

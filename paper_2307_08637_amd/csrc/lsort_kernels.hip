@@ -356,6 +356,61 @@ __device__ uint32_t sample_slice(uint64_t* smp, const uint64_t* fs, uint64_t S, 
     return m;
 }
 
+// A segment whose model exists already (a fine window of its parent's, or
+// the caller's): no sample, only the bookkeeping below.
+__device__ __forceinline__ bool model_given(const Seg& sg) {
+    return (sg.flags & SEG_PREBUILT) || sg.kind == K_RMI_FINE || sg.kind == K_MLP_FINE;
+}
+
+// Bookkeeping of one segment, by one wavefront: the one-tile re-cut (a level
+// of few work units), counts and look-back reservations, the descriptor,
+// cleared counts and the unit list.  The same steps as the workgroup form at
+// the end of k_model, for a segment whose model is given.
+__device__ __forceinline__ void model_book_wave(Params& P, int lvl, uint32_t s, Seg sg, int lane) {
+    const uint32_t nb = sg.nb, words = sg.flags >> 16;
+    if (P.split && sg.ntiles && !(sg.flags & (SEG_FAILED | SEG_RESIDENT))) {
+        const uint32_t nt2 = (uint32_t)((sg.n + TILE - 1) / TILE);
+        uint32_t t0 = 0;
+        if (lane == 0) t0 = atomicAdd(&P.ctl->nsplit[lvl], nt2);
+        sg.tile0 = __shfl(t0, 0);
+        sg.ntiles = nt2;
+        sg.flags = (sg.flags & ~(7u << SEG_USHIFT_POS)) | (USHIFT_TILE << SEG_USHIFT_POS);
+        if ((uint64_t)sg.tile0 + nt2 > P.tile_cap) {
+            if (lane == 0) atomicOr(&P.ctl->overflow, OVF_TILE);
+            sg.flags |= SEG_FAILED;
+        }
+    }
+    uint64_t cb = 0, sb = 0;
+    uint32_t fl = (sg.flags & 0xffffu) | (words << 16);
+    if (lane == 0) {
+        if (!(fl & SEG_FAILED)) {
+            cb = atomicAdd(&P.ctl->counts_used, 2ull * nb);
+            sb = atomicAdd(&P.ctl->status_used, (unsigned long long)sg.ntiles * nb);
+            if (cb + 2ull * nb > P.counts_cap) { atomicOr(&P.ctl->overflow, OVF_COUNTS); fl |= SEG_FAILED; cb = 0; }
+            if (sb + (uint64_t)sg.ntiles * nb > P.status_cap) {
+                atomicOr(&P.ctl->overflow, OVF_STATUS); fl |= SEG_FAILED; sb = 0;
+            }
+        }
+        if (!sg.model) fl |= SEG_FAILED;
+        Seg& o = P.segs[lvl & 1][s];
+        o.cbase = cb; o.sbase = sb; o.flags = fl;
+        o.tile0 = sg.tile0; o.ntiles = sg.ntiles;
+        if (P.flags & FLAG_STATS) {
+            LevelStats& st = P.ctl->lv[lvl];
+            const uint32_t kind = sg.kind;
+            if (kind == K_RMI || kind == K_RMI_FINE || kind == K_MLP || kind == K_MLP_FINE) atomicAdd(&st.learned, 1ull);
+            else if (kind == K_RADIX) atomicAdd(&st.radix, 1ull);
+            else atomicAdd(&st.tree, 1ull);
+        }
+    }
+    cb = __shfl(cb, 0);
+    fl = __shfl(fl, 0);
+    if (!(fl & (SEG_FAILED | SEG_RESIDENT)))  // k_resident writes its counts whole
+        for (uint32_t b = lane; b < nb; b += WAVE) P.counts[cb + b] = 0;
+    for (uint32_t i = lane; i < sg.ntiles; i += WAVE)
+        if ((uint64_t)sg.tile0 + i < P.tile_cap) P.tiles[lvl & 1][sg.tile0 + i] = Tile{s, i};
+}
+
 __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
     __shared__ uint64_t smp[S_LDS];
     __shared__ uint32_t lstart[L_MAX + 1];
@@ -367,12 +422,23 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
     const uint32_t nseg = min(P.ctl->nseg[lvl], (uint32_t)P.seg_cap);
     const uint64_t* src = P.keys[lvl & 1];
     const int u64 = P.u64;
+    // segments whose model is given: one wavefront each (a level of ~1000
+    // fine windows is bookkeeping only, and a workgroup per segment would
+    // hold a CU's LDS for each)
+    {
+        constexpr int MW = M_THREADS / WAVE;
+        const int lane = tid & (WAVE - 1);
+        for (uint32_t s = blockIdx.x * MW + (tid >> 6); s < nseg; s += gridDim.x * MW) {
+            const Seg sg = P.segs[lvl & 1][s];
+            if (model_given(sg)) model_book_wave(P, lvl, s, sg, lane);
+        }
+    }
     for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
         Seg sg = P.segs[lvl & 1][s];
+        if (model_given(sg)) continue;  // done above (uniform over the workgroup)
         uint32_t kind = sg.kind, nb = sg.nb, words = sg.flags >> 16;
         uint64_t model = sg.model;
-        const bool have = (sg.flags & SEG_PREBUILT) || kind == K_RMI_FINE || kind == K_MLP_FINE;
-        if (!have && kind == K_RADIX) {
+        if (kind == K_RADIX) {
             uint64_t lo = ~0ull, hi = 0;
             for (uint64_t i = tid; i < sg.n; i += M_THREADS) {
                 uint64_t o = key_ord(src[sg.off + i], u64);
@@ -398,7 +464,7 @@ __global__ __launch_bounds__(M_THREADS) void k_model(Params P) {
                 RadixModel* h = (RadixModel*)model;
                 h->lo = lo; h->shift = hi > lo ? shift : 64; h->nb = nb;
             }
-        } else if (!have) {
+        } else {
             // sample (Sec. 2.2: ~1% random sample; Alg. 5 Sample) and sort it
             const uint64_t n = sg.n;
             uint32_t Bt = min(P.tree_buckets, max(2u, floor_pow2((uint32_t)min<uint64_t>(n / 16, 1u << 30))));
