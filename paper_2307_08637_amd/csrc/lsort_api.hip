@@ -312,6 +312,8 @@ struct DevPool {
     hipEvent_t last = nullptr;
     hipStream_t last_stream = nullptr;
     uint64_t* pinned = nullptr;  // host read-back slots
+    hipStream_t rb = nullptr;    // read-back stream: a level's counters copied while its scatter runs
+    hipEvent_t scanned = nullptr;  // recorded after each level's k_scan
     int cus = 0;
     uint64_t sig = 0;            // layout of the last call (status pools valid for it)
 };
@@ -409,6 +411,8 @@ static ls_status pool_init(int dev, DevPool*& pool) {
         HIP_TRY(hipDeviceGetAttribute(&pool->cus, hipDeviceAttributeMultiprocessorCount, dev));
         HIP_TRY(hipEventCreateWithFlags(&pool->last, hipEventDisableTiming));
         HIP_TRY(hipHostMalloc((void**)&pool->pinned, std::max<size_t>(4096, sizeof(Ctl)), hipHostMallocDefault));
+        HIP_TRY(hipStreamCreateWithFlags(&pool->rb, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&pool->scanned, hipEventDisableTiming));
     }
     return LS_OK;
 }
@@ -630,6 +634,12 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
     TIMED(KI_SEED, c.st, launch_seed(P, c.offsets, c.m, c.n, prebuilt, persist, seed_grid, c.st));
     const uint32_t cus = (uint32_t)pool->cus;
     const bool fixed = (c.o.flags & LS_FLAG_FIXED_LEVELS) != 0;
+    if (!fixed) {  // the read-backs between levels cannot be captured
+        bool cap = false;
+        ls_status s0 = capturing(c.st, cap);
+        if (s0) return s0;
+        if (cap) return fail(LS_EINVAL, "a call under stream capture needs LS_FLAG_FIXED_LEVELS");
+    }
     const uint32_t max_run = c.one_level ? 1 : std::min<uint32_t>(MAXL - 1, c.o.max_levels + 9);
     uint32_t levels = 0;
     uint32_t next_res = 0;  // resident segments of the next level (read back)
@@ -650,6 +660,8 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         if (P.ids && lvl <= 1) TIMED(KI_MLP_IDS, c.st, launch_mlp_ids(P, cus * 4, c.st));
         TIMED(KI_HIST, c.st, launch_hist(P, cus * 4, c.st));
         TIMED(KI_SCAN, c.st, launch_scan(P, g0, c.st));
+        const bool readback = !c.one_level && !fixed;
+        if (readback) HIP_TRY(hipEventRecord(pool->scanned, c.st));
         TIMED(KI_SCATTER, c.st, launch_scatter(P, cus, c.st));
         levels = lvl + 1;
         if (c.one_level) {
@@ -662,9 +674,15 @@ static ls_status run(const Call& c, const Layout& L, uint8_t* base, DevPool* poo
         if (fixed) continue;
         // read back the next level's work, the overflow flags and this level's
         // keys: the whole control block in one copy (one copy dispatch instead
-        // of one per field)
-        HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.st));
-        HIP_TRY(hipStreamSynchronize(c.st));
+        // of one per field).  Everything read here is final once k_scan is
+        // done, so the copy runs on the read-back stream while k_scatter runs,
+        // and the next level's launches queue behind the scatter before it
+        // ends (the GPU does not idle through the host's round trip).  The
+        // scatter's only flag (a look-back word without this level's tag,
+        // never expected) is seen at the next read-back.
+        HIP_TRY(hipStreamWaitEvent(pool->rb, pool->scanned, 0));
+        HIP_TRY(hipMemcpyAsync(pool->pinned, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, pool->rb));
+        HIP_TRY(hipStreamSynchronize(pool->rb));
         const Ctl* hc = (const Ctl*)pool->pinned;
         uint32_t next = hc->nseg[lvl + 1];
         uint32_t ovf = hc->overflow;

@@ -102,6 +102,28 @@ def test_capture_needs_caller_workspace(dev):
     del g
 
 
+def test_capture_needs_fixed_levels(dev):
+    """Under stream capture a call must launch a fixed number of levels: the
+    read-backs between levels cannot be captured, so a call without
+    LS_FLAG_FIXED_LEVELS is refused (with a caller-owned workspace set)."""
+    keys, off, pay, _ = inputs.segmented(20, seed=45, lo=100, hi=1e4)
+    t, o, p = upload(keys, off, pay, dev)
+    nbytes = lsort.workspace_bytes(keys.size, off.size - 1, payload=True)
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=dev)
+    lsort.set_workspace(ws)
+    try:
+        lsort.sort_segmented(t, o, p, stats=False)  # set-up outside capture: this layout's look-back words
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with pytest.raises(lsort.LsortError, match="FIXED_LEVELS"):
+            with torch.cuda.graph(g):
+                lsort.sort_segmented(t, o, p, stats=False)
+    finally:
+        torch.cuda.synchronize()
+        lsort.set_workspace(None)
+    del g
+
+
 def test_c4_prefix_properties(dev):
     """The batched workload (10,000 arrays, sizes log-uniform in [1e3, 1e6],
     five laws, payload) up to its first 2e8 keys: every array sorted, the
