@@ -74,7 +74,8 @@ typedef enum {
 #define LS_FLAG_FIXED_LEVELS  0x4u  /* no host read-back: launch every level the depth cap allows,
                                        min(max_levels + 9, 31) (max_levels model-based levels, then up to
                                        8 range-radix levels and one more), each exiting at once when it
-                                       has no work; needed for stream capture.  The host cannot see a
+                                       has no work; needed for stream capture (a call under capture
+                                       without it returns LS_EINVAL).  The host cannot see a
                                        workspace overflow then: read ls_get_stats().overflow after the
                                        call (or after a graph replay); nonzero means the output is
                                        invalid */
