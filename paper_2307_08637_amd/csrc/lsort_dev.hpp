@@ -757,52 +757,6 @@ __device__ __forceinline__ void pair_bitonic(uint64_t (&k)[1 << LE], uint32_t (&
     pair_phases<LE, LG, 1>(k, x, lane);
 }
 
-// Bitonic sort of 64*E (key, index) pairs held by one wavefront, lane l
-// holding elements l*E .. l*E+E-1 in registers.  Compare-exchanges between
-// elements of one lane stay in registers; those between lanes exchange
-// through DPP / permlane lane exchanges.  No LDS, no barriers.  Pairs are ordered by
-// key, then index (indices are distinct), so the result is the stable order.
-template <int E, bool PAIRS>
-__device__ __forceinline__ void wave_bitonic(uint64_t (&k)[E], uint32_t (&ix)[E], int lane) {
-    constexpr int N = 64 * E;
-#pragma unroll
-    for (int kk = 2; kk <= N; kk <<= 1) {
-#pragma unroll
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            if (j < E) {
-#pragma unroll
-                for (int e = 0; e < E; e++) {
-                    if ((e & j) == 0) {
-                        const int f = e | j;
-                        const bool up = ((lane * E + e) & kk) == 0;
-                        const bool gt = k[e] > k[f] || (PAIRS && k[e] == k[f] && ix[e] > ix[f]);
-                        if (gt == up) {
-                            uint64_t t = k[e]; k[e] = k[f]; k[f] = t;
-                            if (PAIRS) { uint32_t u = ix[e]; ix[e] = ix[f]; ix[f] = u; }
-                        }
-                    }
-                }
-            } else {
-                const int s = j / E;
-                // keep the smaller of the pair on one side, the larger on the
-                // other: take the partner's element iff (partner < mine) differs
-                // from "keep the larger" (equal elements are interchangeable)
-                const bool keep_max = (((lane * E) & kk) == 0) != ((lane & s) == 0);
-#pragma unroll
-                for (int e = 0; e < E; e++) {
-                    const uint64_t y = xor_lane64(k[e], s, (uint32_t)lane);
-                    const uint32_t iy = PAIRS ? xor_lane32(ix[e], s, (uint32_t)lane) : 0u;
-                    const bool lt = y < k[e] || (PAIRS && y == k[e] && iy < ix[e]);
-                    if (lt != keep_max) {
-                        k[e] = y;
-                        if (PAIRS) ix[e] = iy;
-                    }
-                }
-            }
-        }
-    }
-}
-
 // Bitonic sort of NT*E (key[, index]) pairs by a workgroup of NT threads,
 // thread t holding elements t*E .. t*E+E-1 in registers.  Stages with
 // distance j < E stay in registers, E <= j < 64E exchange through cross-lane
