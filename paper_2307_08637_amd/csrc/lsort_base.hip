@@ -12,13 +12,14 @@ namespace ls {
 
 // ===========================================================================
 // Base case (Sec. 4: sub-arrays below the cutoff are sorted directly).
-// k_base_small: sub-arrays of at most 2048 keys sorted in registers by groups
-// of 4, 8, 16, 32 or 64 lanes (group_bitonic, 16 .. 1 sub-arrays per
-// wavefront); with a payload, sub-arrays of at most 512 keys, one per
-// wavefront, as (key, index) pairs (packed_pair_sort, else pair_bitonic);
-// k_base_pairs: with a payload, 513..1024 keys the same way; k_base_merge:
-// chunk-and-merge items; k_base_big: one workgroup per larger sub-array
-// (up to 8192) sorted in LDS, and the copies of finished runs.
+// k_base_small: keys only, sub-arrays of at most 2048 keys sorted in
+// registers by groups of 4, 8, 16, 32 or 64 lanes (group_bitonic, 16 .. 1
+// sub-arrays per wavefront); k_base_pay_small: with a payload, sub-arrays of
+// at most 512 keys, one per wavefront, as (key, index) pairs
+// (packed_pair_sort, else pair_bitonic); k_base_pairs: with a payload,
+// 513..1024 keys the same way; k_base_merge: chunk-and-merge items;
+// k_base_big: one workgroup per larger sub-array (up to 8192) sorted in LDS,
+// and the copies of finished runs.
 // ===========================================================================
 
 constexpr int BASE_THREADS = 256;
