@@ -311,6 +311,73 @@ __global__ __launch_bounds__(FIT_LT) void k_fit_lsum(FitArgs A) {
     if (threadIdx.x == 0) A.lpart[blockIdx.x * 4 + 0] = s;
 }
 
+// Leaves of at most FIT_SMALL_LEAF points (most of them: a leaf holds ~S / L
+// points), four per workgroup, a quarter of 256 threads each: the mean of x,
+// then the centred sums, into the leaf's slot (piece 0 is slot j).  Larger
+// leaves (the end leaves of a law's tails, and the leaves of several pieces)
+// keep a whole workgroup per piece in k_fit_leaves.
+constexpr int FIT_Q = FIT_LT / 4;
+constexpr uint64_t FIT_SMALL_LEAF = 2ull * FIT_Q * FIT_LU;  // two rounds of loads per thread
+static_assert(FIT_SMALL_LEAF < FIT_PIECE, "a small leaf is one piece");
+__device__ __forceinline__ double quarter_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, q0 = (threadIdx.x / FIT_Q) * (FIT_Q / 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0;
+#pragma unroll
+    for (int i = 0; i < FIT_Q / 64; i++) t += red[q0 + i];
+    return t;
+}
+
+__global__ __launch_bounds__(FIT_LT) void k_fit_leaves1(FitArgs A) {
+    __shared__ double red[FIT_LT / 64];
+    if (A.flag[0] == 0) return;
+    const uint32_t j = blockIdx.x * 4 + threadIdx.x / FIT_Q, t = threadIdx.x % FIT_Q;
+    const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
+    uint64_t lo = 0, hi = 0;
+    if (j < A.L) {
+        lo = bounds[j];
+        hi = bounds[j + 1];
+        if (hi - lo > FIT_SMALL_LEAF) hi = lo;  // k_fit_leaves' leaf (of one piece or several)
+    }
+    const double Sd = (double)A.S, invS = 1.0 / Sd;
+    double s = 0;
+    for (uint64_t i0 = lo + t; i0 < hi; i0 += (uint64_t)FIT_Q * FIT_LU) {
+        uint64_t r[FIT_LU];
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++) r[u] = i0 + (uint64_t)u * FIT_Q < hi ? A.s[i0 + (uint64_t)u * FIT_Q] : 0;
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++)
+            if (i0 + (uint64_t)u * FIT_Q < hi) { double x; key_x(r[u], A.u64, x); s += x; }
+    }
+    s = quarter_sum(s, red);
+    const double mx = hi > lo ? s / (double)(hi - lo) : 0.0, my = ((double)lo + (double)hi - 1.0) / (2.0 * Sd);
+    double sxx = 0, sxy = 0;
+    for (uint64_t i0 = lo + t; i0 < hi; i0 += (uint64_t)FIT_Q * FIT_LU) {
+        uint64_t r[FIT_LU];
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++) r[u] = i0 + (uint64_t)u * FIT_Q < hi ? A.s[i0 + (uint64_t)u * FIT_Q] : 0;
+#pragma unroll
+        for (int u = 0; u < FIT_LU; u++) {
+            const uint64_t i = i0 + (uint64_t)u * FIT_Q;
+            if (i < hi) {
+                double x; key_x(r[u], A.u64, x);
+                double dx = x - mx, dy = (double)i * invS - my;
+                sxx += dx * dx; sxy += dx * dy;
+            }
+        }
+    }
+    sxx = quarter_sum(sxx, red);
+    sxy = quarter_sum(sxy, red);
+    if (t == 0 && j < A.L && (hi > lo || bounds[j + 1] == bounds[j])) {  // this kernel's leaf
+        A.lpart[j * 4 + 0] = s;
+        A.lpart[j * 4 + 1] = sxx;
+        A.lpart[j * 4 + 2] = sxy;
+    }
+}
+
 __global__ __launch_bounds__(FIT_LT) void k_fit_leaves(FitArgs A) {
     __shared__ double red[FIT_LT / 64];
     __shared__ uint64_t red64[FIT_LT / 64];
@@ -322,6 +389,7 @@ __global__ __launch_bounds__(FIT_LT) void k_fit_leaves(FitArgs A) {
     if (!my_piece(A, j, q, ex, np, red64, sh)) return;
     const uint64_t* bounds = (const uint64_t*)(A.leaf + (uint64_t)L_MAX * 8);
     const uint64_t llo = bounds[j], lhi = bounds[j + 1];
+    if (np == 1 && lhi - llo <= FIT_SMALL_LEAF) return;  // k_fit_leaves1
     const uint64_t lo = llo + q * A.piece, hi = min(lhi, lo + A.piece);
     const double Sd = (double)A.S, invS = 1.0 / Sd;
     if (np == 1) {  // the whole leaf: its own sum of x
@@ -578,6 +646,7 @@ hipError_t launch_fit_leaves(const FitArgs& A0, hipStream_t st) {
     if (e != hipSuccess) return e;
     const uint32_t pieces = A.L + (uint32_t)((A.S + A.piece - 1) / A.piece);  // bounds every leaf's piece count
     hipLaunchKernelGGL(k_fit_lsum, dim3(pieces), dim3(FIT_LT), 0, st, A);
+    hipLaunchKernelGGL(k_fit_leaves1, dim3((A.L + 3) / 4), dim3(FIT_LT), 0, st, A);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     LAUNCH(k_fit_leaves, pieces, FIT_LT, st, A);

@@ -31,7 +31,7 @@ struct FitArgs {
     double* lpart;       // leaf least squares: 4 sums per piece of a leaf (set by the launchers)
     uint64_t piece;      // sample points per piece
 };
-constexpr uint64_t FIT_PIECE = 65536;   // sample points per workgroup of a leaf's least-squares passes
+constexpr uint64_t FIT_PIECE = 8192;    // sample points per workgroup of a leaf's least-squares passes
 constexpr uint64_t FIT_PIECES = 1024;   // pieces beyond one per leaf (the piece grows for larger samples)
 
 // MLP training (lsort_mlp.hip)

@@ -65,7 +65,7 @@ def check_fit(gp, s, L, R):
 
 @pytest.mark.parametrize("law,L,S", [("uniform", 1000, 10_000), ("lognormal", 1000, 1_000_000), ("normal", 64, 5000),
                                      ("u64", 1000, 200_000), ("mixgauss", 513, 77_777), ("exponential", 2, 1000),
-                                     # leaves of more than one 65536-point piece (summed by several workgroups)
+                                     # leaves of more than one piece (summed by several workgroups)
                                      ("piecewise", 1000, 1_000_000), ("normal", 3, 400_000)])
 def test_rmi_fit(dev, law, L, S):
     keys = inputs.generate(law, max(S * 10, 100_000), seed=5)
